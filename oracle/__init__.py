@@ -36,6 +36,7 @@ from .wilson import (  # noqa: F401
     clover_apply,
     dwc,
     dwc_mass,
+    dwc_sites,
     gauge_transform,
     spinor_gauge_transform,
 )

@@ -251,3 +251,40 @@ def spinor_gauge_transform(psi: np.ndarray, Lam: np.ndarray) -> np.ndarray:
     """(Lambda psi)(x): colour rotation of every spin component."""
     ps = _spin_colour(psi)
     return np.einsum("vab,vsbn->vsan", Lam, ps).reshape(psi.shape)
+
+
+def dwc_sites(U, Apacked, kappa, psi, dims, sites, t_bc=-1.0) -> np.ndarray:
+    """(D psi)(x) at the listed sites only, shape (len(sites), 12, N).
+
+    Same definition as dwc(), evaluated by gathering the eight neighbours of
+    each requested site explicitly; used to check outputs of lattices too
+    large for a whole-lattice FP64 apply.
+    """
+    Lx, Ly, Lz, Lt = dims
+    L = np.array(dims)
+    stride = np.array([1, Lx, Lx * Ly, Lx * Ly * Lz])
+    sites = np.asarray(sites)
+    X = np.stack([sites % Lx, (sites // Lx) % Ly, (sites // (Lx * Ly)) % Lz, sites // (Lx * Ly * Lz)], axis=1)
+    g = gamma_matrices()
+    I4 = np.eye(4)
+    N = psi.shape[-1]
+    acc = np.zeros((len(sites), 4, 3, N), dtype=np.complex128)
+    for mu in range(4):
+        for sgn in (+1, -1):
+            Y = X.copy()
+            Y[:, mu] = (Y[:, mu] + sgn) % L[mu]
+            nb = Y @ stride
+            wrapped = (X[:, mu] == L[mu] - 1) if sgn > 0 else (X[:, mu] == 0)
+            ph = np.where(wrapped & (mu == 3), t_bc, 1.0)
+            p = np.asarray(psi[nb], dtype=np.complex128).reshape(len(sites), 4, 3, N)
+            if sgn > 0:
+                link = np.asarray(U[sites, mu], dtype=np.complex128)
+                proj = I4 - g[mu]
+            else:
+                link = np.conj(np.swapaxes(np.asarray(U[nb, mu], dtype=np.complex128), -1, -2))
+                proj = I4 + g[mu]
+            t = np.einsum("vab,vsbn->vsan", link, p)
+            acc += ph[:, None, None, None] * np.einsum("st,vtan->vsan", proj, t)
+    A_here = np.asarray(Apacked[sites], dtype=np.float64)
+    here = np.asarray(psi[sites], dtype=np.complex128)
+    return clover_apply(A_here, here) - kappa * acc.reshape(len(sites), 12, N)

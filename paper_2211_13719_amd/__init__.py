@@ -1,0 +1,151 @@
+"""MI355X MRHS Wilson-clover multigrid hot path: thin Python binding over libmrhs.
+
+Every operation runs in the HIP library (``libmrhs.so``, built in-tree for
+gfx950); this module only marshals arguments.  PyTorch provides device
+memory and the stream: fields are CUDA/HIP tensors of dtype complex64 (FP32)
+or complex128 (FP64) laid out [site][component][rhs], exactly the C layout.
+
+    ctx = Context((24, 24, 24, 24), t_bc=-1)
+    ctx.set_gauge(U)                  # (V, 4, 3, 3) complex, host or device
+    ctx.build_clover(csw=1.0, kappa=0.13)
+    ctx.dwc(out, psi)                 # out = (A - kappa H) psi, psi (V, 12, N)
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import BF16, F16, F32, F64, MrhsError  # noqa: F401
+
+lib = _lib.lib
+
+__all__ = ["Context", "MrhsError", "F64", "F32", "BF16", "F16", "lib"]
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _prec_of(t) -> int:
+    torch = _torch()
+    if t.dtype in (torch.complex128, torch.float64):
+        return F64
+    if t.dtype in (torch.complex64, torch.float32):
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr_of(a):
+    """(pointer, prec, on_device) of a numpy array or a torch tensor (contiguous)."""
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        if a.dtype in (np.complex128, np.float64):
+            p = F64
+        elif a.dtype in (np.complex64, np.float32):
+            p = F32
+        else:
+            raise TypeError(f"unsupported dtype {a.dtype}")
+        return a.ctypes.data, p, 0
+    if not a.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return a.data_ptr(), _prec_of(a), int(a.is_cuda)
+
+
+class Context:
+    """One lattice on one GPU; wraps an ``mrhs_ctx``."""
+
+    def __init__(self, dims, t_bc: int = -1, device: int = 0, stream=None):
+        torch = _torch()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = C.c_void_p()
+        d = (C.c_int32 * 4)(*self.dims)
+        st = lib.mrhs_create(C.byref(h), d, int(t_bc), int(device), C.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise MrhsError(st, lib.mrhs_last_error(None).decode())
+        self._h = h
+
+    # -- plumbing -------------------------------------------------------------
+    def _check(self, st: int):
+        if st != 0:
+            raise MrhsError(st, lib.mrhs_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.mrhs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def synchronize(self):
+        self._check(lib.mrhs_synchronize(self._h))
+
+    def set_stream(self, stream):
+        self._stream = stream
+        self._check(lib.mrhs_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    # -- gauge and clover ---------------------------------------------------------
+    def set_gauge(self, U):
+        if tuple(U.shape) != (self.V, 4, 3, 3):
+            raise ValueError(f"gauge shape {tuple(U.shape)} != {(self.V, 4, 3, 3)}")
+        p, prec, dev = _ptr_of(U)
+        self._check(lib.mrhs_set_gauge(self._h, C.c_void_p(p), prec, dev))
+
+    def build_clover(self, csw: float, kappa: float):
+        self._check(lib.mrhs_build_clover(self._h, float(csw), float(kappa)))
+        self.kappa = float(kappa)
+
+    def set_clover(self, A, kappa: float):
+        if tuple(A.shape) != (self.V, 2, 36):
+            raise ValueError(f"clover shape {tuple(A.shape)} != {(self.V, 2, 36)}")
+        p, prec, dev = _ptr_of(A)
+        self._check(lib.mrhs_set_clover(self._h, C.c_void_p(p), prec, dev, float(kappa)))
+        self.kappa = float(kappa)
+
+    def get_clover(self, prec: int = F64) -> np.ndarray:
+        out = np.empty((self.V, 2, 36), dtype=np.float64 if prec == F64 else np.float32)
+        self._check(lib.mrhs_get_clover(self._h, C.c_void_p(out.ctypes.data), prec, 0))
+        return out
+
+    # -- fine operator ---------------------------------------------------------------
+    def _fine(self, fn, out, inp):
+        if inp.dim() != 3 or inp.shape[0] != self.V or inp.shape[1] != 12:
+            raise ValueError(f"field shape {tuple(inp.shape)} is not (V={self.V}, 12, N)")
+        if out.shape != inp.shape or out.dtype != inp.dtype:
+            raise ValueError("out must match in (shape and dtype)")
+        if not (inp.is_cuda and out.is_cuda):
+            raise ValueError("fields must be device tensors")
+        pi, prec, _ = _ptr_of(inp)
+        po, _, _ = _ptr_of(out)
+        self._check(fn(self._h, C.c_void_p(po), C.c_void_p(pi), int(inp.shape[2]), prec))
+        return out
+
+    def dwc(self, out, inp):
+        """out = (A - kappa H) inp."""
+        return self._fine(lib.mrhs_dwc_apply, out, inp)
+
+    def hop(self, out, inp):
+        """out = H inp."""
+        return self._fine(lib.mrhs_hop_apply, out, inp)
+
+    def clover(self, out, inp):
+        """out = A inp."""
+        return self._fine(lib.mrhs_clover_apply, out, inp)

@@ -1,0 +1,70 @@
+"""ctypes loader for libmrhs.so: argument types of every exported entry point.
+
+The library is built in-tree by ``python -m paper_2211_13719_amd.build``.
+Importing this module without the built library raises ImportError: there
+is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmrhs.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+
+STATUS = {
+    0: "MRHS_OK",
+    1: "MRHS_ERR_INVALID_ARG",
+    2: "MRHS_ERR_SHAPE",
+    3: "MRHS_ERR_UNSUPPORTED",
+    4: "MRHS_ERR_STATE",
+    5: "MRHS_ERR_OOM",
+    6: "MRHS_ERR_HIP",
+    7: "MRHS_ERR_NOT_CONVERGED",
+}
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_f64 = C.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mrhs_create": (_i32, [C.POINTER(_vp), C.POINTER(_i32), _i32, _i32, _vp]),
+    "mrhs_destroy": (None, [_vp]),
+    "mrhs_last_error": (C.c_char_p, [_vp]),
+    "mrhs_set_stream": (_i32, [_vp, _vp]),
+    "mrhs_synchronize": (_i32, [_vp]),
+    "mrhs_set_gauge": (_i32, [_vp, _vp, _i32, _i32]),
+    "mrhs_build_clover": (_i32, [_vp, _f64, _f64]),
+    "mrhs_set_clover": (_i32, [_vp, _vp, _i32, _i32, _f64]),
+    "mrhs_get_clover": (_i32, [_vp, _vp, _i32, _i32]),
+    "mrhs_dwc_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
+    "mrhs_hop_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
+    "mrhs_clover_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
+}
+
+
+class MrhsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing; build it with `python -m paper_2211_13719_amd.build` "
+            "(the HIP library is required, there is no CPU fallback)"
+        )
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()

@@ -1,0 +1,279 @@
+// C-ABI entry points of libmrhs: context handling, argument validation and
+// dispatch to the kernel launchers.  Every entry point validates on the host
+// before launching anything and converts failures to an mrhs_status with a
+// message in the context.
+#include <algorithm>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace {
+thread_local std::string g_create_error;
+
+const char* prec_name(mrhs_prec p) {
+  switch (p) {
+    case MRHS_F64:
+      return "f64";
+    case MRHS_F32:
+      return "f32";
+    case MRHS_BF16:
+      return "bf16";
+    case MRHS_F16:
+      return "f16";
+  }
+  return "?";
+}
+}  // namespace
+
+namespace mrhs {
+
+mrhs_status fail(mrhs_ctx ctx, mrhs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx)
+    ctx->err = buf;
+  else
+    g_create_error = buf;
+  return st;
+}
+
+mrhs_status hip_fail(mrhs_ctx ctx, hipError_t e, const char* what) {
+  const mrhs_status st = (e == hipErrorOutOfMemory) ? MRHS_ERR_OOM : MRHS_ERR_HIP;
+  return fail(ctx, st, "%s failed: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+mrhs_status ensure(mrhs_ctx ctx, Buffer& b, size_t bytes) {
+  if (b.p && b.bytes >= bytes) return MRHS_OK;
+  release(b);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MRHS_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.p = p;
+  b.bytes = bytes;
+  return MRHS_OK;
+}
+
+void release(Buffer& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+}  // namespace mrhs
+
+using namespace mrhs;
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+mrhs_status check_field_args(mrhs_ctx ctx, const void* out, const void* in, int32_t nrhs, mrhs_prec prec,
+                             size_t elems_per_rhs_site, int64_t nsites) {
+  if (!out || !in) return fail(ctx, MRHS_ERR_INVALID_ARG, "null field pointer");
+  if (!aligned16(out) || !aligned16(in)) return fail(ctx, MRHS_ERR_INVALID_ARG, "field pointers must be 16-byte aligned");
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  if (prec != MRHS_F32 && prec != MRHS_F64)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "precision %s not supported for this call", prec_name(prec));
+  const size_t csize = (prec == MRHS_F64) ? 16 : 8;
+  const size_t bytes = (size_t)nsites * elems_per_rhs_site * nrhs * csize;
+  const char* a = static_cast<const char*>(in);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return fail(ctx, MRHS_ERR_INVALID_ARG, "in and out overlap");
+  return MRHS_OK;
+}
+
+mrhs_status fine_apply(mrhs_ctx ctx, int mode, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V);
+  if (st != MRHS_OK) return st;
+  if (mode != 2 && !ctx->have_gauge) return fail(ctx, MRHS_ERR_STATE, "gauge field not set");
+  if (mode != 1 && !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "clover term not set");
+  DeviceGuard dg(ctx->device);
+  hipError_t e;
+  if (prec == MRHS_F32)
+    e = launch_fine_f32(ctx->g, ctx->t_bc, mode, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, nrhs,
+                        ctx->stream);
+  else
+    e = launch_fine_f64(ctx->g, ctx->t_bc, mode, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, nrhs, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fine operator launch");
+  return MRHS_OK;
+}
+
+// Copy n doubles or floats (given prec) from a host or device pointer into
+// the FP64 and FP32 library buffers.
+mrhs_status import_real_array(mrhs_ctx ctx, const void* src, mrhs_prec prec, int on_device, size_t n,
+                              Buffer& b64, Buffer& b32) {
+  mrhs_status st = ensure(ctx, b64, n * 8);
+  if (st != MRHS_OK) return st;
+  st = ensure(ctx, b32, n * 4);
+  if (st != MRHS_OK) return st;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (prec == MRHS_F64) {
+    MRHS_HIP(ctx, hipMemcpyAsync(b64.p, src, n * 8, kind, ctx->stream));
+    MRHS_HIP(ctx, launch_convert_f64_to_f32(static_cast<const double*>(b64.p), static_cast<float*>(b32.p), n,
+                                            ctx->stream));
+  } else {
+    MRHS_HIP(ctx, hipMemcpyAsync(b32.p, src, n * 4, kind, ctx->stream));
+    MRHS_HIP(ctx, launch_convert_f32_to_f64(static_cast<const float*>(b32.p), static_cast<double*>(b64.p), n,
+                                            ctx->stream));
+  }
+  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return MRHS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrhs_status mrhs_create(mrhs_ctx* out, const int32_t dims[4], int32_t t_bc, int32_t device, void* stream) {
+  g_create_error.clear();
+  if (!out || !dims) return fail(nullptr, MRHS_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (t_bc != 1 && t_bc != -1) return fail(nullptr, MRHS_ERR_INVALID_ARG, "t_bc must be +1 or -1, got %d", t_bc);
+  int64_t V = 1;
+  for (int m = 0; m < 4; ++m) {
+    if (dims[m] < 2) return fail(nullptr, MRHS_ERR_SHAPE, "lattice extent %d in direction %d is below 2", dims[m], m);
+    V *= dims[m];
+  }
+  if (V * 64 >= (int64_t(1) << 31)) return fail(nullptr, MRHS_ERR_SHAPE, "lattice volume %lld too large", (long long)V);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, MRHS_ERR_INVALID_ARG, "device %d not available (%d devices)", device, ndev);
+  mrhs_ctx ctx = new (std::nothrow) mrhs_ctx_s();
+  if (!ctx) return fail(nullptr, MRHS_ERR_OOM, "host allocation failed");
+  for (int m = 0; m < 4; ++m) ctx->g.L[m] = dims[m];
+  ctx->g.V = (int)V;
+  ctx->g.stride[0] = 1;
+  ctx->g.stride[1] = dims[0];
+  ctx->g.stride[2] = dims[0] * dims[1];
+  ctx->g.stride[3] = dims[0] * dims[1] * dims[2];
+  ctx->t_bc = t_bc;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  *out = ctx;
+  return MRHS_OK;
+}
+
+void mrhs_destroy(mrhs_ctx ctx) {
+  if (!ctx) return;
+  DeviceGuard dg(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  release(ctx->U64);
+  release(ctx->U32);
+  release(ctx->A64);
+  release(ctx->A32);
+  delete ctx;
+}
+
+const char* mrhs_last_error(mrhs_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+mrhs_status mrhs_set_stream(mrhs_ctx ctx, void* stream) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_synchronize(mrhs_ctx ctx) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  DeviceGuard dg(ctx->device);
+  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_set_gauge(mrhs_ctx ctx, const void* U, mrhs_prec prec, int32_t on_device) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (!U) return fail(ctx, MRHS_ERR_INVALID_ARG, "null gauge pointer");
+  if (prec != MRHS_F64 && prec != MRHS_F32)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "gauge precision %s not supported", prec_name(prec));
+  DeviceGuard dg(ctx->device);
+  const size_t n = (size_t)ctx->g.V * 4 * 9 * 2;
+  mrhs_status st = import_real_array(ctx, U, prec, on_device, n, ctx->U64, ctx->U32);
+  if (st != MRHS_OK) return st;
+  ctx->have_gauge = true;
+  ctx->have_clover = false;  // a clover term built from old links is stale
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_build_clover(mrhs_ctx ctx, double csw, double kappa) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (!ctx->have_gauge) return fail(ctx, MRHS_ERR_STATE, "gauge field not set");
+  DeviceGuard dg(ctx->device);
+  const size_t n = (size_t)ctx->g.V * 2 * 36;
+  mrhs_status st = ensure(ctx, ctx->A64, n * 8);
+  if (st != MRHS_OK) return st;
+  st = ensure(ctx, ctx->A32, n * 4);
+  if (st != MRHS_OK) return st;
+  Buffer F;
+  st = ensure(ctx, F, (size_t)ctx->g.V * 6 * 9 * 16);
+  if (st != MRHS_OK) return st;
+  hipError_t e = launch_clover_build(ctx->g, csw, kappa, ctx->U64.p, F.p, ctx->A64.p, ctx->A32.p, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release(F);
+  if (e != hipSuccess) return hip_fail(ctx, e, "clover build");
+  ctx->kappa = kappa;
+  ctx->have_clover = true;
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_set_clover(mrhs_ctx ctx, const void* A, mrhs_prec prec, int32_t on_device, double kappa) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (!A) return fail(ctx, MRHS_ERR_INVALID_ARG, "null clover pointer");
+  if (prec != MRHS_F64 && prec != MRHS_F32)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "clover precision %s not supported", prec_name(prec));
+  DeviceGuard dg(ctx->device);
+  const size_t n = (size_t)ctx->g.V * 2 * 36;
+  mrhs_status st = import_real_array(ctx, A, prec, on_device, n, ctx->A64, ctx->A32);
+  if (st != MRHS_OK) return st;
+  ctx->kappa = kappa;
+  ctx->have_clover = true;
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_get_clover(mrhs_ctx ctx, void* A, mrhs_prec prec, int32_t on_device) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (!A) return fail(ctx, MRHS_ERR_INVALID_ARG, "null clover pointer");
+  if (!ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "clover term not set");
+  if (prec != MRHS_F64 && prec != MRHS_F32)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "clover precision %s not supported", prec_name(prec));
+  DeviceGuard dg(ctx->device);
+  const size_t n = (size_t)ctx->g.V * 2 * 36;
+  const Buffer& b = (prec == MRHS_F64) ? ctx->A64 : ctx->A32;
+  const size_t bytes = n * (prec == MRHS_F64 ? 8 : 4);
+  MRHS_HIP(ctx, hipMemcpyAsync(A, b.p, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               ctx->stream));
+  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_dwc_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
+  return fine_apply(ctx, 0, out, in, nrhs, prec);
+}
+
+mrhs_status mrhs_hop_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
+  return fine_apply(ctx, 1, out, in, nrhs, prec);
+}
+
+mrhs_status mrhs_clover_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
+  return fine_apply(ctx, 2, out, in, nrhs, prec);
+}
+
+}  // extern "C"

@@ -1,0 +1,410 @@
+// Fine-level Wilson-clover operator on Nrhs right-hand sides at once
+// (paper Sec. 4: the hopping term D_hop and the clover term M_ooee).
+//
+//   out = A psi - kappa H psi,   A = 1 + C in two Hermitian 6x6 chiral blocks,
+//   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu).
+//
+// Work decomposition: one thread owns one site and R consecutive right-hand
+// sides.  Fields are [site][12][nrhs] complex, so the nrhs/R threads of a site
+// are adjacent lanes that read contiguous memory for every component, and all
+// of them share the site's links and clover blocks (one cache line serves the
+// whole group: the gauge-field reuse of Sec. 2).  Each neighbour spinor is
+// spin-projected to a half spinor (2 spins x 3 colours) before the SU(3)
+// product, which halves the link arithmetic.
+//
+// The gamma matrices are the chiral basis, gamma_k = [[0, -i s_k], [i s_k, 0]],
+// gamma_4 = [[0, 1], [1, 0]].  Writing psi = (u0, u1, l0, l1) in spin, the
+// projection (1 -+ gamma_mu) psi has upper half h = (h0, h1) and lower half a
+// fixed multiple of h, listed per direction in project()/reconstruct().
+#include "internal.h"
+
+namespace mrhs {
+namespace {
+
+template <typename T>
+struct cplx_t;
+template <>
+struct cplx_t<float> {
+  using type = float2;
+};
+template <>
+struct cplx_t<double> {
+  using type = double2;
+};
+
+template <typename T>
+using cplx = typename cplx_t<T>::type;
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T re, T im) {
+  cplx<T> z;
+  z.x = re;
+  z.y = im;
+  return z;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> add(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> sub(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x - b.x, a.y - b.y);
+}
+// a + i b, a - i b
+template <typename T>
+__device__ __forceinline__ cplx<T> addi(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x - b.y, a.y + b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> subi(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x + b.y, a.y - b.x);
+}
+// acc += a * b ; acc += conj(a) * b
+template <typename T>
+__device__ __forceinline__ void cmac(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+template <typename T>
+__device__ __forceinline__ void cmac_conj(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+
+// Load R consecutive complex numbers starting at p (R-aligned element offset).
+template <typename T, int R>
+__device__ __forceinline__ void load_r(const cplx<T>* __restrict__ p, cplx<T> (&v)[R]) {
+  if constexpr (sizeof(T) == 4 && R % 2 == 0) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int j = 0; j < R / 2; ++j) {
+      float4 w = q[j];
+      v[2 * j] = mk<T>(w.x, w.y);
+      v[2 * j + 1] = mk<T>(w.z, w.w);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = p[j];
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void store_r(cplx<T>* __restrict__ p, const cplx<T> (&v)[R]) {
+  if constexpr (sizeof(T) == 4 && R % 2 == 0) {
+    float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int j = 0; j < R / 2; ++j) q[j] = make_float4(v[2 * j].x, v[2 * j].y, v[2 * j + 1].x, v[2 * j + 1].y);
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) p[j] = v[j];
+  }
+}
+
+// Half spinor of (1 - s*gamma_mu) psi, s = +1 (forward hop) or -1 (backward hop).
+// psi[spin][colour][rhs] -> h[2][3][R]
+template <typename T, int R, int MU, int S>
+__device__ __forceinline__ void project(const cplx<T> (&p)[4][3][R], cplx<T> (&h)[2][3][R]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if constexpr (MU == 0) {  // gamma_1: h0 = u0 +- i l1, h1 = u1 +- i l0
+        h[0][c][j] = S > 0 ? addi<T>(p[0][c][j], p[3][c][j]) : subi<T>(p[0][c][j], p[3][c][j]);
+        h[1][c][j] = S > 0 ? addi<T>(p[1][c][j], p[2][c][j]) : subi<T>(p[1][c][j], p[2][c][j]);
+      } else if constexpr (MU == 1) {  // gamma_2: h0 = u0 +- l1, h1 = u1 -+ l0
+        h[0][c][j] = S > 0 ? add<T>(p[0][c][j], p[3][c][j]) : sub<T>(p[0][c][j], p[3][c][j]);
+        h[1][c][j] = S > 0 ? sub<T>(p[1][c][j], p[2][c][j]) : add<T>(p[1][c][j], p[2][c][j]);
+      } else if constexpr (MU == 2) {  // gamma_3: h0 = u0 +- i l0, h1 = u1 -+ i l1
+        h[0][c][j] = S > 0 ? addi<T>(p[0][c][j], p[2][c][j]) : subi<T>(p[0][c][j], p[2][c][j]);
+        h[1][c][j] = S > 0 ? subi<T>(p[1][c][j], p[3][c][j]) : addi<T>(p[1][c][j], p[3][c][j]);
+      } else {  // gamma_4: h0 = u0 -+ l0, h1 = u1 -+ l1
+        h[0][c][j] = S > 0 ? sub<T>(p[0][c][j], p[2][c][j]) : add<T>(p[0][c][j], p[2][c][j]);
+        h[1][c][j] = S > 0 ? sub<T>(p[1][c][j], p[3][c][j]) : add<T>(p[1][c][j], p[3][c][j]);
+      }
+    }
+}
+
+// acc += (1 - s*gamma_mu)-reconstruction of the transported half spinor w.
+template <typename T, int R, int MU, int S>
+__device__ __forceinline__ void reconstruct(cplx<T> (&acc)[4][3][R], const cplx<T> (&w)[2][3][R]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const cplx<T> a = w[0][c][j], b = w[1][c][j];
+      acc[0][c][j] = add<T>(acc[0][c][j], a);
+      acc[1][c][j] = add<T>(acc[1][c][j], b);
+      if constexpr (MU == 0) {  // l0 = -+ i h1, l1 = -+ i h0
+        acc[2][c][j] = S > 0 ? subi<T>(acc[2][c][j], b) : addi<T>(acc[2][c][j], b);
+        acc[3][c][j] = S > 0 ? subi<T>(acc[3][c][j], a) : addi<T>(acc[3][c][j], a);
+      } else if constexpr (MU == 1) {  // l0 = -+ h1, l1 = +- h0
+        acc[2][c][j] = S > 0 ? sub<T>(acc[2][c][j], b) : add<T>(acc[2][c][j], b);
+        acc[3][c][j] = S > 0 ? add<T>(acc[3][c][j], a) : sub<T>(acc[3][c][j], a);
+      } else if constexpr (MU == 2) {  // l0 = -+ i h0, l1 = +- i h1
+        acc[2][c][j] = S > 0 ? subi<T>(acc[2][c][j], a) : addi<T>(acc[2][c][j], a);
+        acc[3][c][j] = S > 0 ? addi<T>(acc[3][c][j], b) : subi<T>(acc[3][c][j], b);
+      } else {  // l0 = -+ h0, l1 = -+ h1
+        acc[2][c][j] = S > 0 ? sub<T>(acc[2][c][j], a) : add<T>(acc[2][c][j], a);
+        acc[3][c][j] = S > 0 ? sub<T>(acc[3][c][j], b) : add<T>(acc[3][c][j], b);
+      }
+    }
+}
+
+// Forces the accumulator to be materialised here.  Without it the compiler
+// sinks all arithmetic below the loads of all eight neighbours, which keeps
+// eight spinors live at once and exhausts the register file.
+template <typename T, int R>
+__device__ __forceinline__ void pin(cplx<T> (&acc)[4][3][R]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < R; ++j) asm volatile("" : "+v"(acc[sp][c][j].x), "+v"(acc[sp][c][j].y));
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void load_spinor(const cplx<T>* __restrict__ in, int site, int nrhs, int k0,
+                                            cplx<T> (&p)[4][3][R]) {
+  const cplx<T>* base = in + (size_t)site * 12 * nrhs + k0;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) load_r<T, R>(base + (3 * sp + c) * nrhs, p[sp][c]);
+}
+
+// One direction mu, both hops, accumulated into acc.
+template <typename T, int R, int MU>
+__device__ __forceinline__ void hop_dir(const Geom& g, int site, int coord, int nrhs, int k0, T tbc,
+                                        const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
+                                        cplx<T> (&acc)[4][3][R]) {
+  const int L = g.L[MU];
+  const int st = g.stride[MU];
+  // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+  {
+    const int nb = (coord == L - 1) ? site - (L - 1) * st : site + st;
+    const T ph = (MU == 3 && coord == L - 1) ? tbc : T(1);
+    cplx<T> p[4][3][R];
+    load_spinor<T, R>(in, nb, nrhs, k0, p);
+    cplx<T> h[2][3][R];
+    project<T, R, MU, +1>(p, h);
+    const cplx<T>* u = U + ((size_t)site * 4 + MU) * 9;
+    cplx<T> uu[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) uu[a][b] = u[3 * a + b];
+    cplx<T> w[2][3][R];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cplx<T> z = mk<T>(0, 0);
+#pragma unroll
+          for (int b = 0; b < 3; ++b) cmac<T>(z, uu[a][b], h[s][b][j]);
+          w[s][a][j] = mk<T>(ph * z.x, ph * z.y);
+        }
+    reconstruct<T, R, MU, +1>(acc, w);
+    pin<T, R>(acc);
+  }
+  // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
+  {
+    const int nb = (coord == 0) ? site + (L - 1) * st : site - st;
+    const T ph = (MU == 3 && coord == 0) ? tbc : T(1);
+    cplx<T> p[4][3][R];
+    load_spinor<T, R>(in, nb, nrhs, k0, p);
+    cplx<T> h[2][3][R];
+    project<T, R, MU, -1>(p, h);
+    const cplx<T>* u = U + ((size_t)nb * 4 + MU) * 9;
+    cplx<T> uu[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) uu[a][b] = u[3 * a + b];
+    cplx<T> w[2][3][R];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cplx<T> z = mk<T>(0, 0);
+#pragma unroll
+          for (int b = 0; b < 3; ++b) cmac_conj<T>(z, uu[b][a], h[s][b][j]);
+          w[s][a][j] = mk<T>(ph * z.x, ph * z.y);
+        }
+    reconstruct<T, R, MU, -1>(acc, w);
+    pin<T, R>(acc);
+  }
+}
+
+// One chiral 6x6 block times six components (R right-hand sides each).
+template <typename T, int R>
+__device__ __forceinline__ void clover_block(const T* __restrict__ a, const cplx<T> (&x)[6][R],
+                                             cplx<T> (&y)[6][R]) {
+  T m[36];
+  if constexpr (sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(a);  // 144-byte blocks, 16-byte aligned
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float4 w = q[i];
+      m[4 * i] = w.x;
+      m[4 * i + 1] = w.y;
+      m[4 * i + 2] = w.z;
+      m[4 * i + 3] = w.w;
+    }
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(a);
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+      const double2 w = q[i];
+      m[2 * i] = w.x;
+      m[2 * i + 1] = w.y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) y[i][j] = mk<T>(m[i] * x[i][j].x, m[i] * x[i][j].y);
+  int idx = 6;
+#pragma unroll
+  for (int i = 1; i < 6; ++i)
+#pragma unroll
+    for (int k = 0; k < i; ++k) {
+      const cplx<T> l = mk<T>(m[idx], m[idx + 1]);
+      idx += 2;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        cmac<T>(y[i][j], l, x[k][j]);
+        cmac_conj<T>(y[k][j], l, x[i][j]);
+      }
+    }
+}
+
+// MODE 0: out = A psi - kappa H psi ; MODE 1: out = H psi ; MODE 2: out = A psi.
+template <typename T, int R, int MODE, bool XCD>
+__global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T tbc,
+                                                   const cplx<T>* __restrict__ U,
+                                                   const T* __restrict__ A,
+                                                   const cplx<T>* __restrict__ in,
+                                                   cplx<T>* __restrict__ out, int nblocks) {
+  int b = blockIdx.x;
+  if constexpr (XCD) {
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
+    // contiguous slab of sites so that neighbour re-reads hit its own L2.
+    const int per = (nblocks + 7) >> 3;
+    b = (b & 7) * per + (b >> 3);
+    if (b >= nblocks) return;
+  }
+  const int groups = nrhs / R;
+  const long gid = (long)b * 256 + threadIdx.x;
+  if (gid >= (long)g.V * groups) return;
+  const int site = (int)(gid / groups);
+  const int k0 = (int)(gid - (long)site * groups) * R;
+
+  int r = site;
+  const int x = r % g.L[0];
+  r /= g.L[0];
+  const int y = r % g.L[1];
+  r /= g.L[1];
+  const int z = r % g.L[2];
+  const int t = r / g.L[2];
+
+  cplx<T> acc[4][3][R];
+  if constexpr (MODE != 2) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
+    hop_dir<T, R, 0>(g, site, x, nrhs, k0, tbc, U, in, acc);
+    hop_dir<T, R, 1>(g, site, y, nrhs, k0, tbc, U, in, acc);
+    hop_dir<T, R, 2>(g, site, z, nrhs, k0, tbc, U, in, acc);
+    hop_dir<T, R, 3>(g, site, t, nrhs, k0, tbc, U, in, acc);
+  }
+
+  cplx<T>* o = out + (size_t)site * 12 * nrhs + k0;
+  if constexpr (MODE == 1) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c]);
+  } else {
+    const cplx<T>* base = in + (size_t)site * 12 * nrhs + k0;
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      cplx<T> xin[6][R], yout[6][R];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) load_r<T, R>(base + (6 * chi + i) * nrhs, xin[i]);
+      clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        if constexpr (MODE == 0) {
+          const int sp = 2 * chi + i / 3, c = i % 3;
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            yout[i][j].x = fma(-kappa, acc[sp][c][j].x, yout[i][j].x);
+            yout[i][j].y = fma(-kappa, acc[sp][c][j].y, yout[i][j].y);
+          }
+        }
+        store_r<T, R>(o + (6 * chi + i) * nrhs, yout[i]);
+      }
+    }
+  }
+}
+
+template <typename T, int R, int MODE>
+hipError_t launch_r(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
+                    void* out, int nrhs, hipStream_t s) {
+  const long threads = (long)g.V * (nrhs / R);
+  const int nblocks = (int)((threads + 255) / 256);
+  const int grid = ((nblocks + 7) / 8) * 8;
+  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, T(t_bc),
+                     reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
+                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks);
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
+                       void* out, int nrhs, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (nrhs % 4 == 0 && nrhs >= 8) return launch_r<T, 4, MODE>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+    if (nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+  }
+  return launch_r<T, 1, MODE>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+}
+
+template <typename T>
+hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U, const void* A,
+                       const void* in, void* out, int nrhs, hipStream_t s) {
+  switch (mode) {
+    case 0:
+      return launch_mode<T, 0>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+    case 1:
+      return launch_mode<T, 1>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+    default:
+      return launch_mode<T, 2>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U, const void* A,
+                           const void* in, void* out, int nrhs, hipStream_t s) {
+  return launch_fine<float>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s);
+}
+
+hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U, const void* A,
+                           const void* in, void* out, int nrhs, hipStream_t s) {
+  return launch_fine<double>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s);
+}
+
+}  // namespace mrhs

@@ -1,0 +1,81 @@
+// Internal declarations shared by the libmrhs translation units: the context
+// object, error plumbing and the kernel launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/mrhs.h"
+
+namespace mrhs {
+
+// Lattice geometry passed by value to kernels.
+struct Geom {
+  int L[4];     // Lx, Ly, Lz, Lt
+  int V;        // number of sites
+  int stride[4];  // site-index step of +1 in each direction: 1, Lx, Lx*Ly, Lx*Ly*Lz
+};
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace mrhs
+
+struct mrhs_ctx_s {
+  mrhs::Geom g{};
+  int t_bc = -1;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // library-owned device data
+  mrhs::Buffer U64, U32;  // [V][4][3][3] complex
+  mrhs::Buffer A64, A32;  // [V][2][36] real
+  bool have_gauge = false;
+  bool have_clover = false;
+  double kappa = 0.0;
+};
+
+namespace mrhs {
+
+// Status helpers: record a message on the context and return the code.
+mrhs_status fail(mrhs_ctx ctx, mrhs_status st, const char* fmt, ...);
+mrhs_status hip_fail(mrhs_ctx ctx, hipError_t e, const char* what);
+
+#define MRHS_HIP(ctx, call)                                   \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return mrhs::hip_fail(ctx, e_, #call); \
+  } while (0)
+
+// Checks after a kernel launch (launch-time errors only).
+#define MRHS_LAUNCH_CHECK(ctx, name)                               \
+  do {                                                             \
+    hipError_t e_ = hipGetLastError();                             \
+    if (e_ != hipSuccess) return mrhs::hip_fail(ctx, e_, name);    \
+  } while (0)
+
+mrhs_status ensure(mrhs_ctx ctx, Buffer& b, size_t bytes);
+void release(Buffer& b);
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// ---- launchers (fine.hip) ---------------------------------------------------
+// mode: 0 = A - kappa H, 1 = H, 2 = A
+hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U,
+                           const void* A, const void* in, void* out, int nrhs, hipStream_t s);
+hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U,
+                           const void* A, const void* in, void* out, int nrhs, hipStream_t s);
+
+// ---- launchers (clover_build.hip) -------------------------------------------
+hipError_t launch_clover_build(const Geom& g, double csw, double kappa, const void* U64,
+                               void* F_scratch, void* A64, void* A32, hipStream_t s);
+hipError_t launch_convert_f64_to_f32(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_convert_f32_to_f64(const float* in, double* out, size_t n, hipStream_t s);
+
+}  // namespace mrhs

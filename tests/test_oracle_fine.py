@@ -230,3 +230,14 @@ def test_pack_roundtrip_and_layout():
     # entry order: 6 diagonal reals, then (1,0), (2,0), (2,1), ...
     assert p[0, 6] == M[0, 1, 0].real and p[0, 7] == M[0, 1, 0].imag
     assert p[0, 10] == M[0, 2, 1].real and p[0, 35] == M[0, 5, 4].imag
+
+
+def test_dwc_sites_matches_whole_lattice():
+    """The per-site evaluation used for large-lattice sampling equals the full apply."""
+    dims = (4, 2, 6, 4)
+    U = synth.gauge_haar(dims, 1)
+    A = O.clover_packed(U, dims, 1.0, KAPPA)
+    psi = synth.spinor_source(dims, 3, 4)
+    full = O.dwc(U, A, KAPPA, psi, dims)
+    sites = np.array([0, 1, 5, 17, 47, 95, 96, 191])
+    np.testing.assert_allclose(O.dwc_sites(U, A, KAPPA, psi, dims, sites), full[sites], atol=1e-14)
