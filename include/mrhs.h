@@ -130,6 +130,37 @@ mrhs_status mrhs_hop_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs
 mrhs_status mrhs_clover_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs,
                               mrhs_prec prec);
 
+/* ---- batched level-1 operations (paper Sec. 7) ---------------------------
+ * A field here is any [nsites][ncomp][nrhs] complex array in device memory,
+ * prec MRHS_F32 or MRHS_F64 (fine spinors have ncomp = 12, coarse vectors
+ * ncomp = Nb).  Each operation acts on the nrhs columns independently and
+ * makes one pass over the data for all of them: the simultaneous inner
+ * products of Sec. 7, which replace one global reduction per right-hand side
+ * by one for the whole block.  FP32 inputs are widened to FP64 before they
+ * are multiplied and all sums are taken in FP64, in an order fixed by
+ * (nsites, ncomp, nrhs) alone, so results repeat bit for bit.
+ * nsites*ncomp >= 1, 1 <= nrhs <= 64.
+ *
+ * mrhs_dot: out[2k] + i out[2k+1] = <a_k, b_k> = sum_{s,c} conj(a[s][c][k]) b[s][c][k].
+ *   out holds 2*nrhs doubles in host memory (out_on_device = 0: the call
+ *   synchronises) or device memory (out_on_device = 1: asynchronous). */
+mrhs_status mrhs_dot(mrhs_ctx ctx, double* out, const void* a, const void* b, int64_t nsites, int32_t ncomp,
+                     int32_t nrhs, mrhs_prec prec, int32_t out_on_device);
+/* mrhs_norm2: out[k] = ||a_k||^2, nrhs doubles, same rules as mrhs_dot. */
+mrhs_status mrhs_norm2(mrhs_ctx ctx, double* out, const void* a, int64_t nsites, int32_t ncomp, int32_t nrhs,
+                       mrhs_prec prec, int32_t out_on_device);
+/* mrhs_multi_dot: out[2(j*nrhs + k)] + i out[2(j*nrhs + k) + 1] = <v_j,k, w_k> for
+ * j < m, 1 <= m <= 16: the m inner products of one Gram-Schmidt step, reading
+ * w once.  v is a host array of m device field pointers (all of the shape of
+ * w).  out: 2*m*nrhs doubles, host or device as for mrhs_dot. */
+mrhs_status mrhs_multi_dot(mrhs_ctx ctx, double* out, const void* const* v, int32_t m, const void* w,
+                           int64_t nsites, int32_t ncomp, int32_t nrhs, mrhs_prec prec, int32_t out_on_device);
+/* mrhs_axpy: y_k <- y_k + alpha_k x_k per column, alpha_k = alpha[2k] + i alpha[2k+1]
+ * (FP64, host memory if alpha_on_device = 0, else device memory); the update
+ * is computed in FP64 and rounded to prec.  x and y must not overlap. */
+mrhs_status mrhs_axpy(mrhs_ctx ctx, void* y, const double* alpha, const void* x, int64_t nsites, int32_t ncomp,
+                      int32_t nrhs, mrhs_prec prec, int32_t alpha_on_device);
+
 #ifdef __cplusplus
 }
 #endif

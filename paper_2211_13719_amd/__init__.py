@@ -149,3 +149,67 @@ class Context:
     def clover(self, out, inp):
         """out = A inp."""
         return self._fine(lib.mrhs_clover_apply, out, inp)
+
+    # -- batched level-1 operations ---------------------------------------------------
+    @staticmethod
+    def _field_shape(t):
+        if t.dim() != 3:
+            raise ValueError(f"field must be (nsites, ncomp, nrhs), got {tuple(t.shape)}")
+        if not t.is_cuda:
+            raise ValueError("fields must be device tensors")
+        return int(t.shape[0]), int(t.shape[1]), int(t.shape[2])
+
+    def dot(self, a, b, out=None):
+        """Per-column <a_k, b_k> (complex128, FP64 sums).  With ``out`` (a device
+        complex128 tensor of nrhs entries) the call stays asynchronous."""
+        ns, nc, n = self._field_shape(a)
+        if b.shape != a.shape or b.dtype != a.dtype:
+            raise ValueError("a and b must match")
+        pa, prec, _ = _ptr_of(a)
+        pb, _, _ = _ptr_of(b)
+        if out is not None:
+            self._check(lib.mrhs_dot(self._h, C.c_void_p(out.data_ptr()), C.c_void_p(pa), C.c_void_p(pb), ns, nc, n,
+                                     prec, 1))
+            return out
+        res = np.empty(n, dtype=np.complex128)
+        self._check(lib.mrhs_dot(self._h, C.c_void_p(res.ctypes.data), C.c_void_p(pa), C.c_void_p(pb), ns, nc, n,
+                                 prec, 0))
+        return res
+
+    def norm2(self, a, out=None):
+        """Per-column ||a_k||^2 (float64)."""
+        ns, nc, n = self._field_shape(a)
+        pa, prec, _ = _ptr_of(a)
+        if out is not None:
+            self._check(lib.mrhs_norm2(self._h, C.c_void_p(out.data_ptr()), C.c_void_p(pa), ns, nc, n, prec, 1))
+            return out
+        res = np.empty(n, dtype=np.float64)
+        self._check(lib.mrhs_norm2(self._h, C.c_void_p(res.ctypes.data), C.c_void_p(pa), ns, nc, n, prec, 0))
+        return res
+
+    def multi_dot(self, vs, w):
+        """(m, nrhs) complex128 array of <v_j,k, w_k>."""
+        ns, nc, n = self._field_shape(w)
+        m = len(vs)
+        ptrs = (C.c_void_p * m)()
+        for j, v in enumerate(vs):
+            if v.shape != w.shape or v.dtype != w.dtype or not v.is_contiguous():
+                raise ValueError("every v_j must match w")
+            ptrs[j] = v.data_ptr()
+        pw, prec, _ = _ptr_of(w)
+        res = np.empty((m, n), dtype=np.complex128)
+        self._check(lib.mrhs_multi_dot(self._h, C.c_void_p(res.ctypes.data), ptrs, m, C.c_void_p(pw), ns, nc, n,
+                                       prec, 0))
+        return res
+
+    def axpy(self, y, alpha, x):
+        """y_k += alpha_k x_k in place; alpha is a length-nrhs complex sequence."""
+        ns, nc, n = self._field_shape(y)
+        if x.shape != y.shape or x.dtype != y.dtype:
+            raise ValueError("x and y must match")
+        al = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, dtype=np.complex128), (n,)))
+        py, prec, _ = _ptr_of(y)
+        px, _, _ = _ptr_of(x)
+        self._check(lib.mrhs_axpy(self._h, C.c_void_p(py), C.c_void_p(al.ctypes.data), C.c_void_p(px), ns, nc, n,
+                                  prec, 0))
+        return y

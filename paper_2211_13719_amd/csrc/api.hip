@@ -181,6 +181,8 @@ void mrhs_destroy(mrhs_ctx ctx) {
   release(ctx->U32);
   release(ctx->A64);
   release(ctx->A32);
+  release(ctx->work);
+  release(ctx->scal);
   delete ctx;
 }
 
@@ -274,6 +276,114 @@ mrhs_status mrhs_hop_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs
 
 mrhs_status mrhs_clover_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
   return fine_apply(ctx, 2, out, in, nrhs, prec);
+}
+
+}  // extern "C"
+
+// ---- batched level-1 operations ----------------------------------------------
+
+namespace {
+
+mrhs_status check_blas_shape(mrhs_ctx ctx, int64_t nsites, int32_t ncomp, int32_t nrhs, mrhs_prec prec) {
+  if (nsites < 1 || ncomp < 1 || nsites * (int64_t)ncomp > (int64_t(1) << 40))
+    return fail(ctx, MRHS_ERR_SHAPE, "bad field shape nsites=%lld ncomp=%d", (long long)nsites, ncomp);
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  if (prec != MRHS_F32 && prec != MRHS_F64)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "precision %s not supported for this call", prec_name(prec));
+  return MRHS_OK;
+}
+
+// Runs a reduction whose device result has `bytes` bytes: into `out` directly
+// if it is device memory, else into the context's scalar buffer and back.
+template <typename F>
+mrhs_status reduce_to(mrhs_ctx ctx, double* out, int out_on_device, size_t bytes, size_t scratch, F&& launch) {
+  mrhs_status st = ensure(ctx, ctx->work, scratch);
+  if (st != MRHS_OK) return st;
+  void* dst = out;
+  if (!out_on_device) {
+    st = ensure(ctx, ctx->scal, bytes);
+    if (st != MRHS_OK) return st;
+    dst = ctx->scal.p;
+  }
+  hipError_t e = launch(dst, ctx->work.p);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reduction launch");
+  if (!out_on_device) {
+    MRHS_HIP(ctx, hipMemcpyAsync(out, ctx->scal.p, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return MRHS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrhs_status mrhs_dot(mrhs_ctx ctx, double* out, const void* a, const void* b, int64_t nsites, int32_t ncomp,
+                     int32_t nrhs, mrhs_prec prec, int32_t out_on_device) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_blas_shape(ctx, nsites, ncomp, nrhs, prec);
+  if (st != MRHS_OK) return st;
+  if (!out || !a || !b) return fail(ctx, MRHS_ERR_INVALID_ARG, "null pointer");
+  if (!aligned16(a) || !aligned16(b)) return fail(ctx, MRHS_ERR_INVALID_ARG, "field pointers must be 16-byte aligned");
+  DeviceGuard dg(ctx->device);
+  const long rows = (long)nsites * ncomp;
+  return reduce_to(ctx, out, out_on_device, (size_t)nrhs * 16, blas_scratch_bytes(nrhs, 1), [&](void* dst, void* w) {
+    return launch_dot(prec == MRHS_F64, 0, a, b, rows, nrhs, dst, w, ctx->stream);
+  });
+}
+
+mrhs_status mrhs_norm2(mrhs_ctx ctx, double* out, const void* a, int64_t nsites, int32_t ncomp, int32_t nrhs,
+                       mrhs_prec prec, int32_t out_on_device) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_blas_shape(ctx, nsites, ncomp, nrhs, prec);
+  if (st != MRHS_OK) return st;
+  if (!out || !a) return fail(ctx, MRHS_ERR_INVALID_ARG, "null pointer");
+  if (!aligned16(a)) return fail(ctx, MRHS_ERR_INVALID_ARG, "field pointers must be 16-byte aligned");
+  DeviceGuard dg(ctx->device);
+  const long rows = (long)nsites * ncomp;
+  return reduce_to(ctx, out, out_on_device, (size_t)nrhs * 8, blas_scratch_bytes(nrhs, 1), [&](void* dst, void* w) {
+    return launch_dot(prec == MRHS_F64, 1, a, a, rows, nrhs, dst, w, ctx->stream);
+  });
+}
+
+mrhs_status mrhs_multi_dot(mrhs_ctx ctx, double* out, const void* const* v, int32_t m, const void* w,
+                           int64_t nsites, int32_t ncomp, int32_t nrhs, mrhs_prec prec, int32_t out_on_device) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_blas_shape(ctx, nsites, ncomp, nrhs, prec);
+  if (st != MRHS_OK) return st;
+  if (m < 1 || m > kMaxMultiDot) return fail(ctx, MRHS_ERR_SHAPE, "m = %d outside [1, %d]", m, kMaxMultiDot);
+  if (!out || !v || !w) return fail(ctx, MRHS_ERR_INVALID_ARG, "null pointer");
+  if (!aligned16(w)) return fail(ctx, MRHS_ERR_INVALID_ARG, "field pointers must be 16-byte aligned");
+  for (int j = 0; j < m; ++j)
+    if (!v[j] || !aligned16(v[j])) return fail(ctx, MRHS_ERR_INVALID_ARG, "v[%d] null or misaligned", j);
+  DeviceGuard dg(ctx->device);
+  const long rows = (long)nsites * ncomp;
+  return reduce_to(ctx, out, out_on_device, (size_t)m * nrhs * 16, blas_scratch_bytes(nrhs, m),
+                   [&](void* dst, void* wk) {
+                     return launch_multi_dot(prec == MRHS_F64, v, m, w, rows, nrhs, dst, wk, ctx->stream);
+                   });
+}
+
+mrhs_status mrhs_axpy(mrhs_ctx ctx, void* y, const double* alpha, const void* x, int64_t nsites, int32_t ncomp,
+                      int32_t nrhs, mrhs_prec prec, int32_t alpha_on_device) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_blas_shape(ctx, nsites, ncomp, nrhs, prec);
+  if (st != MRHS_OK) return st;
+  if (!y || !alpha || !x) return fail(ctx, MRHS_ERR_INVALID_ARG, "null pointer");
+  st = check_field_args(ctx, y, x, nrhs, prec, (size_t)ncomp, nsites);
+  if (st != MRHS_OK) return st;
+  DeviceGuard dg(ctx->device);
+  const void* al = alpha;
+  if (!alpha_on_device) {
+    st = ensure(ctx, ctx->scal, (size_t)nrhs * 16);
+    if (st != MRHS_OK) return st;
+    MRHS_HIP(ctx, hipMemcpyAsync(ctx->scal.p, alpha, (size_t)nrhs * 16, hipMemcpyHostToDevice, ctx->stream));
+    al = ctx->scal.p;
+  }
+  hipError_t e = launch_axpy(prec == MRHS_F64, y, al, x, (long)nsites * ncomp, nrhs, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "axpy launch");
+  if (!alpha_on_device) MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));  // alpha's host memory may be reused
+  return MRHS_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,492 @@
+// Aggregation-multigrid intergrid operators on Nrhs fields at once (paper
+// Sec. 5: "project" = restriction, "promote" = prolongation; the coarse
+// spinor has nbasis = 2 n_v components because every basis vector is split by
+// chirality).
+//
+// A level has sites s (geometry Geom) and ncomp = 2h components per site, the
+// first h of chirality +, the last h of chirality -.  Aggregates are blocks
+// b = (bx, by, bz, bt) of sites; aggregate A = X + Cx (Y + Cy (Z + Cz T)).
+// The basis of a level is held in the internal layout [site][ncomp][n_v]
+// (basis index fastest), so the n_v values a thread needs at one (site,
+// component) are contiguous.  With v_i(x)_c that basis,
+//
+//   restrict: y(A, chi n_v + i, k) = sum_{x in A} sum_{c in chi} conj(v_i(x)_c) f(x)_{c,k}
+//   prolong:  f(x)_{c,k}           = sum_i v_i(x)_c y(A(x), chi(c) n_v + i, k)
+//
+// and block orthonormalisation makes, for every (aggregate, chirality), the
+// n_v restricted vectors orthonormal: the Q factor of their thin QR with real
+// positive diagonal, by classical Gram-Schmidt applied twice, in FP64.
+#include "internal.h"
+
+namespace mrhs {
+namespace {
+
+template <typename T>
+struct cx;
+template <>
+struct cx<float> {
+  using type = float2;
+};
+template <>
+struct cx<double> {
+  using type = double2;
+};
+template <typename T>
+using cplx = typename cx<T>::type;
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T a, T b) {
+  cplx<T> z;
+  z.x = a;
+  z.y = b;
+  return z;
+}
+
+// Fine site of local offset l inside aggregate A.
+__device__ __forceinline__ int agg_site(const AggGeom& a, int A, int l) {
+  const int X = A % a.C[0];
+  int r = A / a.C[0];
+  const int Y = r % a.C[1];
+  r /= a.C[1];
+  const int Z = r % a.C[2];
+  const int Tt = r / a.C[2];
+  const int lx = l % a.b[0];
+  int q = l / a.b[0];
+  const int ly = q % a.b[1];
+  q /= a.b[1];
+  const int lz = q % a.b[2];
+  const int lt = q / a.b[2];
+  const int x = X * a.b[0] + lx, y = Y * a.b[1] + ly, z = Z * a.b[2] + lz, t = Tt * a.b[3] + lt;
+  return x + a.L[0] * (y + a.L[1] * (z + a.L[2] * t));
+}
+
+__device__ __forceinline__ int site_agg(const AggGeom& a, int s) {
+  const int x = s % a.L[0];
+  int r = s / a.L[0];
+  const int y = r % a.L[1];
+  r /= a.L[1];
+  const int z = r % a.L[2];
+  const int t = r / a.L[2];
+  return x / a.b[0] + a.C[0] * (y / a.b[1] + a.C[1] * (z / a.b[2] + a.C[2] * (t / a.b[3])));
+}
+
+// ---- restriction ----------------------------------------------------------------
+// One workgroup per aggregate.  A thread owns a 4 (basis index) x 4 (RHS)
+// output tile of one chirality and a slice of the aggregate's sites; the
+// slices are summed through LDS at the end in a fixed order.
+constexpr int kRI = 4, kRR = 4;
+
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void restrict_kernel(AggGeom a, int h, int nrhs,
+                                                       const cplx<T>* __restrict__ basis,
+                                                       const cplx<T>* __restrict__ f, cplx<T>* __restrict__ y) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* red = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int A = blockIdx.x;
+  const int ncomp = 2 * h;
+  const int G = (nrhs + kRR - 1) / kRR;
+  const int ntile = 2 * (NV / kRI) * G;
+  const int S = max(1, 256 / ntile);
+  const int t = threadIdx.x;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+
+  cplx<T> acc[kRI][kRR];
+#pragma unroll
+  for (int i = 0; i < kRI; ++i)
+#pragma unroll
+    for (int k = 0; k < kRR; ++k) acc[i][k] = mk<T>(0, 0);
+
+  const int tile = t % ntile;
+  const int slice = t / ntile;
+  const int kg = tile % G;
+  const int ig = (tile / G) % (NV / kRI);
+  const int chi = tile / (G * (NV / kRI));
+  const int k0 = kg * kRR, i0 = ig * kRI;
+  if (slice < S) {
+    for (int l = slice; l < nsa; l += S) {
+      const int s = agg_site(a, A, l);
+      const cplx<T>* fb = f + ((size_t)s * ncomp + chi * h) * nrhs + k0;
+      const cplx<T>* bb = basis + ((size_t)s * ncomp + chi * h) * NV + i0;
+      for (int c = 0; c < h; ++c) {
+        cplx<T> fv[kRR], bv[kRI];
+#pragma unroll
+        for (int k = 0; k < kRR; ++k) fv[k] = (k0 + k < nrhs) ? fb[(size_t)c * nrhs + k] : mk<T>(0, 0);
+#pragma unroll
+        for (int i = 0; i < kRI; ++i) bv[i] = bb[(size_t)c * NV + i];
+#pragma unroll
+        for (int i = 0; i < kRI; ++i)
+#pragma unroll
+          for (int k = 0; k < kRR; ++k) {
+            // conj(b) * f
+            acc[i][k].x = fma(bv[i].x, fv[k].x, acc[i][k].x);
+            acc[i][k].x = fma(bv[i].y, fv[k].y, acc[i][k].x);
+            acc[i][k].y = fma(bv[i].x, fv[k].y, acc[i][k].y);
+            acc[i][k].y = fma(-bv[i].y, fv[k].x, acc[i][k].y);
+          }
+      }
+    }
+    // red[slice][tile][16]
+#pragma unroll
+    for (int i = 0; i < kRI; ++i)
+#pragma unroll
+      for (int k = 0; k < kRR; ++k) red[((size_t)slice * ntile + tile) * (kRI * kRR) + i * kRR + k] = acc[i][k];
+  }
+  __syncthreads();
+  const int nout = ntile * kRI * kRR;
+  for (int o = t; o < nout; o += 256) {
+    cplx<T> sum = red[o];
+    for (int q = 1; q < S; ++q) {
+      const cplx<T> v = red[(size_t)q * nout + o];
+      sum.x += v.x;
+      sum.y += v.y;
+    }
+    const int tl = o / (kRI * kRR);
+    const int ii = (o / kRR) % kRI;
+    const int kk = o % kRR;
+    const int kgo = tl % G, igo = (tl / G) % (NV / kRI), cho = tl / (G * (NV / kRI));
+    const int k = kgo * kRR + kk;
+    if (k < nrhs) y[((size_t)A * 2 * NV + cho * NV + igo * kRI + ii) * nrhs + k] = sum;
+  }
+}
+
+// ---- prolongation -------------------------------------------------------------------
+// One thread per (fine site, chirality, group of R right-hand sides).
+template <typename T, int NV, int H, int R>
+__global__ __launch_bounds__(256) void prolong_kernel(AggGeom a, int nrhs, const cplx<T>* __restrict__ basis,
+                                                      const cplx<T>* __restrict__ y, cplx<T>* __restrict__ f) {
+  const int G = (nrhs + R - 1) / R;
+  const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (long)a.V * 2 * G) return;
+  const int kg = (int)(gid % G);
+  const int chi = (int)((gid / G) % 2);
+  const int s = (int)(gid / (2 * G));
+  const int k0 = kg * R;
+  const int A = site_agg(a, s);
+  constexpr int ncomp = 2 * H;
+  cplx<T> acc[H][R];
+#pragma unroll
+  for (int c = 0; c < H; ++c)
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[c][k] = mk<T>(0, 0);
+  const cplx<T>* yb = y + ((size_t)A * 2 * NV + chi * NV) * nrhs + k0;
+  const cplx<T>* bb = basis + ((size_t)s * ncomp + chi * H) * NV;
+#pragma unroll 4
+  for (int i = 0; i < NV; ++i) {
+    cplx<T> yv[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) yv[k] = (k0 + k < nrhs) ? yb[(size_t)i * nrhs + k] : mk<T>(0, 0);
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+      const cplx<T> b = bb[(size_t)c * NV + i];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        acc[c][k].x = fma(b.x, yv[k].x, acc[c][k].x);
+        acc[c][k].x = fma(-b.y, yv[k].y, acc[c][k].x);
+        acc[c][k].y = fma(b.x, yv[k].y, acc[c][k].y);
+        acc[c][k].y = fma(b.y, yv[k].x, acc[c][k].y);
+      }
+    }
+  }
+  cplx<T>* fb = f + ((size_t)s * ncomp + chi * H) * nrhs + k0;
+#pragma unroll
+  for (int c = 0; c < H; ++c)
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      if (k0 + k < nrhs) fb[(size_t)c * nrhs + k] = acc[c][k];
+}
+
+// ---- block orthonormalisation (FP64) --------------------------------------------------
+__device__ double2 block_sum(double2 v, double2* lds) {
+  // wavefront reduction, then across the 4 wavefronts of the workgroup
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double2 s = lds[0];
+  for (int q = 1; q < 4; ++q) {
+    s.x += lds[q].x;
+    s.y += lds[q].y;
+  }
+  return s;
+}
+
+// One workgroup of 256 threads per (aggregate, chirality).  Vector i of the
+// block is v_i(x)_c for x in A, c in chi; the kernel overwrites the basis in
+// place with the orthonormal Q and reports a rank deficiency through *flag.
+__global__ __launch_bounds__(256) void block_gs_kernel(AggGeom a, int h, int nv, double2* __restrict__ basis,
+                                                       int* __restrict__ flag) {
+  __shared__ double2 lds[4];
+  __shared__ double2 r[64];
+  const int A = blockIdx.x >> 1;
+  const int chi = blockIdx.x & 1;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  const int dim = nsa * h;
+  const int ncomp = 2 * h;
+  auto elem = [&](int e, int i) -> double2* {
+    const int s = agg_site(a, A, e / h);
+    const int c = chi * h + e % h;
+    return basis + ((size_t)s * ncomp + c) * nv + i;
+  };
+  for (int i = 0; i < nv; ++i) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < i; ++j) {
+        double2 p = make_double2(0.0, 0.0);
+        for (int e = threadIdx.x; e < dim; e += 256) {
+          const double2 q = *elem(e, j), v = *elem(e, i);
+          p.x = fma(q.x, v.x, p.x);
+          p.x = fma(q.y, v.y, p.x);
+          p.y = fma(q.x, v.y, p.y);
+          p.y = fma(-q.y, v.x, p.y);
+        }
+        const double2 s = block_sum(p, lds);
+        if (threadIdx.x == 0) r[j] = s;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < dim; e += 256) {
+        double2 v = *elem(e, i);
+        for (int j = 0; j < i; ++j) {
+          const double2 q = *elem(e, j);
+          const double2 c = r[j];
+          v.x -= c.x * q.x - c.y * q.y;
+          v.y -= c.x * q.y + c.y * q.x;
+        }
+        *elem(e, i) = v;
+      }
+      __syncthreads();
+    }
+    double2 p = make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < dim; e += 256) {
+      const double2 v = *elem(e, i);
+      p.x = fma(v.x, v.x, p.x);
+      p.x = fma(v.y, v.y, p.x);
+    }
+    const double nrm = sqrt(block_sum(p, lds).x);
+    if (!(nrm > 0.0)) {
+      if (threadIdx.x == 0) *flag = 1;
+      return;  // uniform across the workgroup
+    }
+    const double inv = 1.0 / nrm;
+    for (int e = threadIdx.x; e < dim; e += 256) {
+      double2* pv = elem(e, i);
+      pv->x *= inv;
+      pv->y *= inv;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- block normalisation -----------------------------------------------------------------
+// One workgroup per aggregate; thread t accumulates |f|^2 for one (chirality,
+// RHS) pair over a slice of sites, the slices are summed in LDS in a fixed
+// order, and the same workgroup then scales the block.
+template <typename T>
+__global__ __launch_bounds__(256) void block_norm_kernel(AggGeom a, int h, int nrhs, cplx<T>* __restrict__ f,
+                                                         double* __restrict__ norms) {
+  __shared__ double part[256];
+  __shared__ double inv[2 * 64];
+  const int A = blockIdx.x;
+  const int ncomp = 2 * h;
+  const int np = 2 * nrhs;
+  const int S = 256 / np;
+  const int t = threadIdx.x;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  double acc = 0.0;
+  const int pair = t % np, slice = t / np;
+  const int chi = pair / nrhs, k = pair % nrhs;
+  if (slice < S) {
+    for (int l = slice; l < nsa; l += S) {
+      const int s = agg_site(a, A, l);
+      const cplx<T>* fb = f + ((size_t)s * ncomp + chi * h) * nrhs + k;
+      for (int c = 0; c < h; ++c) {
+        const cplx<T> v = fb[(size_t)c * nrhs];
+        acc = fma((double)v.x, (double)v.x, acc);
+        acc = fma((double)v.y, (double)v.y, acc);
+      }
+    }
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (t < np) {
+    double s2 = 0.0;
+    for (int q = 0; q < S; ++q) s2 += part[q * np + t];
+    const double n = sqrt(s2);
+    inv[t] = n > 0.0 ? 1.0 / n : 0.0;
+    if (norms) norms[((size_t)A * 2 + chi) * nrhs + k] = n;
+  }
+  __syncthreads();
+  // scale: every thread walks (site, component, rhs) elements of the aggregate
+  const int tot = nsa * ncomp * nrhs;
+  for (int e = t; e < tot; e += 256) {
+    const int kk = e % nrhs;
+    const int c = (e / nrhs) % ncomp;
+    const int l = e / (nrhs * ncomp);
+    const int s = agg_site(a, A, l);
+    cplx<T>* p = f + ((size_t)s * ncomp + c) * nrhs + kk;
+    const T sc = (T)inv[(c / h) * nrhs + kk];
+    cplx<T> v = *p;
+    v.x *= sc;
+    v.y *= sc;
+    *p = v;
+  }
+}
+
+// ---- layout conversion between [site][n_v][ncomp] (interface) and [site][ncomp][n_v] --------
+template <typename Tin, typename Tout>
+__global__ void basis_transpose(const cplx<Tin>* __restrict__ in, cplx<Tout>* __restrict__ out, long nsite, int nv,
+                                int ncomp, int to_internal) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long per = (long)nv * ncomp;
+  if (e >= nsite * per) return;
+  const long s = e / per;
+  const int r = (int)(e % per);
+  long src, dst;
+  if (to_internal) {  // e enumerates the interface layout (i, c)
+    const int i = r / ncomp, c = r % ncomp;
+    src = e;
+    dst = s * per + (long)c * nv + i;
+  } else {  // e enumerates the interface layout of the output
+    const int i = r / ncomp, c = r % ncomp;
+    dst = e;
+    src = s * per + (long)c * nv + i;
+  }
+  const cplx<Tin> v = in[src];
+  out[dst] = mk<Tout>((Tout)v.x, (Tout)v.y);
+}
+
+template <typename T, int NV>
+hipError_t restrict_nv(const AggGeom& a, int h, int nrhs, const void* basis, const void* f, void* y, hipStream_t s) {
+  const int G = (nrhs + kRR - 1) / kRR;
+  const int ntile = 2 * (NV / kRI) * G;
+  if (ntile > 256) return hipErrorInvalidValue;
+  const int S = std::max(1, 256 / ntile);
+  const size_t shmem = (size_t)S * ntile * kRI * kRR * sizeof(cplx<T>);
+  hipLaunchKernelGGL((restrict_kernel<T, NV>), dim3(a.Vc), dim3(256), shmem, s, a, h, nrhs,
+                     static_cast<const cplx<T>*>(basis), static_cast<const cplx<T>*>(f), static_cast<cplx<T>*>(y));
+  return hipGetLastError();
+}
+
+template <typename T, int NV, int H>
+hipError_t prolong_nvh(const AggGeom& a, int nrhs, const void* basis, const void* y, void* f, hipStream_t s) {
+  constexpr int R = (H > 8) ? 2 : 4;
+  const long threads = (long)a.V * 2 * ((nrhs + R - 1) / R);
+  const int nb = (int)((threads + 255) / 256);
+  hipLaunchKernelGGL((prolong_kernel<T, NV, H, R>), dim3(nb), dim3(256), 0, s, a, nrhs,
+                     static_cast<const cplx<T>*>(basis), static_cast<const cplx<T>*>(y), static_cast<cplx<T>*>(f));
+  return hipGetLastError();
+}
+
+template <typename T, int NV>
+hipError_t prolong_nv(const AggGeom& a, int h, int nrhs, const void* basis, const void* y, void* f, hipStream_t s) {
+  switch (h) {
+    case 4:
+      return prolong_nvh<T, NV, 4>(a, nrhs, basis, y, f, s);
+    case 6:
+      return prolong_nvh<T, NV, 6>(a, nrhs, basis, y, f, s);
+    case 8:
+      return prolong_nvh<T, NV, 8>(a, nrhs, basis, y, f, s);
+    case 16:
+      return prolong_nvh<T, NV, 16>(a, nrhs, basis, y, f, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool intergrid_supported(int nv, int h) {
+  return (nv == 4 || nv == 8 || nv == 16) && (h == 4 || h == 6 || h == 8 || h == 16);
+}
+
+hipError_t launch_restrict(int prec64, const AggGeom& a, int h, int nv, int nrhs, const void* basis, const void* f,
+                           void* y, hipStream_t s) {
+  if (prec64) {
+    switch (nv) {
+      case 4:
+        return restrict_nv<double, 4>(a, h, nrhs, basis, f, y, s);
+      case 8:
+        return restrict_nv<double, 8>(a, h, nrhs, basis, f, y, s);
+      case 16:
+        return restrict_nv<double, 16>(a, h, nrhs, basis, f, y, s);
+    }
+  } else {
+    switch (nv) {
+      case 4:
+        return restrict_nv<float, 4>(a, h, nrhs, basis, f, y, s);
+      case 8:
+        return restrict_nv<float, 8>(a, h, nrhs, basis, f, y, s);
+      case 16:
+        return restrict_nv<float, 16>(a, h, nrhs, basis, f, y, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_prolong(int prec64, const AggGeom& a, int h, int nv, int nrhs, const void* basis, const void* y,
+                          void* f, hipStream_t s) {
+  if (prec64) {
+    switch (nv) {
+      case 4:
+        return prolong_nv<double, 4>(a, h, nrhs, basis, y, f, s);
+      case 8:
+        return prolong_nv<double, 8>(a, h, nrhs, basis, y, f, s);
+      case 16:
+        return prolong_nv<double, 16>(a, h, nrhs, basis, y, f, s);
+    }
+  } else {
+    switch (nv) {
+      case 4:
+        return prolong_nv<float, 4>(a, h, nrhs, basis, y, f, s);
+      case 8:
+        return prolong_nv<float, 8>(a, h, nrhs, basis, y, f, s);
+      case 16:
+        return prolong_nv<float, 16>(a, h, nrhs, basis, y, f, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_block_gs(const AggGeom& a, int h, int nv, void* basis64, int* flag_dev, hipStream_t s) {
+  if (nv > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(block_gs_kernel, dim3(2 * a.Vc), dim3(256), 0, s, a, h, nv, static_cast<double2*>(basis64),
+                     flag_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_normalise(int prec64, const AggGeom& a, int h, int nrhs, void* f, double* norms,
+                                  hipStream_t s) {
+  if (2 * nrhs > 256) return hipErrorInvalidValue;
+  if (prec64)
+    hipLaunchKernelGGL((block_norm_kernel<double>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
+                       static_cast<double2*>(f), norms);
+  else
+    hipLaunchKernelGGL((block_norm_kernel<float>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs, static_cast<float2*>(f),
+                       norms);
+  return hipGetLastError();
+}
+
+// in_prec64 / out_prec64 select double2 or float2 on each side.
+hipError_t launch_basis_convert(const void* in, int in_prec64, void* out, int out_prec64, long nsite, int nv, int ncomp,
+                                int to_internal, hipStream_t s) {
+  const long n = nsite * nv * ncomp;
+  const int nb = (int)((n + 255) / 256);
+  if (in_prec64 && out_prec64)
+    hipLaunchKernelGGL((basis_transpose<double, double>), dim3(nb), dim3(256), 0, s, static_cast<const double2*>(in),
+                       static_cast<double2*>(out), nsite, nv, ncomp, to_internal);
+  else if (in_prec64)
+    hipLaunchKernelGGL((basis_transpose<double, float>), dim3(nb), dim3(256), 0, s, static_cast<const double2*>(in),
+                       static_cast<float2*>(out), nsite, nv, ncomp, to_internal);
+  else if (out_prec64)
+    hipLaunchKernelGGL((basis_transpose<float, double>), dim3(nb), dim3(256), 0, s, static_cast<const float2*>(in),
+                       static_cast<double2*>(out), nsite, nv, ncomp, to_internal);
+  else
+    hipLaunchKernelGGL((basis_transpose<float, float>), dim3(nb), dim3(256), 0, s, static_cast<const float2*>(in),
+                       static_cast<float2*>(out), nsite, nv, ncomp, to_internal);
+  return hipGetLastError();
+}
+
+}  // namespace mrhs

@@ -19,6 +19,16 @@ struct Geom {
   int stride[4];  // site-index step of +1 in each direction: 1, Lx, Lx*Ly, Lx*Ly*Lz
 };
 
+// Aggregation geometry of one coarsening step: fine lattice L, aggregate
+// extent b, coarse lattice C = L / b.
+struct AggGeom {
+  int L[4];
+  int b[4];
+  int C[4];
+  int V;   // fine sites
+  int Vc;  // aggregates
+};
+
 struct Buffer {
   void* p = nullptr;
   size_t bytes = 0;
@@ -39,6 +49,10 @@ struct mrhs_ctx_s {
   bool have_gauge = false;
   bool have_clover = false;
   double kappa = 0.0;
+
+  // workspaces: reduction partials, small per-RHS scalar arrays
+  mrhs::Buffer work;
+  mrhs::Buffer scal;
 };
 
 namespace mrhs {
@@ -77,5 +91,30 @@ hipError_t launch_clover_build(const Geom& g, double csw, double kappa, const vo
                                void* F_scratch, void* A64, void* A32, hipStream_t s);
 hipError_t launch_convert_f64_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 hipError_t launch_convert_f32_to_f64(const float* in, double* out, size_t n, hipStream_t s);
+
+// ---- launchers (blas.hip) ---------------------------------------------------
+constexpr int kMaxMultiDot = 16;
+size_t blas_scratch_bytes(int nrhs, int m);
+// mode 0: out (double2[nrhs]) = <a, b>; mode 1: out (double[nrhs]) = ||a||^2.  Device out.
+hipError_t launch_dot(int prec64, int mode, const void* a, const void* b, long rows, int nrhs, void* out,
+                      void* scratch, hipStream_t s);
+// out (double2[m][nrhs]) = <v_j, w>
+hipError_t launch_multi_dot(int prec64, const void* const* v, int m, const void* w, long rows, int nrhs,
+                            void* out, void* scratch, hipStream_t s);
+// y += alpha (double2[nrhs] on the device) * x
+hipError_t launch_axpy(int prec64, void* y, const void* alpha_dev, const void* x, long rows, int nrhs,
+                       hipStream_t s);
+
+// ---- launchers (intergrid.hip) ------------------------------------------------
+bool intergrid_supported(int nv, int h);
+hipError_t launch_restrict(int prec64, const AggGeom& a, int h, int nv, int nrhs, const void* basis, const void* f,
+                           void* y, hipStream_t s);
+hipError_t launch_prolong(int prec64, const AggGeom& a, int h, int nv, int nrhs, const void* basis, const void* y,
+                          void* f, hipStream_t s);
+hipError_t launch_block_gs(const AggGeom& a, int h, int nv, void* basis64, int* flag_dev, hipStream_t s);
+hipError_t launch_block_normalise(int prec64, const AggGeom& a, int h, int nrhs, void* f, double* norms,
+                                  hipStream_t s);
+hipError_t launch_basis_convert(const void* in, int in_prec64, void* out, int out_prec64, long nsite, int nv, int ncomp,
+                                int to_internal, hipStream_t s);
 
 }  // namespace mrhs
