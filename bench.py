@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--cold-reps", type=int, default=0,
                     help="also time each apply after a 1 GiB cache-evicting write (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (reference for HBM byte counters)")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -109,6 +111,14 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     V = int(np.prod(DIMS))
+
+    if a.calib_copy:
+        src_c = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst_c = torch.empty_like(src_c)
+        for _ in range(3):
+            dst_c.copy_(src_c)
+        torch.cuda.synchronize()
+        del src_c, dst_c
 
     t_setup = time.perf_counter()
     U = synth.gauge_haar(DIMS, 1)

@@ -54,6 +54,7 @@ extern "C" {
 #endif
 
 #define MRHS_MAX_NRHS 64
+#define MRHS_MAX_LEVELS 3
 
 typedef struct mrhs_ctx_s* mrhs_ctx;
 
@@ -160,6 +161,88 @@ mrhs_status mrhs_multi_dot(mrhs_ctx ctx, double* out, const void* const* v, int3
  * is computed in FP64 and rounded to prec.  x and y must not overlap. */
 mrhs_status mrhs_axpy(mrhs_ctx ctx, void* y, const double* alpha, const void* x, int64_t nsites, int32_t ncomp,
                       int32_t nrhs, mrhs_prec prec, int32_t alpha_on_device);
+
+/* ---- multigrid hierarchy (paper Secs. 5 and 6) ---------------------------
+ * Levels are numbered from 0 (the fine lattice of the context, 12 spinor
+ * components per site) to nlevels - 1.  Coarsening step l (level l -> l + 1)
+ * groups the sites of level l into aggregates of extent block[l] (x, y, z, t)
+ * and keeps n_v[l] basis vectors, each split by chirality, so level l + 1 has
+ * the lattice dims(l) / block[l] and ncomp(l + 1) = Nb = 2 n_v[l] components
+ * per site ("nbasis = twice the number of basis vectors", Sec. 5).  On every
+ * level the first half of the components has chirality + and the second
+ * half chirality -; aggregate A = X + Cx (Y + Cy (Z + Cz T)) is the coarse
+ * site.  Fields on level l are [site][ncomp(l)][nrhs] complex, like fine
+ * fields.  Supported: n_v in {4, 8, 16}; the matrix-core stencil needs Nb = 32.
+ */
+typedef struct mrhs_mg_s* mrhs_mg;
+
+typedef struct {
+  int32_t nlevels;      /* 2 or 3 */
+  int32_t block[2][4];  /* aggregate extent of step l; must divide dims(l) */
+  int32_t n_v[2];       /* basis vectors per step */
+} mrhs_mg_params;
+
+/* Creates the hierarchy on ctx's lattice (ctx must outlive it).  MRHS_ERR_SHAPE
+ * if a block does not divide its lattice, MRHS_ERR_UNSUPPORTED for n_v
+ * outside the supported set. */
+mrhs_status mrhs_mg_create(mrhs_ctx ctx, const mrhs_mg_params* params, mrhs_mg* mg);
+void mrhs_mg_destroy(mrhs_mg mg);
+/* Lattice extents and components per site of a level. */
+mrhs_status mrhs_mg_level_info(mrhs_mg mg, int32_t level, int32_t dims[4], int32_t* ncomp);
+
+/* mrhs_mg_set_basis: the n_v[level] basis vectors of step `level` (0 <= level
+ * < nlevels - 1) as [site][n_v][ncomp(level)] complex (vector i at site s,
+ * component c at (s n_v + i) ncomp + c), prec MRHS_F64 or MRHS_F32, host or
+ * device.  Copied in; the library keeps an FP64 master and an FP32 copy.
+ * Synchronises.  Invalidates the blocks of the coarser levels. */
+mrhs_status mrhs_mg_set_basis(mrhs_mg mg, int32_t level, const void* vecs, mrhs_prec prec, int32_t on_device);
+/* Copies the (current) basis out in the layout above.  Synchronises. */
+mrhs_status mrhs_mg_get_basis(mrhs_mg mg, int32_t level, void* vecs, mrhs_prec prec, int32_t on_device);
+/* mrhs_mg_block_orthonormalise: for every aggregate A and chirality chi the
+ * n_v vectors restricted to (A, chi) are replaced by the Q factor of their
+ * thin QR decomposition with real positive diagonal of R (unique), computed
+ * on the GPU in FP64 by Gram-Schmidt applied twice.  MRHS_ERR_STATE if some
+ * (A, chi) block is rank-deficient.  Synchronises. */
+mrhs_status mrhs_mg_block_orthonormalise(mrhs_mg mg, int32_t level);
+
+/* mrhs_restrict ("project", Sec. 5): coarse = P^dag fine for nrhs fields,
+ *   coarse(A, chi n_v + i, k) = sum_{x in A} sum_{c in chi} conj(v_i(x)_c) fine(x, c, k),
+ * fine on level `level`, coarse on level + 1; prec MRHS_F32 or MRHS_F64
+ * (both fields in that precision, sums in that precision). */
+mrhs_status mrhs_restrict(mrhs_mg mg, int32_t level, void* coarse, const void* fine, int32_t nrhs, mrhs_prec prec);
+/* mrhs_prolong ("promote", Sec. 5): fine = P coarse,
+ *   fine(x, c, k) = sum_i v_i(x)_c coarse(A(x), chi(c) n_v + i, k). */
+mrhs_status mrhs_prolong(mrhs_mg mg, int32_t level, void* fine, const void* coarse, int32_t nrhs, mrhs_prec prec);
+/* mrhs_block_normalise: for every RHS k, aggregate A of step `level` and
+ * chirality chi, divides the (A, chi) block of field k by its 2-norm (a zero
+ * block stays zero).  norms: optional device array [A][chi][k] of FP64 norms
+ * (may be NULL).  Norms are summed in FP64. */
+mrhs_status mrhs_block_normalise(mrhs_mg mg, int32_t level, void* fields, int32_t nrhs, mrhs_prec prec,
+                                 double* norms);
+
+/* mrhs_coarse_set_blocks: stencil blocks of coarse level `level` (>= 1) as
+ * [site][d][i][j] complex, d in (self, +x, -x, +y, -y, +z, -z, +t, -t),
+ * i, j < ncomp(level), prec MRHS_F64 or MRHS_F32, host or device; the
+ * operator is (D_c e)(A) = sum_d B_d(A) e(A + d), periodic, no boundary
+ * phase.  Synchronises. */
+mrhs_status mrhs_coarse_set_blocks(mrhs_mg mg, int32_t level, const void* blocks, mrhs_prec prec, int32_t on_device);
+/* Copies the FP64 blocks out (prec must be MRHS_F64).  Synchronises. */
+mrhs_status mrhs_coarse_get_blocks(mrhs_mg mg, int32_t level, void* blocks, mrhs_prec prec, int32_t on_device);
+/* mrhs_mg_build_coarse: Galerkin blocks of level `level` from level - 1,
+ * B_d(A) = sum_{x in A} W(x)^dag (D_d W)(x), with W the chirality-split basis
+ * of step level - 1 and D_d the piece of the level - 1 operator that couples
+ * A to A + d: for d = self the clover/self term and the hops that stay inside
+ * A, for d = +-mu the hops that leave A through its +-mu face (so with a
+ * coarse extent of 2 the +mu and -mu blocks stay distinct).  The fine
+ * operator is the context's D = A - kappa H.  FP64 throughout.  Synchronises. */
+mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
+/* mrhs_coarse_apply (Sec. 6): out = D_c in on coarse level `level`.
+ * prec MRHS_F64: FP64 fields and arithmetic; MRHS_F32: FP32 fields and
+ * arithmetic; MRHS_BF16 / MRHS_F16: FP32 fields, blocks and vectors rounded
+ * to BF16 / FP16 (nearest even; blocks via FP32) and multiplied on the
+ * matrix cores with FP32 accumulation (Nb = 32 only; FP16 vectors are scaled
+ * per RHS by a power of two first, exactly undone on output). */
+mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ from ._lib import BF16, F16, F32, F64, MrhsError  # noqa: F401
 
 lib = _lib.lib
 
-__all__ = ["Context", "MrhsError", "F64", "F32", "BF16", "F16", "lib"]
+__all__ = ["Context", "Multigrid", "MrhsError", "F64", "F32", "BF16", "F16", "lib"]
 
 
 def _torch():
@@ -213,3 +213,129 @@ class Context:
         self._check(lib.mrhs_axpy(self._h, C.c_void_p(py), C.c_void_p(al.ctypes.data), C.c_void_p(px), ns, nc, n,
                                   prec, 0))
         return y
+
+
+_PREC_NAMES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+
+
+class Multigrid:
+    """Aggregation hierarchy on a Context's lattice; wraps an ``mrhs_mg``.
+
+    blocks[l] is the aggregate extent of coarsening step l and n_v[l] its
+    number of basis vectors; level l + 1 has 2 n_v[l] components per site.
+    """
+
+    def __init__(self, ctx: Context, blocks, n_v):
+        self.ctx = ctx
+        nlev = len(blocks) + 1
+        if len(n_v) != len(blocks):
+            raise ValueError("need one n_v per coarsening step")
+        p = _lib.MgParams()
+        p.nlevels = nlev
+        for l, b in enumerate(blocks):
+            for m in range(4):
+                p.block[l][m] = int(b[m])
+            p.n_v[l] = int(n_v[l])
+        h = C.c_void_p()
+        ctx._check(lib.mrhs_mg_create(ctx.handle, C.byref(p), C.byref(h)))
+        self._h = h
+        self.nlevels = nlev
+        self.n_v = [int(v) for v in n_v]
+        self.dims, self.ncomp = [], []
+        for l in range(nlev):
+            d = (C.c_int32 * 4)()
+            nc = C.c_int32()
+            ctx._check(lib.mrhs_mg_level_info(h, l, d, C.byref(nc)))
+            self.dims.append(tuple(d))
+            self.ncomp.append(int(nc.value))
+        self.volume = [int(np.prod(d)) for d in self.dims]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.mrhs_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, st):
+        self.ctx._check(st)
+
+    # -- basis --------------------------------------------------------------------------
+    def set_basis(self, level: int, vecs):
+        want = (self.volume[level], self.n_v[level], self.ncomp[level])
+        if tuple(vecs.shape) != want:
+            raise ValueError(f"basis shape {tuple(vecs.shape)} != {want}")
+        p, prec, dev = _ptr_of(vecs)
+        self._check(lib.mrhs_mg_set_basis(self._h, level, C.c_void_p(p), prec, dev))
+
+    def get_basis(self, level: int) -> np.ndarray:
+        out = np.empty((self.volume[level], self.n_v[level], self.ncomp[level]), dtype=np.complex128)
+        self._check(lib.mrhs_mg_get_basis(self._h, level, C.c_void_p(out.ctypes.data), F64, 0))
+        return out
+
+    def block_orthonormalise(self, level: int):
+        self._check(lib.mrhs_mg_block_orthonormalise(self._h, level))
+
+    # -- intergrid ----------------------------------------------------------------------
+    def _pair(self, a, b, la, lb):
+        for t, l in ((a, la), (b, lb)):
+            if t.dim() != 3 or t.shape[0] != self.volume[l] or t.shape[1] != self.ncomp[l]:
+                raise ValueError(f"field {tuple(t.shape)} is not (V={self.volume[l]}, {self.ncomp[l]}, N) on level {l}")
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("fields must be contiguous device tensors")
+        if a.shape[2] != b.shape[2] or a.dtype != b.dtype:
+            raise ValueError("fields must share nrhs and dtype")
+        return int(a.shape[2]), _prec_of(a)
+
+    def restrict(self, level: int, coarse, fine):
+        n, prec = self._pair(coarse, fine, level + 1, level)
+        self._check(lib.mrhs_restrict(self._h, level, C.c_void_p(coarse.data_ptr()), C.c_void_p(fine.data_ptr()), n,
+                                      prec))
+        return coarse
+
+    def prolong(self, level: int, fine, coarse):
+        n, prec = self._pair(fine, coarse, level, level + 1)
+        self._check(lib.mrhs_prolong(self._h, level, C.c_void_p(fine.data_ptr()), C.c_void_p(coarse.data_ptr()), n,
+                                     prec))
+        return fine
+
+    def block_normalise(self, level: int, fields, norms=None):
+        n, prec = self._pair(fields, fields, level, level)
+        pn = C.c_void_p(norms.data_ptr()) if norms is not None else None
+        self._check(lib.mrhs_block_normalise(self._h, level, C.c_void_p(fields.data_ptr()), n, prec, pn))
+        return fields
+
+    # -- coarse operator ------------------------------------------------------------------
+    def set_blocks(self, level: int, blocks):
+        nb = self.ncomp[level]
+        want = (self.volume[level], 9, nb, nb)
+        if tuple(blocks.shape) != want:
+            raise ValueError(f"block shape {tuple(blocks.shape)} != {want}")
+        p, prec, dev = _ptr_of(blocks)
+        self._check(lib.mrhs_coarse_set_blocks(self._h, level, C.c_void_p(p), prec, dev))
+
+    def get_blocks(self, level: int) -> np.ndarray:
+        nb = self.ncomp[level]
+        out = np.empty((self.volume[level], 9, nb, nb), dtype=np.complex128)
+        self._check(lib.mrhs_coarse_get_blocks(self._h, level, C.c_void_p(out.ctypes.data), F64, 0))
+        return out
+
+    def build_coarse(self, level: int):
+        self._check(lib.mrhs_mg_build_coarse(self._h, level))
+
+    def coarse_apply(self, level: int, out, inp, prec=None):
+        """out = D_c inp on coarse level ``level``; prec is "f64", "f32", "bf16" or "f16"
+        (default: the fields' own precision)."""
+        n, fprec = self._pair(out, inp, level, level)
+        p = fprec if prec is None else _PREC_NAMES[prec]
+        self._check(lib.mrhs_coarse_apply(self._h, level, C.c_void_p(out.data_ptr()), C.c_void_p(inp.data_ptr()), n,
+                                          p))
+        return out

@@ -48,7 +48,24 @@ SIGNATURES = {
     "mrhs_norm2": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32]),
     "mrhs_multi_dot": (_i32, [_vp, _vp, C.POINTER(_vp), _i32, _vp, _i64, _i32, _i32, _i32, _i32]),
     "mrhs_axpy": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32]),
+    "mrhs_mg_create": (_i32, [_vp, _vp, C.POINTER(_vp)]),
+    "mrhs_mg_destroy": (None, [_vp]),
+    "mrhs_mg_level_info": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32)]),
+    "mrhs_mg_set_basis": (_i32, [_vp, _i32, _vp, _i32, _i32]),
+    "mrhs_mg_get_basis": (_i32, [_vp, _i32, _vp, _i32, _i32]),
+    "mrhs_mg_block_orthonormalise": (_i32, [_vp, _i32]),
+    "mrhs_restrict": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
+    "mrhs_prolong": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
+    "mrhs_block_normalise": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp]),
+    "mrhs_coarse_set_blocks": (_i32, [_vp, _i32, _vp, _i32, _i32]),
+    "mrhs_coarse_get_blocks": (_i32, [_vp, _i32, _vp, _i32, _i32]),
+    "mrhs_mg_build_coarse": (_i32, [_vp, _i32]),
+    "mrhs_coarse_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
 }
+
+
+class MgParams(C.Structure):
+    _fields_ = [("nlevels", _i32), ("block", (_i32 * 4) * 2), ("n_v", _i32 * 2)]
 
 
 class MrhsError(RuntimeError):

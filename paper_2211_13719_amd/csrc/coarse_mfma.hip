@@ -1,0 +1,249 @@
+// Coarse-level 9-point stencil on the matrix cores (paper Sec. 6), for
+// Nb = 32 components per site: with many right-hand sides the coarse operator
+// becomes, site by site, a sum of nine dense complex 32 x 32 by 32 x Nrhs
+// products, which gfx950 runs as BF16 or FP16 MFMA with FP32 accumulation.
+//
+// Complex arithmetic is split into real products,
+//   Re O += Re B Re E - Im B Im E,   Im O += Re B Im E + Im B Re E,
+// four v_mfma_f32_32x32x16 per 16-wide slice of the contraction index j.
+// One wavefront owns one site and a 32-column tile of right-hand sides and
+// walks the nine directions; rows of the 32 x 32 output are the 32 coarse
+// components i, columns the right-hand sides.
+//
+// Operand layouts of v_mfma_f32_32x32x16_{bf16,f16} (lane l, 8 values each):
+//   A (blocks):  A[i = l % 32][j = 8 (l / 32) + q], q = 0..7
+//   B (vectors): B[j = 8 (l / 32) + q][col = l % 32]
+//   D (output):  D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator r = 0..15
+// Blocks are pre-packed once per level in exactly the A order,
+// [site][d][j-slice][re|im][lane][8], so every A load is one 16-byte load per
+// lane and 1 KiB contiguous per wavefront.  Vectors stay FP32 in memory
+// ([site][j][rhs]); each lane reads its eight values (256-byte contiguous runs
+// across the wavefront) and rounds them to BF16/FP16 (round to nearest even)
+// on the fly.  FP16 operands are first scaled per right-hand side by a power
+// of two, 2^-E with max_k |x| = m 2^E, m in [0.5, 1), and the output is
+// scaled back in FP32; the power of two keeps the scaling exact.
+#include "mg_internal.h"
+
+namespace mrhs {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kNb = 32;
+
+template <bool F16>
+struct Op;
+template <>
+struct Op<false> {
+  using vec = bf16x8;
+  static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec cvt(const float (&x)[8]) {
+    vec v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (__bf16)x[q];
+    return v;
+  }
+};
+template <>
+struct Op<true> {
+  using vec = f16x8;
+  static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec cvt(const float (&x)[8]) {
+    vec v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (_Float16)x[q];
+    return v;
+  }
+};
+
+template <bool F16>
+__global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
+                                                          const float2* __restrict__ in, float2* __restrict__ out,
+                                                          const float* __restrict__ scale) {
+  using O = Op<F16>;
+  using vec = typename O::vec;
+  const int l = threadIdx.x & 63;
+  const int ntiles = (nrhs + 31) >> 5;
+  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= (long)g.V * ntiles) return;
+  const int s = (int)(w / ntiles);
+  const int col = (int)(w % ntiles) * 32 + (l & 31);
+  const bool colok = col < nrhs;
+  const int jh = 8 * (l >> 5);
+  const float sc = (F16 && colok) ? scale[col] : 1.0f;
+
+  int x[4];
+  {
+    int r = s;
+    x[0] = r % g.L[0];
+    r /= g.L[0];
+    x[1] = r % g.L[1];
+    r /= g.L[1];
+    x[2] = r % g.L[2];
+    x[3] = r / g.L[2];
+  }
+  f32x16 accR = {}, accI = {};
+  for (int d = 0; d < 9; ++d) {
+    int nbr = s;
+    if (d > 0) {
+      const int mu = (d - 1) >> 1;
+      const int c = x[mu] + (((d - 1) & 1) ? -1 : 1);
+      const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
+      nbr = s + (cw - x[mu]) * g.stride[mu];
+    }
+    const uint4* bp = Bp + ((size_t)s * 9 + d) * 256;
+    const float2* e = in + (size_t)nbr * kNb * nrhs + col;
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const uint4 br = bp[(kc * 2 + 0) * 64 + l];
+      const uint4 bi = bp[(kc * 2 + 1) * 64 + l];
+      float er[8], ei[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float2 v = colok ? e[(size_t)(kc * 16 + jh + q) * nrhs] : make_float2(0.f, 0.f);
+        er[q] = v.x * sc;
+        ei[q] = v.y * sc;
+      }
+      const vec vr = O::cvt(er), vi = O::cvt(ei);
+      const uint4 nbi = make_uint4(bi.x ^ 0x80008000u, bi.y ^ 0x80008000u, bi.z ^ 0x80008000u, bi.w ^ 0x80008000u);
+      const vec ar = __builtin_bit_cast(vec, br);
+      const vec ai = __builtin_bit_cast(vec, bi);
+      const vec an = __builtin_bit_cast(vec, nbi);
+      accR = O::mma(ar, vr, accR);
+      accR = O::mma(an, vi, accR);
+      accI = O::mma(ar, vi, accI);
+      accI = O::mma(ai, vr, accI);
+    }
+  }
+  if (!colok) return;
+  const float inv = F16 ? 1.0f / sc : 1.0f;  // exact: sc is a power of two
+  float2* o = out + (size_t)s * kNb * nrhs + col;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    o[(size_t)row * nrhs] = make_float2(accR[r] * inv, accI[r] * inv);
+  }
+}
+
+// FP64 blocks [site][9][32][32] complex -> packed A-operand order; the value is
+// rounded to FP32 first, then to BF16/FP16 (nearest even).
+template <bool F16>
+__global__ void pack_kernel(const double2* __restrict__ B, unsigned short* __restrict__ P, long nblk) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;  // one thread per packed element pair (re, im)
+  if (e >= nblk * kNb * kNb) return;
+  const long blk = e / (kNb * kNb);
+  const int r = (int)(e % (kNb * kNb));
+  const int i = r / kNb, j = r % kNb;
+  const int kc = j / 16, jj = j % 16;
+  const int lane = i + 32 * (jj / 8), q = jj % 8;
+  const double2 v = B[e];
+  const float fr = (float)v.x, fi = (float)v.y;
+  unsigned short hr, hi;
+  if constexpr (F16) {
+    const _Float16 a = (_Float16)fr, b = (_Float16)fi;
+    hr = __builtin_bit_cast(unsigned short, a);
+    hi = __builtin_bit_cast(unsigned short, b);
+  } else {
+    const __bf16 a = (__bf16)fr, b = (__bf16)fi;
+    hr = __builtin_bit_cast(unsigned short, a);
+    hi = __builtin_bit_cast(unsigned short, b);
+  }
+  unsigned short* base = P + blk * (2 * 2 * 64 * 8);
+  base[((kc * 2 + 0) * 64 + lane) * 8 + q] = hr;
+  base[((kc * 2 + 1) * 64 + lane) * 8 + q] = hi;
+}
+
+// scale[k] = 2^-E with max over the column of |re|, |im| = m 2^E, m in [0.5, 1); 1 for a zero column.
+__global__ void colmax_init(unsigned int* __restrict__ m, int nrhs) {
+  if ((int)threadIdx.x < nrhs) m[threadIdx.x] = 0u;
+}
+__global__ void colmax_kernel(const float2* __restrict__ in, long rows, int nrhs, unsigned int* __restrict__ m) {
+  const long e0 = (long)blockIdx.x * 256 + threadIdx.x;
+  const long n = rows * nrhs;
+  const long stride = (long)gridDim.x * 256;
+  // the stride is a multiple of nrhs when launched as below, so the column is fixed
+  const int k = (int)(e0 % nrhs);
+  float mx = 0.f;
+  for (long e = e0; e < n; e += stride) {
+    const float2 v = in[e];
+    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  if (e0 < n) atomicMax(m + k, __float_as_uint(mx));
+}
+__global__ void colmax_to_scale(const unsigned int* __restrict__ m, float* __restrict__ scale, int nrhs) {
+  const int k = threadIdx.x;
+  if (k >= nrhs) return;
+  const float mx = __uint_as_float(m[k]);
+  int E = 0;
+  (void)frexpf(mx, &E);
+  scale[k] = mx > 0.f ? ldexpf(1.0f, -E) : 1.0f;
+}
+
+}  // namespace
+
+bool mfma_supported(int nb) { return nb == kNb; }
+
+size_t mfma_pack_bytes(long nsite) { return (size_t)nsite * 9 * kNb * kNb * 2 * 2; }
+
+hipError_t launch_pack_blocks(int f16, const void* B64, void* packed, long nsite, hipStream_t s) {
+  const long n = nsite * 9 * kNb * kNb;
+  const int blocks = (int)((n + 255) / 256);
+  if (f16)
+    hipLaunchKernelGGL((pack_kernel<true>), dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(B64),
+                       static_cast<unsigned short*>(packed), nsite * 9);
+  else
+    hipLaunchKernelGGL((pack_kernel<false>), dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(B64),
+                       static_cast<unsigned short*>(packed), nsite * 9);
+  return hipGetLastError();
+}
+
+hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, float* scale, hipStream_t s) {
+  unsigned int* m = static_cast<unsigned int*>(work);
+  hipLaunchKernelGGL(colmax_init, dim3(1), dim3(64), 0, s, m, nrhs);
+  // workgroup stride must be a multiple of nrhs: use blocks of 256 threads and
+  // a grid such that 256 * grid % nrhs == 0
+  int grid = 256;
+  while ((256L * grid) % nrhs) ++grid;
+  hipLaunchKernelGGL(colmax_kernel, dim3(grid), dim3(256), 0, s, static_cast<const float2*>(in), rows, nrhs, m);
+  hipLaunchKernelGGL(colmax_to_scale, dim3(1), dim3(64), 0, s, m, scale, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
+                              const float* scale, hipStream_t s) {
+  if (nb != kNb) return hipErrorInvalidValue;
+  const long waves = (long)g.V * ((nrhs + 31) / 32);
+  const int blocks = (int)((waves + 3) / 4);
+  if (f16)
+    hipLaunchKernelGGL((coarse_mfma_kernel<true>), dim3(blocks), dim3(256), 0, s, g, nrhs,
+                       static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
+                       scale);
+  else
+    hipLaunchKernelGGL((coarse_mfma_kernel<false>), dim3(blocks), dim3(256), 0, s, g, nrhs,
+                       static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
+                       scale);
+  return hipGetLastError();
+}
+
+// Packs both low-precision copies of a level's blocks from the FP64 master.
+mrhs_status pack_blocks_mfma(mrhs_mg mg, int level) {
+  LevelData& L = mg->lv[level];
+  if (!mfma_supported(L.ncomp)) return MRHS_OK;
+  mrhs_ctx ctx = mg->ctx;
+  const size_t bytes = mfma_pack_bytes(L.g.V);
+  mrhs_status st = ensure(ctx, L.Bbf16, bytes);
+  if (st != MRHS_OK) return st;
+  st = ensure(ctx, L.Bf16, bytes);
+  if (st != MRHS_OK) return st;
+  MRHS_HIP(ctx, launch_pack_blocks(0, L.B64.p, L.Bbf16.p, L.g.V, ctx->stream));
+  MRHS_HIP(ctx, launch_pack_blocks(1, L.B64.p, L.Bf16.p, L.g.V, ctx->stream));
+  return MRHS_OK;
+}
+
+}  // namespace mrhs

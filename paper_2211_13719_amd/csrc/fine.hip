@@ -181,11 +181,11 @@ __device__ __forceinline__ void load_spinor(const cplx<T>* __restrict__ in, int 
 template <typename T, int R, int MU>
 __device__ __forceinline__ void hop_dir(const Geom& g, int site, int coord, int nrhs, int k0, T tbc,
                                         const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
-                                        cplx<T> (&acc)[4][3][R]) {
+                                        cplx<T> (&acc)[4][3][R], bool inc_f = true, bool inc_b = true) {
   const int L = g.L[MU];
   const int st = g.stride[MU];
   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
-  {
+  if (inc_f) {
     const int nb = (coord == L - 1) ? site - (L - 1) * st : site + st;
     const T ph = (MU == 3 && coord == L - 1) ? tbc : T(1);
     cplx<T> p[4][3][R];
@@ -214,7 +214,7 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int site, int coord, int 
     pin<T, R>(acc);
   }
   // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
-  {
+  if (inc_b) {
     const int nb = (coord == 0) ? site + (L - 1) * st : site - st;
     const T ph = (MU == 3 && coord == 0) ? tbc : T(1);
     cplx<T> p[4][3][R];
@@ -287,13 +287,30 @@ __device__ __forceinline__ void clover_block(const T* __restrict__ a, const cplx
     }
 }
 
+// Which hops into a site whose coordinate along mu is c the direction-resolved
+// operator of the Galerkin construction keeps (aggregate extent b along mu).
+__device__ __forceinline__ void galerkin_keep(const DirFilter& f, int mu, int c, bool& inc_f, bool& inc_b) {
+  const int r = c % f.b[mu];
+  const bool fface = (r == f.b[mu] - 1), bface = (r == 0);
+  if (f.sign == 0) {
+    inc_f = !fface;
+    inc_b = !bface;
+  } else {
+    inc_f = (f.sign == 1 && f.mu == mu && fface);
+    inc_b = (f.sign == -1 && f.mu == mu && bface);
+  }
+}
+
 // MODE 0: out = A psi - kappa H psi ; MODE 1: out = H psi ; MODE 2: out = A psi.
+// MODE 3: the direction-resolved piece D_d of MODE 0 selected by the filter
+// (sign 0: A psi and the hops that stay inside the aggregate; sign +-1: only
+// the -kappa hops that cross the +-mu face), used to build coarse blocks.
 template <typename T, int R, int MODE, bool XCD>
 __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T tbc,
                                                    const cplx<T>* __restrict__ U,
                                                    const T* __restrict__ A,
                                                    const cplx<T>* __restrict__ in,
-                                                   cplx<T>* __restrict__ out, int nblocks) {
+                                                   cplx<T>* __restrict__ out, int nblocks, DirFilter filt) {
   int b = blockIdx.x;
   if constexpr (XCD) {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
@@ -324,10 +341,22 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
-    hop_dir<T, R, 0>(g, site, x, nrhs, k0, tbc, U, in, acc);
-    hop_dir<T, R, 1>(g, site, y, nrhs, k0, tbc, U, in, acc);
-    hop_dir<T, R, 2>(g, site, z, nrhs, k0, tbc, U, in, acc);
-    hop_dir<T, R, 3>(g, site, t, nrhs, k0, tbc, U, in, acc);
+    if constexpr (MODE == 3) {
+      bool f0, b0, f1, b1, f2, b2, f3, b3;
+      galerkin_keep(filt, 0, x, f0, b0);
+      galerkin_keep(filt, 1, y, f1, b1);
+      galerkin_keep(filt, 2, z, f2, b2);
+      galerkin_keep(filt, 3, t, f3, b3);
+      hop_dir<T, R, 0>(g, site, x, nrhs, k0, tbc, U, in, acc, f0, b0);
+      hop_dir<T, R, 1>(g, site, y, nrhs, k0, tbc, U, in, acc, f1, b1);
+      hop_dir<T, R, 2>(g, site, z, nrhs, k0, tbc, U, in, acc, f2, b2);
+      hop_dir<T, R, 3>(g, site, t, nrhs, k0, tbc, U, in, acc, f3, b3);
+    } else {
+      hop_dir<T, R, 0>(g, site, x, nrhs, k0, tbc, U, in, acc);
+      hop_dir<T, R, 1>(g, site, y, nrhs, k0, tbc, U, in, acc);
+      hop_dir<T, R, 2>(g, site, z, nrhs, k0, tbc, U, in, acc);
+      hop_dir<T, R, 3>(g, site, t, nrhs, k0, tbc, U, in, acc);
+    }
   }
 
   cplx<T>* o = out + (size_t)site * 12 * nrhs + k0;
@@ -343,10 +372,17 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
       cplx<T> xin[6][R], yout[6][R];
 #pragma unroll
       for (int i = 0; i < 6; ++i) load_r<T, R>(base + (6 * chi + i) * nrhs, xin[i]);
-      clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
+      if (MODE != 3 || filt.sign == 0) {
+        clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+          for (int j = 0; j < R; ++j) yout[i][j] = mk<T>(0, 0);
+      }
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        if constexpr (MODE == 0) {
+        if constexpr (MODE == 0 || MODE == 3) {
           const int sp = 2 * chi + i / 3, c = i % 3;
 #pragma unroll
           for (int j = 0; j < R; ++j) {
@@ -362,13 +398,13 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
 
 template <typename T, int R, int MODE>
 hipError_t launch_r(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
-                    void* out, int nrhs, hipStream_t s) {
+                    void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}) {
   const long threads = (long)g.V * (nrhs / R);
   const int nblocks = (int)((threads + 255) / 256);
   const int grid = ((nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL((fine_kernel<T, R, MODE, true>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, T(t_bc),
                      reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
-                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks);
+                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f);
   return hipGetLastError();
 }
 
@@ -405,6 +441,11 @@ hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U, const void* A,
                            const void* in, void* out, int nrhs, hipStream_t s) {
   return launch_fine<double>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s);
+}
+
+hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,
+                               void* out, int nrhs, const DirFilter& f, hipStream_t s) {
+  return launch_r<double, 1, 3>(g, t_bc, kappa, U, A, in, out, nrhs, s, f);
 }
 
 }  // namespace mrhs

@@ -29,6 +29,16 @@ struct AggGeom {
   int Vc;  // aggregates
 };
 
+// Selects the direction-resolved piece of an operator for the Galerkin
+// construction: sign 2 = the whole operator; sign 0 = self term plus the hops
+// that stay inside the next level's aggregate (extent b); sign +1 / -1 with
+// direction mu = the hops leaving the aggregate through its +mu / -mu face.
+struct DirFilter {
+  int sign = 2;
+  int mu = 0;
+  int b[4] = {1, 1, 1, 1};
+};
+
 struct Buffer {
   void* p = nullptr;
   size_t bytes = 0;
@@ -86,6 +96,9 @@ hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U,
                            const void* A, const void* in, void* out, int nrhs, hipStream_t s);
 
+hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,
+                               void* out, int nrhs, const DirFilter& f, hipStream_t s);
+
 // ---- launchers (clover_build.hip) -------------------------------------------
 hipError_t launch_clover_build(const Geom& g, double csw, double kappa, const void* U64,
                                void* F_scratch, void* A64, void* A32, hipStream_t s);
@@ -116,5 +129,11 @@ hipError_t launch_block_normalise(int prec64, const AggGeom& a, int h, int nrhs,
                                   hipStream_t s);
 hipError_t launch_basis_convert(const void* in, int in_prec64, void* out, int out_prec64, long nsite, int nv, int ncomp,
                                 int to_internal, hipStream_t s);
+
+// ---- launchers (coarse.hip) ----------------------------------------------------
+hipError_t launch_coarse_valu(int prec64, const Geom& g, int nb, int nrhs, const void* BT, const void* in, void* out,
+                              const DirFilter& f, hipStream_t s);
+hipError_t launch_block_transpose(const void* in, int in64, void* out, int out64, long nblk, int nb, hipStream_t s);
+hipError_t launch_basis_columns(int prec64, const void* basis, void* W, long nsite, int ncomp, int nv, hipStream_t s);
 
 }  // namespace mrhs

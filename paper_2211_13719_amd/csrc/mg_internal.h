@@ -1,0 +1,56 @@
+// Multigrid hierarchy object shared by the multigrid translation units.
+#pragma once
+
+#include "internal.h"
+
+namespace mrhs {
+
+// One level of the hierarchy.  Level 0 is the fine lattice (12 spinor
+// components); level l >= 1 has ncomp = 2 n_v(l-1) components per site.
+struct LevelData {
+  Geom g{};
+  int ncomp = 0;
+  // basis prolongating from level + 1 (internal layout [site][ncomp][nv])
+  int nv = 0;
+  AggGeom agg{};
+  Buffer basis64, basis32;
+  bool have_basis = false;
+  // stencil blocks (levels >= 1): FP64 master [site][9][i][j], transposed
+  // copies [site][9][j][i] for the vector-ALU kernels, MFMA packs
+  Buffer B64, BT32, BT64, Bbf16, Bf16;
+  bool have_blocks = false;
+};
+
+struct SolverState;
+
+}  // namespace mrhs
+
+struct mrhs_mg_s {
+  mrhs_ctx ctx = nullptr;
+  int nlevels = 0;
+  mrhs::LevelData lv[MRHS_MAX_LEVELS];
+  mrhs::Buffer tmpA, tmpB, tmpC;  // setup scratch
+  mrhs::Buffer colscale;          // per-RHS FP16 scales and their reduction words
+  int* flag = nullptr;            // device flag (rank deficiency)
+  mrhs::SolverState* solver = nullptr;
+};
+
+namespace mrhs {
+
+mrhs_status refresh_blocks(mrhs_mg mg, int level);
+mrhs_status refresh_basis32(mrhs_mg mg, int level);
+
+// coarse_mfma.hip
+bool mfma_supported(int nb);
+size_t mfma_pack_bytes(long nsite);
+mrhs_status pack_blocks_mfma(mrhs_mg mg, int level);
+hipError_t launch_pack_blocks(int f16, const void* B64, void* packed, long nsite, hipStream_t s);
+// scale[k] for FP16 operands; work holds nrhs 32-bit words
+hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, float* scale, hipStream_t s);
+hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
+                              const float* scale, hipStream_t s);
+
+// solver (mg_solve.hip)
+void mg_solver_release(mrhs_mg mg);
+
+}  // namespace mrhs

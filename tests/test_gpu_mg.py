@@ -1,0 +1,337 @@
+"""GPU parity of the multigrid pieces against the FP64 oracle: block
+orthonormalisation, restriction / prolongation, block normalisation, the
+coarse stencil (FP64, FP32, BF16 and FP16 matrix cores) and the Galerkin
+construction of the coarse blocks.
+
+Tolerances (relative L2 unless stated):
+  FP64 paths      1e-12  (same operations as the oracle, other summation order)
+  FP32 paths      1e-6   (unit roundoff 6e-8 times a short sum; expected ~1e-7)
+  BF16/FP16 paths 2e-2 against the oracle on the original operands, and
+                  1e-6 against the oracle on the same rounded operands (the
+                  MFMA products are exact, only the FP32 accumulation rounds)
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KAPPA, CSW = 0.13, 1.0
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def make_mg(mrhs, dims, blocks, n_v, U=None, t_bc=-1):
+    ctx = mrhs.Context(dims, t_bc=t_bc)
+    if U is not None:
+        ctx.set_gauge(U)
+        ctx.build_clover(CSW, KAPPA)
+    return ctx, mrhs.Multigrid(ctx, blocks, n_v)
+
+
+# ---- basis and intergrid -------------------------------------------------------------
+
+GEOMS = [
+    # dims, block, n_v
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16),
+    ((4, 8, 4, 6), (2, 4, 2, 3), 8),
+    ((4, 4, 2, 2), (2, 2, 2, 1), 4),
+]
+
+
+@pytest.mark.parametrize("dims,block,nv", GEOMS)
+def test_block_orthonormalise(gpu_lib, dims, block, nv):
+    ctx, mg = make_mg(gpu_lib, dims, [block], [nv])
+    V = synth.volume(dims)
+    v = synth.gaussian_vectors(V, nv, 12, 31)
+    mg.set_basis(0, v)
+    np.testing.assert_array_equal(mg.get_basis(0), v)  # round trip through the internal layout
+    mg.block_orthonormalise(0)
+    got = mg.get_basis(0)
+    want = O.block_orthonormalise(v, dims, block)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_block_orthonormalise_rank_deficient(gpu_lib):
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    ctx, mg = make_mg(gpu_lib, dims, [block], [4])
+    v = synth.gaussian_vectors(synth.volume(dims), 4, 12, 5)
+    v[:, 3] = v[:, 1]  # vector 3 repeats vector 1 everywhere
+    mg.set_basis(0, v)
+    with pytest.raises(gpu_lib.MrhsError, match="STATE"):
+        mg.block_orthonormalise(0)
+
+
+@pytest.mark.parametrize("dims,block,nv", GEOMS)
+@pytest.mark.parametrize("nrhs", [1, 5, 24, 64])
+@pytest.mark.parametrize("dt", [np.complex64, np.complex128])
+def test_restrict_prolong(gpu_lib, dims, block, nv, nrhs, dt):
+    import torch
+
+    ctx, mg = make_mg(gpu_lib, dims, [block], [nv])
+    V = synth.volume(dims)
+    basis = O.block_orthonormalise(synth.gaussian_vectors(V, nv, 12, 3), dims, block)
+    mg.set_basis(0, basis)
+    b_used = basis.astype(dt).astype(np.complex128)  # the kernel's basis precision
+    f = synth.spinor_source(dims, nrhs, 40, dt)
+    Vc = mg.volume[1]
+    y = torch.empty((Vc, 2 * nv, nrhs), dtype=torch.complex64 if dt == np.complex64 else torch.complex128,
+                    device="cuda")
+    mg.restrict(0, y, dev(f))
+    tol = 1e-6 if dt == np.complex64 else 1e-12
+    assert rel(host(y), O.restrict(b_used, f, dims, block)) < tol
+    yc = synth.coarse_source(Vc, 2 * nv, nrhs, 70, dt)
+    fo = torch.empty((V, 12, nrhs), dtype=y.dtype, device="cuda")
+    mg.prolong(0, fo, dev(yc))
+    assert rel(host(fo), O.prolong(b_used, yc, dims, block)) < tol
+
+
+def test_restrict_prolong_coarse_level(gpu_lib):
+    """Step 1 (coarse -> coarser) with 16 components per chirality, in FP64."""
+    import torch
+
+    dims = (4, 4, 4, 4)
+    ctx, mg = make_mg(gpu_lib, dims, [(2, 2, 2, 2), (2, 1, 2, 1)], [16, 8])
+    d1 = mg.dims[1]
+    V1 = mg.volume[1]
+    basis = O.block_orthonormalise(synth.gaussian_vectors(V1, 8, 32, 8), d1, (2, 1, 2, 1))
+    mg.set_basis(1, basis)
+    f = synth.coarse_source(V1, 32, 7, 9)
+    y = torch.empty((mg.volume[2], 16, 7), dtype=torch.complex128, device="cuda")
+    mg.restrict(1, y, dev(f))
+    assert rel(host(y), O.restrict(basis, f, d1, (2, 1, 2, 1))) < 1e-12
+    yc = synth.coarse_source(mg.volume[2], 16, 7, 10)
+    fo = torch.empty((V1, 32, 7), dtype=torch.complex128, device="cuda")
+    mg.prolong(1, fo, dev(yc))
+    assert rel(host(fo), O.prolong(basis, yc, d1, (2, 1, 2, 1))) < 1e-12
+
+
+def test_intergrid_config4_full(gpu_lib):
+    """24^4 fine lattice, 4^4 aggregates, 16 Gaussian vectors block-orthonormalised
+    in FP64 on the GPU, restrict / prolong / block-normalise of Nrhs = 24 FP32 fields."""
+    import torch
+
+    dims, block, nv, nrhs = (24, 24, 24, 24), (4, 4, 4, 4), 16, 24
+    ctx, mg = make_mg(gpu_lib, dims, [block], [nv])
+    V = synth.volume(dims)
+    v = synth.gaussian_vectors(V, nv, 12, 2024)
+    mg.set_basis(0, v)
+    mg.block_orthonormalise(0)
+    basis = O.block_orthonormalise(v, dims, block)
+    assert np.max(np.abs(mg.get_basis(0) - basis)) < 1e-12
+    b32 = basis.astype(np.complex64).astype(np.complex128)
+    f = synth.spinor_source(dims, nrhs, 500, np.complex64)
+    y = torch.empty((mg.volume[1], 32, nrhs), dtype=torch.complex64, device="cuda")
+    tf = dev(f)
+    mg.restrict(0, y, tf)
+    assert rel(host(y), O.restrict(b32, f, dims, block)) < 1e-6
+    fo = torch.empty_like(tf)
+    mg.prolong(0, fo, y)
+    assert rel(host(fo), O.prolong(b32, host(y), dims, block)) < 1e-6
+    norms = torch.empty((mg.volume[1], 2, nrhs), dtype=torch.float64, device="cuda")
+    mg.block_normalise(0, tf, norms)
+    want, want_n = O.block_normalise(f, dims, block)
+    assert rel(host(tf), want) < 1e-6
+    np.testing.assert_allclose(host(norms), want_n, rtol=1e-12)
+
+
+@pytest.mark.parametrize("dt", [np.complex64, np.complex128])
+def test_block_normalise_small(gpu_lib, dt):
+    import torch
+
+    dims, block = (4, 8, 4, 6), (2, 4, 2, 3)
+    ctx, mg = make_mg(gpu_lib, dims, [block], [8])
+    f = synth.spinor_source(dims, 5, 1, dt)
+    f[:32] = 0  # some all-zero blocks stay zero
+    t = dev(f)
+    norms = torch.empty((mg.volume[1], 2, 5), dtype=torch.float64, device="cuda")
+    mg.block_normalise(0, t, norms)
+    want, want_n = O.block_normalise(f, dims, block)
+    assert rel(host(t), want) < (1e-6 if dt == np.complex64 else 1e-13)
+    np.testing.assert_allclose(host(norms), want_n, rtol=1e-12, atol=0)
+
+
+# ---- coarse stencil --------------------------------------------------------------------
+
+def coarse_mg(mrhs, cdims, nb):
+    """A hierarchy whose level 1 has lattice cdims and nb components (blocks set directly)."""
+    fine = tuple(2 * c for c in cdims)
+    return make_mg(mrhs, fine, [(2, 2, 2, 2)], [nb // 2])
+
+
+@pytest.mark.parametrize("cdims", [(6, 6, 6, 6), (3, 3, 3, 3), (2, 3, 1, 2)])
+@pytest.mark.parametrize("nrhs", [1, 12, 24, 48, 64])
+def test_coarse_apply_all_precisions(gpu_lib, cdims, nrhs):
+    import torch
+
+    nb = 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 7)
+    mg.set_blocks(1, B)
+    np.testing.assert_array_equal(mg.get_blocks(1), B)
+    e64 = synth.coarse_source(Vc, nb, nrhs, 11)
+    e32 = e64.astype(np.complex64)
+    want64 = O.coarse_apply(B, e64, cdims)
+    out = torch.empty((Vc, nb, nrhs), dtype=torch.complex128, device="cuda")
+    mg.coarse_apply(1, out, dev(e64), "f64")
+    assert rel(host(out), want64) < 1e-12
+    B32 = B.astype(np.complex64)
+    want32 = O.coarse_apply(B32, e32, cdims)
+    o32 = torch.empty((Vc, nb, nrhs), dtype=torch.complex64, device="cuda")
+    mg.coarse_apply(1, o32, dev(e32), "f32")
+    assert rel(host(o32), want32) < 1e-6
+    for fmt in ("bf16", "f16"):
+        o = torch.empty_like(o32)
+        mg.coarse_apply(1, o, dev(e32), fmt)
+        got = host(o)
+        assert rel(got, O.coarse_apply(B, e32, cdims)) < 2e-2, fmt
+        assert rel(got, O.coarse_apply_lowprec(B, e32, cdims, fmt)) < 1e-6, fmt
+
+
+def test_coarse_apply_nb8_valu(gpu_lib):
+    import torch
+
+    cdims, nb = (2, 2, 4, 2), 8
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 3)
+    mg.set_blocks(1, B)
+    e = synth.coarse_source(Vc, nb, 6, 1)
+    out = torch.empty((Vc, nb, 6), dtype=torch.complex128, device="cuda")
+    mg.coarse_apply(1, out, dev(e), "f64")
+    assert rel(host(out), O.coarse_apply(B, e, cdims)) < 1e-12
+    with pytest.raises(gpu_lib.MrhsError, match="UNSUPPORTED"):
+        mg.coarse_apply(1, out.to(torch.complex64), dev(e.astype(np.complex64)), "bf16")
+
+
+def test_coarse_mfma_mrhs_equals_columns(gpu_lib):
+    """Within one tile configuration each column of a batched BF16 apply equals
+    the column applied alone (the per-column arithmetic does not depend on N)."""
+    import torch
+
+    cdims, nb = (3, 3, 3, 3), 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    mg.set_blocks(1, synth.gaussian_blocks(Vc, nb, 9))
+    e = synth.coarse_source(Vc, nb, 24, 2, np.complex64)
+    out = torch.empty((Vc, nb, 24), dtype=torch.complex64, device="cuda")
+    mg.coarse_apply(1, out, dev(e), "bf16")
+    for k in (0, 13, 23):
+        ok = torch.empty((Vc, nb, 1), dtype=torch.complex64, device="cuda")
+        mg.coarse_apply(1, ok, dev(e[:, :, k:k + 1]), "bf16")
+        np.testing.assert_array_equal(host(ok)[:, :, 0], host(out)[:, :, k])
+
+
+# ---- Galerkin construction -------------------------------------------------------------
+
+def test_galerkin_two_levels_vs_oracle(gpu_lib):
+    """8^4 Haar links -> 2^4 (4^4 aggregates, extent-2 aliasing) -> 1^4 (2^4
+    aggregates, extent-1 aliasing), n_v = 16 at both steps, FP64."""
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_haar(dims, 12)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx, mg = make_mg(gpu_lib, dims, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16], U=U)
+    V = synth.volume(dims)
+    v0 = synth.gaussian_vectors(V, 16, 12, 100)
+    mg.set_basis(0, v0)
+    mg.block_orthonormalise(0)
+    b0 = O.block_orthonormalise(v0, dims, (4, 4, 4, 4))
+    mg.build_coarse(1)
+    B1 = O.galerkin_fine(U, A, KAPPA, b0, dims, (4, 4, 4, 4))
+    got1 = mg.get_blocks(1)
+    assert rel(got1, B1) < 1e-12
+    d1 = mg.dims[1]
+    v1 = synth.gaussian_vectors(mg.volume[1], 16, 32, 200)
+    mg.set_basis(1, v1)
+    mg.block_orthonormalise(1)
+    b1 = O.block_orthonormalise(v1, d1, (2, 2, 2, 2))
+    mg.build_coarse(2)
+    B2 = O.galerkin_coarse(B1, b1, d1, (2, 2, 2, 2))
+    assert rel(mg.get_blocks(2), B2) < 1e-12
+
+
+def test_galerkin_nonsquare_periodic(gpu_lib):
+    dims = (4, 2, 6, 4)
+    U = synth.gauge_haar(dims, 5)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx = gpu_lib.Context(dims, t_bc=+1)
+    ctx.set_gauge(U)
+    ctx.build_clover(CSW, KAPPA)
+    mg = gpu_lib.Multigrid(ctx, [(2, 2, 3, 2)], [4])
+    v0 = synth.gaussian_vectors(synth.volume(dims), 4, 12, 1)
+    mg.set_basis(0, v0)
+    mg.block_orthonormalise(0)
+    mg.build_coarse(1)
+    b0 = O.block_orthonormalise(v0, dims, (2, 2, 3, 2))
+    want = O.galerkin_fine(U, A, KAPPA, b0, dims, (2, 2, 3, 2), t_bc=1.0)
+    assert rel(mg.get_blocks(1), want) < 1e-12
+
+
+def test_galerkin_config3_full(gpu_lib):
+    """Config 3 blocks at full size: 24^4 Haar links (csw 1, kappa 0.13), 16
+    Gaussian vectors -> 6^4, then 16 more -> 3^4.  Checked by what holds at
+    any size: D_c e = P^dag D P e for the GPU's own P and D (FP64), and the
+    coarse gamma_5-hermiticity B_{-mu}(A + mu) = G5 B_{+mu}(A)^dag G5,
+    B_self = G5 B_self^dag G5."""
+    import torch
+
+    dims = (24, 24, 24, 24)
+    U = synth.gauge_haar(dims, 2024)
+    ctx, mg = make_mg(gpu_lib, dims, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16], U=U)
+    V = synth.volume(dims)
+    mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
+    mg.block_orthonormalise(0)
+    mg.build_coarse(1)
+    mg.set_basis(1, synth.gaussian_vectors(mg.volume[1], 16, 32, 400))
+    mg.block_orthonormalise(1)
+    mg.build_coarse(2)
+    for lev in (1, 2):
+        n = 3
+        e = synth.coarse_source(mg.volume[lev], 32, n, 50 + lev, np.complex128)
+        te = dev(e)
+        # P^dag D P e on the GPU
+        finer = torch.empty((mg.volume[lev - 1], mg.ncomp[lev - 1], n), dtype=torch.complex128, device="cuda")
+        mg.prolong(lev - 1, finer, te)
+        applied = torch.empty_like(finer)
+        if lev == 1:
+            ctx.dwc(applied, finer)
+        else:
+            mg.coarse_apply(1, applied, finer, "f64")
+        want = torch.empty_like(te)
+        mg.restrict(lev - 1, want, applied)
+        got = torch.empty_like(te)
+        mg.coarse_apply(lev, got, te, "f64")
+        assert rel(host(got), host(want)) < 1e-12, lev
+        B = mg.get_blocks(lev)
+        g5 = np.diag(np.r_[np.ones(16), -np.ones(16)])
+        cd = mg.dims[lev]
+        Vc = mg.volume[lev]
+        s = np.arange(Vc)
+        coord = np.stack([s % cd[0], (s // cd[0]) % cd[1], (s // (cd[0] * cd[1])) % cd[2],
+                          s // (cd[0] * cd[1] * cd[2])], axis=1)
+        stride = np.array([1, cd[0], cd[0] * cd[1], cd[0] * cd[1] * cd[2]])
+        herm = g5 @ np.conj(np.swapaxes(B[:, 0], -1, -2)) @ g5
+        assert np.max(np.abs(herm - B[:, 0])) < 1e-12 * np.max(np.abs(B[:, 0]))
+        for mu in range(4):
+            nbr = ((coord + np.eye(4, dtype=int)[mu]) % np.array(cd)) @ stride
+            lhs = B[nbr, 2 + 2 * mu]
+            rhs = g5 @ np.conj(np.swapaxes(B[:, 1 + 2 * mu], -1, -2)) @ g5
+            assert np.max(np.abs(lhs - rhs)) < 1e-12 * np.max(np.abs(B[:, 1 + 2 * mu])), (lev, mu)
