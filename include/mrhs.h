@@ -244,6 +244,67 @@ mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
  * per RHS by a power of two first, exactly undone on output). */
 mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 
+/* ---- multigrid-preconditioned solve (paper Sec. 8) -----------------------
+ * The paper solves with FGMRES preconditioned by multigrid, on many RHS at
+ * once; it does not describe its smoother, cycle or setup, so the ones below
+ * are this library's.  All of them act on Nrhs columns at once with one
+ * independent Krylov space / scalar set per column.
+ *
+ * V-cycle (the preconditioner, FP32 fields): on each level above the
+ * coarsest, nu_pre minimal-residual (MR) steps x += a r, r -= a D r with
+ * a = <D r, r> / ||D r||^2 per column, the coarse-grid correction
+ * x += P V(R r), the residual r = b - D x and nu_post MR steps; on the
+ * coarsest level coarsest_iters MR steps from x = 0.  The fine operator runs
+ * in FP32; coarse levels in coarse_prec (MRHS_F32 vector ALU, MRHS_BF16 or
+ * MRHS_F16 matrix cores with FP32 accumulation, Nb = 32). */
+typedef struct {
+  int32_t nu_pre;
+  int32_t nu_post;
+  int32_t coarsest_iters;
+  mrhs_prec coarse_prec;
+} mrhs_vcycle_params;
+
+typedef struct {
+  double tol;           /* stop when ||b_k - D x_k|| / ||b_k|| <= tol for every k (FP64 true residual) */
+  int32_t restart;      /* FGMRES cycle length m, 1 <= m <= 15 */
+  int32_t max_iters;    /* total preconditioned steps */
+  int32_t precondition; /* 1: V-cycle; 0: none (plain restarted GMRES with FP32-rounded directions) */
+  int32_t use_graph;    /* 1: replay the V-cycle from a captured HIP graph */
+  int32_t timers;       /* 1: per-phase device timers (no graph; slower) */
+  mrhs_vcycle_params vc;
+} mrhs_solve_params;
+
+typedef struct {
+  int32_t nrhs;
+  int32_t iters;                    /* preconditioned steps (shared by all columns) */
+  int32_t cycles;                   /* restart cycles */
+  int32_t converged[MRHS_MAX_NRHS]; /* 1 if column k met tol */
+  double rel_resid[MRHS_MAX_NRHS];  /* final true ||b_k - D x_k|| / ||b_k||, FP64 */
+  double seconds_total;             /* host wall clock of the call */
+  double seconds_precond;           /* V-cycles (with timers) */
+  double seconds_phase[4];          /* with timers: fine level, restrict, prolong, coarse levels (device) */
+} mrhs_solve_stats;
+
+/* mrhs_mg_precondition: z = V-cycle(v) for nrhs FP32 fine fields (device,
+ * [V][12][nrhs]).  Needs the bases and coarse operators of every level.
+ * Synchronises. */
+mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrhs, const mrhs_vcycle_params* vc);
+/* mrhs_mg_setup: from the starting vectors already set with
+ * mrhs_mg_set_basis on every step (e.g. Gaussian), level by level:
+ * setup_iters sweeps of smooth_steps MR steps on D x = 0 starting from the
+ * vectors (which damps their high modes), column normalisation, block
+ * orthonormalisation (FP64) and the Galerkin operator of the next level.
+ * Synchronises. */
+mrhs_status mrhs_mg_setup(mrhs_mg mg, int32_t setup_iters, int32_t smooth_steps);
+/* mrhs_mg_solve: solves D x_k = b_k for the context's fine operator
+ * D = A - kappa H (for the mass form D_m = D / (2 kappa) pass 2 kappa b), by
+ * FGMRES(m) in FP64 with the V-cycle as preconditioner.  x: device FP64
+ * [V][12][nrhs], in: initial guess, out: solution; b: device FP64, not
+ * overlapping x.  Returns MRHS_ERR_NOT_CONVERGED (stats filled, x holds the
+ * last iterate) if max_iters is reached first.  Synchronises. */
+mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, const mrhs_solve_params* params,
+                          mrhs_solve_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

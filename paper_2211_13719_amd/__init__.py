@@ -339,3 +339,55 @@ class Multigrid:
         self._check(lib.mrhs_coarse_apply(self._h, level, C.c_void_p(out.data_ptr()), C.c_void_p(inp.data_ptr()), n,
                                           p))
         return out
+
+    # -- solver ---------------------------------------------------------------------------
+    @staticmethod
+    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16"):
+        v = _lib.VcycleParams()
+        v.nu_pre, v.nu_post, v.coarsest_iters = int(nu_pre), int(nu_post), int(coarsest_iters)
+        v.coarse_prec = _PREC_NAMES[coarse_prec]
+        return v
+
+    def setup(self, setup_iters: int = 3, smooth_steps: int = 8):
+        """Refine the basis vectors already set on every step (inverse-iteration-like
+        smoothing of D x = 0), block-orthonormalise them and build all coarse operators."""
+        self._check(lib.mrhs_mg_setup(self._h, int(setup_iters), int(smooth_steps)))
+
+    def precondition(self, z, v, **vc):
+        """z = V-cycle(v) for FP32 fine fields (V, 12, N)."""
+        n, prec = self._pair(z, v, 0, 0)
+        if prec != F32:
+            raise TypeError("the V-cycle works on complex64 fields")
+        p = self._vc(**vc)
+        self._check(lib.mrhs_mg_precondition(self._h, C.c_void_p(z.data_ptr()), C.c_void_p(v.data_ptr()), n,
+                                             C.byref(p)))
+        return z
+
+    def solve(self, x, b, tol=1e-10, restart=8, max_iters=500, precondition=True, use_graph=True, timers=False,
+              check=True, **vc):
+        """Solve D x_k = b_k (complex128 fields (V, 12, N); x holds the initial guess).
+        Returns a dict of statistics; raises MrhsError unless converged when check is set."""
+        n, prec = self._pair(x, b, 0, 0)
+        if prec != F64:
+            raise TypeError("x and b must be complex128")
+        p = _lib.SolveParams()
+        p.tol, p.restart, p.max_iters = float(tol), int(restart), int(max_iters)
+        p.precondition, p.use_graph, p.timers = int(bool(precondition)), int(bool(use_graph)), int(bool(timers))
+        p.vc = self._vc(**vc)
+        st = _lib.SolveStats()
+        status = lib.mrhs_mg_solve(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(b.data_ptr()), n, C.byref(p),
+                                   C.byref(st))
+        out = {
+            "nrhs": st.nrhs,
+            "iters": st.iters,
+            "cycles": st.cycles,
+            "converged": [bool(st.converged[k]) for k in range(n)],
+            "rel_resid": [float(st.rel_resid[k]) for k in range(n)],
+            "seconds_total": st.seconds_total,
+            "seconds_precond": st.seconds_precond,
+            "seconds_phase": dict(zip(("fine", "restrict", "prolong", "coarse"), list(st.seconds_phase))),
+            "status": status,
+        }
+        if check and status != 0:
+            self._check(status)
+        return out

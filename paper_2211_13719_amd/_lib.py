@@ -61,7 +61,25 @@ SIGNATURES = {
     "mrhs_coarse_get_blocks": (_i32, [_vp, _i32, _vp, _i32, _i32]),
     "mrhs_mg_build_coarse": (_i32, [_vp, _i32]),
     "mrhs_coarse_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
+    "mrhs_mg_precondition": (_i32, [_vp, _vp, _vp, _i32, _vp]),
+    "mrhs_mg_setup": (_i32, [_vp, _i32, _i32]),
+    "mrhs_mg_solve": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
 }
+
+
+class VcycleParams(C.Structure):
+    _fields_ = [("nu_pre", _i32), ("nu_post", _i32), ("coarsest_iters", _i32), ("coarse_prec", _i32)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", _f64), ("restart", _i32), ("max_iters", _i32), ("precondition", _i32), ("use_graph", _i32),
+                ("timers", _i32), ("vc", VcycleParams)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("nrhs", _i32), ("iters", _i32), ("cycles", _i32), ("converged", _i32 * 64),
+                ("rel_resid", _f64 * 64), ("seconds_total", _f64), ("seconds_precond", _f64),
+                ("seconds_phase", _f64 * 4)]
 
 
 class MgParams(C.Structure):

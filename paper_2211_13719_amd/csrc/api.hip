@@ -166,6 +166,7 @@ mrhs_status mrhs_create(mrhs_ctx* out, const int32_t dims[4], int32_t t_bc, int3
   ctx->g.stride[1] = dims[0];
   ctx->g.stride[2] = dims[0] * dims[1];
   ctx->g.stride[3] = dims[0] * dims[1] * dims[2];
+  set_tile(ctx->g);
   ctx->t_bc = t_bc;
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(stream);

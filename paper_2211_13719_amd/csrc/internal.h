@@ -17,7 +17,22 @@ struct Geom {
   int L[4];     // Lx, Ly, Lz, Lt
   int V;        // number of sites
   int stride[4];  // site-index step of +1 in each direction: 1, Lx, Lx*Ly, Lx*Ly*Lz
+  int T[4] = {1, 1, 1, 1};  // traversal tile of the fine kernels (divides L)
 };
+
+// Traversal tile: extent 8 (x) or 4 (others) where it divides the lattice,
+// else the largest of 4, 2, 1 that does.
+inline void set_tile(Geom& g) {
+  for (int m = 0; m < 4; ++m) {
+    const int pref[4] = {m == 0 ? 8 : 4, 4, 2, 1};
+    g.T[m] = 1;
+    for (int c : pref)
+      if (g.L[m] % c == 0) {
+        g.T[m] = c;
+        break;
+      }
+  }
+}
 
 // Aggregation geometry of one coarsening step: fine lattice L, aggregate
 // extent b, coarse lattice C = L / b.

@@ -45,6 +45,7 @@ Geom make_geom(const int L[4]) {
   g.stride[1] = L[0];
   g.stride[2] = L[0] * L[1];
   g.stride[3] = L[0] * L[1] * L[2];
+  set_tile(g);
   return g;
 }
 

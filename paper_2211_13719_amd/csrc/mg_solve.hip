@@ -1,6 +1,613 @@
-// Placeholder translation unit for the multigrid solver state.
+// Multigrid-preconditioned flexible GMRES on Nrhs right-hand sides at once
+// (paper Sec. 8: FGMRES preconditioned by multigrid, applied to many RHS
+// simultaneously so that every operator application and every inner product
+// serves the whole block).
+//
+// Outer solver: FGMRES(m) in FP64, one independent Krylov space per
+// right-hand side (batched, not block Krylov): per-RHS Hessenberg matrices
+// and Givens rotations live on the host, the vectors on the device, and all
+// inner products of one Gram-Schmidt step are computed in one pass (classical
+// Gram-Schmidt applied twice).  The preconditioned directions Z are stored in
+// FP32; since the same FP32 values enter both D Z and the update x += Z y, the
+// Arnoldi relation holds to FP64 rounding and the FP64 true residual can reach
+// 1e-10 although the preconditioner works in lower precision.
+//
+// Preconditioner: a V-cycle over the aggregation hierarchy, all fields FP32.
+// On every level above the coarsest: nu_pre minimal-residual (MR) steps, the
+// coarse-grid correction x += P V(R r), the residual r = b - D x, nu_post MR
+// steps.  On the coarsest level: coarsest_iters MR steps from zero.  The fine
+// operator is the FP32 Wilson-clover kernel, coarse operators the stencil in
+// the requested arithmetic (FP32 vector ALU, or BF16/FP16 matrix cores with
+// FP32 accumulation).  The MR step sizes alpha_k = <D r_k, r_k> / ||D r_k||^2
+// are computed and consumed on the device, so one V-cycle is a fixed sequence
+// of kernel launches that can be captured once into a HIP graph and replayed.
+//
+// Setup (the paper does not describe one): starting from the caller's basis
+// vectors on each level, setup_iters sweeps of MR on the homogeneous system
+// D x = 0 (each sweep multiplies the vectors by prod_i (1 - alpha_i D), which
+// damps the high modes and keeps the near-null space), column normalisation,
+// block orthonormalisation in FP64 and the Galerkin coarse operator.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
 #include "mg_internal.h"
 
 namespace mrhs {
-void mg_solver_release(mrhs_mg) {}
+
+// solver_kernels.hip
+size_t solver_scratch_bytes(int nrhs);
+hipError_t launch_mr_alpha(const void* p, const void* r, long rows, int nrhs, void* alpha, void* scratch,
+                           hipStream_t s);
+hipError_t launch_mr_update(void* x, void* r, const void* p, const void* alpha, long rows, int nrhs, hipStream_t s);
+hipError_t launch_multi_axpy(int x64, void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
+                             int nrhs, hipStream_t s);
+hipError_t launch_scale_cols(int prec64, void* y, const void* x, const double* sdev, long rows, int nrhs,
+                             hipStream_t s);
+hipError_t launch_inv_sqrt(const double* q, double* sdev, int nrhs, double f, hipStream_t s);
+hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long n, hipStream_t s);
+hipError_t launch_add_f32(void* y, const void* x, long n, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+enum Phase { kFine = 0, kRestrict, kProlong, kCoarse, kPhases };
+
+struct SolverState {
+  hipStream_t stream = nullptr;  // private stream: graphs cannot capture the null stream
+  int n = 0;                     // right-hand sides the level buffers hold
+  Buffer lb[MRHS_MAX_LEVELS], lx[MRHS_MAX_LEVELS], lr[MRHS_MAX_LEVELS], lp[MRHS_MAX_LEVELS];
+  Buffer alpha, part, scl, coef, qn;
+  // outer Krylov
+  int m = 0, on = 0;
+  Buffer V64, Z32, w64, t64, r64;
+  // graph of one V-cycle
+  hipGraphExec_t gexec = nullptr;
+  int g_n = 0;
+  mrhs_vcycle_params g_vc{};
+  // phase timers
+  bool timing = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+};
+
+void mg_solver_release(mrhs_mg mg) {
+  SolverState* st = mg->solver;
+  if (!st) return;
+  if (st->stream) (void)hipStreamSynchronize(st->stream);
+  for (int l = 0; l < MRHS_MAX_LEVELS; ++l) {
+    release(st->lb[l]);
+    release(st->lx[l]);
+    release(st->lr[l]);
+    release(st->lp[l]);
+  }
+  Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->V64, &st->Z32, &st->w64, &st->t64, &st->r64};
+  for (Buffer* x : b) release(*x);
+  if (st->gexec) (void)hipGraphExecDestroy(st->gexec);
+  for (hipEvent_t e : st->evpool) (void)hipEventDestroy(e);
+  if (st->stream) (void)hipStreamDestroy(st->stream);
+  delete st;
+  mg->solver = nullptr;
+}
+
+namespace {
+
+#define SOLVER_HIP(call)                             \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+long level_rows(mrhs_mg mg, int l) { return (long)mg->lv[l].g.V * mg->lv[l].ncomp; }
+
+mrhs_status state_of(mrhs_mg mg, SolverState** out) {
+  if (!mg->solver) {
+    mg->solver = new (std::nothrow) SolverState();
+    if (!mg->solver) return fail(mg->ctx, MRHS_ERR_OOM, "host allocation failed");
+    hipError_t e = hipStreamCreateWithFlags(&mg->solver->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(mg->ctx, e, "hipStreamCreateWithFlags");
+  }
+  *out = mg->solver;
+  return MRHS_OK;
+}
+
+mrhs_status ensure_levels(mrhs_mg mg, SolverState* st, int n) {
+  mrhs_ctx ctx = mg->ctx;
+  if (n > st->n) {
+    if (st->gexec) {
+      (void)hipGraphExecDestroy(st->gexec);
+      st->gexec = nullptr;
+    }
+    for (int l = 0; l < mg->nlevels; ++l) {
+      const size_t bytes = (size_t)level_rows(mg, l) * n * 8;
+      Buffer* bs[] = {&st->lb[l], &st->lx[l], &st->lr[l], &st->lp[l]};
+      for (Buffer* b : bs) {
+        release(*b);
+        mrhs_status s = ensure(ctx, *b, bytes);
+        if (s != MRHS_OK) return s;
+      }
+    }
+    st->n = n;
+  }
+  mrhs_status s = ensure(ctx, st->alpha, MRHS_MAX_NRHS * 16);
+  if (s == MRHS_OK) s = ensure(ctx, st->part, std::max(solver_scratch_bytes(MRHS_MAX_NRHS),
+                                                        blas_scratch_bytes(MRHS_MAX_NRHS, kMaxMultiDot)));
+  if (s == MRHS_OK) s = ensure(ctx, st->scl, MRHS_MAX_NRHS * 8);
+  if (s == MRHS_OK) s = ensure(ctx, st->coef, (size_t)kMaxMultiDot * MRHS_MAX_NRHS * 16);
+  if (s == MRHS_OK) s = ensure(ctx, st->qn, MRHS_MAX_NRHS * 8);
+  if (s == MRHS_OK) s = ensure(ctx, mg->colscale, 2 * MRHS_MAX_NRHS * sizeof(float));
+  return s;
+}
+
+hipEvent_t next_event(SolverState* st) {
+  if (st->evused == st->evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    st->evpool.push_back(e);
+  }
+  return st->evpool[st->evused++];
+}
+
+struct PhaseMark {
+  SolverState* st;
+  int phase;
+  hipEvent_t a = nullptr;
+  PhaseMark(SolverState* s, int p) : st(s), phase(p) {
+    if (st->timing) {
+      a = next_event(st);
+      if (a) (void)hipEventRecord(a, st->stream);
+    }
+  }
+  ~PhaseMark() {
+    if (st->timing && a) {
+      hipEvent_t b = next_event(st);
+      if (b) {
+        (void)hipEventRecord(b, st->stream);
+        st->marks.push_back({phase, {a, b}});
+      }
+    }
+  }
+};
+
+// out = D_l in for FP32 fields.
+hipError_t apply_level(mrhs_mg mg, int l, void* out, const void* in, int n, mrhs_prec cp, hipStream_t s) {
+  mrhs_ctx ctx = mg->ctx;
+  if (l == 0)
+    return launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, n, s);
+  LevelData& L = mg->lv[l];
+  if (cp == MRHS_F32 || !mfma_supported(L.ncomp))
+    return launch_coarse_valu(0, L.g, L.ncomp, n, L.BT32.p, in, out, DirFilter{}, s);
+  const float* scale = nullptr;
+  if (cp == MRHS_F16) {
+    float* sc = static_cast<float*>(mg->colscale.p);
+    hipError_t e = launch_column_scale(in, level_rows(mg, l), n, sc + MRHS_MAX_NRHS, sc, s);
+    if (e != hipSuccess) return e;
+    scale = sc;
+  }
+  return launch_coarse_mfma(cp == MRHS_F16, L.g, L.ncomp, n, cp == MRHS_F16 ? L.Bf16.p : L.Bbf16.p, in, out, scale, s);
+}
+
+// nu MR steps on D_l x = b with x and r = b - D x kept up to date.
+hipError_t mr_steps(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* p, int n, int nu, mrhs_prec cp) {
+  const long rows = level_rows(mg, l);
+  for (int i = 0; i < nu; ++i) {
+    hipError_t e = apply_level(mg, l, p, r, n, cp, st->stream);
+    if (e == hipSuccess) e = launch_mr_alpha(p, r, rows, n, st->alpha.p, st->part.p, st->stream);
+    if (e == hipSuccess) e = launch_mr_update(x, r, p, st->alpha.p, rows, n, st->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// x_l ~ D_l^{-1} b_l (buffers lb[l] -> lx[l]).
+hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_params& vc) {
+  const long rows = level_rows(mg, l);
+  const size_t bytes = (size_t)rows * n * 8;
+  void* b = st->lb[l].p;
+  void* x = st->lx[l].p;
+  void* r = st->lr[l].p;
+  void* p = st->lp[l].p;
+  const mrhs_prec cp = vc.coarse_prec;
+  const int ph = l == 0 ? kFine : kCoarse;
+  hipError_t e;
+  {
+    PhaseMark pm(st, ph);
+    e = launch_zero(x, bytes, st->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st->stream);
+    if (e != hipSuccess) return e;
+    if (l == mg->nlevels - 1) return mr_steps(mg, st, l, x, r, p, n, vc.coarsest_iters, cp);
+    e = mr_steps(mg, st, l, x, r, p, n, vc.nu_pre, cp);
+    if (e != hipSuccess) return e;
+  }
+  LevelData& L = mg->lv[l];
+  {
+    PhaseMark pm(st, kRestrict);
+    e = launch_restrict(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, r, st->lb[l + 1].p, st->stream);
+    if (e != hipSuccess) return e;
+  }
+  e = vcycle(mg, st, l + 1, n, vc);
+  if (e != hipSuccess) return e;
+  {
+    PhaseMark pm(st, kProlong);
+    e = launch_prolong(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, st->lx[l + 1].p, p, st->stream);
+    if (e != hipSuccess) return e;
+  }
+  PhaseMark pm(st, ph);
+  e = launch_add_f32(x, p, rows * n, st->stream);
+  if (e == hipSuccess) e = apply_level(mg, l, p, x, n, cp, st->stream);
+  if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, st->stream);
+  if (e == hipSuccess) e = mr_steps(mg, st, l, x, r, p, n, vc.nu_post, cp);
+  return e;
+}
+
+// Runs one V-cycle on lb[0] -> lx[0], from a captured graph when asked.
+mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_params& vc, bool graph) {
+  mrhs_ctx ctx = mg->ctx;
+  if (!graph || st->timing) {
+    SOLVER_HIP(vcycle(mg, st, 0, n, vc));
+    return MRHS_OK;
+  }
+  const bool same = st->gexec && st->g_n == n && st->g_vc.nu_pre == vc.nu_pre && st->g_vc.nu_post == vc.nu_post &&
+                    st->g_vc.coarsest_iters == vc.coarsest_iters && st->g_vc.coarse_prec == vc.coarse_prec;
+  if (!same) {
+    if (st->gexec) {
+      (void)hipGraphExecDestroy(st->gexec);
+      st->gexec = nullptr;
+    }
+    hipGraph_t gr = nullptr;
+    SOLVER_HIP(hipStreamBeginCapture(st->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = vcycle(mg, st, 0, n, vc);
+    hipError_t e2 = hipStreamEndCapture(st->stream, &gr);
+    if (e != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return hip_fail(ctx, e, "V-cycle capture");
+    }
+    SOLVER_HIP(e2);
+    e = hipGraphInstantiate(&st->gexec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    SOLVER_HIP(e);
+    st->g_n = n;
+    st->g_vc = vc;
+  }
+  SOLVER_HIP(hipGraphLaunch(st->gexec, st->stream));
+  return MRHS_OK;
+}
+
+mrhs_status check_vc(mrhs_mg mg, const mrhs_vcycle_params* vc) {
+  if (!vc) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "null V-cycle parameters");
+  if (vc->nu_pre < 0 || vc->nu_post < 0 || vc->coarsest_iters < 0 || vc->nu_pre + vc->nu_post > 64 ||
+      vc->coarsest_iters > 1000)
+    return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "V-cycle iteration counts out of range");
+  if (vc->coarse_prec != MRHS_F32 && vc->coarse_prec != MRHS_BF16 && vc->coarse_prec != MRHS_F16)
+    return fail(mg->ctx, MRHS_ERR_UNSUPPORTED, "coarse precision must be f32, bf16 or f16");
+  return MRHS_OK;
+}
+
+mrhs_status check_ready(mrhs_mg mg) {
+  mrhs_ctx ctx = mg->ctx;
+  if (!ctx->have_gauge || !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "fine operator not set");
+  for (int l = 0; l + 1 < mg->nlevels; ++l)
+    if (!mg->lv[l].have_basis) return fail(ctx, MRHS_ERR_STATE, "basis of level %d not set", l);
+  for (int l = 1; l < mg->nlevels; ++l)
+    if (!mg->lv[l].have_blocks) return fail(ctx, MRHS_ERR_STATE, "coarse operator of level %d not built", l);
+  return MRHS_OK;
+}
+
+// Orders the private stream after everything already queued on the context stream.
+mrhs_status join_ctx_stream(mrhs_mg mg, SolverState* st) {
+  mrhs_ctx ctx = mg->ctx;
+  hipEvent_t e = next_event(st);
+  if (!e) return fail(ctx, MRHS_ERR_HIP, "hipEventCreate failed");
+  SOLVER_HIP(hipEventRecord(e, ctx->stream));
+  SOLVER_HIP(hipStreamWaitEvent(st->stream, e, 0));
+  return MRHS_OK;
+}
+
+}  // namespace
 }  // namespace mrhs
+
+using namespace mrhs;
+
+extern "C" {
+
+mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrhs, const mrhs_vcycle_params* vc) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_ctx ctx = mg->ctx;
+  if (!z || !v || !aligned16(z) || !aligned16(v)) return fail(ctx, MRHS_ERR_INVALID_ARG, "null or misaligned field");
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  mrhs_status s = check_vc(mg, vc);
+  if (s == MRHS_OK) s = check_ready(mg);
+  if (s != MRHS_OK) return s;
+  SolverState* st;
+  s = state_of(mg, &st);
+  if (s == MRHS_OK) s = ensure_levels(mg, st, nrhs);
+  if (s != MRHS_OK) return s;
+  st->timing = false;
+  st->evused = 0;
+  s = join_ctx_stream(mg, st);
+  if (s != MRHS_OK) return s;
+  const size_t bytes = (size_t)level_rows(mg, 0) * nrhs * 8;
+  SOLVER_HIP(hipMemcpyAsync(st->lb[0].p, v, bytes, hipMemcpyDeviceToDevice, st->stream));
+  s = run_vcycle(mg, st, nrhs, *vc, false);
+  if (s != MRHS_OK) return s;
+  SOLVER_HIP(hipMemcpyAsync(z, st->lx[0].p, bytes, hipMemcpyDeviceToDevice, st->stream));
+  SOLVER_HIP(hipStreamSynchronize(st->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_mg_setup(mrhs_mg mg, int32_t setup_iters, int32_t smooth_steps) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_ctx ctx = mg->ctx;
+  if (!ctx->have_gauge || !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "fine operator not set");
+  if (setup_iters < 0 || smooth_steps < 0 || setup_iters > 100 || smooth_steps > 1000)
+    return fail(ctx, MRHS_ERR_INVALID_ARG, "setup iteration counts out of range");
+  for (int l = 0; l + 1 < mg->nlevels; ++l)
+    if (!mg->lv[l].have_basis) return fail(ctx, MRHS_ERR_STATE, "starting vectors of level %d not set", l);
+  SolverState* st;
+  mrhs_status s = state_of(mg, &st);
+  if (s != MRHS_OK) return s;
+  int nmax = 0;
+  for (int l = 0; l + 1 < mg->nlevels; ++l) nmax = std::max(nmax, mg->lv[l].nv);
+  s = ensure_levels(mg, st, nmax);
+  if (s != MRHS_OK) return s;
+  st->timing = false;
+  st->evused = 0;
+  s = join_ctx_stream(mg, st);
+  if (s != MRHS_OK) return s;
+  hipStream_t ss = st->stream;
+  std::vector<double> minus(MRHS_MAX_NRHS, -1.0);
+  for (int l = 0; l + 1 < mg->nlevels; ++l) {
+    LevelData& L = mg->lv[l];
+    const int n = L.nv;
+    const long rows = level_rows(mg, l);
+    // the internal basis [site][ncomp][nv] is a level-l field with nv columns
+    void* v = L.basis32.p;
+    void* r = st->lr[l].p;
+    void* p = st->lp[l].p;
+    for (int it = 0; it < setup_iters; ++it) {
+      SOLVER_HIP(apply_level(mg, l, r, v, n, MRHS_F32, ss));
+      SOLVER_HIP(hipMemcpyAsync(st->scl.p, minus.data(), n * 8, hipMemcpyHostToDevice, ss));
+      SOLVER_HIP(launch_scale_cols(0, r, r, static_cast<const double*>(st->scl.p), rows, n, ss));
+      SOLVER_HIP(mr_steps(mg, st, l, v, r, p, n, smooth_steps, MRHS_F32));
+      SOLVER_HIP(launch_dot(0, 1, v, v, rows, n, st->qn.p, st->part.p, ss));
+      SOLVER_HIP(launch_inv_sqrt(static_cast<const double*>(st->qn.p), static_cast<double*>(st->scl.p), n, 1.0, ss));
+      SOLVER_HIP(launch_scale_cols(0, v, v, static_cast<const double*>(st->scl.p), rows, n, ss));
+      SOLVER_HIP(hipStreamSynchronize(ss));  // the host array `minus` is reused next sweep
+    }
+    const size_t cnt = (size_t)L.g.V * L.ncomp * L.nv;
+    SOLVER_HIP(launch_convert_f32_to_f64(static_cast<const float*>(L.basis32.p), static_cast<double*>(L.basis64.p),
+                                         2 * cnt, ss));
+    SOLVER_HIP(hipStreamSynchronize(ss));
+    s = mrhs_mg_block_orthonormalise(mg, l);
+    if (s != MRHS_OK) return s;
+    s = mrhs_mg_build_coarse(mg, l + 1);
+    if (s != MRHS_OK) return s;
+  }
+  if (st->gexec) {  // the graph holds pointers into rebuilt operators only, but keep it simple
+    (void)hipGraphExecDestroy(st->gexec);
+    st->gexec = nullptr;
+  }
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, const mrhs_solve_params* prm,
+                          mrhs_solve_stats* stats) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_ctx ctx = mg->ctx;
+  if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(ctx, MRHS_ERR_INVALID_ARG, "null or misaligned field");
+  if (!prm) return fail(ctx, MRHS_ERR_INVALID_ARG, "null parameters");
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  const int m = prm->restart;
+  if (m < 1 || m >= kMaxMultiDot) return fail(ctx, MRHS_ERR_INVALID_ARG, "restart %d outside [1, %d]", m, kMaxMultiDot - 1);
+  if (!(prm->tol > 0.0) || prm->max_iters < 1) return fail(ctx, MRHS_ERR_INVALID_ARG, "bad tol or max_iters");
+  mrhs_status s = MRHS_OK;
+  if (prm->precondition) {
+    s = check_vc(mg, &prm->vc);
+    if (s == MRHS_OK) s = check_ready(mg);
+  } else if (!ctx->have_gauge || !ctx->have_clover) {
+    s = fail(ctx, MRHS_ERR_STATE, "fine operator not set");
+  }
+  if (s != MRHS_OK) return s;
+  const long rows = level_rows(mg, 0);
+  {
+    const char* xa = static_cast<const char*>(x);
+    const char* ba = static_cast<const char*>(b);
+    const size_t bytes = (size_t)rows * nrhs * 16;
+    if (xa < ba + bytes && ba < xa + bytes) return fail(ctx, MRHS_ERR_INVALID_ARG, "x and b overlap");
+  }
+  SolverState* st;
+  s = state_of(mg, &st);
+  if (s == MRHS_OK) s = ensure_levels(mg, st, nrhs);
+  if (s != MRHS_OK) return s;
+  const int n = nrhs;
+  const size_t f64 = (size_t)rows * n * 16, f32 = (size_t)rows * n * 8;
+  if (st->m < m || st->on < n) {
+    release(st->V64);
+    release(st->Z32);
+    s = ensure(ctx, st->V64, (size_t)(m + 1) * f64);
+    if (s == MRHS_OK) s = ensure(ctx, st->Z32, (size_t)m * f32);
+    if (s == MRHS_OK) s = ensure(ctx, st->w64, f64);
+    if (s == MRHS_OK) s = ensure(ctx, st->t64, f64);
+    if (s == MRHS_OK) s = ensure(ctx, st->r64, f64);
+    if (s != MRHS_OK) return s;
+    st->m = m;
+    st->on = n;
+  }
+  st->timing = prm->timers != 0;
+  st->evused = 0;
+  st->marks.clear();
+  s = join_ctx_stream(mg, st);
+  if (s != MRHS_OK) return s;
+  hipStream_t ss = st->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  double t_pre = 0.0;
+
+  auto Vj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->V64.p) + (size_t)j * f64); };
+  auto Zj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->Z32.p) + (size_t)j * f32); };
+  auto D64 = [&](void* out, const void* in) {
+    return launch_fine_f64(ctx->g, ctx->t_bc, 0, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, n, ss);
+  };
+  auto norms = [&](const void* a, std::vector<double>& q) -> mrhs_status {
+    SOLVER_HIP(launch_dot(1, 1, a, a, rows, n, st->qn.p, st->part.p, ss));
+    SOLVER_HIP(hipMemcpyAsync(q.data(), st->qn.p, n * 8, hipMemcpyDeviceToHost, ss));
+    SOLVER_HIP(hipStreamSynchronize(ss));
+    return MRHS_OK;
+  };
+  auto scale_by = [&](void* y, const void* xx, const std::vector<double>& sc) -> mrhs_status {
+    SOLVER_HIP(hipMemcpyAsync(st->scl.p, sc.data(), n * 8, hipMemcpyHostToDevice, ss));
+    SOLVER_HIP(launch_scale_cols(1, y, xx, static_cast<const double*>(st->scl.p), rows, n, ss));
+    SOLVER_HIP(hipStreamSynchronize(ss));  // sc is host memory the caller may change
+    return MRHS_OK;
+  };
+
+  using cd = std::complex<double>;
+  std::vector<double> bn(n), q(n), rel(n, 1.0), sc(n);
+  s = norms(b, bn);
+  if (s != MRHS_OK) return s;
+  for (int k = 0; k < n; ++k) bn[k] = std::sqrt(bn[k]);
+  std::vector<int> done(n, 0);
+  std::vector<cd> H((size_t)n * (m + 1) * m), g((size_t)n * (m + 1)), cs((size_t)n * m), sn((size_t)n * m);
+  std::vector<cd> hc((size_t)(m + 1) * n), hc2((size_t)(m + 1) * n), y((size_t)m * n);
+  int iters = 0, cycles = 0;
+  bool all_done = false;
+  auto Hel = [&](int k, int i, int j) -> cd& { return H[((size_t)k * (m + 1) + i) * m + j]; };
+
+  while (true) {
+    // true residual r = b - D x in FP64
+    SOLVER_HIP(D64(st->w64.p, x));
+    SOLVER_HIP(launch_sub(1, st->r64.p, b, st->w64.p, rows * n, ss));
+    s = norms(st->r64.p, q);
+    if (s != MRHS_OK) return s;
+    all_done = true;
+    for (int k = 0; k < n; ++k) {
+      const double beta = std::sqrt(q[k]);
+      rel[k] = bn[k] > 0 ? beta / bn[k] : 0.0;
+      done[k] = rel[k] <= prm->tol;
+      all_done = all_done && done[k];
+      sc[k] = (beta > 0 && !done[k]) ? 1.0 / beta : 0.0;
+      g[(size_t)k * (m + 1)] = done[k] ? 0.0 : beta;
+      for (int i = 1; i <= m; ++i) g[(size_t)k * (m + 1) + i] = 0.0;
+    }
+    if (all_done || iters >= prm->max_iters) break;
+    ++cycles;
+    s = scale_by(Vj(0), st->r64.p, sc);
+    if (s != MRHS_OK) return s;
+    int jdone = 0;
+    for (int j = 0; j < m && iters < prm->max_iters; ++j) {
+      ++iters;
+      // z_j = M v_j
+      {
+        auto tp = std::chrono::steady_clock::now();
+        if (prm->precondition) {
+          SOLVER_HIP(launch_convert_f64_to_f32(static_cast<const double*>(Vj(j)), static_cast<float*>(st->lb[0].p),
+                                               2 * rows * n, ss));
+          s = run_vcycle(mg, st, n, prm->vc, prm->use_graph != 0);
+          if (s != MRHS_OK) return s;
+          SOLVER_HIP(hipMemcpyAsync(Zj(j), st->lx[0].p, f32, hipMemcpyDeviceToDevice, ss));
+        } else {
+          SOLVER_HIP(launch_convert_f64_to_f32(static_cast<const double*>(Vj(j)), static_cast<float*>(Zj(j)),
+                                               2 * rows * n, ss));
+        }
+        if (st->timing) {
+          SOLVER_HIP(hipStreamSynchronize(ss));
+          t_pre += std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
+        }
+      }
+      // w = D z_j in FP64
+      SOLVER_HIP(launch_convert_f32_to_f64(static_cast<const float*>(Zj(j)), static_cast<double*>(st->t64.p),
+                                           2 * rows * n, ss));
+      SOLVER_HIP(D64(st->w64.p, st->t64.p));
+      // classical Gram-Schmidt, twice
+      std::vector<const void*> vs(j + 1);
+      for (int i = 0; i <= j; ++i) vs[i] = Vj(i);
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<cd>& dst = pass ? hc2 : hc;
+        SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
+        SOLVER_HIP(launch_multi_axpy(1, st->w64.p, st->coef.p, vs.data(), j + 1, -1.0, rows, n, ss));
+        SOLVER_HIP(hipMemcpyAsync(dst.data(), st->coef.p, (size_t)(j + 1) * n * 16, hipMemcpyDeviceToHost, ss));
+      }
+      s = norms(st->w64.p, q);  // synchronises, so hc and hc2 are complete
+      if (s != MRHS_OK) return s;
+      bool all_conv = true;
+      for (int k = 0; k < n; ++k) {
+        for (int i = 0; i <= j; ++i) Hel(k, i, j) = hc[(size_t)i * n + k] + hc2[(size_t)i * n + k];
+        const double hn = std::sqrt(q[k]);
+        Hel(k, j + 1, j) = hn;
+        sc[k] = hn > 0 ? 1.0 / hn : 0.0;
+        // apply the previous rotations to column j, then a new one
+        for (int i = 0; i < j; ++i) {
+          const cd a = Hel(k, i, j), c = Hel(k, i + 1, j);
+          const cd ci = cs[(size_t)k * m + i], si = sn[(size_t)k * m + i];
+          Hel(k, i, j) = std::conj(ci) * a + std::conj(si) * c;
+          Hel(k, i + 1, j) = -si * a + ci * c;
+        }
+        const cd a = Hel(k, j, j), c = Hel(k, j + 1, j);
+        const double den = std::sqrt(std::norm(a) + std::norm(c));
+        cd ci = 1.0, si = 0.0;
+        if (den > 0) {
+          ci = a / den;
+          si = c / den;
+        }
+        cs[(size_t)k * m + j] = ci;
+        sn[(size_t)k * m + j] = si;
+        Hel(k, j, j) = std::conj(ci) * a + std::conj(si) * c;
+        Hel(k, j + 1, j) = 0.0;
+        const cd gj = g[(size_t)k * (m + 1) + j];
+        g[(size_t)k * (m + 1) + j] = std::conj(ci) * gj;
+        g[(size_t)k * (m + 1) + j + 1] = -si * gj;
+        const double est = bn[k] > 0 ? std::abs(g[(size_t)k * (m + 1) + j + 1]) / bn[k] : 0.0;
+        if (!done[k] && est > prm->tol) all_conv = false;
+      }
+      s = scale_by(Vj(j + 1), st->w64.p, sc);
+      if (s != MRHS_OK) return s;
+      jdone = j + 1;
+      if (all_conv) break;
+    }
+    // y = R^{-1} g per RHS, x += Z y
+    for (int k = 0; k < n; ++k) {
+      for (int i = jdone - 1; i >= 0; --i) {
+        cd acc = g[(size_t)k * (m + 1) + i];
+        for (int l = i + 1; l < jdone; ++l) acc -= Hel(k, i, l) * y[(size_t)l * n + k];
+        const cd d = Hel(k, i, i);
+        y[(size_t)i * n + k] = (done[k] || std::abs(d) == 0.0) ? cd(0.0) : acc / d;
+      }
+    }
+    if (jdone > 0) {
+      SOLVER_HIP(hipMemcpyAsync(st->coef.p, y.data(), (size_t)jdone * n * 16, hipMemcpyHostToDevice, ss));
+      std::vector<const void*> zs(jdone);
+      for (int i = 0; i < jdone; ++i) zs[i] = Zj(i);
+      SOLVER_HIP(launch_multi_axpy(0, x, st->coef.p, zs.data(), jdone, 1.0, rows, n, ss));
+      SOLVER_HIP(hipStreamSynchronize(ss));  // y is host memory reused next cycle
+    }
+  }
+  SOLVER_HIP(hipStreamSynchronize(ss));
+  const double t_tot = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->nrhs = n;
+    stats->iters = iters;
+    stats->cycles = cycles;
+    for (int k = 0; k < n; ++k) {
+      stats->converged[k] = done[k];
+      stats->rel_resid[k] = rel[k];
+    }
+    stats->seconds_total = t_tot;
+    stats->seconds_precond = t_pre;
+    if (st->timing) {
+      for (auto& mk : st->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, mk.second.first, mk.second.second) == hipSuccess)
+          stats->seconds_phase[mk.first] += ms * 1e-3;
+      }
+    }
+  }
+  st->marks.clear();
+  if (!all_done) return fail(ctx, MRHS_ERR_NOT_CONVERGED, "not converged after %d iterations", iters);
+  return MRHS_OK;
+}
+
+}  // extern "C"

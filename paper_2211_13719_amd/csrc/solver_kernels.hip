@@ -1,0 +1,265 @@
+// Level-1 kernels of the solver on MRHS fields [rows][nrhs] (rows = sites x
+// components), every right-hand side with its own scalars, which live in
+// device memory so that a whole smoothing sweep runs without the host.
+//
+//   minimal-residual step (smoother):  alpha_k = <p_k, r_k> / ||p_k||^2,
+//                                      x_k += alpha_k r_k,  r_k -= alpha_k p_k
+//   Gram-Schmidt update (outer Krylov): y_k += s sum_i c_{i,k} x_{i,k}
+//   column scaling, normalisation, differences, zero fill.
+//
+// Reductions are deterministic (fixed-order partials, then a fixed tree),
+// with FP64 sums.
+#include "internal.h"
+
+namespace mrhs {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kMaxPart = 1024;
+
+template <typename T>
+struct c2;
+template <>
+struct c2<float> {
+  using type = float2;
+};
+template <>
+struct c2<double> {
+  using type = double2;
+};
+
+int tpb_of(int nrhs) { return (kB / nrhs) * nrhs; }
+int nblk_of(long rows, int nrhs) {
+  const long rpb = tpb_of(nrhs) / nrhs;
+  long nb = (rows + rpb - 1) / rpb;
+  if (nb > kMaxPart) nb = kMaxPart;
+  return (int)(nb < 1 ? 1 : nb);
+}
+
+// partial[b][k] = (Re <p,r>, Im <p,r>, ||p||^2, 0)
+__global__ __launch_bounds__(kB) void mr_partial(const float2* __restrict__ p, const float2* __restrict__ r, long rows,
+                                                 int nrhs, int tpb, double4* __restrict__ part) {
+  __shared__ double4 red[kB];
+  const int t = threadIdx.x;
+  double4 acc = make_double4(0, 0, 0, 0);
+  if (t < tpb) {
+    const int k = t % nrhs;
+    const int rpb = tpb / nrhs;
+    const long step = (long)gridDim.x * rpb;
+    for (long row = (long)blockIdx.x * rpb + t / nrhs; row < rows; row += step) {
+      const long e = row * nrhs + k;
+      const float2 a = p[e], b = r[e];
+      const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+      acc.x = fma(ax, bx, fma(ay, by, acc.x));
+      acc.y = fma(ax, by, fma(-ay, bx, acc.y));
+      acc.z = fma(ax, ax, fma(ay, ay, acc.z));
+    }
+  }
+  red[t] = acc;
+  __syncthreads();
+  if (t < nrhs) {
+    double4 s = red[t];
+    for (int j = t + nrhs; j < tpb; j += nrhs) {
+      s.x += red[j].x;
+      s.y += red[j].y;
+      s.z += red[j].z;
+    }
+    part[(long)blockIdx.x * nrhs + t] = s;
+  }
+}
+
+__global__ __launch_bounds__(kB) void mr_final(const double4* __restrict__ part, int nblk, int nrhs,
+                                               double2* __restrict__ alpha) {
+  __shared__ double4 red[kB];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double4 s = make_double4(0, 0, 0, 0);
+  for (int j = t; j < nblk; j += kB) {
+    const double4 v = part[(long)j * nrhs + k];
+    s.x += v.x;
+    s.y += v.y;
+    s.z += v.z;
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int w = kB / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      red[t].x += red[t + w].x;
+      red[t].y += red[t + w].y;
+      red[t].z += red[t + w].z;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double pp = red[0].z;
+    alpha[k] = pp > 0.0 ? make_double2(red[0].x / pp, red[0].y / pp) : make_double2(0.0, 0.0);
+  }
+}
+
+// x += alpha r ; r -= alpha p  (FP32 fields)
+__global__ __launch_bounds__(kB) void mr_update(float2* __restrict__ x, float2* __restrict__ r,
+                                                const float2* __restrict__ p, const double2* __restrict__ alpha,
+                                                long n, int nrhs) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  const double2 a = alpha[e % nrhs];
+  const float ar = (float)a.x, ai = (float)a.y;
+  const float2 rv = r[e], pv = p[e];
+  float2 xv = x[e];
+  xv.x = fmaf(ar, rv.x, fmaf(-ai, rv.y, xv.x));
+  xv.y = fmaf(ar, rv.y, fmaf(ai, rv.x, xv.y));
+  float2 rn;
+  rn.x = fmaf(-ar, pv.x, fmaf(ai, pv.y, rv.x));
+  rn.y = fmaf(-ar, pv.y, fmaf(-ai, pv.x, rv.y));
+  x[e] = xv;
+  r[e] = rn;
+}
+
+// y_k += s sum_i c[i][k] x_i   (y FP64; x_i FP32 or FP64)
+struct Ptrs {
+  const void* p[kMaxMultiDot];
+};
+template <typename TX>
+__global__ __launch_bounds__(kB) void multi_axpy(double2* __restrict__ y, const double2* __restrict__ c, Ptrs xs,
+                                                 int m, double s, long n, int nrhs) {
+  using CX = typename c2<TX>::type;
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  const int k = (int)(e % nrhs);
+  double2 acc = y[e];
+#pragma unroll 4
+  for (int i = 0; i < m; ++i) {
+    const CX xv = static_cast<const CX*>(xs.p[i])[e];
+    const double2 ci = c[i * nrhs + k];
+    const double cr = s * ci.x, cim = s * ci.y;
+    acc.x = fma(cr, (double)xv.x, fma(-cim, (double)xv.y, acc.x));
+    acc.y = fma(cr, (double)xv.y, fma(cim, (double)xv.x, acc.y));
+  }
+  y[e] = acc;
+}
+
+// y_k = s_k x_k, s real per column (device array)
+template <typename T>
+__global__ __launch_bounds__(kB) void scale_cols(typename c2<T>::type* __restrict__ y,
+                                                 const typename c2<T>::type* __restrict__ x,
+                                                 const double* __restrict__ s, long n, int nrhs) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  const T f = (T)s[e % nrhs];
+  typename c2<T>::type v = x[e];
+  v.x *= f;
+  v.y *= f;
+  y[e] = v;
+}
+
+// s_k = f / sqrt(q_k)  (0 if q_k == 0)
+__global__ void inv_sqrt_cols(const double* __restrict__ q, double* __restrict__ s, int nrhs, double f) {
+  const int k = threadIdx.x;
+  if (k < nrhs) s[k] = q[k] > 0.0 ? f / sqrt(q[k]) : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void sub_fields(typename c2<T>::type* __restrict__ out,
+                                                 const typename c2<T>::type* __restrict__ a,
+                                                 const typename c2<T>::type* __restrict__ b, long n) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  typename c2<T>::type u = a[e], v = b[e];
+  u.x -= v.x;
+  u.y -= v.y;
+  out[e] = u;
+}
+
+__global__ __launch_bounds__(kB) void add_f32(float2* __restrict__ y, const float2* __restrict__ x, long n) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  float2 u = y[e];
+  const float2 v = x[e];
+  u.x += v.x;
+  u.y += v.y;
+  y[e] = u;
+}
+
+__global__ __launch_bounds__(kB) void zero_words(uint4* __restrict__ p, long n16) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e < n16) p[e] = make_uint4(0, 0, 0, 0);
+}
+
+int grid_of(long n) { return (int)((n + kB - 1) / kB); }
+
+}  // namespace
+
+size_t solver_scratch_bytes(int nrhs) { return (size_t)kMaxPart * nrhs * sizeof(double4); }
+
+hipError_t launch_mr_alpha(const void* p, const void* r, long rows, int nrhs, void* alpha, void* scratch,
+                           hipStream_t s) {
+  const int tpb = tpb_of(nrhs), nb = nblk_of(rows, nrhs);
+  hipLaunchKernelGGL(mr_partial, dim3(nb), dim3(kB), 0, s, static_cast<const float2*>(p),
+                     static_cast<const float2*>(r), rows, nrhs, tpb, static_cast<double4*>(scratch));
+  hipLaunchKernelGGL(mr_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double4*>(scratch), nb, nrhs,
+                     static_cast<double2*>(alpha));
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_update(void* x, void* r, const void* p, const void* alpha, long rows, int nrhs, hipStream_t s) {
+  const long n = rows * nrhs;
+  hipLaunchKernelGGL(mr_update, dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(x), static_cast<float2*>(r),
+                     static_cast<const float2*>(p), static_cast<const double2*>(alpha), n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(int x64, void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
+                             int nrhs, hipStream_t s) {
+  if (m < 1 || m > kMaxMultiDot) return hipErrorInvalidValue;
+  Ptrs P{};
+  for (int i = 0; i < m; ++i) P.p[i] = xs[i];
+  const long n = rows * nrhs;
+  if (x64)
+    hipLaunchKernelGGL((multi_axpy<double>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<double2*>(y),
+                       static_cast<const double2*>(coef), P, m, sgn, n, nrhs);
+  else
+    hipLaunchKernelGGL((multi_axpy<float>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<double2*>(y),
+                       static_cast<const double2*>(coef), P, m, sgn, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(int prec64, void* y, const void* x, const double* sdev, long rows, int nrhs,
+                             hipStream_t s) {
+  const long n = rows * nrhs;
+  if (prec64)
+    hipLaunchKernelGGL((scale_cols<double>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<double2*>(y),
+                       static_cast<const double2*>(x), sdev, n, nrhs);
+  else
+    hipLaunchKernelGGL((scale_cols<float>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(y),
+                       static_cast<const float2*>(x), sdev, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_sqrt(const double* q, double* sdev, int nrhs, double f, hipStream_t s) {
+  hipLaunchKernelGGL(inv_sqrt_cols, dim3(1), dim3(64), 0, s, q, sdev, nrhs, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long n, hipStream_t s) {
+  if (prec64)
+    hipLaunchKernelGGL((sub_fields<double>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<double2*>(out),
+                       static_cast<const double2*>(a), static_cast<const double2*>(b), n);
+  else
+    hipLaunchKernelGGL((sub_fields<float>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(out),
+                       static_cast<const float2*>(a), static_cast<const float2*>(b), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f32(void* y, const void* x, long n, hipStream_t s) {
+  hipLaunchKernelGGL(add_f32, dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(y), static_cast<const float2*>(x),
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes % 16) return hipErrorInvalidValue;
+  const long n16 = (long)(bytes / 16);
+  hipLaunchKernelGGL(zero_words, dim3(grid_of(n16)), dim3(kB), 0, s, static_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
+
+}  // namespace mrhs
