@@ -1,23 +1,29 @@
 #!/usr/bin/env python3
-"""Benchmark of the MRHS Wilson-clover hot path on one MI355X.
+"""Benchmark of the MRHS Wilson-clover multigrid hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs 1,6,12,24,48,64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu-baseline]
 
-Workload: the fine Wilson-clover operator D = A - kappa H on a 24^4 lattice,
-antiperiodic in time, Haar-random SU(3) links (seeded), clover term built on
-the GPU with csw = 1.0, kappa = 0.13, Gaussian sources seeded per RHS, FP32,
-fields laid out [site][12][Nrhs].  One step applies D once for every Nrhs in
-the sweep.  The timed region holds exactly K steps with inputs resident in
-device memory; it is bracketed by device synchronisation.
+One step is one pass over every operator of the hot path, each on its
+workload shape (inputs resident in device memory, all synthetic and seeded):
 
-Reported (one JSON line on stdout):
-  value       aggregate GFLOP/s over the sweep (1920 flops per site per RHS)
-  per_nrhs    per-Nrhs time, GFLOP/s, algorithmic GB/s and roofline fraction,
-              back-to-back ("warm"); with --cold-reps also after a 1 GiB
-              cache-evicting write ("cold")
-  roofline    for the dominant kernel (the R=4 instantiation used for Nrhs >= 12):
-              algorithmic bytes per launch / mean launch time from HIP events
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+  fine D_wc      24^4, FP32, Haar SU(3) links, csw 1.0, kappa 0.13, antiperiodic t,
+                 Gaussian sources; one apply for each Nrhs in 1, 6, 12, 24, 48, 64
+  coarse D_c     Galerkin blocks of that operator (16 Gaussian vectors per step,
+                 FP64 block-orthonormalised, 4^4 then 2^4 aggregates): 6^4 and 3^4
+                 coarse lattices, Nb = 32, Nrhs in 12, 24, 48, 64; FP32 vector ALU
+                 and BF16 / FP16 matrix cores
+  intergrid      restrict, prolong, block-normalise 24^4 <-> 6^4 at Nrhs = 24, FP32
+  reductions     dot and norm of 24^4 fields at Nrhs = 24, FP64 sums
+
+The timed region holds exactly K steps, bracketed by device synchronisation.
+`value` is the step's algorithmic GFLOP/s (flops of every apply / step time);
+`per_op` gives per-operator times, GFLOP/s and algorithmic GB/s from HIP
+events on the stream the kernels run on; `roofline` is for the dominant
+kernel.  After the timed region (not part of `value`), `solve` times the
+mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels,
+graph-replayed V-cycle) on 24^3 x 128 smooth links for a batch of RHS and the
+same solver on one RHS with FP32 coarse levels, in seconds per RHS to a true
+residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on a sample.
 """
 
 from __future__ import annotations
@@ -30,75 +36,146 @@ import time
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 DIMS = (24, 24, 24, 24)
 KAPPA, CSW = 0.13, 1.0
-FLOPS_PER_SITE_RHS = 1920          # hop 1320 + clover 552 + combine 48
-HBM_PEAK_GBS = 8000.0              # MI355X HBM3E, published
-NRHS_DEFAULT = (1, 6, 12, 24, 48, 64)
+NRHS_FINE = (1, 6, 12, 24, 48, 64)
+NRHS_COARSE = (12, 24, 48, 64)
+N_INTER = 24
+NB = 32
+HBM_PEAK_GBS = 8000.0
+
+FLOPS_DWC = 1920          # per site per RHS: hop 1320 + clover 552 + combine 48
+SOLVE_DIMS = (24, 24, 24, 128)
 
 
-def alg_bytes(V: int, nrhs: int) -> int:
-    """Algorithmic HBM bytes of one FP32 apply: links 288 + clover 288 + in/out 2*96*N per site."""
-    return V * (288 + 288 + 192 * nrhs)
+def fine_bytes(V, n):
+    return V * (288 + 288 + 192 * n)
 
 
-def kernel_name(nrhs: int) -> str:
-    if nrhs % 4 == 0 and nrhs >= 8:
-        r = 4
-    elif nrhs % 2 == 0:
-        r = 2
-    else:
-        r = 1
-    return f"fine_kernel<float, {r}, 0, true>"
+def coarse_bytes(V, n, prec):
+    blk = 9 * NB * NB * (4 if prec in ("bf16", "f16") else 8)
+    return V * (blk + NB * n * 16)
 
 
-def cpu_baseline(dims, nrhs_sample: int = 2):
-    """The FP64 oracle's D apply on the full 24^4 lattice for a few RHS."""
+def coarse_flops(V, n):
+    return 8 * 9 * NB * NB * V * n
+
+
+def fine_kernel_name(n):
+    return f"fine_kernel<float, {2 if n % 2 == 0 else 1}, 0, true>"
+
+
+def cpu_baseline(nrhs_sample=8):
+    """The FP64 oracle's D_wc apply on the full 24^4 lattice for a few RHS."""
     import oracle as O
     import synth
 
-    try:
-        from threadpoolctl import threadpool_info
+    U = synth.gauge_haar(DIMS, 1)
+    A = O.clover_packed_direct(U, DIMS, CSW, KAPPA)
+    psi = synth.spinor_source(DIMS, nrhs_sample, 100)
+    from threadpoolctl import threadpool_limits
 
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    U = synth.gauge_haar(dims, 1)
-    A = O.clover_packed_direct(U, dims, CSW, KAPPA)
-    psi = synth.spinor_source(dims, nrhs_sample, 100)
-    t0 = time.perf_counter()
-    O.dwc(U, A, KAPPA, psi, dims)
-    dt = time.perf_counter() - t0
-    V = int(np.prod(dims))
+    with threadpool_limits(limits=1):  # the oracle as written: numpy on one thread
+        t0 = time.perf_counter()
+        O.dwc(U, A, KAPPA, psi, DIMS)
+        dt = time.perf_counter() - t0
+    V = int(np.prod(DIMS))
     return {
-        "value": FLOPS_PER_SITE_RHS * V * nrhs_sample / dt / 1e9,
+        "value": FLOPS_DWC * V * nrhs_sample / dt / 1e9,
         "unit": "GFLOP/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one FP64 D apply, 24^4, Nrhs={nrhs_sample} ({dt:.1f} s; numpy einsum, single-threaded;"
-        f" BLAS pool {threads} threads unused by this path)",
+        "sample": f"one FP64 D_wc apply on 24^4 with Nrhs={nrhs_sample} ({dt:.1f} s, numpy on one thread)",
     }
+
+
+class Timer:
+    def __init__(self, torch, stream):
+        self.torch, self.stream, self.ev = torch, stream, []
+
+    def __call__(self, key, fn):
+        e0 = self.torch.cuda.Event(enable_timing=True)
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        fn()
+        e1.record(self.stream)
+        self.ev.append((key, e0, e1))
+
+    def times(self):
+        out = {}
+        for key, e0, e1 in self.ev:
+            out.setdefault(key, []).append(e0.elapsed_time(e1))
+        return out
+
+
+def run_solve(mrhs, torch, synth, nrhs_mrhs, mass):
+    """MRHS mixed-precision solve vs the same solver on one RHS with FP32 coarse levels."""
+    kappa = mass["kappa"]
+    U = synth.gauge_smooth(SOLVE_DIMS, 5)
+    ctx = mrhs.Context(SOLVE_DIMS, t_bc=-1)
+    ctx.set_gauge(U)
+    del U
+    ctx.build_clover(CSW, kappa)
+    mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
+    t0 = time.perf_counter()
+    for l in range(2):
+        mg.set_basis(l, synth.gaussian_vectors(mg.volume[l], 16, mg.ncomp[l], 600 + l))
+    mg.setup(3, 8)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    V = int(np.prod(SOLVE_DIMS))
+    vc = dict(nu_pre=0, nu_post=4, coarsest_iters=24)
+    b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, nrhs_mrhs, 4000)).cuda()
+    x = torch.zeros_like(b)
+    st = mg.solve(x, b, tol=1e-10, restart=8, max_iters=2000, use_graph=True, coarse_prec="bf16", **vc)
+    mrhs_s = st["seconds_total"] / nrhs_mrhs
+    # per-phase breakdown from a second, timed (graph-free) solve of the same batch
+    x.zero_()
+    stt = mg.solve(x, b, tol=1e-10, restart=8, max_iters=2000, use_graph=False, timers=True, coarse_prec="bf16",
+                   **vc)
+    b1 = b[:, :, :1].contiguous()
+    x1 = torch.zeros_like(b1)
+    s1 = mg.solve(x1, b1, tol=1e-10, restart=8, max_iters=2000, use_graph=True, coarse_prec="f32", **vc)
+    out = {
+        "workload": "24^3x128, smooth links U = exp(0.3 i H), csw 1.0, antiperiodic t, "
+                    f"m0 {mass['m0']:.4f} (kappa {kappa:.6f}), 3 levels 24^3x128 -> 6^3x32 -> 3^3x16, "
+                    "16 basis vectors per step, Gaussian sources",
+        "nrhs": nrhs_mrhs,
+        "setup_s": round(setup_s, 3),
+        "mrhs_s_per_rhs": round(mrhs_s, 4),
+        "mrhs_iters": st["iters"],
+        "mrhs_max_true_resid": max(st["rel_resid"]),
+        "srhs_s_per_rhs": round(s1["seconds_total"], 4),
+        "srhs_iters": s1["iters"],
+        "srhs_true_resid": s1["rel_resid"][0],
+        "speedup": round(s1["seconds_total"] / mrhs_s, 3),
+        "mrhs_phase_s": {k: round(v, 4) for k, v in stt["seconds_phase"].items()},
+        "mrhs_total_timed_s": round(stt["seconds_total"], 4),
+        "config": "FP64 FGMRES(8), V-cycle nu_post 4, coarsest 24 MR steps; MRHS: BF16 coarse, graph; "
+                  "SRHS comparator: same solver, one RHS, FP32 coarse",
+        "sigma_min_8^4": mass.get("sigma_min"),
+    }
+    mg.close()
+    ctx.close()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--nrhs", type=str, default=",".join(map(str, NRHS_DEFAULT)))
-    ap.add_argument("--cold-reps", type=int, default=0,
-                    help="also time each apply after a 1 GiB cache-evicting write (0 = skip)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--solve-nrhs", type=int, default=12)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for HBM byte counters)")
     a = ap.parse_args()
 
     if a.gpus != 1:
-        print(
-            f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-            "(the multi-GPU domain decomposition is not part of this build)",
-            file=sys.stderr,
-        )
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the lattice domain decomposition "
+              "across GPUs is not part of this build)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -106,12 +183,9 @@ def main():
     import paper_2211_13719_amd as mrhs
     import synth
 
-    nrhs_list = [int(x) for x in a.nrhs.split(",") if x]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    V = int(np.prod(DIMS))
-
     if a.calib_copy:
         src_c = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst_c = torch.empty_like(src_c)
@@ -121,99 +195,115 @@ def main():
         del src_c, dst_c
 
     t_setup = time.perf_counter()
+    V = int(np.prod(DIMS))
     U = synth.gauge_haar(DIMS, 1)
     ctx = mrhs.Context(DIMS, t_bc=-1, stream=stream)
     ctx.set_gauge(U)
+    del U
     ctx.build_clover(CSW, KAPPA)
-    nmax = max(nrhs_list)
-    src = synth.spinor_source(DIMS, nmax, 100, np.complex64)
-    fields = {}
-    for n in nrhs_list:
+    mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
+    mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
+    mg.block_orthonormalise(0)
+    mg.build_coarse(1)
+    mg.set_basis(1, synth.gaussian_vectors(mg.volume[1], 16, 32, 400))
+    mg.block_orthonormalise(1)
+    mg.build_coarse(2)
+    src = synth.spinor_source(DIMS, max(NRHS_FINE), 100, np.complex64)
+    fine = {}
+    for n in NRHS_FINE:
         x = torch.from_numpy(np.ascontiguousarray(src[:, :, :n])).to(dev)
-        fields[n] = (x, torch.empty_like(x))
+        fine[n] = (x, torch.empty_like(x))
     del src
+    coarse = {}
+    for lev in (1, 2):
+        for n in NRHS_COARSE:
+            e = torch.from_numpy(synth.coarse_source(mg.volume[lev], NB, n, 50 * lev, np.complex64)).to(dev)
+            coarse[(lev, n)] = (e, torch.empty_like(e))
+    fi, _ = fine[N_INTER]
+    fb = fi.clone()
+    y = torch.empty((mg.volume[1], NB, N_INTER), dtype=torch.complex64, device=dev)
+    fo = torch.empty_like(fi)
+    dres = torch.empty(N_INTER, dtype=torch.complex128, device=dev)
+    nres = torch.empty(N_INTER, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-    print(f"[bench] setup {setup_s:.1f} s, sweep {nrhs_list}", file=sys.stderr, flush=True)
+    print(f"[bench] setup {setup_s:.1f} s", file=sys.stderr, flush=True)
 
-    def step(events=None):
-        for n in nrhs_list:
-            x, y = fields[n]
-            if events is not None:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                ctx.dwc(y, x)
-                e1.record(stream)
-                events.append((n, e0, e1))
+    # (key, flops, alg bytes, callable)
+    ops = []
+    for n in NRHS_FINE:
+        x, yf = fine[n]
+        ops.append((("dwc", n), FLOPS_DWC * V * n, fine_bytes(V, n), lambda x=x, yf=yf: ctx.dwc(yf, x)))
+    for lev in (1, 2):
+        Vc = mg.volume[lev]
+        for prec in ("f32", "bf16", "f16"):
+            for n in NRHS_COARSE:
+                e, o = coarse[(lev, n)]
+                ops.append(((f"coarse_l{lev}_{prec}", n), coarse_flops(Vc, n), coarse_bytes(Vc, n, prec),
+                            lambda lev=lev, o=o, e=e, p=prec: mg.coarse_apply(lev, o, e, p)))
+    Vc1 = mg.volume[1]
+    ig_flops = 8 * 6 * 2 * 16 * V * N_INTER
+    ops.append((("restrict", N_INTER), ig_flops, V * (12 * 16 * 8 + 96 * N_INTER) + Vc1 * NB * N_INTER * 8,
+                lambda: mg.restrict(0, y, fi)))
+    ops.append((("prolong", N_INTER), ig_flops, V * (12 * 16 * 8 + 96 * N_INTER) + Vc1 * NB * N_INTER * 8,
+                lambda: mg.prolong(0, fo, y)))
+    ops.append((("block_normalise", N_INTER), 6 * V * 12 * N_INTER, 2 * V * 96 * N_INTER,
+                lambda: mg.block_normalise(0, fb)))
+    ops.append((("dot", N_INTER), 8 * V * 12 * N_INTER, 2 * V * 96 * N_INTER, lambda: ctx.dot(fi, fo, out=dres)))
+    ops.append((("norm", N_INTER), 4 * V * 12 * N_INTER, V * 96 * N_INTER, lambda: ctx.norm2(fi, out=nres)))
+
+    def step(timer=None):
+        for key, _, _, fn in ops:
+            if timer is None:
+                fn()
             else:
-                ctx.dwc(y, x)
+                timer(key, fn)
 
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
 
-    # ---- timed region: exactly K steps --------------------------------------------
-    events = []
+    timer = Timer(torch, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        step(events)
+        step(timer)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     print(f"[bench] timed {a.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
-    per = {}
-    for n in nrhs_list:
-        ts = [e0.elapsed_time(e1) for (m, e0, e1) in events if m == n]
-        per[n] = {"warm_ms": float(np.median(ts)), "warm_mean_ms": float(np.mean(ts))}
+    times = timer.times()
+    per_op = {}
+    for key, flops, nbytes, _ in ops:
+        ms = float(np.median(times[key]))
+        name = f"{key[0]}@{key[1]}"
+        per_op[name] = {
+            "ms": round(ms, 5),
+            "gflops": round(flops / ms / 1e6, 1),
+            "alg_gbs": round(nbytes / ms / 1e6, 1),
+            "hbm_frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+        }
+    if ("dwc", 1) in times:
+        t1 = float(np.median(times[("dwc", 1)]))
+        for n in NRHS_FINE:
+            per_op[f"dwc@{n}"]["mrhs_speedup"] = round(n * t1 / float(np.median(times[("dwc", n)])), 3)
 
-    # ---- cold: evict the 256 MB last-level cache before every apply -------------------
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev) if a.cold_reps else None  # 1 GiB
-    for n in (nrhs_list if a.cold_reps else []):
-        x, y = fields[n]
-        ts = []
-        for _ in range(a.cold_reps):
-            flush.fill_(1.0)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ctx.dwc(y, x)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        per[n]["cold_ms"] = float(np.median(ts))
-    del flush
-
-    for n in nrhs_list:
-        b = alg_bytes(V, n)
-        f = FLOPS_PER_SITE_RHS * V * n
-        for tag in ("warm", "cold") if a.cold_reps else ("warm",):
-            ms = per[n][f"{tag}_ms"]
-            per[n][f"{tag}_gflops"] = f / ms / 1e6
-            per[n][f"{tag}_gbs"] = b / ms / 1e6
-            per[n][f"{tag}_hbm_frac"] = b / ms / 1e6 / HBM_PEAK_GBS
-        per[n]["kernel"] = kernel_name(n)
-        per[n]["srhs_speedup"] = None
-
-    if 1 in per:
-        for n in nrhs_list:
-            per[n]["srhs_speedup"] = n * per[1]["warm_ms"] / per[n]["warm_ms"]
-
-    # dominant kernel: the instantiation with the largest share of the step
+    # dominant kernel: the fine D_wc instantiation with the largest share of the step
     share = {}
-    for n in nrhs_list:
-        share.setdefault(kernel_name(n), []).append(n)
-    dom = max(share, key=lambda k: sum(per[n]["warm_mean_ms"] for n in share[k]))
-    launches = [(m, e0.elapsed_time(e1)) for (m, e0, e1) in events if kernel_name(m) == dom]
-    mean_bytes = float(np.mean([alg_bytes(V, m) for m, _ in launches]))
+    for n in NRHS_FINE:
+        share.setdefault(fine_kernel_name(n), []).append(n)
+    dom = max(share, key=lambda k: sum(np.mean(times[("dwc", n)]) for n in share[k]))
+    launches = [(n, t) for n in share[dom] for t in times[("dwc", n)]]
+    mean_bytes = float(np.mean([fine_bytes(V, n) for n, _ in launches]))
     mean_ms = float(np.mean([t for _, t in launches]))
     achieved = mean_bytes / mean_ms / 1e6
 
-    total_flops = sum(FLOPS_PER_SITE_RHS * V * n for n in nrhs_list)
+    total_flops = sum(f for _, f, _, _ in ops)
     ms_per_step = wall * 1e3 / a.steps
     value = total_flops / (ms_per_step * 1e-3) / 1e9
 
     result = {
-        "metric": "MRHS Dslash GFLOP/s vs Nrhs (fine Wilson-clover D_wc, FP32)",
+        "metric": "MRHS Dslash/coarse-stencil GFLOP/s vs Nrhs; mixed-prec MG s/RHS to 1e-10",
         "value": round(value, 1),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -226,10 +316,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "fine MRHS Wilson-clover D_wc+clover, 24^4, FP32, Haar SU(3) links, csw=1.0, kappa=0.13, "
-            "antiperiodic t, Gaussian sources; one step = one apply per Nrhs in the sweep",
+            "workload": "MRHS Wilson-clover hot path, one pass: fine D_wc 24^4 FP32 Nrhs 1..64 (Haar links, "
+                        "csw 1.0, kappa 0.13, antiperiodic t); Galerkin coarse stencil 6^4 and 3^4, Nb 32, "
+                        "Nrhs 12..64, FP32/BF16/FP16; restrict/prolong/block-normalise 24^4<->6^4 and dot/norm, "
+                        "Nrhs 24",
             "lattice": list(DIMS),
-            "nrhs": nrhs_list,
+            "nrhs_fine": list(NRHS_FINE),
+            "nrhs_coarse": list(NRHS_COARSE),
         },
         "roofline": {
             "bound": "hbm",
@@ -239,19 +332,31 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "mean_alg_bytes_per_launch": mean_bytes,
-            "mean_launch_ms": mean_ms,
+            "alg_bytes_per_launch_mean": mean_bytes,
+            "launch_ms_mean": round(mean_ms, 5),
             "launches_per_step": len(share[dom]),
         },
-        "per_nrhs": {str(n): {k: (round(v, 4) if isinstance(v, float) else v) for k, v in per[n].items()}
-                     for n in nrhs_list},
+        "per_op": per_op,
+        "solve": None,
         "cpu_baseline": None,
     }
+    mg.close()
+    ctx.close()
+    del fine, coarse
+    torch.cuda.empty_cache()
+    if not a.no_solve:
+        mpath = os.path.join(HERE, "tests", "golden", "smooth_links_mass.json")
+        if os.path.exists(mpath):
+            with open(mpath) as fh:
+                mass = json.load(fh)
+        else:
+            mass = {"m0": 0.0, "kappa": 0.125, "sigma_min": None}
+        print("[bench] solve ...", file=sys.stderr, flush=True)
+        result["solve"] = run_solve(mrhs, torch, synth, a.solve_nrhs, mass)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(DIMS)
+        result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

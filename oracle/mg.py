@@ -62,7 +62,8 @@ def block_orthonormalise(vecs: np.ndarray, dims, block) -> np.ndarray:
     For every aggregate A and chirality chi, the restrictions w_i = P_chi v_i|_A
     (i = 1..n_v, in order) are replaced by the Q factor of their thin QR
     decomposition W = Q R with real positive diag(R); that Q is unique, so any
-    Gram-Schmidt ordering reproduces it up to rounding.
+    Gram-Schmidt ordering reproduces it up to rounding.  Raises LinAlgError when
+    some |R_ii| <= 1e-10 |w_i| (a numerically rank-deficient block).
     """
     V, n_v, ncomp = vecs.shape
     h = ncomp // 2
@@ -75,7 +76,9 @@ def block_orthonormalise(vecs: np.ndarray, dims, block) -> np.ndarray:
         W = np.transpose(W, (0, 1, 3, 2)).reshape(sites.shape[0], -1, n_v)
         Q, R = np.linalg.qr(W)
         d = np.diagonal(R, axis1=-2, axis2=-1)
-        if np.any(np.abs(d) == 0):
+        # rank deficiency: |R_ii| (the part of w_i not spanned by w_0..w_{i-1})
+        # below 1e-10 |w_i|
+        if np.any(np.abs(d) <= 1e-10 * np.linalg.norm(W, axis=1)):
             raise np.linalg.LinAlgError("rank-deficient aggregate")
         Q = Q * (d / np.abs(d))[:, None, :]
         Q = Q.reshape(sites.shape[0], sites.shape[1], h, n_v).transpose(0, 1, 3, 2)
@@ -119,9 +122,11 @@ def prolong(basis: np.ndarray, y: np.ndarray, dims, block) -> np.ndarray:
 
 def block_normalise(f: np.ndarray, dims, block):
     """Divide every (RHS, aggregate, chirality) block of f by its 2-norm; a zero
-    block stays zero.  Returns (normalised field, norms (Vc, 2, N))."""
+    block stays zero.  Lower-precision inputs are widened to FP64 before the
+    norms are formed.  Returns (normalised field, norms (Vc, 2, N))."""
     V, ncomp, N = f.shape
     h = ncomp // 2
+    f = np.asarray(f).astype(np.complex128)  # widen before squaring, as for inner products
     agg = aggregate_index(dims, block)
     Vc = int(agg.max()) + 1
     out = np.empty_like(f, dtype=np.complex128)

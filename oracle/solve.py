@@ -89,7 +89,7 @@ def true_residual(U, Apacked, kappa, x, b, dims, t_bc=-1.0):
     return np.linalg.norm(r.reshape(-1, N), axis=0) / np.linalg.norm(np.asarray(b).reshape(-1, N), axis=0)
 
 
-def sigma_min(U, Apacked, kappa, dims, t_bc=-1.0, mass_form=True, inner_rtol=1e-12):
+def sigma_min(U, Apacked, kappa, dims, t_bc=-1.0, mass_form=True, inner_rtol=1e-12, tol=1e-8):
     """Smallest singular value of D (or of D_m = D / (2 kappa) with mass_form),
     as 1 / sqrt(largest eigenvalue of D^-1 D^-dag), by Lanczos on that
     Hermitian operator; each application solves with D^dag and D by GMRES."""
@@ -106,6 +106,6 @@ def sigma_min(U, Apacked, kappa, dims, t_bc=-1.0, mass_form=True, inner_rtol=1e-
         return z
 
     op = spla.LinearOperator((n, n), matvec=mv, dtype=np.complex128)
-    lam = spla.eigsh(op, k=1, which="LM", return_eigenvectors=False, tol=1e-8, ncv=16)[0]
+    lam = spla.eigsh(op, k=1, which="LM", return_eigenvectors=False, tol=tol, ncv=16)[0]
     s = 1.0 / np.sqrt(lam)
     return s / (2.0 * kappa) if mass_form else s

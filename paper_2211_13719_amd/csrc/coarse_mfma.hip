@@ -33,6 +33,15 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kNb = 32;
 
+// FP32 -> BF16 bits, round to nearest, ties to even, written on the bit
+// pattern (NaN stays NaN).  The plain (__bf16) conversion was measured to
+// round exact ties away from the even neighbour on this toolchain.
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 template <bool F16>
 struct Op;
 template <>
@@ -42,10 +51,12 @@ struct Op<false> {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ vec cvt(const float (&x)[8]) {
-    vec v;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (__bf16)x[q];
-    return v;
+    uint4 w;
+    w.x = bf16_rne(x[0]) | ((unsigned)bf16_rne(x[1]) << 16);
+    w.y = bf16_rne(x[2]) | ((unsigned)bf16_rne(x[3]) << 16);
+    w.z = bf16_rne(x[4]) | ((unsigned)bf16_rne(x[5]) << 16);
+    w.w = bf16_rne(x[6]) | ((unsigned)bf16_rne(x[7]) << 16);
+    return __builtin_bit_cast(vec, w);
   }
 };
 template <>
@@ -150,9 +161,8 @@ __global__ void pack_kernel(const double2* __restrict__ B, unsigned short* __res
     hr = __builtin_bit_cast(unsigned short, a);
     hi = __builtin_bit_cast(unsigned short, b);
   } else {
-    const __bf16 a = (__bf16)fr, b = (__bf16)fi;
-    hr = __builtin_bit_cast(unsigned short, a);
-    hi = __builtin_bit_cast(unsigned short, b);
+    hr = bf16_rne(fr);
+    hi = bf16_rne(fi);
   }
   unsigned short* base = P + blk * (2 * 2 * 64 * 8);
   base[((kc * 2 + 0) * 64 + lane) * 8 + q] = hr;

@@ -196,6 +196,10 @@ __global__ __launch_bounds__(256) void prolong_kernel(AggGeom a, int nrhs, const
 }
 
 // ---- block orthonormalisation (FP64) --------------------------------------------------
+// A (aggregate, chirality) block is rank-deficient when the part of v_i left
+// after projecting out v_0..v_{i-1} is below kRankTol times |v_i|.
+constexpr double kRankTol = 1e-10;
+
 __device__ double2 block_sum(double2 v, double2* lds) {
   // wavefront reduction, then across the 4 wavefronts of the workgroup
 #pragma unroll
@@ -233,6 +237,13 @@ __global__ __launch_bounds__(256) void block_gs_kernel(AggGeom a, int h, int nv,
     return basis + ((size_t)s * ncomp + c) * nv + i;
   };
   for (int i = 0; i < nv; ++i) {
+    double2 p0 = make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < dim; e += 256) {
+      const double2 v = *elem(e, i);
+      p0.x = fma(v.x, v.x, p0.x);
+      p0.x = fma(v.y, v.y, p0.x);
+    }
+    const double nrm0 = sqrt(block_sum(p0, lds).x);
     for (int pass = 0; pass < 2; ++pass) {
       for (int j = 0; j < i; ++j) {
         double2 p = make_double2(0.0, 0.0);
@@ -266,7 +277,8 @@ __global__ __launch_bounds__(256) void block_gs_kernel(AggGeom a, int h, int nv,
       p.x = fma(v.y, v.y, p.x);
     }
     const double nrm = sqrt(block_sum(p, lds).x);
-    if (!(nrm > 0.0)) {
+    // rank deficiency: what is left after the projections is rounding-sized
+    if (!(nrm > kRankTol * nrm0)) {
       if (threadIdx.x == 0) *flag = 1;
       return;  // uniform across the workgroup
     }

@@ -192,3 +192,13 @@ def test_coarse_gamma5_hermiticity():
             np.testing.assert_allclose(
                 B[An, 2 + 2 * mu], G5 @ B[Ac, 1 + 2 * mu].conj().T @ G5, atol=1e-14
             )
+
+
+def test_block_orthonormalise_flags_rank_deficiency():
+    import pytest
+
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    v = synth.gaussian_vectors(synth.volume(dims), 4, 12, 5)
+    v[:, 3] = v[:, 1]
+    with pytest.raises(np.linalg.LinAlgError):
+        O.block_orthonormalise(v, dims, block)
