@@ -150,6 +150,21 @@ class Context:
         """out = A inp."""
         return self._fine(lib.mrhs_clover_apply, out, inp)
 
+    # -- autotuning ------------------------------------------------------------------------
+    def tune(self, nrhs_list, cache_path=None):
+        """Pick the fastest FP32 fine-kernel launch configuration for each nrhs."""
+        arr = (C.c_int32 * len(nrhs_list))(*[int(n) for n in nrhs_list])
+        path = cache_path.encode() if cache_path else None
+        self._check(lib.mrhs_tune(self._h, arr, len(nrhs_list), path))
+
+    def get_tuning(self, nrhs: int):
+        """(rhs_per_thread, tile, microseconds) in use for nrhs (zeros when untuned)."""
+        r = C.c_int32()
+        t = (C.c_int32 * 4)()
+        us = C.c_float()
+        self._check(lib.mrhs_get_tuning(self._h, int(nrhs), C.byref(r), t, C.byref(us)))
+        return int(r.value), tuple(t), float(us.value)
+
     # -- batched level-1 operations ---------------------------------------------------
     @staticmethod
     def _field_shape(t):

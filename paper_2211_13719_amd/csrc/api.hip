@@ -110,7 +110,7 @@ mrhs_status fine_apply(mrhs_ctx ctx, int mode, void* out, const void* in, int32_
   hipError_t e;
   if (prec == MRHS_F32)
     e = launch_fine_f32(ctx->g, ctx->t_bc, mode, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, nrhs,
-                        ctx->stream);
+                        ctx->stream, &ctx->fine_cfg[nrhs]);
   else
     e = launch_fine_f64(ctx->g, ctx->t_bc, mode, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, nrhs, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "fine operator launch");

@@ -18,11 +18,12 @@
 // [site][d][j-slice][re|im][lane][8], so every A load is one 16-byte load per
 // lane and 1 KiB contiguous per wavefront.  Vectors stay FP32 in memory
 // ([site][j][rhs]); each lane reads its eight values (256-byte contiguous runs
-// across the wavefront) and rounds them to BF16/FP16 (round to nearest even)
-// on the fly.  FP16 operands are first scaled per right-hand side by a power
+// across the wavefront) and rounds them to BF16/FP16 (round to nearest even,
+// rounding.h) on the fly.  FP16 operands are first scaled per right-hand side by a power
 // of two, 2^-E with max_k |x| = m 2^E, m in [0.5, 1), and the output is
 // scaled back in FP32; the power of two keeps the scaling exact.
 #include "mg_internal.h"
+#include "rounding.h"
 
 namespace mrhs {
 namespace {
@@ -33,14 +34,8 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kNb = 32;
 
-// FP32 -> BF16 bits, round to nearest, ties to even, written on the bit
-// pattern (NaN stays NaN).  The plain (__bf16) conversion was measured to
-// round exact ties away from the even neighbour on this toolchain.
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  const unsigned u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+__device__ __forceinline__ unsigned short bf16_rne(float f) { return bf16_rne_bits(__float_as_uint(f)); }
+__device__ __forceinline__ unsigned short f16_rne(float f) { return f16_rne_bits(__float_as_uint(f)); }
 
 template <bool F16>
 struct Op;
@@ -66,10 +61,12 @@ struct Op<true> {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ vec cvt(const float (&x)[8]) {
-    vec v;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (_Float16)x[q];
-    return v;
+    uint4 w;
+    w.x = f16_rne(x[0]) | ((unsigned)f16_rne(x[1]) << 16);
+    w.y = f16_rne(x[2]) | ((unsigned)f16_rne(x[3]) << 16);
+    w.z = f16_rne(x[4]) | ((unsigned)f16_rne(x[5]) << 16);
+    w.w = f16_rne(x[6]) | ((unsigned)f16_rne(x[7]) << 16);
+    return __builtin_bit_cast(vec, w);
   }
 };
 
@@ -157,9 +154,8 @@ __global__ void pack_kernel(const double2* __restrict__ B, unsigned short* __res
   const float fr = (float)v.x, fi = (float)v.y;
   unsigned short hr, hi;
   if constexpr (F16) {
-    const _Float16 a = (_Float16)fr, b = (_Float16)fi;
-    hr = __builtin_bit_cast(unsigned short, a);
-    hi = __builtin_bit_cast(unsigned short, b);
+    hr = f16_rne(fr);
+    hi = f16_rne(fi);
   } else {
     hr = bf16_rne(fr);
     hi = bf16_rne(fi);

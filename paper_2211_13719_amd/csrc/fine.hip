@@ -5,7 +5,8 @@
 //   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu).
 //
 // Work decomposition: one thread owns one site and R consecutive right-hand
-// sides (R = 2 for even Nrhs in FP32, else 1).  Fields are [site][12][nrhs] complex, so the nrhs/R threads of a site
+// sides (R in 1, 2, 4 and the traversal tile below are chosen per Nrhs by the
+// autotuner; untuned: R = 2 for even Nrhs in FP32, else 1).  Fields are [site][12][nrhs] complex, so the nrhs/R threads of a site
 // are adjacent lanes that read contiguous memory for every component, and all
 // of them share the site's links and clover blocks (one cache line serves the
 // whole group: the gauge-field reuse of Sec. 2).  Each neighbour spinor is
@@ -436,38 +437,47 @@ hipError_t launch_r(const Geom& g, int t_bc, T kappa, const void* U, const void*
 
 template <typename T, int MODE>
 hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
-                       void* out, int nrhs, hipStream_t s) {
-  // Two right-hand sides per thread (one 16-byte load per component) measured
-  // fastest for every even Nrhs on a 24^4 lattice; one otherwise.
-  if constexpr (sizeof(T) == 4) {
-    if (nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+                       void* out, int nrhs, hipStream_t s, const FineCfg* cfg) {
+  Geom gg = g;
+  int R = 0;
+  if (cfg && cfg->R > 0) {
+    R = cfg->R;
+    if (cfg->T[0] > 0)
+      for (int m = 0; m < 4; ++m) gg.T[m] = cfg->T[m];
   }
-  return launch_r<T, 1, MODE>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+  if constexpr (sizeof(T) == 4) {
+    // Untuned default: two right-hand sides per thread (one 16-byte load per
+    // component) for even Nrhs, one otherwise.
+    if (R == 0) R = (nrhs % 2 == 0) ? 2 : 1;
+    if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(gg, t_bc, kappa, U, A, in, out, nrhs, s);
+    if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(gg, t_bc, kappa, U, A, in, out, nrhs, s);
+  }
+  return launch_r<T, 1, MODE>(gg, t_bc, kappa, U, A, in, out, nrhs, s);
 }
 
 template <typename T>
 hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U, const void* A,
-                       const void* in, void* out, int nrhs, hipStream_t s) {
+                       const void* in, void* out, int nrhs, hipStream_t s, const FineCfg* cfg) {
   switch (mode) {
     case 0:
-      return launch_mode<T, 0>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+      return launch_mode<T, 0>(g, t_bc, kappa, U, A, in, out, nrhs, s, cfg);
     case 1:
-      return launch_mode<T, 1>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+      return launch_mode<T, 1>(g, t_bc, kappa, U, A, in, out, nrhs, s, cfg);
     default:
-      return launch_mode<T, 2>(g, t_bc, kappa, U, A, in, out, nrhs, s);
+      return launch_mode<T, 2>(g, t_bc, kappa, U, A, in, out, nrhs, s, cfg);
   }
 }
 
 }  // namespace
 
 hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U, const void* A,
-                           const void* in, void* out, int nrhs, hipStream_t s) {
-  return launch_fine<float>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s);
+                           const void* in, void* out, int nrhs, hipStream_t s, const FineCfg* cfg) {
+  return launch_fine<float>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s, cfg);
 }
 
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U, const void* A,
                            const void* in, void* out, int nrhs, hipStream_t s) {
-  return launch_fine<double>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s);
+  return launch_fine<double>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s, nullptr);
 }
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,

@@ -48,6 +48,15 @@ struct AggGeom {
 // construction: sign 2 = the whole operator; sign 0 = self term plus the hops
 // that stay inside the next level's aggregate (extent b); sign +1 / -1 with
 // direction mu = the hops leaving the aggregate through its +mu / -mu face.
+// Launch configuration of the FP32 fine kernel: right-hand sides per thread
+// (1, 2 or 4; 0 = untuned default) and traversal tile (T[0] = 0: the
+// context's default tile).
+struct FineCfg {
+  int R = 0;
+  int T[4] = {0, 0, 0, 0};
+  float us = 0.f;  // measured time of the choice
+};
+
 struct DirFilter {
   int sign = 2;
   int mu = 0;
@@ -78,6 +87,9 @@ struct mrhs_ctx_s {
   // workspaces: reduction partials, small per-RHS scalar arrays
   mrhs::Buffer work;
   mrhs::Buffer scal;
+
+  // autotuned launch configurations of the FP32 fine kernel, by nrhs
+  mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
 };
 
 namespace mrhs {
@@ -107,7 +119,8 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 // ---- launchers (fine.hip) ---------------------------------------------------
 // mode: 0 = A - kappa H, 1 = H, 2 = A
 hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U,
-                           const void* A, const void* in, void* out, int nrhs, hipStream_t s);
+                           const void* A, const void* in, void* out, int nrhs, hipStream_t s,
+                           const FineCfg* cfg = nullptr);
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U,
                            const void* A, const void* in, void* out, int nrhs, hipStream_t s);
 

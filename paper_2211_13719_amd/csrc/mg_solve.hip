@@ -177,7 +177,8 @@ struct PhaseMark {
 hipError_t apply_level(mrhs_mg mg, int l, void* out, const void* in, int n, mrhs_prec cp, hipStream_t s) {
   mrhs_ctx ctx = mg->ctx;
   if (l == 0)
-    return launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, n, s);
+    return launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, n, s,
+                           &ctx->fine_cfg[n]);
   LevelData& L = mg->lv[l];
   if (cp == MRHS_F32 || !mfma_supported(L.ncomp))
     return launch_coarse_valu(0, L.g, L.ncomp, n, L.BT32.p, in, out, DirFilter{}, s);

@@ -178,3 +178,30 @@ def test_fp32_24444_sampled(big, nrhs):
     assert rel_l2(got[sites], want) < 1e-6
     if nrhs == 1:
         assert rel_l2(got, O.dwc(U, A, KAPPA, psi, dims)) < 1e-6
+
+
+def test_autotune_bitwise_and_cache(small, tmp_path):
+    """Tuned launch configurations give bit-identical results; the cache file
+    is written and read back."""
+    import torch
+
+    dims, U, A, ctx = small
+    outs = {}
+    for n in (1, 6, 12):
+        x = _dev(torch, synth.spinor_source(dims, n, 6000 + n, np.complex64))
+        y = torch.empty_like(x)
+        ctx.dwc(y, x)
+        outs[n] = (x, y.clone())
+    cache = str(tmp_path / "tune.txt")
+    ctx.tune([1, 6, 12], cache)
+    for n, (x, y0) in outs.items():
+        R, tile, us = ctx.get_tuning(n)
+        assert R in (1, 2, 4) and n % R == 0 and us > 0
+        assert all(t >= 1 and L % t == 0 for t, L in zip(tile, dims))
+        y = torch.empty_like(x)
+        ctx.dwc(y, x)
+        assert torch.equal(y, y0)
+    lines = open(cache).read().split("\n")
+    assert sum(1 for l in lines if l.strip()) == 3
+    ctx.tune([12], cache)  # served from the cache, no new line
+    assert sum(1 for l in open(cache).read().split("\n") if l.strip()) == 3
