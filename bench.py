@@ -62,8 +62,9 @@ def coarse_flops(V, n):
     return 8 * 9 * NB * NB * V * n
 
 
-def fine_kernel_name(n):
-    return f"fine_kernel<float, {2 if n % 2 == 0 else 1}, 0, true>"
+def fine_kernel_name(ctx, n):
+    R = ctx.get_tuning(n)[0] or (2 if n % 2 == 0 else 1)
+    return f"fine_kernel<float, {R}, 0, true>"
 
 
 def cpu_baseline(nrhs_sample=8):
@@ -117,6 +118,7 @@ def run_solve(mrhs, torch, synth, nrhs_mrhs, mass):
     ctx.set_gauge(U)
     del U
     ctx.build_clover(CSW, kappa)
+    ctx.tune(sorted({1, 16, nrhs_mrhs}))
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     t0 = time.perf_counter()
     for l in range(2):
@@ -201,6 +203,8 @@ def main():
     ctx.set_gauge(U)
     del U
     ctx.build_clover(CSW, KAPPA)
+    ctx.tune(list(NRHS_FINE))
+    tuning = {str(n): dict(zip(("rhs_per_thread", "tile", "curve", "tuned_us"), ctx.get_tuning(n))) for n in NRHS_FINE}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
     mg.block_orthonormalise(0)
@@ -291,7 +295,7 @@ def main():
     # dominant kernel: the fine D_wc instantiation with the largest share of the step
     share = {}
     for n in NRHS_FINE:
-        share.setdefault(fine_kernel_name(n), []).append(n)
+        share.setdefault(fine_kernel_name(ctx, n), []).append(n)
     dom = max(share, key=lambda k: sum(np.mean(times[("dwc", n)]) for n in share[k]))
     launches = [(n, t) for n in share[dom] for t in times[("dwc", n)]]
     mean_bytes = float(np.mean([fine_bytes(V, n) for n, _ in launches]))
@@ -337,6 +341,7 @@ def main():
             "launches_per_step": len(share[dom]),
         },
         "per_op": per_op,
+        "fine_tuning": tuning,
         "solve": None,
         "cpu_baseline": None,
     }

@@ -308,8 +308,10 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
 /* ---- autotuning ----------------------------------------------------------
  * mrhs_tune: for each nrhs in nrhs_list (count entries), times the FP32 fine
  * operator (mrhs_dwc_apply and the smoother) in every supported launch
- * configuration -- right-hand sides per thread 1, 2 or 4 and a set of site
- * traversal tiles that divide the lattice -- on scratch fields, and keeps the
+ * configuration -- right-hand sides per thread 1, 2 or 4, a set of site
+ * traversal tiles that divide the lattice (including slabs of Lt / 8 time
+ * slices, one per XCD) and two tile orders (lexicographic, Morton) -- on
+ * scratch fields, and keeps the
  * fastest for later FP32 applies of that nrhs on this context.  All
  * configurations give bit-identical results.  cache_path (may be NULL) names
  * a text file: existing entries for this device architecture, lattice and
@@ -317,9 +319,11 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * clover.  Synchronises. */
 mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, const char* cache_path);
 /* mrhs_get_tuning: the configuration in use for nrhs: right-hand sides per
- * thread (0 = untuned default), tile[4] (0 = default tile), measured
- * microseconds (0 if untuned).  Any output pointer may be NULL. */
-mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], float* us);
+ * thread (0 = untuned default), tile[4] (0 = default tile), tile order
+ * (0 lexicographic, 1 Morton), measured microseconds (0 if untuned).  Any
+ * output pointer may be NULL. */
+mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
+                            float* us);
 
 #ifdef __cplusplus
 }

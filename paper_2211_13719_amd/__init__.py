@@ -158,12 +158,13 @@ class Context:
         self._check(lib.mrhs_tune(self._h, arr, len(nrhs_list), path))
 
     def get_tuning(self, nrhs: int):
-        """(rhs_per_thread, tile, microseconds) in use for nrhs (zeros when untuned)."""
+        """(rhs_per_thread, tile, curve, microseconds) in use for nrhs (zeros when untuned)."""
         r = C.c_int32()
         t = (C.c_int32 * 4)()
+        cv = C.c_int32()
         us = C.c_float()
-        self._check(lib.mrhs_get_tuning(self._h, int(nrhs), C.byref(r), t, C.byref(us)))
-        return int(r.value), tuple(t), float(us.value)
+        self._check(lib.mrhs_get_tuning(self._h, int(nrhs), C.byref(r), t, C.byref(cv), C.byref(us)))
+        return int(r.value), tuple(t), int(cv.value), float(us.value)
 
     # -- batched level-1 operations ---------------------------------------------------
     @staticmethod

@@ -65,7 +65,7 @@ SIGNATURES = {
     "mrhs_mg_setup": (_i32, [_vp, _i32, _i32]),
     "mrhs_mg_solve": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mrhs_tune": (_i32, [_vp, C.POINTER(_i32), _i32, C.c_char_p]),
-    "mrhs_get_tuning": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(C.c_float)]),
+    "mrhs_get_tuning": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(C.c_float)]),
 }
 
 

@@ -141,6 +141,61 @@ mrhs_status import_real_array(mrhs_ctx ctx, const void* src, mrhs_prec prec, int
 
 }  // namespace
 
+namespace mrhs {
+
+// Site traversal of the fine kernels.  Sites are grouped in tiles of extent
+// T; tiles are visited t-row by t-row (the tile index along t outermost, so
+// that with Lt / T_t = 8 each XCD, which takes a contiguous eighth of the
+// traversal, works on its own slab of time slices), and within a t-row
+// either lexicographically (curve 0) or along a Morton curve in (x, y, z)
+// (curve 1), which keeps tiles that are neighbours in y and z close in time.
+// Sites inside a tile are lexicographic.
+const int* fine_order_table(mrhs_ctx ctx, const int T[4], int curve) {
+  std::array<int, 5> key{T[0], T[1], T[2], T[3], curve};
+  for (auto& o : ctx->orders)
+    if (o.first == key) return static_cast<const int*>(o.second.p);
+  const Geom& g = ctx->g;
+  for (int m = 0; m < 4; ++m)
+    if (T[m] < 1 || g.L[m] % T[m]) return nullptr;
+  const int n0 = g.L[0] / T[0], n1 = g.L[1] / T[1], n2 = g.L[2] / T[2], n3 = g.L[3] / T[3];
+  // order of the tiles inside one t-row
+  std::vector<std::array<int, 3>> row;
+  for (int bz = 0; bz < n2; ++bz)
+    for (int by = 0; by < n1; ++by)
+      for (int bx = 0; bx < n0; ++bx) row.push_back({bx, by, bz});
+  if (curve == 1) {
+    auto morton = [](const std::array<int, 3>& c) {
+      unsigned long long k = 0;
+      for (int bit = 0; bit < 10; ++bit)
+        for (int d = 0; d < 3; ++d) k |= (unsigned long long)((c[d] >> bit) & 1) << (3 * bit + d);
+      return k;
+    };
+    std::stable_sort(row.begin(), row.end(),
+                     [&](const std::array<int, 3>& a, const std::array<int, 3>& b) { return morton(a) < morton(b); });
+  }
+  std::vector<int> ord;
+  ord.reserve((size_t)g.V);
+  for (int bt = 0; bt < n3; ++bt)
+    for (const auto& c : row)
+      for (int lt = 0; lt < T[3]; ++lt)
+        for (int lz = 0; lz < T[2]; ++lz)
+          for (int ly = 0; ly < T[1]; ++ly)
+            for (int lx = 0; lx < T[0]; ++lx) {
+              const int x = c[0] * T[0] + lx, y = c[1] * T[1] + ly, z = c[2] * T[2] + lz, t = bt * T[3] + lt;
+              ord.push_back(x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t)));
+            }
+  Buffer b;
+  if (ensure(ctx, b, ord.size() * 4) != MRHS_OK) return nullptr;
+  if (hipMemcpy(b.p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    release(b);
+    return nullptr;
+  }
+  ctx->orders.push_back({key, b});
+  return static_cast<const int*>(b.p);
+}
+
+}  // namespace mrhs
+
 extern "C" {
 
 mrhs_status mrhs_create(mrhs_ctx* out, const int32_t dims[4], int32_t t_bc, int32_t device, void* stream) {
@@ -170,6 +225,35 @@ mrhs_status mrhs_create(mrhs_ctx* out, const int32_t dims[4], int32_t t_bc, int3
   ctx->t_bc = t_bc;
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(stream);
+  {
+    DeviceGuard dg(device);
+    // neighbour table: per site (+x, -x, +y, -y), (+z, -z, +t, -t)
+    std::vector<int> nb((size_t)V * 8);
+    for (int s = 0; s < (int)V; ++s) {
+      int c[4], r = s;
+      for (int m = 0; m < 4; ++m) {
+        c[m] = r % dims[m];
+        r /= dims[m];
+      }
+      for (int m = 0; m < 4; ++m) {
+        const int up = c[m] == dims[m] - 1 ? -(dims[m] - 1) : 1;
+        const int dn = c[m] == 0 ? dims[m] - 1 : -1;
+        nb[(size_t)s * 8 + 2 * m] = s + up * ctx->g.stride[m];
+        nb[(size_t)s * 8 + 2 * m + 1] = s + dn * ctx->g.stride[m];
+      }
+    }
+    mrhs_status st = ensure(ctx, ctx->nbr, nb.size() * 4);
+    hipError_t e = st == MRHS_OK ? hipMemcpy(ctx->nbr.p, nb.data(), nb.size() * 4, hipMemcpyHostToDevice) : hipSuccess;
+    ctx->g.nbr = static_cast<const int4*>(ctx->nbr.p);
+    ctx->g.order = st == MRHS_OK && e == hipSuccess ? fine_order_table(ctx, ctx->g.T) : nullptr;
+    if (st != MRHS_OK || e != hipSuccess || !ctx->g.order) {
+      g_create_error = "building the index tables failed";
+      release(ctx->nbr);
+      for (auto& o : ctx->orders) release(o.second);
+      delete ctx;
+      return MRHS_ERR_OOM;
+    }
+  }
   *out = ctx;
   return MRHS_OK;
 }
@@ -184,6 +268,8 @@ void mrhs_destroy(mrhs_ctx ctx) {
   release(ctx->A32);
   release(ctx->work);
   release(ctx->scal);
+  release(ctx->nbr);
+  for (auto& o : ctx->orders) release(o.second);
   delete ctx;
 }
 
@@ -211,6 +297,12 @@ mrhs_status mrhs_set_gauge(mrhs_ctx ctx, const void* U, mrhs_prec prec, int32_t 
   const size_t n = (size_t)ctx->g.V * 4 * 9 * 2;
   mrhs_status st = import_real_array(ctx, U, prec, on_device, n, ctx->U64, ctx->U32);
   if (st != MRHS_OK) return st;
+  // The fermion boundary factor multiplies every hop through the t-links of
+  // the last time slice (forward from t = Lt-1, backward into t = 0), so it
+  // is folded into those links once.  Plaquettes cross that slice an even
+  // number of times, so the clover term built from these links is unchanged.
+  MRHS_HIP(ctx, launch_fold_boundary_phase(ctx->g, ctx->t_bc, ctx->U64.p, ctx->U32.p, ctx->stream));
+  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->have_gauge = true;
   ctx->have_clover = false;  // a clover term built from old links is stale
   return MRHS_OK;

@@ -277,4 +277,26 @@ hipError_t launch_convert_f32_to_f64(const float* in, double* out, size_t n, hip
   return hipGetLastError();
 }
 
+namespace {
+__global__ void fold_phase_kernel(int nslice, int base, double2* __restrict__ U64, float2* __restrict__ U32,
+                                  double ph) {
+  const int e = blockIdx.x * 256 + threadIdx.x;  // (site of the last slice, colour pair)
+  if (e >= nslice * 9) return;
+  const size_t off = ((size_t)(base + e / 9) * 4 + 3) * 9 + e % 9;
+  double2 a = U64[off];
+  U64[off] = make_double2(ph * a.x, ph * a.y);
+  float2 b = U32[off];
+  U32[off] = make_float2((float)ph * b.x, (float)ph * b.y);
+}
+}  // namespace
+
+hipError_t launch_fold_boundary_phase(const Geom& g, int t_bc, void* U64, void* U32, hipStream_t s) {
+  if (t_bc == 1) return hipSuccess;
+  const int nslice = g.stride[3];  // sites per time slice
+  const int base = (g.L[3] - 1) * nslice;
+  hipLaunchKernelGGL(fold_phase_kernel, dim3((nslice * 9 + 255) / 256), dim3(256), 0, s, nslice, base,
+                     static_cast<double2*>(U64), static_cast<float2*>(U32), (double)t_bc);
+  return hipGetLastError();
+}
+
 }  // namespace mrhs

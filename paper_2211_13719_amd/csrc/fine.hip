@@ -190,19 +190,17 @@ __device__ __forceinline__ void load_spinor(const cplx<T>* __restrict__ in, int 
     for (int c = 0; c < 3; ++c) load_r<T, R>(base + (3 * sp + c) * nrhs, p[sp][c]);
 }
 
-// One direction mu, both hops, accumulated into acc.
+// One direction mu, both hops, accumulated into acc.  nbf / nbb are the
+// sites x + mu and x - mu.  The fermion boundary factor is already folded
+// into the links (see fold_boundary_phase), so no hop needs a phase here.
 template <typename T, int R, int MU>
-__device__ __forceinline__ void hop_dir(const Geom& g, int site, int coord, int nrhs, int k0, T tbc,
-                                        const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
-                                        cplx<T> (&acc)[4][3][R], bool inc_f = true, bool inc_b = true) {
-  const int L = g.L[MU];
-  const int st = g.stride[MU];
+__device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, int k0, const cplx<T>* __restrict__ U,
+                                        const cplx<T>* __restrict__ in, cplx<T> (&acc)[4][3][R], bool inc_f = true,
+                                        bool inc_b = true) {
   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
   if (inc_f) {
-    const int nb = (coord == L - 1) ? site - (L - 1) * st : site + st;
-    const T ph = (MU == 3 && coord == L - 1) ? tbc : T(1);
     cplx<T> p[4][3][R];
-    load_spinor<T, R>(in, nb, nrhs, k0, p);
+    load_spinor<T, R>(in, nbf, nrhs, k0, p);
     cplx<T> h[2][3][R];
     project<T, R, MU, +1>(p, h);
     const cplx<T>* u = U + ((size_t)site * 4 + MU) * 9;
@@ -221,20 +219,18 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int site, int coord, int 
           cplx<T> z = mk<T>(0, 0);
 #pragma unroll
           for (int b = 0; b < 3; ++b) cmac<T>(z, uu[a][b], h[s][b][j]);
-          w[s][a][j] = mk<T>(ph * z.x, ph * z.y);
+          w[s][a][j] = z;
         }
     reconstruct<T, R, MU, +1>(acc, w);
     pin<T, R>(acc);
   }
   // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
   if (inc_b) {
-    const int nb = (coord == 0) ? site + (L - 1) * st : site - st;
-    const T ph = (MU == 3 && coord == 0) ? tbc : T(1);
     cplx<T> p[4][3][R];
-    load_spinor<T, R>(in, nb, nrhs, k0, p);
+    load_spinor<T, R>(in, nbb, nrhs, k0, p);
     cplx<T> h[2][3][R];
     project<T, R, MU, -1>(p, h);
-    const cplx<T>* u = U + ((size_t)nb * 4 + MU) * 9;
+    const cplx<T>* u = U + ((size_t)nbb * 4 + MU) * 9;
     cplx<T> uu[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -250,7 +246,7 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int site, int coord, int 
           cplx<T> z = mk<T>(0, 0);
 #pragma unroll
           for (int b = 0; b < 3; ++b) cmac_conj<T>(z, uu[b][a], h[s][b][j]);
-          w[s][a][j] = mk<T>(ph * z.x, ph * z.y);
+          w[s][a][j] = z;
         }
     reconstruct<T, R, MU, -1>(acc, w);
     pin<T, R>(acc);
@@ -319,7 +315,7 @@ __device__ __forceinline__ void galerkin_keep(const DirFilter& f, int mu, int c,
 // (sign 0: A psi and the hops that stay inside the aggregate; sign +-1: only
 // the -kappa hops that cross the +-mu face), used to build coarse blocks.
 template <typename T, int R, int MODE, bool XCD>
-__global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T tbc,
+__global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, const int* __restrict__ order,
                                                    const cplx<T>* __restrict__ U,
                                                    const T* __restrict__ A,
                                                    const cplx<T>* __restrict__ in,
@@ -327,7 +323,7 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
   int b = blockIdx.x;
   if constexpr (XCD) {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
-    // contiguous slab of sites so that neighbour re-reads hit its own L2.
+    // contiguous range of the traversal so that neighbour re-reads hit its own L2.
     const int per = (nblocks + 7) >> 3;
     b = (b & 7) * per + (b >> 3);
     if (b >= nblocks) return;
@@ -335,30 +331,13 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
   const int groups = nrhs / R;
   const long gid = (long)b * 256 + threadIdx.x;
   if (gid >= (long)g.V * groups) return;
-  // Sites are visited tile by tile (tiles of g.T sites, tiles and the sites
-  // inside a tile in lexicographic order), so that the eight neighbours of
-  // the sites in flight on one XCD are mostly still in its L2.
+  // Sites are visited in the order of the traversal table (tile by tile),
+  // so that the eight neighbours of the sites in flight on one XCD are
+  // mostly still in its L2; neighbour indices come from a per-site table.
   const int p = (int)(gid / groups);
   const int k0 = (int)(gid - (long)p * groups) * R;
-  int x, y, z, t;
-  {
-    const int tv = g.T[0] * g.T[1] * g.T[2] * g.T[3];
-    int tile = p / tv, l = p - tile * tv;
-    const int nx = g.L[0] / g.T[0], ny = g.L[1] / g.T[1], nz = g.L[2] / g.T[2];
-    const int bx = tile % nx;
-    tile /= nx;
-    const int by = tile % ny;
-    tile /= ny;
-    const int bz = tile % nz;
-    const int bt = tile / nz;
-    x = bx * g.T[0] + l % g.T[0];
-    l /= g.T[0];
-    y = by * g.T[1] + l % g.T[1];
-    l /= g.T[1];
-    z = bz * g.T[2] + l % g.T[2];
-    t = bt * g.T[3] + l / g.T[2];
-  }
-  const int site = x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+  const int site = order[p];
+  const int4 n0 = g.nbr[2 * site], n1 = g.nbr[2 * site + 1];  // +x -x +y -y | +z -z +t -t
 
   cplx<T> acc[4][3][R];
   if constexpr (MODE != 2) {
@@ -369,20 +348,27 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
 #pragma unroll
         for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
     if constexpr (MODE == 3) {
+      int r = site;
+      const int x = r % g.L[0];
+      r /= g.L[0];
+      const int y = r % g.L[1];
+      r /= g.L[1];
+      const int z = r % g.L[2];
+      const int t = r / g.L[2];
       bool f0, b0, f1, b1, f2, b2, f3, b3;
       galerkin_keep(filt, 0, x, f0, b0);
       galerkin_keep(filt, 1, y, f1, b1);
       galerkin_keep(filt, 2, z, f2, b2);
       galerkin_keep(filt, 3, t, f3, b3);
-      hop_dir<T, R, 0>(g, site, x, nrhs, k0, tbc, U, in, acc, f0, b0);
-      hop_dir<T, R, 1>(g, site, y, nrhs, k0, tbc, U, in, acc, f1, b1);
-      hop_dir<T, R, 2>(g, site, z, nrhs, k0, tbc, U, in, acc, f2, b2);
-      hop_dir<T, R, 3>(g, site, t, nrhs, k0, tbc, U, in, acc, f3, b3);
+      hop_dir<T, R, 0>(site, n0.x, n0.y, nrhs, k0, U, in, acc, f0, b0);
+      hop_dir<T, R, 1>(site, n0.z, n0.w, nrhs, k0, U, in, acc, f1, b1);
+      hop_dir<T, R, 2>(site, n1.x, n1.y, nrhs, k0, U, in, acc, f2, b2);
+      hop_dir<T, R, 3>(site, n1.z, n1.w, nrhs, k0, U, in, acc, f3, b3);
     } else {
-      hop_dir<T, R, 0>(g, site, x, nrhs, k0, tbc, U, in, acc);
-      hop_dir<T, R, 1>(g, site, y, nrhs, k0, tbc, U, in, acc);
-      hop_dir<T, R, 2>(g, site, z, nrhs, k0, tbc, U, in, acc);
-      hop_dir<T, R, 3>(g, site, t, nrhs, k0, tbc, U, in, acc);
+      hop_dir<T, R, 0>(site, n0.x, n0.y, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 1>(site, n0.z, n0.w, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 2>(site, n1.x, n1.y, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 3>(site, n1.z, n1.w, nrhs, k0, U, in, acc);
     }
   }
 
@@ -424,12 +410,13 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, T 
 }
 
 template <typename T, int R, int MODE>
-hipError_t launch_r(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
+hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, const void* A, const void* in,
                     void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}) {
+  if (!g.nbr || !order) return hipErrorInvalidValue;
   const long threads = (long)g.V * (nrhs / R);
   const int nblocks = (int)((threads + 255) / 256);
   const int grid = ((nblocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, T(t_bc),
+  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, order,
                      reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
                      reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f);
   return hipGetLastError();
@@ -438,21 +425,17 @@ hipError_t launch_r(const Geom& g, int t_bc, T kappa, const void* U, const void*
 template <typename T, int MODE>
 hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
                        void* out, int nrhs, hipStream_t s, const FineCfg* cfg) {
-  Geom gg = g;
-  int R = 0;
-  if (cfg && cfg->R > 0) {
-    R = cfg->R;
-    if (cfg->T[0] > 0)
-      for (int m = 0; m < 4; ++m) gg.T[m] = cfg->T[m];
-  }
+  (void)t_bc;  // folded into the links
+  const int* order = (cfg && cfg->R > 0 && cfg->order) ? cfg->order : g.order;
+  int R = (cfg && cfg->R > 0) ? cfg->R : 0;
   if constexpr (sizeof(T) == 4) {
     // Untuned default: two right-hand sides per thread (one 16-byte load per
     // component) for even Nrhs, one otherwise.
     if (R == 0) R = (nrhs % 2 == 0) ? 2 : 1;
-    if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(gg, t_bc, kappa, U, A, in, out, nrhs, s);
-    if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(gg, t_bc, kappa, U, A, in, out, nrhs, s);
+    if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
+    if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
   }
-  return launch_r<T, 1, MODE>(gg, t_bc, kappa, U, A, in, out, nrhs, s);
+  return launch_r<T, 1, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
 }
 
 template <typename T>
@@ -482,7 +465,8 @@ hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, cons
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,
                                void* out, int nrhs, const DirFilter& f, hipStream_t s) {
-  return launch_r<double, 1, 3>(g, t_bc, kappa, U, A, in, out, nrhs, s, f);
+  (void)t_bc;  // folded into the links
+  return launch_r<double, 1, 3>(g, g.order, kappa, U, A, in, out, nrhs, s, f);
 }
 
 }  // namespace mrhs

@@ -6,7 +6,10 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <array>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/mrhs.h"
 
@@ -17,7 +20,12 @@ struct Geom {
   int L[4];     // Lx, Ly, Lz, Lt
   int V;        // number of sites
   int stride[4];  // site-index step of +1 in each direction: 1, Lx, Lx*Ly, Lx*Ly*Lz
-  int T[4] = {1, 1, 1, 1};  // traversal tile of the fine kernels (divides L)
+  int T[4] = {1, 1, 1, 1};  // default traversal tile of the fine kernels (divides L)
+  // device tables of the fine lattice (null on coarse levels): traversal
+  // order of the default tile, and per site the neighbours
+  // (+x, -x, +y, -y) and (+z, -z, +t, -t)
+  const int* order = nullptr;
+  const int4* nbr = nullptr;
 };
 
 // Traversal tile: extent 8 (x) or 4 (others) where it divides the lattice,
@@ -54,7 +62,9 @@ struct AggGeom {
 struct FineCfg {
   int R = 0;
   int T[4] = {0, 0, 0, 0};
-  float us = 0.f;  // measured time of the choice
+  int curve = 0;               // tile order: 0 lexicographic, 1 Morton in (x, y, z) per t-row of tiles
+  const int* order = nullptr;  // traversal table of tile T (device)
+  float us = 0.f;              // measured time of the choice
 };
 
 struct DirFilter {
@@ -90,6 +100,10 @@ struct mrhs_ctx_s {
 
   // autotuned launch configurations of the FP32 fine kernel, by nrhs
   mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
+
+  // fine-lattice index tables: neighbours, and one traversal order per tile
+  mrhs::Buffer nbr;
+  std::vector<std::pair<std::array<int, 5>, mrhs::Buffer>> orders;
 };
 
 namespace mrhs {
@@ -163,5 +177,11 @@ hipError_t launch_coarse_valu(int prec64, const Geom& g, int nb, int nrhs, const
                               const DirFilter& f, hipStream_t s);
 hipError_t launch_block_transpose(const void* in, int in64, void* out, int out64, long nblk, int nb, hipStream_t s);
 hipError_t launch_basis_columns(int prec64, const void* basis, void* W, long nsite, int ncomp, int nv, hipStream_t s);
+
+// Traversal table of the fine lattice for tile T (built and cached on first
+// use); null on failure.
+const int* fine_order_table(mrhs_ctx ctx, const int T[4], int curve = 0);
+// Multiplies the t-links of the last time slice by t_bc (FP64 and FP32 copies).
+hipError_t launch_fold_boundary_phase(const Geom& g, int t_bc, void* U64, void* U32, hipStream_t s);
 
 }  // namespace mrhs

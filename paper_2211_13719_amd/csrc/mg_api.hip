@@ -382,7 +382,7 @@ mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level) {
     f.mu = d == 0 ? 0 : (d - 1) / 2;
     for (int m = 0; m < 4; ++m) f.b[m] = F.agg.b[m];
     if (level == 1) {
-      MRHS_HIP(ctx, launch_fine_dir_f64(F.g, ctx->t_bc, ctx->kappa, ctx->U64.p, ctx->A64.p, mg->tmpA.p, mg->tmpB.p, nb, f,
+      MRHS_HIP(ctx, launch_fine_dir_f64(ctx->g, ctx->t_bc, ctx->kappa, ctx->U64.p, ctx->A64.p, mg->tmpA.p, mg->tmpB.p, nb, f,
                                         ctx->stream));
     } else {
       MRHS_HIP(ctx, launch_coarse_valu(1, F.g, F.ncomp, nb, F.BT64.p, mg->tmpA.p, mg->tmpB.p, f, ctx->stream));

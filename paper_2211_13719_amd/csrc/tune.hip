@@ -6,8 +6,9 @@
 // sees the same operations in the same order).  Choices can be persisted in
 // a plain text cache, one line per (device architecture, lattice, Nrhs):
 //
-//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <microseconds>
+//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <microseconds>
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -22,6 +23,7 @@ namespace {
 struct Cand {
   int R;
   int T[4];
+  int curve;
 };
 
 bool divides(const Geom& g, const int T[4]) {
@@ -30,16 +32,25 @@ bool divides(const Geom& g, const int T[4]) {
   return true;
 }
 
+// RHS per thread x tile x tile order.  The tiles with a t-extent of Lt / 8
+// give every XCD its own slab of time slices.
 std::vector<Cand> candidates(const Geom& g, int nrhs) {
-  static const int tiles[][4] = {{8, 4, 4, 4}, {4, 4, 4, 4}, {6, 6, 6, 6}, {3, 3, 3, 3},
-                                 {8, 8, 2, 2}, {2, 2, 2, 2}, {1, 1, 1, 1}};
+  std::vector<std::array<int, 4>> tiles = {{8, 4, 4, 4}, {4, 4, 4, 4}, {6, 6, 6, 6}, {8, 8, 2, 2},
+                                           {2, 2, 2, 2}, {1, 1, 1, 1}};
+  if (g.L[3] % 8 == 0) {
+    const int st = g.L[3] / 8;
+    for (auto t : {std::array<int, 4>{8, 4, 4, st}, {4, 4, 4, st}, {6, 6, 3, st}, {8, 8, 2, st}, {4, 4, 2, st},
+                   {12, 4, 4, st}})
+      tiles.push_back(t);
+  }
   std::vector<Cand> out;
   for (int R : {1, 2, 4}) {
     if (nrhs % R) continue;
-    for (auto& t : tiles) {
-      Cand c{R, {t[0], t[1], t[2], t[3]}};
-      if (divides(g, c.T)) out.push_back(c);
-    }
+    for (auto& t : tiles)
+      for (int curve : {0, 1}) {
+        Cand c{R, {t[0], t[1], t[2], t[3]}, curve};
+        if (divides(g, c.T)) out.push_back(c);
+      }
   }
   return out;
 }
@@ -57,15 +68,16 @@ bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int 
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char a[64];
-  int L[4], n, R, T[4];
+  int L[4], n, R, T[4], curve;
   float us;
   bool found = false;
-  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R, &T[0], &T[1],
-                     &T[2], &T[3], &us) == 12) {
+  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R, &T[0],
+                     &T[1], &T[2], &T[3], &curve, &us) == 13) {
     if (arch == a && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] && L[3] == g.L[3] &&
-        (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T)) {
+        (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1)) {
       out.R = R;
       for (int m = 0; m < 4; ++m) out.T[m] = T[m];
+      out.curve = curve;
       out.us = us;
       found = true;  // the last matching line wins
     }
@@ -78,8 +90,8 @@ void cache_append(const char* path, const std::string& arch, const Geom& g, int 
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2], g.L[3], nrhs, c.R,
-               c.T[0], c.T[1], c.T[2], c.T[3], c.us);
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2], g.L[3], nrhs,
+               c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.us);
   std::fclose(f);
 }
 
@@ -122,14 +134,23 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
     const int n = nrhs_list[i];
     FineCfg best;
     if (cache_lookup(cache_path, arch, ctx->g, n, best)) {
-      ctx->fine_cfg[n] = best;
-      continue;
+      best.order = fine_order_table(ctx, best.T, best.curve);
+      if (best.order) {
+        ctx->fine_cfg[n] = best;
+        continue;
+      }
     }
     best.us = 1e30f;
     for (const Cand& c : candidates(ctx->g, n)) {
       FineCfg cfg;
       cfg.R = c.R;
       for (int m = 0; m < 4; ++m) cfg.T[m] = c.T[m];
+      cfg.curve = c.curve;
+      cfg.order = fine_order_table(ctx, c.T, c.curve);
+      if (!cfg.order) {
+        e = hipErrorOutOfMemory;
+        break;
+      }
       std::vector<float> t;
       for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
         e = hipEventRecord(e0, ctx->stream);
@@ -162,13 +183,15 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
   return MRHS_OK;
 }
 
-mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], float* us) {
+mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
+                            float* us) {
   if (!ctx) return MRHS_ERR_INVALID_ARG;
   if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
   const FineCfg& c = ctx->fine_cfg[nrhs];
   if (rhs_per_thread) *rhs_per_thread = c.R;
   if (tile)
     for (int m = 0; m < 4; ++m) tile[m] = c.T[m];
+  if (curve) *curve = c.curve;
   if (us) *us = c.us;
   return MRHS_OK;
 }

@@ -106,7 +106,8 @@ def test_unpreconditioned_and_warm_restart(small, gpu_lib):
 
 def test_plane_wave_eigenvector_one_step(gpu_lib):
     """On unit links a plane wave times an eigenvector of D(p) is an exact
-    eigenvector of D: unpreconditioned GMRES ends after one step."""
+    eigenvector of D: unpreconditioned GMRES ends after one step, up to the
+    FP32 rounding of the stored direction (relative residual ~1e-8)."""
     import torch
 
     dims = (4, 4, 4, 4)
@@ -121,8 +122,8 @@ def test_plane_wave_eigenvector_one_step(gpu_lib):
     chi = np.kron(vecs[:, 0], np.array([1.0, 0.5j, -0.25]))
     b = (np.exp(1j * (X @ p))[:, None] * chi[None, :]).reshape(-1, 12, 1)
     x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
-    st = mg.solve(x, dev(b), precondition=False, restart=4, max_iters=10)
-    assert st["iters"] == 1 and st["converged"][0]
+    st = mg.solve(x, dev(b), tol=1e-6, precondition=False, restart=4, max_iters=10)
+    assert st["iters"] == 1 and st["converged"][0] and st["rel_resid"][0] < 1e-6
 
 
 def test_solve_16_four_config_shapes(gpu_lib):
