@@ -126,19 +126,23 @@ def run_solve(mrhs, torch, synth, nrhs_mrhs, mass):
     mg.setup(3, 8)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    print(f"[bench] solve setup {setup_s:.1f} s", file=sys.stderr, flush=True)
     V = int(np.prod(SOLVE_DIMS))
     vc = dict(nu_pre=0, nu_post=4, coarsest_iters=24)
     b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, nrhs_mrhs, 4000)).cuda()
     x = torch.zeros_like(b)
     st = mg.solve(x, b, tol=1e-10, restart=8, max_iters=2000, use_graph=True, coarse_prec="bf16", **vc)
     mrhs_s = st["seconds_total"] / nrhs_mrhs
+    print(f"[bench] MRHS solve {st['seconds_total']:.2f} s, {st['iters']} iterations", file=sys.stderr, flush=True)
     # per-phase breakdown from a second, timed (graph-free) solve of the same batch
     x.zero_()
     stt = mg.solve(x, b, tol=1e-10, restart=8, max_iters=2000, use_graph=False, timers=True, coarse_prec="bf16",
                    **vc)
+    print(f"[bench] timed MRHS solve {stt['seconds_total']:.2f} s", file=sys.stderr, flush=True)
     b1 = b[:, :, :1].contiguous()
     x1 = torch.zeros_like(b1)
     s1 = mg.solve(x1, b1, tol=1e-10, restart=8, max_iters=2000, use_graph=True, coarse_prec="f32", **vc)
+    print(f"[bench] SRHS solve {s1['seconds_total']:.2f} s, {s1['iters']} iterations", file=sys.stderr, flush=True)
     out = {
         "workload": "24^3x128, smooth links U = exp(0.3 i H), csw 1.0, antiperiodic t, "
                     f"m0 {mass['m0']:.4f} (kappa {kappa:.6f}), 3 levels 24^3x128 -> 6^3x32 -> 3^3x16, "
@@ -204,7 +208,7 @@ def main():
     del U
     ctx.build_clover(CSW, KAPPA)
     ctx.tune(list(NRHS_FINE))
-    tuning = {str(n): dict(zip(("rhs_per_thread", "tile", "curve", "tuned_us"), ctx.get_tuning(n))) for n in NRHS_FINE}
+    tuning = {str(n): dict(zip(("rhs_per_thread", "tile", "variant", "tuned_us"), ctx.get_tuning(n))) for n in NRHS_FINE}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
     mg.block_orthonormalise(0)

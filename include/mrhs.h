@@ -238,7 +238,8 @@ mrhs_status mrhs_coarse_get_blocks(mrhs_mg mg, int32_t level, void* blocks, mrhs
 mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
 /* mrhs_coarse_apply (Sec. 6): out = D_c in on coarse level `level`.
  * prec MRHS_F64: FP64 fields and arithmetic; MRHS_F32: FP32 fields and
- * arithmetic; MRHS_BF16 / MRHS_F16: FP32 fields, blocks and vectors rounded
+ * arithmetic (on the FP32 matrix cores for Nb = 32 and nrhs >= 8, else the
+ * vector ALU); MRHS_BF16 / MRHS_F16: FP32 fields, blocks and vectors rounded
  * to BF16 / FP16 (nearest even; blocks via FP32) and multiplied on the
  * matrix cores with FP32 accumulation (Nb = 32 only; FP16 vectors are scaled
  * per RHS by a power of two first, exactly undone on output). */
@@ -310,7 +311,9 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * operator (mrhs_dwc_apply and the smoother) in every supported launch
  * configuration -- right-hand sides per thread 1, 2 or 4, a set of site
  * traversal tiles that divide the lattice (including slabs of Lt / 8 time
- * slices, one per XCD) and two tile orders (lexicographic, Morton) -- on
+ * slices, one per XCD), two tile orders (lexicographic, Morton) and two
+ * register budgets (the compiler's, and one that admits 4 wavefronts per
+ * SIMD) -- on
  * scratch fields, and keeps the
  * fastest for later FP32 applies of that nrhs on this context.  All
  * configurations give bit-identical results.  cache_path (may be NULL) names
@@ -319,9 +322,10 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * clover.  Synchronises. */
 mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, const char* cache_path);
 /* mrhs_get_tuning: the configuration in use for nrhs: right-hand sides per
- * thread (0 = untuned default), tile[4] (0 = default tile), tile order
- * (0 lexicographic, 1 Morton), measured microseconds (0 if untuned).  Any
- * output pointer may be NULL. */
+ * thread (0 = untuned default), tile[4] (0 = default tile), variant = tile
+ * order (0 lexicographic, 1 Morton) + 2 if compiled for at least 4
+ * wavefronts per SIMD, measured microseconds (0 if untuned).  Any output
+ * pointer may be NULL. */
 mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
                             float* us);
 

@@ -70,15 +70,25 @@ struct Op<true> {
   }
 };
 
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that every XCD
+// works on one contiguous range of sites (and keeps their neighbours' vectors
+// in its own L2).  The grid is a multiple of 8; surplus workgroups get an
+// index past the end and exit.
+__device__ __forceinline__ int xcd_block(int nblocks) {
+  const int b = blockIdx.x;
+  const int per = (nblocks + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
 template <bool F16>
 __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
                                                           const float2* __restrict__ in, float2* __restrict__ out,
-                                                          const float* __restrict__ scale) {
+                                                          const float* __restrict__ scale, int nblocks) {
   using O = Op<F16>;
   using vec = typename O::vec;
   const int l = threadIdx.x & 63;
   const int ntiles = (nrhs + 31) >> 5;
-  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long w = (long)xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
   if (w >= (long)g.V * ntiles) return;
   const int s = (int)(w / ntiles);
   const int col = (int)(w % ntiles) * 32 + (l & 31);
@@ -137,6 +147,87 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
     const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
     o[(size_t)row * nrhs] = make_float2(accR[r] * inv, accI[r] * inv);
   }
+}
+
+// FP32 operands on v_mfma_f32_32x32x2_f32 (full-rate FP32 matrix cores):
+//   A[i = l % 32][k = l / 32], B[k = l / 32][col = l % 32], D as above,
+// so one instruction contracts two values of j.  Blocks are packed
+// [site][d][re|im][lane][16] with element q of lane l holding
+// B[i = l % 32][j = 2 q + l / 32]: four 16-byte loads per lane per part.
+__global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, const float4* __restrict__ Bp,
+                                                              const float2* __restrict__ in,
+                                                              float2* __restrict__ out, int nblocks) {
+  const int l = threadIdx.x & 63;
+  const int ntiles = (nrhs + 31) >> 5;
+  const long w = (long)xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
+  if (w >= (long)g.V * ntiles) return;
+  const int s = (int)(w / ntiles);
+  const int col = (int)(w % ntiles) * 32 + (l & 31);
+  const bool colok = col < nrhs;
+  const int jh = l >> 5;
+  int x[4];
+  {
+    int r = s;
+    x[0] = r % g.L[0];
+    r /= g.L[0];
+    x[1] = r % g.L[1];
+    r /= g.L[1];
+    x[2] = r % g.L[2];
+    x[3] = r / g.L[2];
+  }
+  f32x16 accR = {}, accI = {};
+  for (int d = 0; d < 9; ++d) {
+    int nbr = s;
+    if (d > 0) {
+      const int mu = (d - 1) >> 1;
+      const int c = x[mu] + (((d - 1) & 1) ? -1 : 1);
+      const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
+      nbr = s + (cw - x[mu]) * g.stride[mu];
+    }
+    const float4* bp = Bp + ((size_t)s * 9 + d) * 2 * 64 * 4;
+    float br[16], bi[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 a = bp[(0 * 64 + l) * 4 + q], b = bp[(1 * 64 + l) * 4 + q];
+      br[4 * q] = a.x;
+      br[4 * q + 1] = a.y;
+      br[4 * q + 2] = a.z;
+      br[4 * q + 3] = a.w;
+      bi[4 * q] = b.x;
+      bi[4 * q + 1] = b.y;
+      bi[4 * q + 2] = b.z;
+      bi[4 * q + 3] = b.w;
+    }
+    const float2* e = in + (size_t)nbr * kNb * nrhs + col;
+#pragma unroll
+    for (int kc = 0; kc < 16; ++kc) {
+      const float2 v = colok ? e[(size_t)(2 * kc + jh) * nrhs] : make_float2(0.f, 0.f);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(br[kc], v.x, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-bi[kc], v.y, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(br[kc], v.y, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(bi[kc], v.x, accI, 0, 0, 0);
+    }
+  }
+  if (!colok) return;
+  float2* o = out + (size_t)s * kNb * nrhs + col;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    o[(size_t)row * nrhs] = make_float2(accR[r], accI[r]);
+  }
+}
+
+__global__ void pack_f32_kernel(const double2* __restrict__ B, float* __restrict__ P, long nblk) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nblk * kNb * kNb) return;
+  const long blk = e / (kNb * kNb);
+  const int r = (int)(e % (kNb * kNb));
+  const int i = r / kNb, j = r % kNb;
+  const int lane = i + 32 * (j & 1), q = j >> 1;
+  const double2 v = B[e];
+  float* base = P + blk * (2 * 64 * 16);
+  base[(0 * 64 + lane) * 16 + q] = (float)v.x;
+  base[(1 * 64 + lane) * 16 + q] = (float)v.y;
 }
 
 // FP64 blocks [site][9][32][32] complex -> packed A-operand order; the value is
@@ -226,14 +317,26 @@ hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const vo
   if (nb != kNb) return hipErrorInvalidValue;
   const long waves = (long)g.V * ((nrhs + 31) / 32);
   const int blocks = (int)((waves + 3) / 4);
+  const int grid = ((blocks + 7) / 8) * 8;
   if (f16)
-    hipLaunchKernelGGL((coarse_mfma_kernel<true>), dim3(blocks), dim3(256), 0, s, g, nrhs,
+    hipLaunchKernelGGL((coarse_mfma_kernel<true>), dim3(grid), dim3(256), 0, s, g, nrhs,
                        static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
-                       scale);
+                       scale, blocks);
   else
-    hipLaunchKernelGGL((coarse_mfma_kernel<false>), dim3(blocks), dim3(256), 0, s, g, nrhs,
+    hipLaunchKernelGGL((coarse_mfma_kernel<false>), dim3(grid), dim3(256), 0, s, g, nrhs,
                        static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
-                       scale);
+                       scale, blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_mfma_f32(const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
+                                  hipStream_t s) {
+  if (nb != kNb) return hipErrorInvalidValue;
+  const long waves = (long)g.V * ((nrhs + 31) / 32);
+  const int blocks = (int)((waves + 3) / 4);
+  const int grid = ((blocks + 7) / 8) * 8;
+  hipLaunchKernelGGL(coarse_mfma_f32_kernel, dim3(grid), dim3(256), 0, s, g, nrhs, static_cast<const float4*>(packed),
+                     static_cast<const float2*>(in), static_cast<float2*>(out), blocks);
   return hipGetLastError();
 }
 
@@ -247,8 +350,14 @@ mrhs_status pack_blocks_mfma(mrhs_mg mg, int level) {
   if (st != MRHS_OK) return st;
   st = ensure(ctx, L.Bf16, bytes);
   if (st != MRHS_OK) return st;
+  st = ensure(ctx, L.Bf32p, 2 * bytes);
+  if (st != MRHS_OK) return st;
   MRHS_HIP(ctx, launch_pack_blocks(0, L.B64.p, L.Bbf16.p, L.g.V, ctx->stream));
   MRHS_HIP(ctx, launch_pack_blocks(1, L.B64.p, L.Bf16.p, L.g.V, ctx->stream));
+  const long n = (long)L.g.V * 9 * kNb * kNb;
+  hipLaunchKernelGGL(pack_f32_kernel, dim3((int)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const double2*>(L.B64.p), static_cast<float*>(L.Bf32p.p), (long)L.g.V * 9);
+  MRHS_HIP(ctx, hipGetLastError());
   return MRHS_OK;
 }
 

@@ -129,6 +129,69 @@ __device__ __forceinline__ void project(const cplx<T> (&p)[4][3][R], cplx<T> (&h
     }
 }
 
+// Spin components that the two halves of (1 - s*gamma_mu) psi combine:
+// half 0 uses (0, SA0), half 1 uses (1, SA1) with the lower spin index given
+// below (x, y: 3 and 2; z, t: 2 and 3).
+template <int MU>
+struct HalfPair {
+  static constexpr int lo0 = (MU <= 1) ? 3 : 2;
+  static constexpr int lo1 = (MU <= 1) ? 2 : 3;
+};
+
+// h = half `HALF` of (1 - s*gamma_mu) psi from the upper spin u = psi[HALF]
+// and the lower spin l it combines with (see project()).
+template <typename T, int R, int MU, int S, int HALF>
+__device__ __forceinline__ void project_half(const cplx<T> (&u)[3][R], const cplx<T> (&l)[3][R],
+                                             cplx<T> (&h)[3][R]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if constexpr (MU == 0) {  // h0 = u0 +- i l1, h1 = u1 +- i l0
+        h[c][j] = S > 0 ? addi<T>(u[c][j], l[c][j]) : subi<T>(u[c][j], l[c][j]);
+      } else if constexpr (MU == 1) {  // h0 = u0 +- l1, h1 = u1 -+ l0
+        if constexpr (HALF == 0)
+          h[c][j] = S > 0 ? add<T>(u[c][j], l[c][j]) : sub<T>(u[c][j], l[c][j]);
+        else
+          h[c][j] = S > 0 ? sub<T>(u[c][j], l[c][j]) : add<T>(u[c][j], l[c][j]);
+      } else if constexpr (MU == 2) {  // h0 = u0 +- i l0, h1 = u1 -+ i l1
+        if constexpr (HALF == 0)
+          h[c][j] = S > 0 ? addi<T>(u[c][j], l[c][j]) : subi<T>(u[c][j], l[c][j]);
+        else
+          h[c][j] = S > 0 ? subi<T>(u[c][j], l[c][j]) : addi<T>(u[c][j], l[c][j]);
+      } else {  // h0 = u0 -+ l0, h1 = u1 -+ l1
+        h[c][j] = S > 0 ? sub<T>(u[c][j], l[c][j]) : add<T>(u[c][j], l[c][j]);
+      }
+    }
+}
+
+// Half spinor h of the neighbour at site nb, loading only the two spin
+// components each half needs (keeps half as many values live as loading the
+// whole spinor first).
+template <typename T, int R, int MU, int S>
+__device__ __forceinline__ void load_project(const cplx<T>* __restrict__ in, int nb, int nrhs, int k0,
+                                             cplx<T> (&h)[2][3][R]) {
+  const cplx<T>* base = in + (size_t)nb * 12 * nrhs + k0;
+  {
+    cplx<T> u[3][R], l[3][R];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      load_r<T, R>(base + (0 * 3 + c) * nrhs, u[c]);
+      load_r<T, R>(base + (HalfPair<MU>::lo0 * 3 + c) * nrhs, l[c]);
+    }
+    project_half<T, R, MU, S, 0>(u, l, h[0]);
+  }
+  {
+    cplx<T> u[3][R], l[3][R];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      load_r<T, R>(base + (1 * 3 + c) * nrhs, u[c]);
+      load_r<T, R>(base + (HalfPair<MU>::lo1 * 3 + c) * nrhs, l[c]);
+    }
+    project_half<T, R, MU, S, 1>(u, l, h[1]);
+  }
+}
+
 // acc += (1 - s*gamma_mu)-reconstruction of the transported half spinor w.
 template <typename T, int R, int MU, int S>
 __device__ __forceinline__ void reconstruct(cplx<T> (&acc)[4][3][R], const cplx<T> (&w)[2][3][R]) {
@@ -193,16 +256,20 @@ __device__ __forceinline__ void load_spinor(const cplx<T>* __restrict__ in, int 
 // One direction mu, both hops, accumulated into acc.  nbf / nbb are the
 // sites x + mu and x - mu.  The fermion boundary factor is already folded
 // into the links (see fold_boundary_phase), so no hop needs a phase here.
-template <typename T, int R, int MU>
+template <typename T, int R, int MU, bool SPLIT>
 __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, int k0, const cplx<T>* __restrict__ U,
                                         const cplx<T>* __restrict__ in, cplx<T> (&acc)[4][3][R], bool inc_f = true,
                                         bool inc_b = true) {
   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
   if (inc_f) {
-    cplx<T> p[4][3][R];
-    load_spinor<T, R>(in, nbf, nrhs, k0, p);
     cplx<T> h[2][3][R];
-    project<T, R, MU, +1>(p, h);
+    if (SPLIT) {
+      load_project<T, R, MU, +1>(in, nbf, nrhs, k0, h);
+    } else {
+      cplx<T> p[4][3][R];
+      load_spinor<T, R>(in, nbf, nrhs, k0, p);
+      project<T, R, MU, +1>(p, h);
+    }
     const cplx<T>* u = U + ((size_t)site * 4 + MU) * 9;
     cplx<T> uu[3][3];
 #pragma unroll
@@ -226,10 +293,14 @@ __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, in
   }
   // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
   if (inc_b) {
-    cplx<T> p[4][3][R];
-    load_spinor<T, R>(in, nbb, nrhs, k0, p);
     cplx<T> h[2][3][R];
-    project<T, R, MU, -1>(p, h);
+    if (SPLIT) {
+      load_project<T, R, MU, -1>(in, nbb, nrhs, k0, h);
+    } else {
+      cplx<T> p[4][3][R];
+      load_spinor<T, R>(in, nbb, nrhs, k0, p);
+      project<T, R, MU, -1>(p, h);
+    }
     const cplx<T>* u = U + ((size_t)nbb * 4 + MU) * 9;
     cplx<T> uu[3][3];
 #pragma unroll
@@ -314,8 +385,11 @@ __device__ __forceinline__ void galerkin_keep(const DirFilter& f, int mu, int c,
 // MODE 3: the direction-resolved piece D_d of MODE 0 selected by the filter
 // (sign 0: A psi and the hops that stay inside the aggregate; sign +-1: only
 // the -kappa hops that cross the +-mu face), used to build coarse blocks.
-template <typename T, int R, int MODE, bool XCD>
-__global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, const int* __restrict__ order,
+// OCC > 0 asks the compiler for at least OCC wavefronts per SIMD (it then
+// keeps the register count at or below 512 / OCC, spilling if it must); the
+// autotuner measures whether that pays.
+template <typename T, int R, int MODE, bool XCD, bool SPLIT, int OCC>
+__global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, int nrhs, T kappa, const int* __restrict__ order,
                                                    const cplx<T>* __restrict__ U,
                                                    const T* __restrict__ A,
                                                    const cplx<T>* __restrict__ in,
@@ -360,15 +434,15 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, co
       galerkin_keep(filt, 1, y, f1, b1);
       galerkin_keep(filt, 2, z, f2, b2);
       galerkin_keep(filt, 3, t, f3, b3);
-      hop_dir<T, R, 0>(site, n0.x, n0.y, nrhs, k0, U, in, acc, f0, b0);
-      hop_dir<T, R, 1>(site, n0.z, n0.w, nrhs, k0, U, in, acc, f1, b1);
-      hop_dir<T, R, 2>(site, n1.x, n1.y, nrhs, k0, U, in, acc, f2, b2);
-      hop_dir<T, R, 3>(site, n1.z, n1.w, nrhs, k0, U, in, acc, f3, b3);
+      hop_dir<T, R, 0, SPLIT>(site, n0.x, n0.y, nrhs, k0, U, in, acc, f0, b0);
+      hop_dir<T, R, 1, SPLIT>(site, n0.z, n0.w, nrhs, k0, U, in, acc, f1, b1);
+      hop_dir<T, R, 2, SPLIT>(site, n1.x, n1.y, nrhs, k0, U, in, acc, f2, b2);
+      hop_dir<T, R, 3, SPLIT>(site, n1.z, n1.w, nrhs, k0, U, in, acc, f3, b3);
     } else {
-      hop_dir<T, R, 0>(site, n0.x, n0.y, nrhs, k0, U, in, acc);
-      hop_dir<T, R, 1>(site, n0.z, n0.w, nrhs, k0, U, in, acc);
-      hop_dir<T, R, 2>(site, n1.x, n1.y, nrhs, k0, U, in, acc);
-      hop_dir<T, R, 3>(site, n1.z, n1.w, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 0, SPLIT>(site, n0.x, n0.y, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 1, SPLIT>(site, n0.z, n0.w, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 2, SPLIT>(site, n1.x, n1.y, nrhs, k0, U, in, acc);
+      hop_dir<T, R, 3, SPLIT>(site, n1.z, n1.w, nrhs, k0, U, in, acc);
     }
   }
 
@@ -409,14 +483,14 @@ __global__ __launch_bounds__(256) void fine_kernel(Geom g, int nrhs, T kappa, co
   }
 }
 
-template <typename T, int R, int MODE>
+template <typename T, int R, int MODE, int OCC = 0>
 hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, const void* A, const void* in,
                     void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}) {
   if (!g.nbr || !order) return hipErrorInvalidValue;
   const long threads = (long)g.V * (nrhs / R);
   const int nblocks = (int)((threads + 255) / 256);
   const int grid = ((nblocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, order,
+  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true, true, OCC>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, order,
                      reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
                      reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f);
   return hipGetLastError();
@@ -432,6 +506,14 @@ hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const vo
     // Untuned default: two right-hand sides per thread (one 16-byte load per
     // component) for even Nrhs, one otherwise.
     if (R == 0) R = (nrhs % 2 == 0) ? 2 : 1;
+    const bool occ4 = MODE == 0 && cfg && cfg->occ == 4;
+    if constexpr (MODE == 0) {
+      if (occ4) {
+        if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s);
+        if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s);
+        return launch_r<T, 1, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s);
+      }
+    }
     if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
     if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
   }

@@ -63,6 +63,7 @@ struct FineCfg {
   int R = 0;
   int T[4] = {0, 0, 0, 0};
   int curve = 0;               // tile order: 0 lexicographic, 1 Morton in (x, y, z) per t-row of tiles
+  int occ = 0;                 // 0: compiler's register choice; 4: at least 4 wavefronts per SIMD
   const int* order = nullptr;  // traversal table of tile T (device)
   float us = 0.f;              // measured time of the choice
 };

@@ -158,7 +158,7 @@ void mrhs_mg_destroy(mrhs_mg mg) {
   DevGuard dg(mg->ctx->device);
   (void)hipStreamSynchronize(mg->ctx->stream);
   for (auto& L : mg->lv) {
-    Buffer* bufs[] = {&L.basis64, &L.basis32, &L.B64, &L.BT32, &L.BT64, &L.Bbf16, &L.Bf16};
+    Buffer* bufs[] = {&L.basis64, &L.basis32, &L.B64, &L.BT32, &L.BT64, &L.Bbf16, &L.Bf16, &L.Bf32p};
     for (Buffer* b : bufs) release(*b);
   }
   release(mg->tmpA);
@@ -421,7 +421,12 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
       e = launch_coarse_valu(1, L.g, L.ncomp, nrhs, L.BT64.p, in, out, DirFilter{}, ctx->stream);
       break;
     case MRHS_F32:
-      e = launch_coarse_valu(0, L.g, L.ncomp, nrhs, L.BT32.p, in, out, DirFilter{}, ctx->stream);
+      // matrix cores from 8 right-hand sides on (a 32-column tile would idle
+      // below that); the vector-ALU kernel, bound by the block bytes, below
+      if (mfma_supported(L.ncomp) && nrhs >= 8)
+        e = launch_coarse_mfma_f32(L.g, L.ncomp, nrhs, L.Bf32p.p, in, out, ctx->stream);
+      else
+        e = launch_coarse_valu(0, L.g, L.ncomp, nrhs, L.BT32.p, in, out, DirFilter{}, ctx->stream);
       break;
     case MRHS_BF16:
     case MRHS_F16: {

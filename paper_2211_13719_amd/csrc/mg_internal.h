@@ -17,7 +17,7 @@ struct LevelData {
   bool have_basis = false;
   // stencil blocks (levels >= 1): FP64 master [site][9][i][j], transposed
   // copies [site][9][j][i] for the vector-ALU kernels, MFMA packs
-  Buffer B64, BT32, BT64, Bbf16, Bf16;
+  Buffer B64, BT32, BT64, Bbf16, Bf16, Bf32p;
   bool have_blocks = false;
 };
 
@@ -49,6 +49,9 @@ hipError_t launch_pack_blocks(int f16, const void* B64, void* packed, long nsite
 hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, float* scale, hipStream_t s);
 hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
                               const float* scale, hipStream_t s);
+// FP32 operands on the FP32 matrix cores (Nb = 32)
+hipError_t launch_coarse_mfma_f32(const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
+                                  hipStream_t s);
 
 // solver (mg_solve.hip)
 void mg_solver_release(mrhs_mg mg);

@@ -6,7 +6,7 @@
 // sees the same operations in the same order).  Choices can be persisted in
 // a plain text cache, one line per (device architecture, lattice, Nrhs):
 //
-//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <microseconds>
+//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <microseconds>
 #include <algorithm>
 #include <array>
 #include <cstdio>
@@ -24,6 +24,7 @@ struct Cand {
   int R;
   int T[4];
   int curve;
+  int occ;
 };
 
 bool divides(const Geom& g, const int T[4]) {
@@ -47,10 +48,11 @@ std::vector<Cand> candidates(const Geom& g, int nrhs) {
   for (int R : {1, 2, 4}) {
     if (nrhs % R) continue;
     for (auto& t : tiles)
-      for (int curve : {0, 1}) {
-        Cand c{R, {t[0], t[1], t[2], t[3]}, curve};
-        if (divides(g, c.T)) out.push_back(c);
-      }
+      for (int curve : {0, 1})
+        for (int occ : {0, 4}) {
+          Cand c{R, {t[0], t[1], t[2], t[3]}, curve, occ};
+          if (divides(g, c.T)) out.push_back(c);
+        }
   }
   return out;
 }
@@ -68,16 +70,18 @@ bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int 
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char a[64];
-  int L[4], n, R, T[4], curve;
+  int L[4], n, R, T[4], curve, occ;
   float us;
   bool found = false;
-  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R, &T[0],
-                     &T[1], &T[2], &T[3], &curve, &us) == 13) {
+  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R, &T[0],
+                     &T[1], &T[2], &T[3], &curve, &occ, &us) == 14) {
     if (arch == a && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] && L[3] == g.L[3] &&
-        (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1)) {
+        (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1) &&
+        (occ == 0 || occ == 4)) {
       out.R = R;
       for (int m = 0; m < 4; ++m) out.T[m] = T[m];
       out.curve = curve;
+      out.occ = occ;
       out.us = us;
       found = true;  // the last matching line wins
     }
@@ -90,8 +94,8 @@ void cache_append(const char* path, const std::string& arch, const Geom& g, int 
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2], g.L[3], nrhs,
-               c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.us);
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2], g.L[3],
+               nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.us);
   std::fclose(f);
 }
 
@@ -146,6 +150,7 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
       cfg.R = c.R;
       for (int m = 0; m < 4; ++m) cfg.T[m] = c.T[m];
       cfg.curve = c.curve;
+      cfg.occ = c.occ;
       cfg.order = fine_order_table(ctx, c.T, c.curve);
       if (!cfg.order) {
         e = hipErrorOutOfMemory;
@@ -191,7 +196,7 @@ mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread,
   if (rhs_per_thread) *rhs_per_thread = c.R;
   if (tile)
     for (int m = 0; m < 4; ++m) tile[m] = c.T[m];
-  if (curve) *curve = c.curve;
+  if (curve) *curve = c.curve + 2 * (c.occ == 4);
   if (us) *us = c.us;
   return MRHS_OK;
 }
