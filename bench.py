@@ -63,8 +63,11 @@ def coarse_flops(V, n):
 
 
 def fine_kernel_name(ctx, n):
-    R = ctx.get_tuning(n)[0] or (2 if n % 2 == 0 else 1)
-    return f"fine_kernel<float, {R}, 0, true>"
+    """Template instance of the FP32 fine kernel the tuned configuration of n uses."""
+    R, _, variant, _ = ctx.get_tuning(n)
+    R = R or (2 if n % 2 == 0 else 1)
+    occ = 4 if variant & 2 else 0
+    return f"fine_kernel<float, {R}, 0, true, true, {occ}>"
 
 
 def cpu_baseline(nrhs_sample=8):

@@ -279,6 +279,7 @@ typedef struct {
   int32_t nrhs;
   int32_t iters;                    /* preconditioned steps (shared by all columns) */
   int32_t cycles;                   /* restart cycles */
+  int32_t reorth;                   /* Gram-Schmidt steps that needed a second pass */
   int32_t converged[MRHS_MAX_NRHS]; /* 1 if column k met tol */
   double rel_resid[MRHS_MAX_NRHS];  /* final true ||b_k - D x_k|| / ||b_k||, FP64 */
   double seconds_total;             /* host wall clock of the call */
@@ -311,9 +312,9 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * operator (mrhs_dwc_apply and the smoother) in every supported launch
  * configuration -- right-hand sides per thread 1, 2 or 4, a set of site
  * traversal tiles that divide the lattice (including slabs of Lt / 8 time
- * slices, one per XCD), two tile orders (lexicographic, Morton) and two
+ * slices, one per XCD), two tile orders (lexicographic, Morton), two
  * register budgets (the compiler's, and one that admits 4 wavefronts per
- * SIMD) -- on
+ * SIMD) and ordinary or non-temporal output stores -- on
  * scratch fields, and keeps the
  * fastest for later FP32 applies of that nrhs on this context.  All
  * configurations give bit-identical results.  cache_path (may be NULL) names
@@ -324,8 +325,9 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
 /* mrhs_get_tuning: the configuration in use for nrhs: right-hand sides per
  * thread (0 = untuned default), tile[4] (0 = default tile), variant = tile
  * order (0 lexicographic, 1 Morton) + 2 if compiled for at least 4
- * wavefronts per SIMD, measured microseconds (0 if untuned).  Any output
- * pointer may be NULL. */
+ * wavefronts per SIMD + 4 if the output is written with non-temporal
+ * stores, measured microseconds (0 if untuned).  Any output pointer may be
+ * NULL. */
 mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
                             float* us);
 

@@ -397,6 +397,7 @@ class Multigrid:
             "nrhs": st.nrhs,
             "iters": st.iters,
             "cycles": st.cycles,
+            "reorth": st.reorth,
             "converged": [bool(st.converged[k]) for k in range(n)],
             "rel_resid": [float(st.rel_resid[k]) for k in range(n)],
             "seconds_total": st.seconds_total,

@@ -79,7 +79,7 @@ class SolveParams(C.Structure):
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("nrhs", _i32), ("iters", _i32), ("cycles", _i32), ("converged", _i32 * 64),
+    _fields_ = [("nrhs", _i32), ("iters", _i32), ("cycles", _i32), ("reorth", _i32), ("converged", _i32 * 64),
                 ("rel_resid", _f64 * 64), ("seconds_total", _f64), ("seconds_precond", _f64),
                 ("seconds_phase", _f64 * 4)]
 

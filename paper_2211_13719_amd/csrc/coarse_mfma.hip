@@ -18,8 +18,9 @@
 // [site][d][j-slice][re|im][lane][8], so every A load is one 16-byte load per
 // lane and 1 KiB contiguous per wavefront.  Vectors stay FP32 in memory
 // ([site][j][rhs]); each lane reads its eight values (256-byte contiguous runs
-// across the wavefront) and rounds them to BF16/FP16 (round to nearest even,
-// rounding.h) on the fly.  FP16 operands are first scaled per right-hand side by a power
+// across the wavefront) and rounds them from FP32 to BF16/FP16 on the fly
+// (hardware conversion, round to nearest even; the one-time block pack,
+// which starts from FP64, uses the explicit conversions of rounding.h).  FP16 operands are first scaled per right-hand side by a power
 // of two, 2^-E with max_k |x| = m 2^E, m in [0.5, 1), and the output is
 // scaled back in FP32; the power of two keeps the scaling exact.
 #include "mg_internal.h"
@@ -45,13 +46,13 @@ struct Op<false> {
   static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
+  // FP32 -> BF16 by the hardware conversion, which rounds to nearest even
+  // (checked on exact ties; the parity tests compare with the emulation)
   static __device__ __forceinline__ vec cvt(const float (&x)[8]) {
-    uint4 w;
-    w.x = bf16_rne(x[0]) | ((unsigned)bf16_rne(x[1]) << 16);
-    w.y = bf16_rne(x[2]) | ((unsigned)bf16_rne(x[3]) << 16);
-    w.z = bf16_rne(x[4]) | ((unsigned)bf16_rne(x[5]) << 16);
-    w.w = bf16_rne(x[6]) | ((unsigned)bf16_rne(x[7]) << 16);
-    return __builtin_bit_cast(vec, w);
+    vec v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (__bf16)x[q];
+    return v;
   }
 };
 template <>
@@ -61,12 +62,10 @@ struct Op<true> {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ vec cvt(const float (&x)[8]) {
-    uint4 w;
-    w.x = f16_rne(x[0]) | ((unsigned)f16_rne(x[1]) << 16);
-    w.y = f16_rne(x[2]) | ((unsigned)f16_rne(x[3]) << 16);
-    w.z = f16_rne(x[4]) | ((unsigned)f16_rne(x[5]) << 16);
-    w.w = f16_rne(x[6]) | ((unsigned)f16_rne(x[7]) << 16);
-    return __builtin_bit_cast(vec, w);
+    vec v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (_Float16)x[q];
+    return v;
   }
 };
 
@@ -257,9 +256,6 @@ __global__ void pack_kernel(const double2* __restrict__ B, unsigned short* __res
 }
 
 // scale[k] = 2^-E with max over the column of |re|, |im| = m 2^E, m in [0.5, 1); 1 for a zero column.
-__global__ void colmax_init(unsigned int* __restrict__ m, int nrhs) {
-  if ((int)threadIdx.x < nrhs) m[threadIdx.x] = 0u;
-}
 __global__ void colmax_kernel(const float2* __restrict__ in, long rows, int nrhs, unsigned int* __restrict__ m) {
   const long e0 = (long)blockIdx.x * 256 + threadIdx.x;
   const long n = rows * nrhs;
@@ -273,13 +269,16 @@ __global__ void colmax_kernel(const float2* __restrict__ in, long rows, int nrhs
   }
   if (e0 < n) atomicMax(m + k, __float_as_uint(mx));
 }
-__global__ void colmax_to_scale(const unsigned int* __restrict__ m, float* __restrict__ scale, int nrhs) {
+// Also clears the reduction words, so that the next call starts from zero
+// without a separate launch.
+__global__ void colmax_to_scale(unsigned int* __restrict__ m, float* __restrict__ scale, int nrhs) {
   const int k = threadIdx.x;
   if (k >= nrhs) return;
   const float mx = __uint_as_float(m[k]);
   int E = 0;
   (void)frexpf(mx, &E);
   scale[k] = mx > 0.f ? ldexpf(1.0f, -E) : 1.0f;
+  m[k] = 0u;
 }
 
 }  // namespace
@@ -300,9 +299,9 @@ hipError_t launch_pack_blocks(int f16, const void* B64, void* packed, long nsite
   return hipGetLastError();
 }
 
+// work: nrhs 32-bit words that are zero on entry (and are left zero).
 hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, float* scale, hipStream_t s) {
   unsigned int* m = static_cast<unsigned int*>(work);
-  hipLaunchKernelGGL(colmax_init, dim3(1), dim3(64), 0, s, m, nrhs);
   // workgroup stride must be a multiple of nrhs: use blocks of 256 threads and
   // a grid such that 256 * grid % nrhs == 0
   int grid = 256;

@@ -93,12 +93,34 @@ __device__ __forceinline__ void load_r(const cplx<T>* __restrict__ p, cplx<T> (&
   }
 }
 
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+typedef float f32x2_nt __attribute__((ext_vector_type(2)));
+
+// nt: non-temporal store (the output is not read again by this kernel, so it
+// should not displace neighbour spinors from the caches).
 template <typename T, int R>
-__device__ __forceinline__ void store_r(cplx<T>* __restrict__ p, const cplx<T> (&v)[R]) {
+__device__ __forceinline__ void store_r(cplx<T>* __restrict__ p, const cplx<T> (&v)[R], bool nt = false) {
   if constexpr (sizeof(T) == 4 && R % 2 == 0) {
     float4* q = reinterpret_cast<float4*>(p);
 #pragma unroll
-    for (int j = 0; j < R / 2; ++j) q[j] = make_float4(v[2 * j].x, v[2 * j].y, v[2 * j + 1].x, v[2 * j + 1].y);
+    for (int j = 0; j < R / 2; ++j) {
+      if (nt) {
+        const f32x4_nt w = {v[2 * j].x, v[2 * j].y, v[2 * j + 1].x, v[2 * j + 1].y};
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x4_nt*>(q + j));
+      } else {
+        q[j] = make_float4(v[2 * j].x, v[2 * j].y, v[2 * j + 1].x, v[2 * j + 1].y);
+      }
+    }
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (nt) {
+        const f32x2_nt w = {v[j].x, v[j].y};
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x2_nt*>(p + j));
+      } else {
+        p[j] = v[j];
+      }
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < R; ++j) p[j] = v[j];
@@ -393,7 +415,8 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
                                                    const cplx<T>* __restrict__ U,
                                                    const T* __restrict__ A,
                                                    const cplx<T>* __restrict__ in,
-                                                   cplx<T>* __restrict__ out, int nblocks, DirFilter filt) {
+                                                   cplx<T>* __restrict__ out, int nblocks, DirFilter filt,
+                                                   int nt_out) {
   int b = blockIdx.x;
   if constexpr (XCD) {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
@@ -451,7 +474,7 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c]);
+      for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c], nt_out);
   } else {
     const cplx<T>* base = in + (size_t)site * 12 * nrhs + k0;
 #pragma unroll
@@ -477,7 +500,7 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
             yout[i][j].y = fma(-kappa, acc[sp][c][j].y, yout[i][j].y);
           }
         }
-        store_r<T, R>(o + (6 * chi + i) * nrhs, yout[i]);
+        store_r<T, R>(o + (6 * chi + i) * nrhs, yout[i], nt_out);
       }
     }
   }
@@ -485,14 +508,14 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
 
 template <typename T, int R, int MODE, int OCC = 0>
 hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, const void* A, const void* in,
-                    void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}) {
+                    void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}, int nt = 0) {
   if (!g.nbr || !order) return hipErrorInvalidValue;
   const long threads = (long)g.V * (nrhs / R);
   const int nblocks = (int)((threads + 255) / 256);
   const int grid = ((nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL((fine_kernel<T, R, MODE, true, true, OCC>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, order,
                      reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
-                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f);
+                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f, nt);
   return hipGetLastError();
 }
 
@@ -507,15 +530,18 @@ hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const vo
     // component) for even Nrhs, one otherwise.
     if (R == 0) R = (nrhs % 2 == 0) ? 2 : 1;
     const bool occ4 = MODE == 0 && cfg && cfg->occ == 4;
+    const int nt = (cfg && cfg->R > 0) ? cfg->nt : 0;
+    const DirFilter f;
     if constexpr (MODE == 0) {
       if (occ4) {
-        if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s);
-        if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s);
-        return launch_r<T, 1, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s);
+        if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
+        if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
+        return launch_r<T, 1, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
       }
     }
-    if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
-    if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
+    if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
+    if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
+    return launch_r<T, 1, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
   }
   return launch_r<T, 1, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
 }

@@ -64,6 +64,7 @@ struct FineCfg {
   int T[4] = {0, 0, 0, 0};
   int curve = 0;               // tile order: 0 lexicographic, 1 Morton in (x, y, z) per t-row of tiles
   int occ = 0;                 // 0: compiler's register choice; 4: at least 4 wavefronts per SIMD
+  int nt = 0;                  // 1: non-temporal output stores
   const int* order = nullptr;  // traversal table of tile T (device)
   float us = 0.f;              // measured time of the choice
 };

@@ -85,6 +85,14 @@ mrhs_status refresh_blocks(mrhs_mg mg, int level) {
   return MRHS_OK;
 }
 
+mrhs_status ensure_colscale(mrhs_mg mg) {
+  if (mg->colscale.p) return MRHS_OK;
+  mrhs_status st = ensure(mg->ctx, mg->colscale, 2 * MRHS_MAX_NRHS * sizeof(float));
+  if (st != MRHS_OK) return st;
+  MRHS_HIP(mg->ctx, hipMemset(mg->colscale.p, 0, 2 * MRHS_MAX_NRHS * sizeof(float)));
+  return MRHS_OK;
+}
+
 // Refreshes the FP32 copy of a level's basis from the FP64 master.
 mrhs_status refresh_basis32(mrhs_mg mg, int level) {
   mrhs_ctx ctx = mg->ctx;
@@ -434,7 +442,7 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
         return fail(ctx, MRHS_ERR_UNSUPPORTED, "matrix-core stencil needs Nb = 32, got %d", L.ncomp);
       const float* scale = nullptr;
       if (prec == MRHS_F16) {
-        st = ensure(ctx, mg->colscale, 2 * MRHS_MAX_NRHS * sizeof(float));
+        st = ensure_colscale(mg);
         if (st != MRHS_OK) return st;
         float* sc = static_cast<float*>(mg->colscale.p);
         e = launch_column_scale(in, (long)L.g.V * L.ncomp, nrhs, sc + MRHS_MAX_NRHS, sc, ctx->stream);

@@ -38,6 +38,8 @@ struct mrhs_mg_s {
 namespace mrhs {
 
 mrhs_status refresh_blocks(mrhs_mg mg, int level);
+// per-RHS FP16 scales and their reduction words (zeroed when first allocated)
+mrhs_status ensure_colscale(mrhs_mg mg);
 mrhs_status refresh_basis32(mrhs_mg mg, int level);
 
 // coarse_mfma.hip
@@ -45,7 +47,7 @@ bool mfma_supported(int nb);
 size_t mfma_pack_bytes(long nsite);
 mrhs_status pack_blocks_mfma(mrhs_mg mg, int level);
 hipError_t launch_pack_blocks(int f16, const void* B64, void* packed, long nsite, hipStream_t s);
-// scale[k] for FP16 operands; work holds nrhs 32-bit words
+// scale[k] for FP16 operands; work holds nrhs 32-bit words, zero on entry and exit
 hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, float* scale, hipStream_t s);
 hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
                               const float* scale, hipStream_t s);

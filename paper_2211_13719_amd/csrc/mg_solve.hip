@@ -7,7 +7,8 @@
 // right-hand side (batched, not block Krylov): per-RHS Hessenberg matrices
 // and Givens rotations live on the host, the vectors on the device, and all
 // inner products of one Gram-Schmidt step are computed in one pass (classical
-// Gram-Schmidt applied twice).  The preconditioned directions Z are stored in
+// Gram-Schmidt, repeated once when the first pass lost more than half of the
+// vector's norm).  The preconditioned directions Z are stored in
 // FP32; since the same FP32 values enter both D Z and the update x += Z y, the
 // Arnoldi relation holds to FP64 rounding and the FP64 true residual can reach
 // 1e-10 although the preconditioner works in lower precision.
@@ -56,6 +57,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 enum Phase { kFine = 0, kRestrict, kProlong, kCoarse, kPhases };
 
+constexpr int kGraphSlots = kMaxMultiDot;
+
+struct GraphSlot {
+  hipGraphExec_t exec = nullptr;
+  int n = 0;
+  void* out = nullptr;
+  mrhs_vcycle_params vc{};
+};
+
 struct SolverState {
   hipStream_t stream = nullptr;  // private stream: graphs cannot capture the null stream
   int n = 0;                     // right-hand sides the level buffers hold
@@ -64,10 +74,8 @@ struct SolverState {
   // outer Krylov
   int m = 0, on = 0;
   Buffer V64, Z32, w64, t64, r64;
-  // graph of one V-cycle
-  hipGraphExec_t gexec = nullptr;
-  int g_n = 0;
-  mrhs_vcycle_params g_vc{};
+  // captured V-cycles, one per destination slot
+  GraphSlot graphs[kGraphSlots];
   // phase timers
   bool timing = false;
   std::vector<hipEvent_t> evpool;
@@ -87,7 +95,8 @@ void mg_solver_release(mrhs_mg mg) {
   }
   Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->V64, &st->Z32, &st->w64, &st->t64, &st->r64};
   for (Buffer* x : b) release(*x);
-  if (st->gexec) (void)hipGraphExecDestroy(st->gexec);
+  for (auto& gs : st->graphs)
+    if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
   for (hipEvent_t e : st->evpool) (void)hipEventDestroy(e);
   if (st->stream) (void)hipStreamDestroy(st->stream);
   delete st;
@@ -118,9 +127,9 @@ mrhs_status state_of(mrhs_mg mg, SolverState** out) {
 mrhs_status ensure_levels(mrhs_mg mg, SolverState* st, int n) {
   mrhs_ctx ctx = mg->ctx;
   if (n > st->n) {
-    if (st->gexec) {
-      (void)hipGraphExecDestroy(st->gexec);
-      st->gexec = nullptr;
+    for (auto& gs : st->graphs) {
+      if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
+      gs = GraphSlot{};
     }
     for (int l = 0; l < mg->nlevels; ++l) {
       const size_t bytes = (size_t)level_rows(mg, l) * n * 8;
@@ -139,7 +148,7 @@ mrhs_status ensure_levels(mrhs_mg mg, SolverState* st, int n) {
   if (s == MRHS_OK) s = ensure(ctx, st->scl, MRHS_MAX_NRHS * 8);
   if (s == MRHS_OK) s = ensure(ctx, st->coef, (size_t)kMaxMultiDot * MRHS_MAX_NRHS * 16);
   if (s == MRHS_OK) s = ensure(ctx, st->qn, MRHS_MAX_NRHS * 8);
-  if (s == MRHS_OK) s = ensure(ctx, mg->colscale, 2 * MRHS_MAX_NRHS * sizeof(float));
+  if (s == MRHS_OK) s = ensure_colscale(mg);
   return s;
 }
 
@@ -206,11 +215,11 @@ hipError_t mr_steps(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* 
 }
 
 // x_l ~ D_l^{-1} b_l (buffers lb[l] -> lx[l]).
-hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_params& vc) {
+hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_params& vc, void* xout = nullptr) {
   const long rows = level_rows(mg, l);
   const size_t bytes = (size_t)rows * n * 8;
   void* b = st->lb[l].p;
-  void* x = st->lx[l].p;
+  void* x = xout ? xout : st->lx[l].p;
   void* r = st->lr[l].p;
   void* p = st->lp[l].p;
   const mrhs_prec cp = vc.coarse_prec;
@@ -246,37 +255,51 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   return e;
 }
 
-// Runs one V-cycle on lb[0] -> lx[0], from a captured graph when asked.
-mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_params& vc, bool graph) {
+// Runs one V-cycle on lb[0] -> xout (lx[0] if null), from a captured graph
+// when asked.  One graph is kept per slot (the outer solver uses slot j for
+// its direction Z_j), so the V-cycle writes straight into its destination.
+mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_params& vc, bool graph,
+                       void* xout = nullptr, int slot = 0) {
   mrhs_ctx ctx = mg->ctx;
   if (!graph || st->timing) {
-    SOLVER_HIP(vcycle(mg, st, 0, n, vc));
+    SOLVER_HIP(vcycle(mg, st, 0, n, vc, xout));
     return MRHS_OK;
   }
-  const bool same = st->gexec && st->g_n == n && st->g_vc.nu_pre == vc.nu_pre && st->g_vc.nu_post == vc.nu_post &&
-                    st->g_vc.coarsest_iters == vc.coarsest_iters && st->g_vc.coarse_prec == vc.coarse_prec;
+  if (slot < 0 || slot >= kGraphSlots) return fail(ctx, MRHS_ERR_INVALID_ARG, "graph slot %d out of range", slot);
+  GraphSlot& gs = st->graphs[slot];
+  const bool same = gs.exec && gs.n == n && gs.out == xout && gs.vc.nu_pre == vc.nu_pre &&
+                    gs.vc.nu_post == vc.nu_post && gs.vc.coarsest_iters == vc.coarsest_iters &&
+                    gs.vc.coarse_prec == vc.coarse_prec;
   if (!same) {
-    if (st->gexec) {
-      (void)hipGraphExecDestroy(st->gexec);
-      st->gexec = nullptr;
+    if (gs.exec) {
+      (void)hipGraphExecDestroy(gs.exec);
+      gs.exec = nullptr;
     }
     hipGraph_t gr = nullptr;
     SOLVER_HIP(hipStreamBeginCapture(st->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = vcycle(mg, st, 0, n, vc);
+    hipError_t e = vcycle(mg, st, 0, n, vc, xout);
     hipError_t e2 = hipStreamEndCapture(st->stream, &gr);
     if (e != hipSuccess) {
       if (gr) (void)hipGraphDestroy(gr);
       return hip_fail(ctx, e, "V-cycle capture");
     }
     SOLVER_HIP(e2);
-    e = hipGraphInstantiate(&st->gexec, gr, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&gs.exec, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     SOLVER_HIP(e);
-    st->g_n = n;
-    st->g_vc = vc;
+    gs.n = n;
+    gs.vc = vc;
+    gs.out = xout;
   }
-  SOLVER_HIP(hipGraphLaunch(st->gexec, st->stream));
+  SOLVER_HIP(hipGraphLaunch(gs.exec, st->stream));
   return MRHS_OK;
+}
+
+void drop_graphs(SolverState* st) {
+  for (auto& gs : st->graphs) {
+    if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
+    gs = GraphSlot{};
+  }
 }
 
 mrhs_status check_vc(mrhs_mg mg, const mrhs_vcycle_params* vc) {
@@ -389,10 +412,7 @@ mrhs_status mrhs_mg_setup(mrhs_mg mg, int32_t setup_iters, int32_t smooth_steps)
     s = mrhs_mg_build_coarse(mg, l + 1);
     if (s != MRHS_OK) return s;
   }
-  if (st->gexec) {  // the graph holds pointers into rebuilt operators only, but keep it simple
-    (void)hipGraphExecDestroy(st->gexec);
-    st->gexec = nullptr;
-  }
+  drop_graphs(st);  // the graphs only hold pointers into rebuilt operators, but keep it simple
   return MRHS_OK;
 }
 
@@ -428,6 +448,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   const int n = nrhs;
   const size_t f64 = (size_t)rows * n * 16, f32 = (size_t)rows * n * 8;
   if (st->m < m || st->on < n) {
+    drop_graphs(st);  // they write into Z, which is reallocated
     release(st->V64);
     release(st->Z32);
     s = ensure(ctx, st->V64, (size_t)(m + 1) * f64);
@@ -473,8 +494,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   for (int k = 0; k < n; ++k) bn[k] = std::sqrt(bn[k]);
   std::vector<int> done(n, 0);
   std::vector<cd> H((size_t)n * (m + 1) * m), g((size_t)n * (m + 1)), cs((size_t)n * m), sn((size_t)n * m);
-  std::vector<cd> hc((size_t)(m + 1) * n), hc2((size_t)(m + 1) * n), y((size_t)m * n);
-  int iters = 0, cycles = 0;
+  std::vector<cd> hc((size_t)(m + 2) * n), hc2((size_t)(m + 2) * n), y((size_t)m * n);
+  int iters = 0, cycles = 0, reorth = 0;
   bool all_done = false;
   auto Hel = [&](int k, int i, int j) -> cd& { return H[((size_t)k * (m + 1) + i) * m + j]; };
 
@@ -507,9 +528,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
         if (prm->precondition) {
           SOLVER_HIP(launch_convert_f64_to_f32(static_cast<const double*>(Vj(j)), static_cast<float*>(st->lb[0].p),
                                                2 * rows * n, ss));
-          s = run_vcycle(mg, st, n, prm->vc, prm->use_graph != 0);
+          s = run_vcycle(mg, st, n, prm->vc, prm->use_graph != 0, Zj(j), j);
           if (s != MRHS_OK) return s;
-          SOLVER_HIP(hipMemcpyAsync(Zj(j), st->lx[0].p, f32, hipMemcpyDeviceToDevice, ss));
         } else {
           SOLVER_HIP(launch_convert_f64_to_f32(static_cast<const double*>(Vj(j)), static_cast<float*>(Zj(j)),
                                                2 * rows * n, ss));
@@ -523,17 +543,30 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       SOLVER_HIP(launch_convert_f32_to_f64(static_cast<const float*>(Zj(j)), static_cast<double*>(st->t64.p),
                                            2 * rows * n, ss));
       SOLVER_HIP(D64(st->w64.p, st->t64.p));
-      // classical Gram-Schmidt, twice
-      std::vector<const void*> vs(j + 1);
+      // classical Gram-Schmidt; the first pass also yields ||w||^2 (w is the
+      // last vector of the multi-dot), and a second pass is made only when
+      // the projection removed more than half of ||w||^2 for some
+      // right-hand side ("twice is enough")
+      std::vector<const void*> vs(j + 2);
       for (int i = 0; i <= j; ++i) vs[i] = Vj(i);
-      for (int pass = 0; pass < 2; ++pass) {
-        std::vector<cd>& dst = pass ? hc2 : hc;
+      vs[j + 1] = st->w64.p;
+      SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 2, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
+      SOLVER_HIP(launch_multi_axpy(1, st->w64.p, st->coef.p, vs.data(), j + 1, -1.0, rows, n, ss));
+      SOLVER_HIP(hipMemcpyAsync(hc.data(), st->coef.p, (size_t)(j + 2) * n * 16, hipMemcpyDeviceToHost, ss));
+      s = norms(st->w64.p, q);  // synchronises, so hc is complete
+      if (s != MRHS_OK) return s;
+      bool again = false;
+      for (int k = 0; k < n; ++k)
+        if (!done[k] && q[k] < 0.5 * hc[(size_t)(j + 1) * n + k].real()) again = true;
+      std::fill(hc2.begin(), hc2.end(), cd(0.0));
+      if (again) {
         SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
         SOLVER_HIP(launch_multi_axpy(1, st->w64.p, st->coef.p, vs.data(), j + 1, -1.0, rows, n, ss));
-        SOLVER_HIP(hipMemcpyAsync(dst.data(), st->coef.p, (size_t)(j + 1) * n * 16, hipMemcpyDeviceToHost, ss));
+        SOLVER_HIP(hipMemcpyAsync(hc2.data(), st->coef.p, (size_t)(j + 1) * n * 16, hipMemcpyDeviceToHost, ss));
+        s = norms(st->w64.p, q);
+        if (s != MRHS_OK) return s;
+        ++reorth;
       }
-      s = norms(st->w64.p, q);  // synchronises, so hc and hc2 are complete
-      if (s != MRHS_OK) return s;
       bool all_conv = true;
       for (int k = 0; k < n; ++k) {
         for (int i = 0; i <= j; ++i) Hel(k, i, j) = hc[(size_t)i * n + k] + hc2[(size_t)i * n + k];
@@ -593,6 +626,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
     stats->nrhs = n;
     stats->iters = iters;
     stats->cycles = cycles;
+    stats->reorth = reorth;
     for (int k = 0; k < n; ++k) {
       stats->converged[k] = done[k];
       stats->rel_resid[k] = rel[k];

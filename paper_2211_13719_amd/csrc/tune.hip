@@ -1,12 +1,14 @@
 // Autotuner of the FP32 fine Wilson-clover kernel: for each requested Nrhs it
-// times every supported launch configuration -- right-hand sides per thread
-// (1, 2, 4) times traversal tile -- on scratch fields of the context's
-// lattice and keeps the fastest for all later FP32 applies of that Nrhs
+// times launch configurations -- traversal tile and tile order, right-hand
+// sides per thread (1, 2, 4), register budget, ordinary or non-temporal
+// output stores -- on scratch fields of the context's lattice, by coordinate
+// descent in that order, and keeps the fastest for all later FP32 applies of
+// that Nrhs
 // (the configurations compute bit-identical results: each output element
 // sees the same operations in the same order).  Choices can be persisted in
 // a plain text cache, one line per (device architecture, lattice, Nrhs):
 //
-//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <microseconds>
+//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <nt> <microseconds>
 #include <algorithm>
 #include <array>
 #include <cstdio>
@@ -20,22 +22,15 @@ using namespace mrhs;
 
 namespace {
 
-struct Cand {
-  int R;
-  int T[4];
-  int curve;
-  int occ;
-};
-
 bool divides(const Geom& g, const int T[4]) {
   for (int m = 0; m < 4; ++m)
     if (T[m] < 1 || g.L[m] % T[m]) return false;
   return true;
 }
 
-// RHS per thread x tile x tile order.  The tiles with a t-extent of Lt / 8
-// give every XCD its own slab of time slices.
-std::vector<Cand> candidates(const Geom& g, int nrhs) {
+// Tiles to try.  Those with a t-extent of Lt / 8 give every XCD its own slab
+// of time slices.
+std::vector<std::array<int, 4>> tile_candidates(const Geom& g) {
   std::vector<std::array<int, 4>> tiles = {{8, 4, 4, 4}, {4, 4, 4, 4}, {6, 6, 6, 6}, {8, 8, 2, 2},
                                            {2, 2, 2, 2}, {1, 1, 1, 1}};
   if (g.L[3] % 8 == 0) {
@@ -44,15 +39,10 @@ std::vector<Cand> candidates(const Geom& g, int nrhs) {
                    {12, 4, 4, st}})
       tiles.push_back(t);
   }
-  std::vector<Cand> out;
-  for (int R : {1, 2, 4}) {
-    if (nrhs % R) continue;
-    for (auto& t : tiles)
-      for (int curve : {0, 1})
-        for (int occ : {0, 4}) {
-          Cand c{R, {t[0], t[1], t[2], t[3]}, curve, occ};
-          if (divides(g, c.T)) out.push_back(c);
-        }
+  std::vector<std::array<int, 4>> out;
+  for (auto& t : tiles) {
+    const int T[4] = {t[0], t[1], t[2], t[3]};
+    if (divides(g, T)) out.push_back(t);
   }
   return out;
 }
@@ -70,18 +60,19 @@ bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int 
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char a[64];
-  int L[4], n, R, T[4], curve, occ;
+  int L[4], n, R, T[4], curve, occ, nt;
   float us;
   bool found = false;
-  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R, &T[0],
-                     &T[1], &T[2], &T[3], &curve, &occ, &us) == 14) {
+  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R,
+                     &T[0], &T[1], &T[2], &T[3], &curve, &occ, &nt, &us) == 15) {
     if (arch == a && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] && L[3] == g.L[3] &&
         (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1) &&
-        (occ == 0 || occ == 4)) {
+        (occ == 0 || occ == 4) && (nt == 0 || nt == 1)) {
       out.R = R;
       for (int m = 0; m < 4; ++m) out.T[m] = T[m];
       out.curve = curve;
       out.occ = occ;
+      out.nt = nt;
       out.us = us;
       found = true;  // the last matching line wins
     }
@@ -94,8 +85,8 @@ void cache_append(const char* path, const std::string& arch, const Geom& g, int 
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2], g.L[3],
-               nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.us);
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2],
+               g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.nt, c.us);
   std::fclose(f);
 }
 
@@ -144,34 +135,62 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
         continue;
       }
     }
-    best.us = 1e30f;
-    for (const Cand& c : candidates(ctx->g, n)) {
-      FineCfg cfg;
-      cfg.R = c.R;
-      for (int m = 0; m < 4; ++m) cfg.T[m] = c.T[m];
-      cfg.curve = c.curve;
-      cfg.occ = c.occ;
-      cfg.order = fine_order_table(ctx, c.T, c.curve);
-      if (!cfg.order) {
-        e = hipErrorOutOfMemory;
-        break;
-      }
+    // coordinate descent: tile and tile order first (two RHS per thread for
+    // even Nrhs), then RHS per thread, register budget and store kind
+    auto time_cfg = [&](FineCfg& cfg) -> hipError_t {
+      cfg.order = fine_order_table(ctx, cfg.T, cfg.curve);
+      if (!cfg.order) return hipErrorOutOfMemory;
       std::vector<float> t;
-      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-        e = hipEventRecord(e0, ctx->stream);
-        if (e == hipSuccess)
-          e = launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in.p, out.p, n,
-                              ctx->stream, &cfg);
-        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
+      hipError_t err = hipSuccess;
+      for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e0, ctx->stream);
+        if (err == hipSuccess)
+          err = launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in.p, out.p, n,
+                                ctx->stream, &cfg);
+        if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
         if (rep > 0) t.push_back(ms * 1000.f);  // the first launch is a warm-up
       }
-      if (e != hipSuccess) break;
+      if (err != hipSuccess) return err;
       std::sort(t.begin(), t.end());
       cfg.us = t[t.size() / 2];
-      if (cfg.us < best.us) best = cfg;
+      return hipSuccess;
+    };
+    best.R = (n % 2 == 0) ? 2 : 1;
+    best.us = 1e30f;
+    FineCfg base = best;
+    for (const auto& t : tile_candidates(ctx->g)) {
+      for (int curve : {0, 1}) {
+        FineCfg cfg = base;
+        for (int m = 0; m < 4; ++m) cfg.T[m] = t[m];
+        cfg.curve = curve;
+        e = time_cfg(cfg);
+        if (e != hipSuccess) break;
+        if (cfg.us < best.us) best = cfg;
+      }
+      if (e != hipSuccess) break;
+    }
+    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
+      const FineCfg cur = best;
+      const std::vector<int> opts = stage == 0 ? std::vector<int>{1, 2, 4} : std::vector<int>{0, stage == 1 ? 4 : 1};
+      for (int v : opts) {
+        FineCfg cfg = cur;
+        if (stage == 0) {
+          if (n % v || v == cur.R) continue;
+          cfg.R = v;
+        } else if (stage == 1) {
+          if (v == cur.occ) continue;
+          cfg.occ = v;
+        } else {
+          if (v == cur.nt) continue;
+          cfg.nt = v;
+        }
+        e = time_cfg(cfg);
+        if (e != hipSuccess) break;
+        if (cfg.us < best.us) best = cfg;
+      }
     }
     if (e == hipSuccess) {
       ctx->fine_cfg[n] = best;
@@ -196,7 +215,7 @@ mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread,
   if (rhs_per_thread) *rhs_per_thread = c.R;
   if (tile)
     for (int m = 0; m < 4; ++m) tile[m] = c.T[m];
-  if (curve) *curve = c.curve + 2 * (c.occ == 4);
+  if (curve) *curve = c.curve + 2 * (c.occ == 4) + 4 * c.nt;
   if (us) *us = c.us;
   return MRHS_OK;
 }
