@@ -2,6 +2,7 @@
 """Benchmark of the MRHS Wilson-clover multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu-baseline]
+                    [--tune-cache PATH | --retune]
 
 One step is one pass over every operator of the hot path, each on its
 workload shape (inputs resident in device memory, all synthetic and seeded):
@@ -24,11 +25,16 @@ mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels,
 graph-replayed V-cycle) on 24^3 x 128 smooth links for a batch of RHS and the
 same solver on one RHS with FP32 coarse levels, in seconds per RHS to a true
 residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on a sample.
+
+Fine-kernel launch configurations come from the autotuner's text cache
+(paper_2211_13719_amd/tuning/fine.txt, tuned on an MI355X); lattices or Nrhs
+missing there are tuned on the spot and appended, and --retune ignores it.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -47,6 +53,31 @@ HBM_PEAK_GBS = 8000.0
 
 FLOPS_DWC = 1920          # per site per RHS: hop 1320 + clover 552 + combine 48
 SOLVE_DIMS = (24, 24, 24, 128)
+TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
+FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
+
+# HBM traffic of the dominant fine kernel per launch (bytes; rocprofv3
+# FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by what the counter reads
+# for a 1 GiB device copy), recorded with a digest of the kernel's sources and
+# the launch configurations it was counted under.  `roofline.traffic` carries
+# it only while the kernel name, sources and configurations still match.
+FINE_TRAFFIC = {
+    "kernel": "fine_kernel<float, 2, 0, true, true, 0>",
+    "sources": "c6ddb6fa66f66a52",
+    "configs": {"6": [2, [8, 8, 2, 3], 0], "12": [2, [12, 4, 4, 3], 0], "24": [2, [8, 8, 2, 3], 4],
+                "48": [2, [8, 4, 4, 3], 4], "64": [2, [8, 4, 4, 3], 5]},
+    "bytes_per_launch": 6.419e9,
+    "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
+            "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
+}
+
+
+def fine_sources_digest():
+    h = hashlib.sha256()
+    for f in FINE_SOURCES:
+        with open(os.path.join(HERE, "paper_2211_13719_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def fine_bytes(V, n):
@@ -113,7 +144,7 @@ class Timer:
         return out
 
 
-def run_solve(mrhs, torch, synth, nrhs_mrhs, mass):
+def run_solve(mrhs, torch, synth, nrhs_mrhs, mass, cache):
     """MRHS mixed-precision solve vs the same solver on one RHS with FP32 coarse levels."""
     kappa = mass["kappa"]
     U = synth.gauge_smooth(SOLVE_DIMS, 5)
@@ -121,7 +152,7 @@ def run_solve(mrhs, torch, synth, nrhs_mrhs, mass):
     ctx.set_gauge(U)
     del U
     ctx.build_clover(CSW, kappa)
-    ctx.tune(sorted({1, 16, nrhs_mrhs}))
+    ctx.tune(sorted({1, 16, nrhs_mrhs}), cache)
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     t0 = time.perf_counter()
     for l in range(2):
@@ -178,6 +209,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solve-nrhs", type=int, default=12)
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner text cache (read, appended)")
+    ap.add_argument("--retune", action="store_true", help="tune the fine kernel afresh, ignoring the cache")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for HBM byte counters)")
     a = ap.parse_args()
@@ -210,7 +243,10 @@ def main():
     ctx.set_gauge(U)
     del U
     ctx.build_clover(CSW, KAPPA)
-    ctx.tune(list(NRHS_FINE))
+    cache = None if a.retune else a.tune_cache
+    if cache:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+    ctx.tune(list(NRHS_FINE), cache)
     tuning = {str(n): dict(zip(("rhs_per_thread", "tile", "variant", "tuned_us"), ctx.get_tuning(n))) for n in NRHS_FINE}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
@@ -308,6 +344,12 @@ def main():
     mean_bytes = float(np.mean([fine_bytes(V, n) for n, _ in launches]))
     mean_ms = float(np.mean([t for _, t in launches]))
     achieved = mean_bytes / mean_ms / 1e6
+    traffic = None
+    cfg_now = {str(n): [tuning[str(n)]["rhs_per_thread"], list(tuning[str(n)]["tile"]), tuning[str(n)]["variant"]]
+               for n in share[dom]}
+    if (FINE_TRAFFIC and FINE_TRAFFIC["kernel"] == dom and FINE_TRAFFIC["sources"] == fine_sources_digest()
+            and FINE_TRAFFIC["configs"] == cfg_now):
+        traffic = FINE_TRAFFIC["bytes_per_launch"]
 
     total_flops = sum(f for _, f, _, _ in ops)
     ms_per_step = wall * 1e3 / a.steps
@@ -342,13 +384,16 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_note": FINE_TRAFFIC["note"] if traffic else "no counter record for this kernel build "
+                            "and configuration",
             "alg_bytes_per_launch_mean": mean_bytes,
             "launch_ms_mean": round(mean_ms, 5),
             "launches_per_step": len(share[dom]),
         },
         "per_op": per_op,
         "fine_tuning": tuning,
+        "fine_sources": fine_sources_digest(),
         "solve": None,
         "cpu_baseline": None,
     }
@@ -364,7 +409,7 @@ def main():
         else:
             mass = {"m0": 0.0, "kappa": 0.125, "sigma_min": None}
         print("[bench] solve ...", file=sys.stderr, flush=True)
-        result["solve"] = run_solve(mrhs, torch, synth, a.solve_nrhs, mass)
+        result["solve"] = run_solve(mrhs, torch, synth, a.solve_nrhs, mass, cache)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline()

@@ -4,14 +4,15 @@ The workload asks for the mass at which the smallest singular value of the
 mass-normalised operator D_m = D / (2 kappa), kappa = 1 / (2 (4 + m0)), on an
 8^4 lattice of smooth links U = exp(0.3 i H) (H = sum_a h_a lambda_a / 2,
 h_a ~ N(0, 1)), csw = 1, antiperiodic in time, is about 0.01.  sigma_min(m0)
-has a single minimum near the critical mass; this script scans m0 (three
-significant digits of sigma_min are enough to place the mass), then
-minimises |sigma_min - 0.01| by golden-section search on the bracket around
-the best scan point, and writes the result (and the attained value, which
-may stay above 0.01 if the links are too smooth to produce such a small
-singular value at this volume) to tests/golden/smooth_links_mass.json.
+has a single minimum near the critical mass; this script scans m0 on a
+grid (three significant digits of sigma_min are enough to place the mass),
+takes one parabolic-interpolation step through the three grid points around
+the one closest to the target, and writes the better of the two (and the
+attained value, which stays above 0.01 when the lowest momentum the volume
+allows keeps the smallest singular value away from zero) to
+tests/golden/smooth_links_mass.json.
 
-    python -m oracle.tune_mass [--seed S] [--out PATH]
+    python -m oracle.tune_mass [--seed S] [--grid M0 M0 M0 ...] [--out PATH]
 """
 
 from __future__ import annotations
@@ -43,31 +44,28 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "..", "tests", "golden",
                                                   "smooth_links_mass.json"))
+    ap.add_argument("--grid", type=float, nargs="+", default=[-0.2, -0.25, -0.3])
     a = ap.parse_args()
     U = synth.gauge_smooth(DIMS, a.seed)
     t0 = time.time()
     scan = {}
-    for m0 in (0.0, -0.1, -0.2, -0.25, -0.3, -0.35, -0.4):
+    for m0 in a.grid:
         scan[float(m0)] = sig(U, float(m0))
         print(f"m0 {m0:+.3f}  sigma_min {scan[float(m0)]:.5f}  ({time.time() - t0:.0f} s)", flush=True)
-    f = lambda m: abs(sig(U, m) - TARGET)
-    best = min(scan, key=lambda m: abs(scan[m] - TARGET))
-    lo, hi = best - 0.05, best + 0.05
-    gr = (np.sqrt(5) - 1) / 2
-    c, d = hi - gr * (hi - lo), lo + gr * (hi - lo)
-    fc, fd = f(c), f(d)
-    for _ in range(8):
-        if fc < fd:
-            hi, d, fd = d, c, fc
-            c = hi - gr * (hi - lo)
-            fc = f(c)
-        else:
-            lo, c, fc = c, d, fd
-            d = lo + gr * (hi - lo)
-            fd = f(d)
-        print(f"bracket [{lo:+.5f}, {hi:+.5f}]  ({time.time() - t0:.0f} s)", flush=True)
-    m0 = 0.5 * (lo + hi)
-    s = sig(U, m0)
+    f = lambda m: abs(scan[m] - TARGET)
+    grid = sorted(scan)
+    i = min(range(len(grid)), key=lambda k: f(grid[k]))
+    m0, s = grid[i], scan[grid[i]]
+    if 0 < i < len(grid) - 1:
+        (x0, x1, x2), (y0, y1, y2) = grid[i - 1:i + 2], [f(g) for g in grid[i - 1:i + 2]]
+        den = (x1 - x0) * (y1 - y2) - (x1 - x2) * (y1 - y0)
+        if den != 0:
+            xv = x1 - 0.5 * ((x1 - x0) ** 2 * (y1 - y2) - (x1 - x2) ** 2 * (y1 - y0)) / den
+            if x0 < xv < x2:
+                sv = sig(U, xv)
+                print(f"m0 {xv:+.5f}  sigma_min {sv:.5f}  (vertex, {time.time() - t0:.0f} s)", flush=True)
+                if abs(sv - TARGET) < f(m0):
+                    m0, s = xv, sv
     res = {
         "lattice": list(DIMS),
         "links": "smooth, U = exp(0.3 i H), seed %d" % a.seed,
@@ -77,7 +75,7 @@ def main():
         "m0": m0,
         "kappa": 1.0 / (2.0 * (4.0 + m0)),
         "sigma_min": s,
-        "scan": scan,
+        "scan": {str(k): v for k, v in scan.items()},
         "written_by": "python -m oracle.tune_mass (oracle only)",
     }
     with open(a.out, "w") as fh:

@@ -29,7 +29,9 @@ bool divides(const Geom& g, const int T[4]) {
 }
 
 // Tiles to try.  Those with a t-extent of Lt / 8 give every XCD its own slab
-// of time slices.
+// of time slices; those with the full t-extent are columns swept along t, so
+// that the +-t neighbours of a site are one small cross-section apart in the
+// traversal and only the column faces are re-read from outside the L2.
 std::vector<std::array<int, 4>> tile_candidates(const Geom& g) {
   std::vector<std::array<int, 4>> tiles = {{8, 4, 4, 4}, {4, 4, 4, 4}, {6, 6, 6, 6}, {8, 8, 2, 2},
                                            {2, 2, 2, 2}, {1, 1, 1, 1}};
@@ -39,6 +41,10 @@ std::vector<std::array<int, 4>> tile_candidates(const Geom& g) {
                    {12, 4, 4, st}})
       tiles.push_back(t);
   }
+  const int lt = g.L[3];
+  for (auto t : {std::array<int, 4>{4, 4, 4, lt}, {6, 6, 4, lt}, {8, 4, 4, lt}, {6, 6, 6, lt}, {8, 8, 4, lt},
+                 {8, 6, 6, lt}, {12, 6, 4, lt}, {12, 12, 4, lt}, {8, 8, 8, lt}})
+    tiles.push_back(t);
   std::vector<std::array<int, 4>> out;
   for (auto& t : tiles) {
     const int T[4] = {t[0], t[1], t[2], t[3]};
