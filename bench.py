@@ -63,10 +63,10 @@ FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 # it only while the kernel name, sources and configurations still match.
 FINE_TRAFFIC = {
     "kernel": "fine_kernel<float, 2, 0, true, true, 0>",
-    "sources": "c6ddb6fa66f66a52",
-    "configs": {"6": [2, [8, 8, 2, 3], 0], "12": [2, [12, 4, 4, 3], 0], "24": [2, [8, 8, 2, 3], 4],
-                "48": [2, [8, 4, 4, 3], 4], "64": [2, [8, 4, 4, 3], 5]},
-    "bytes_per_launch": 6.419e9,
+    "sources": "2b6a54d4e2f02f8b",
+    "configs": {"6": [2, [12, 4, 4, 3], 32], "12": [2, [8, 8, 2, 3], 64], "24": [2, [8, 8, 2, 3], 68],
+                "48": [2, [8, 4, 4, 3], 68], "64": [2, [8, 4, 4, 3], 5]},
+    "bytes_per_launch": 5.527e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }

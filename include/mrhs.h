@@ -312,8 +312,10 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * operator (mrhs_dwc_apply and the smoother) in every supported launch
  * configuration -- right-hand sides per thread 1, 2 or 4, a set of site
  * traversal tiles that divide the lattice (including slabs of Lt / 8 time
- * slices, one per XCD), two tile orders (lexicographic, Morton), two
- * register budgets (the compiler's, and one that admits 4 wavefronts per
+ * slices, one per XCD, and columns of the full time extent), two tile orders
+ * (lexicographic, Morton), the right-hand sides split into 1, 2 or 4 chunks
+ * swept one after the other, at most 1 or 2 workgroups per CU or no limit,
+ * two register budgets (the compiler's, and one that admits 4 wavefronts per
  * SIMD) and ordinary or non-temporal output stores -- on
  * scratch fields, and keeps the
  * fastest for later FP32 applies of that nrhs on this context.  All
@@ -326,8 +328,8 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
  * thread (0 = untuned default), tile[4] (0 = default tile), variant = tile
  * order (0 lexicographic, 1 Morton) + 2 if compiled for at least 4
  * wavefronts per SIMD + 4 if the output is written with non-temporal
- * stores, measured microseconds (0 if untuned).  Any output pointer may be
- * NULL. */
+ * stores + 8 log2(RHS chunks) + 32 (workgroups-per-CU limit, 0 = none),
+ * measured microseconds (0 if untuned).  Any output pointer may be NULL. */
 mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
                             float* us);
 

@@ -416,23 +416,29 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
                                                    const T* __restrict__ A,
                                                    const cplx<T>* __restrict__ in,
                                                    cplx<T>* __restrict__ out, int nblocks, DirFilter filt,
-                                                   int nt_out) {
+                                                   int nt_out, int nc) {
   int b = blockIdx.x;
+  int chunk = 0;
   if constexpr (XCD) {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
-    // contiguous range of the traversal so that neighbour re-reads hit its own L2.
+    // contiguous range of the traversal so that neighbour re-reads hit its
+    // own L2.  The right-hand sides are split into chunks of nc that are
+    // swept one after the other (the launch has nblocks workgroups per
+    // chunk), which shrinks the bytes per site that one sweep keeps in L2.
     const int per = (nblocks + 7) >> 3;
-    b = (b & 7) * per + (b >> 3);
+    const int j = b >> 3;
+    chunk = j / per;
+    b = (b & 7) * per + (j - chunk * per);
     if (b >= nblocks) return;
   }
-  const int groups = nrhs / R;
+  const int groups = nc / R;
   const long gid = (long)b * 256 + threadIdx.x;
   if (gid >= (long)g.V * groups) return;
   // Sites are visited in the order of the traversal table (tile by tile),
   // so that the eight neighbours of the sites in flight on one XCD are
   // mostly still in its L2; neighbour indices come from a per-site table.
   const int p = (int)(gid / groups);
-  const int k0 = (int)(gid - (long)p * groups) * R;
+  const int k0 = chunk * nc + (int)(gid - (long)p * groups) * R;
   const int site = order[p];
   const int4 n0 = g.nbr[2 * site], n1 = g.nbr[2 * site + 1];  // +x -x +y -y | +z -z +t -t
 
@@ -506,16 +512,23 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
   }
 }
 
+// chunks: RHS chunks swept in turn (nrhs / chunks must be a multiple of R);
+// lds: dynamic LDS reserved per workgroup (unused by the kernel) to cap the
+// number of workgroups resident on one CU.
 template <typename T, int R, int MODE, int OCC = 0>
 hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, const void* A, const void* in,
-                    void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}, int nt = 0) {
+                    void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}, int nt = 0,
+                    int chunks = 1, unsigned lds = 0) {
   if (!g.nbr || !order) return hipErrorInvalidValue;
-  const long threads = (long)g.V * (nrhs / R);
+  if (chunks < 1 || nrhs % chunks || (nrhs / chunks) % R) return hipErrorInvalidValue;
+  const int nc = nrhs / chunks;
+  const long threads = (long)g.V * (nc / R);
   const int nblocks = (int)((threads + 255) / 256);
-  const int grid = ((nblocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true, true, OCC>), dim3(grid), dim3(256), 0, s, g, nrhs, kappa, order,
-                     reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
-                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f, nt);
+  const long grid = (long)((nblocks + 7) / 8) * 8 * chunks;
+  if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true, true, OCC>), dim3((unsigned)grid), dim3(256), lds, s, g, nrhs,
+                     kappa, order, reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
+                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f, nt, nc);
   return hipGetLastError();
 }
 
@@ -530,18 +543,24 @@ hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const vo
     // component) for even Nrhs, one otherwise.
     if (R == 0) R = (nrhs % 2 == 0) ? 2 : 1;
     const bool occ4 = MODE == 0 && cfg && cfg->occ == 4;
-    const int nt = (cfg && cfg->R > 0) ? cfg->nt : 0;
+    const bool tuned = cfg && cfg->R > 0;
+    const int nt = tuned ? cfg->nt : 0;
+    int ch = tuned ? cfg->chunks : 1;
+    const unsigned lds = tuned ? cfg->lds : 0u;
+    if (R == 4 && nrhs % 4) R = 2;
+    if (R == 2 && nrhs % 2) R = 1;
+    if (ch < 1 || nrhs % ch || (nrhs / ch) % R) ch = 1;
     const DirFilter f;
     if constexpr (MODE == 0) {
       if (occ4) {
-        if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
-        if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
-        return launch_r<T, 1, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
+        if (R == 4) return launch_r<T, 4, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
+        if (R == 2) return launch_r<T, 2, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
+        return launch_r<T, 1, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
       }
     }
-    if (R == 4 && nrhs % 4 == 0) return launch_r<T, 4, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
-    if (R >= 2 && nrhs % 2 == 0) return launch_r<T, 2, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
-    return launch_r<T, 1, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt);
+    if (R == 4) return launch_r<T, 4, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
+    if (R == 2) return launch_r<T, 2, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
+    return launch_r<T, 1, MODE>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
   }
   return launch_r<T, 1, MODE>(g, order, kappa, U, A, in, out, nrhs, s);
 }

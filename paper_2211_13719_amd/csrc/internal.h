@@ -65,6 +65,9 @@ struct FineCfg {
   int curve = 0;               // tile order: 0 lexicographic, 1 Morton in (x, y, z) per t-row of tiles
   int occ = 0;                 // 0: compiler's register choice; 4: at least 4 wavefronts per SIMD
   int nt = 0;                  // 1: non-temporal output stores
+  int chunks = 1;              // RHS chunks swept one after the other (1, 2, 4)
+  int cap = 0;                 // 0: no limit; k: at most k workgroups per CU (via an LDS reservation)
+  unsigned lds = 0;            // dynamic LDS bytes per workgroup that realise cap (0 when cap is 0)
   const int* order = nullptr;  // traversal table of tile T (device)
   float us = 0.f;              // measured time of the choice
 };

@@ -1,14 +1,15 @@
 // Autotuner of the FP32 fine Wilson-clover kernel: for each requested Nrhs it
 // times launch configurations -- traversal tile and tile order, right-hand
-// sides per thread (1, 2, 4), register budget, ordinary or non-temporal
-// output stores -- on scratch fields of the context's lattice, by coordinate
-// descent in that order, and keeps the fastest for all later FP32 applies of
-// that Nrhs
+// sides per thread (1, 2, 4), RHS chunks swept in turn (1, 2, 4; the tiles
+// are scanned again if chunking wins), a cap on resident workgroups per CU,
+// register budget, ordinary or non-temporal output stores -- on scratch
+// fields of the context's lattice, by coordinate descent in that order, and
+// keeps the fastest for all later FP32 applies of that Nrhs
 // (the configurations compute bit-identical results: each output element
 // sees the same operations in the same order).  Choices can be persisted in
 // a plain text cache, one line per (device architecture, lattice, Nrhs):
 //
-//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <nt> <microseconds>
+//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <nt> <chunks> <cap> <microseconds>
 #include <algorithm>
 #include <array>
 #include <cstdio>
@@ -21,6 +22,21 @@
 using namespace mrhs;
 
 namespace {
+
+// Tuning input: uniform values in [-1, 1) from an integer hash of the index
+// (timing on zeros would understate the power draw, hence the clock drop, of
+// real data).
+__global__ void fill_hash(float* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32);
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    p[i] = (float)(h >> 8) * (2.0f / 16777216.0f) - 1.0f;
+  }
+}
 
 bool divides(const Geom& g, const int T[4]) {
   for (int m = 0; m < 4; ++m)
@@ -61,24 +77,43 @@ std::string arch_name(int dev) {
   return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
+// Dynamic LDS per workgroup that leaves room for at most cap resident
+// workgroups on one CU (0 if cap is 0 or the device cannot express it).
+unsigned cap_lds(int dev, int cap) {
+  if (cap <= 0) return 0;
+  int per_cu = 0, per_block = 0;
+  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0;
+  const unsigned lds = (unsigned)(per_cu / (cap + 1) + 1024);
+  if ((long)lds * cap > per_cu || (long)lds > per_block) return 0;
+  return lds;
+}
+
 bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int nrhs, FineCfg& out) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
-  char a[64];
-  int L[4], n, R, T[4], curve, occ, nt;
-  float us;
+  char line[512];
   bool found = false;
-  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n, &R,
-                     &T[0], &T[1], &T[2], &T[3], &curve, &occ, &nt, &us) == 15) {
+  while (std::fgets(line, sizeof(line), f)) {
+    char a[64];
+    int L[4], n, R, T[4], curve, occ, nt, ch, cap;
+    float us;
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n,
+                    &R, &T[0], &T[1], &T[2], &T[3], &curve, &occ, &nt, &ch, &cap, &us) != 17)
+      continue;  // lines of other formats are ignored
     if (arch == a && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] && L[3] == g.L[3] &&
         (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1) &&
-        (occ == 0 || occ == 4) && (nt == 0 || nt == 1)) {
+        (occ == 0 || occ == 4) && (nt == 0 || nt == 1) && (ch == 1 || ch == 2 || ch == 4) && nrhs % ch == 0 &&
+        (nrhs / ch) % R == 0 && cap >= 0 && cap <= 2) {
       out.R = R;
       for (int m = 0; m < 4; ++m) out.T[m] = T[m];
       out.curve = curve;
       out.occ = occ;
       out.nt = nt;
+      out.chunks = ch;
+      out.cap = cap;
       out.us = us;
       found = true;  // the last matching line wins
     }
@@ -91,8 +126,8 @@ void cache_append(const char* path, const std::string& arch, const Geom& g, int 
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2],
-               g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.nt, c.us);
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2],
+               g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.nt, c.chunks, c.cap, c.us);
   std::fclose(f);
 }
 
@@ -130,12 +165,17 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = hipMemsetAsync(in.p, 0, bytes, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(fill_hash, dim3(2048), dim3(256), 0, ctx->stream, static_cast<float*>(in.p), bytes / 4);
+    e = hipGetLastError();
+  }
   for (int i = 0; i < count && e == hipSuccess; ++i) {
     const int n = nrhs_list[i];
     FineCfg best;
     if (cache_lookup(cache_path, arch, ctx->g, n, best)) {
       best.order = fine_order_table(ctx, best.T, best.curve);
+      best.lds = cap_lds(ctx->device, best.cap);
+      if (best.cap && !best.lds) best.cap = 0;
       if (best.order) {
         ctx->fine_cfg[n] = best;
         continue;
@@ -166,27 +206,42 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
     };
     best.R = (n % 2 == 0) ? 2 : 1;
     best.us = 1e30f;
-    FineCfg base = best;
-    for (const auto& t : tile_candidates(ctx->g)) {
-      for (int curve : {0, 1}) {
-        FineCfg cfg = base;
-        for (int m = 0; m < 4; ++m) cfg.T[m] = t[m];
-        cfg.curve = curve;
-        e = time_cfg(cfg);
-        if (e != hipSuccess) break;
-        if (cfg.us < best.us) best = cfg;
+    auto scan_tiles = [&](const FineCfg& base) {
+      for (const auto& t : tile_candidates(ctx->g)) {
+        for (int curve : {0, 1}) {
+          FineCfg cfg = base;
+          for (int m = 0; m < 4; ++m) cfg.T[m] = t[m];
+          cfg.curve = curve;
+          e = time_cfg(cfg);
+          if (e != hipSuccess) return;
+          if (cfg.us < best.us) best = cfg;
+        }
       }
-      if (e != hipSuccess) break;
-    }
-    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
+    };
+    scan_tiles(best);
+    // stages: 0 RHS per thread, 1 RHS chunks, 2 workgroups per CU, 3 register budget, 4 store kind
+    for (int stage = 0; stage < 5 && e == hipSuccess; ++stage) {
       const FineCfg cur = best;
-      const std::vector<int> opts = stage == 0 ? std::vector<int>{1, 2, 4} : std::vector<int>{0, stage == 1 ? 4 : 1};
+      std::vector<int> opts;
+      if (stage == 0) opts = {1, 2, 4};
+      if (stage == 1) opts = {1, 2, 4};
+      if (stage == 2) opts = {0, 1, 2};
+      if (stage == 3) opts = {0, 4};
+      if (stage == 4) opts = {0, 1};
       for (int v : opts) {
         FineCfg cfg = cur;
         if (stage == 0) {
-          if (n % v || v == cur.R) continue;
+          if (n % v || v == cur.R || (n / cur.chunks) % v) continue;
           cfg.R = v;
         } else if (stage == 1) {
+          if (v == cur.chunks || n % v || (n / v) % cur.R) continue;
+          cfg.chunks = v;
+        } else if (stage == 2) {
+          if (v == cur.cap) continue;
+          cfg.cap = v;
+          cfg.lds = cap_lds(ctx->device, v);
+          if (v && !cfg.lds) continue;
+        } else if (stage == 3) {
           if (v == cur.occ) continue;
           cfg.occ = v;
         } else {
@@ -197,6 +252,8 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
         if (e != hipSuccess) break;
         if (cfg.us < best.us) best = cfg;
       }
+      // chunking changes the bytes per site a sweep keeps in L2: re-scan the tiles
+      if (stage == 1 && e == hipSuccess && best.chunks != cur.chunks) scan_tiles(best);
     }
     if (e == hipSuccess) {
       ctx->fine_cfg[n] = best;
@@ -221,7 +278,7 @@ mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread,
   if (rhs_per_thread) *rhs_per_thread = c.R;
   if (tile)
     for (int m = 0; m < 4; ++m) tile[m] = c.T[m];
-  if (curve) *curve = c.curve + 2 * (c.occ == 4) + 4 * c.nt;
+  if (curve) *curve = c.curve + 2 * (c.occ == 4) + 4 * c.nt + 8 * (c.chunks == 4 ? 2 : c.chunks == 2 ? 1 : 0) + 32 * c.cap;
   if (us) *us = c.us;
   return MRHS_OK;
 }

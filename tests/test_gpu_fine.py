@@ -196,7 +196,7 @@ def test_autotune_bitwise_and_cache(small, tmp_path):
     ctx.tune([1, 6, 12], cache)
     for n, (x, y0) in outs.items():
         R, tile, curve, us = ctx.get_tuning(n)
-        assert R in (1, 2, 4) and n % R == 0 and us > 0 and 0 <= curve < 8
+        assert R in (1, 2, 4) and n % R == 0 and us > 0 and 0 <= curve < 128
         assert all(t >= 1 and L % t == 0 for t, L in zip(tile, dims))
         y = torch.empty_like(x)
         ctx.dwc(y, x)
@@ -205,3 +205,39 @@ def test_autotune_bitwise_and_cache(small, tmp_path):
     assert sum(1 for l in lines if l.strip()) == 3
     ctx.tune([12], cache)  # served from the cache, no new line
     assert sum(1 for l in open(cache).read().split("\n") if l.strip()) == 3
+
+
+@pytest.mark.parametrize(
+    "R,tile,curve,occ,nt,chunks,cap",
+    [
+        (2, (2, 2, 2, 2), 0, 0, 0, 2, 0),
+        (1, (4, 4, 4, 8), 1, 4, 1, 4, 0),
+        (4, (8, 4, 4, 1), 0, 0, 0, 2, 2),
+        (2, (2, 2, 2, 8), 1, 0, 1, 1, 1),
+        (4, (1, 1, 1, 1), 0, 4, 0, 1, 2),
+    ],
+)
+def test_launch_configurations_bitwise(small, tmp_path, R, tile, curve, occ, nt, chunks, cap):
+    """Every launch configuration the tuner can pick -- RHS per thread, tile and
+    order, register budget, store kind, RHS chunks swept in turn, workgroups
+    per CU -- gives the default launch's result bit for bit (set through a
+    cache file, which the tuner reads without timing)."""
+    import torch
+
+    dims, U, A, ctx = small
+    n = 24
+    x = _dev(torch, synth.spinor_source(dims, n, 6100, np.complex64))
+    y0 = torch.empty_like(x)
+    ctx.dwc(y0, x)  # untuned default (or whatever an earlier test left): compare with FP32 oracle below
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "cfg.txt"
+    cache.write_text(f"{arch} {' '.join(map(str, dims))} {n} {R} {' '.join(map(str, tile))} {curve} {occ} {nt} "
+                     f"{chunks} {cap} 1.0\n")
+    ctx.tune([n], str(cache))
+    got = ctx.get_tuning(n)
+    assert got[0] == R and tuple(got[1]) == tile
+    assert got[2] & 1 == curve and bool(got[2] & 2) == (occ == 4) and bool(got[2] & 4) == bool(nt)
+    assert 1 << ((got[2] >> 3) & 3) == chunks
+    y = torch.empty_like(x)
+    ctx.dwc(y, x)
+    assert torch.equal(y, y0)
