@@ -13,7 +13,8 @@ workload shape (inputs resident in device memory, all synthetic and seeded):
                  FP64 block-orthonormalised, 4^4 then 2^4 aggregates): 6^4 and 3^4
                  coarse lattices, Nb = 32, Nrhs in 12, 24, 48, 64; FP32 vector ALU
                  and BF16 / FP16 matrix cores
-  intergrid      restrict, prolong, block-normalise 24^4 <-> 6^4 at Nrhs = 24, FP32
+  intergrid      restrict, prolong (FP32 vector ALU and BF16 matrix cores), block-normalise
+                 24^4 <-> 6^4 at Nrhs = 24, FP32 fields
   reductions     dot and norm of 24^4 fields at Nrhs = 24, FP64 sums
 
 The timed region holds exactly K steps, bracketed by device synchronisation.
@@ -53,6 +54,10 @@ HBM_PEAK_GBS = 8000.0
 
 FLOPS_DWC = 1920          # per site per RHS: hop 1320 + clover 552 + combine 48
 SOLVE_DIMS = (24, 24, 24, 128)
+# multigrid set-up and V-cycle of the solve workload (hyper-parameters, not from the paper)
+SOLVE_SETUP = dict(setup_iters=6, smooth_steps=20, adapt_iters=0)
+SOLVE_VC = dict(nu_pre=0, nu_post=6, coarsest_iters=64)
+SOLVE_RESTART, SOLVE_MAXIT = 8, 1000
 TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
 FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 
@@ -157,25 +162,25 @@ def run_solve(mrhs, torch, synth, nrhs_mrhs, mass, cache):
     t0 = time.perf_counter()
     for l in range(2):
         mg.set_basis(l, synth.gaussian_vectors(mg.volume[l], 16, mg.ncomp[l], 600 + l))
-    mg.setup(3, 8)
+    mg.setup(**SOLVE_SETUP, coarse_prec="bf16", **SOLVE_VC)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] solve setup {setup_s:.1f} s", file=sys.stderr, flush=True)
-    V = int(np.prod(SOLVE_DIMS))
-    vc = dict(nu_pre=0, nu_post=4, coarsest_iters=24)
+    vc = SOLVE_VC
     b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, nrhs_mrhs, 4000)).cuda()
     x = torch.zeros_like(b)
-    st = mg.solve(x, b, tol=1e-10, restart=8, max_iters=2000, use_graph=True, coarse_prec="bf16", **vc)
+    kw = dict(tol=1e-10, restart=SOLVE_RESTART, max_iters=SOLVE_MAXIT, check=False)
+    st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", **kw, **vc)
     mrhs_s = st["seconds_total"] / nrhs_mrhs
-    print(f"[bench] MRHS solve {st['seconds_total']:.2f} s, {st['iters']} iterations", file=sys.stderr, flush=True)
+    print(f"[bench] MRHS solve {st['seconds_total']:.2f} s, {st['iters']} iterations, "
+          f"{sum(st['converged'])}/{nrhs_mrhs} converged", file=sys.stderr, flush=True)
     # per-phase breakdown from a second, timed (graph-free) solve of the same batch
     x.zero_()
-    stt = mg.solve(x, b, tol=1e-10, restart=8, max_iters=2000, use_graph=False, timers=True, coarse_prec="bf16",
-                   **vc)
+    stt = mg.solve(x, b, use_graph=False, timers=True, coarse_prec="bf16", **kw, **vc)
     print(f"[bench] timed MRHS solve {stt['seconds_total']:.2f} s", file=sys.stderr, flush=True)
     b1 = b[:, :, :1].contiguous()
     x1 = torch.zeros_like(b1)
-    s1 = mg.solve(x1, b1, tol=1e-10, restart=8, max_iters=2000, use_graph=True, coarse_prec="f32", **vc)
+    s1 = mg.solve(x1, b1, use_graph=True, coarse_prec="f32", **kw, **vc)
     print(f"[bench] SRHS solve {s1['seconds_total']:.2f} s, {s1['iters']} iterations", file=sys.stderr, flush=True)
     out = {
         "workload": "24^3x128, smooth links U = exp(0.3 i H), csw 1.0, antiperiodic t, "
@@ -186,14 +191,17 @@ def run_solve(mrhs, torch, synth, nrhs_mrhs, mass, cache):
         "mrhs_s_per_rhs": round(mrhs_s, 4),
         "mrhs_iters": st["iters"],
         "mrhs_max_true_resid": max(st["rel_resid"]),
+        "mrhs_converged": int(sum(st["converged"])),
         "srhs_s_per_rhs": round(s1["seconds_total"], 4),
         "srhs_iters": s1["iters"],
         "srhs_true_resid": s1["rel_resid"][0],
+        "srhs_converged": int(s1["converged"][0]),
         "speedup": round(s1["seconds_total"] / mrhs_s, 3),
         "mrhs_phase_s": {k: round(v, 4) for k, v in stt["seconds_phase"].items()},
         "mrhs_total_timed_s": round(stt["seconds_total"], 4),
-        "config": "FP64 FGMRES(8), V-cycle nu_post 4, coarsest 24 MR steps; MRHS: BF16 coarse, graph; "
-                  "SRHS comparator: same solver, one RHS, FP32 coarse",
+        "config": f"FP64 FGMRES({SOLVE_RESTART}), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
+                  "levels and BF16 matrix-core restrict/prolong, graph replay; SRHS comparator: same solver, one "
+                  "RHS, FP32 coarse levels and FP32 intergrid",
         "sigma_min_8^4": mass.get("sigma_min"),
     }
     mg.close()
@@ -294,6 +302,9 @@ def main():
                 lambda: mg.restrict(0, y, fi)))
     ops.append((("prolong", N_INTER), ig_flops, V * (12 * 16 * 8 + 96 * N_INTER) + Vc1 * NB * N_INTER * 8,
                 lambda: mg.prolong(0, fo, y)))
+    ig_bytes_bf16 = V * (12 * 16 * 4 + 96 * N_INTER) + Vc1 * NB * N_INTER * 8
+    ops.append((("restrict_bf16", N_INTER), ig_flops, ig_bytes_bf16, lambda: mg.restrict(0, y, fi, prec="bf16")))
+    ops.append((("prolong_bf16", N_INTER), ig_flops, ig_bytes_bf16, lambda: mg.prolong(0, fo, y, prec="bf16")))
     ops.append((("block_normalise", N_INTER), 6 * V * 12 * N_INTER, 2 * V * 96 * N_INTER,
                 lambda: mg.block_normalise(0, fb)))
     ops.append((("dot", N_INTER), 8 * V * 12 * N_INTER, 2 * V * 96 * N_INTER, lambda: ctx.dot(fi, fo, out=dres)))
@@ -409,7 +420,11 @@ def main():
         else:
             mass = {"m0": 0.0, "kappa": 0.125, "sigma_min": None}
         print("[bench] solve ...", file=sys.stderr, flush=True)
-        result["solve"] = run_solve(mrhs, torch, synth, a.solve_nrhs, mass, cache)
+        try:
+            result["solve"] = run_solve(mrhs, torch, synth, a.solve_nrhs, mass, cache)
+        except Exception as exc:  # report the failure in the JSON line instead of losing the kernel results
+            result["solve"] = {"error": f"{type(exc).__name__}: {exc}"}
+            print(f"[bench] solve failed: {exc}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline()

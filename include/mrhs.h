@@ -291,13 +291,25 @@ typedef struct {
  * [V][12][nrhs]).  Needs the bases and coarse operators of every level.
  * Synchronises. */
 mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrhs, const mrhs_vcycle_params* vc);
-/* mrhs_mg_setup: from the starting vectors already set with
- * mrhs_mg_set_basis on every step (e.g. Gaussian), level by level:
- * setup_iters sweeps of smooth_steps MR steps on D x = 0 starting from the
- * vectors (which damps their high modes), column normalisation, block
- * orthonormalisation (FP64) and the Galerkin operator of the next level.
+typedef struct {
+  int32_t setup_iters;    /* smoothing sweeps per level, 0..100 */
+  int32_t smooth_steps;   /* MR steps per sweep, 0..1000 */
+  int32_t adapt_iters;    /* adaptive passes (below), 0..50 */
+  mrhs_vcycle_params vc;  /* cycle the adaptive passes use */
+} mrhs_setup_params;
+
+/* mrhs_mg_setup: near-null-space setup of the hierarchy (not specified by
+ * the paper).  From the starting vectors already set with mrhs_mg_set_basis
+ * on every step (e.g. Gaussian), level by level: setup_iters sweeps of
+ * smooth_steps MR steps on D x = 0 starting from the vectors (which damps
+ * their high modes), column normalisation, block orthonormalisation (FP64)
+ * and the Galerkin operator of the next level.  Then adapt_iters passes of
+ * inverse iteration with the hierarchy itself: on every level l, each
+ * vector becomes K v with K the V-cycle from level l down (an approximate
+ * inverse of D, so the low modes grow); the vectors are renormalised and
+ * re-orthonormalised and the next level rebuilt.
  * Synchronises. */
-mrhs_status mrhs_mg_setup(mrhs_mg mg, int32_t setup_iters, int32_t smooth_steps);
+mrhs_status mrhs_mg_setup(mrhs_mg mg, const mrhs_setup_params* params);
 /* mrhs_mg_solve: solves D x_k = b_k for the context's fine operator
  * D = A - kappa H (for the mass form D_m = D / (2 kappa) pass 2 kappa b), by
  * FGMRES(m) in FP64 with the V-cycle as preconditioner.  x: device FP64

@@ -53,5 +53,5 @@ from .mg import (  # noqa: F401
     coarse_apply_dir,
 )
 from .blas import dot, norm2  # noqa: F401
-from .lowprec import round_bf16, round_f16, column_scale, coarse_apply_lowprec  # noqa: F401
+from .lowprec import round_bf16, round_f16, column_scale, coarse_apply_lowprec, restrict_lowprec, prolong_lowprec  # noqa: F401
 from .solve import dwc_sparse, solve_ref, true_residual, sigma_min  # noqa: F401

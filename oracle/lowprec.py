@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .mg import coarse_apply
+from .mg import coarse_apply, prolong, restrict
 
 
 def round_bf16(x) -> np.ndarray:
@@ -58,3 +58,20 @@ def coarse_apply_lowprec(B, e, dims, fmt: str) -> np.ndarray:
         eq = _round_complex((e32 * sc.astype(np.float32)).astype(np.complex64), fmt)
         return coarse_apply(Bq, eq, dims) / sc
     return coarse_apply(Bq, _round_complex(e32, fmt), dims)
+
+
+def restrict_lowprec(basis, f, dims, block) -> np.ndarray:
+    """P^dag f (Sec. 5 project) with the basis and the fine field rounded to
+    BF16 as above (basis via its FP32 copy), products and sums exact (FP64):
+    what matrix-core BF16 operands with exact products compute, up to the
+    order of the FP32 accumulation."""
+    bq = _round_complex(np.asarray(basis, dtype=np.complex128).astype(np.complex64), "bf16")
+    fq = _round_complex(np.asarray(f, dtype=np.complex64), "bf16")
+    return restrict(bq, fq, dims, block)
+
+
+def prolong_lowprec(basis, y, dims, block) -> np.ndarray:
+    """P y (Sec. 5 promote) with basis and coarse field rounded to BF16, exact sums."""
+    bq = _round_complex(np.asarray(basis, dtype=np.complex128).astype(np.complex64), "bf16")
+    yq = _round_complex(np.asarray(y, dtype=np.complex64), "bf16")
+    return prolong(bq, yq, dims, block)

@@ -311,16 +311,27 @@ class Multigrid:
             raise ValueError("fields must share nrhs and dtype")
         return int(a.shape[2]), _prec_of(a)
 
-    def restrict(self, level: int, coarse, fine):
-        n, prec = self._pair(coarse, fine, level + 1, level)
+    def _ig_prec(self, prec, field_prec):
+        if prec is None:
+            return field_prec
+        if field_prec != F32:
+            raise ValueError("matrix-core intergrid operators take FP32 fields")
+        return _PREC_NAMES[prec]
+
+    def restrict(self, level: int, coarse, fine, prec=None):
+        """coarse = P^dag fine; prec "bf16" runs on the matrix cores (FP32 fields)."""
+        n, p = self._pair(coarse, fine, level + 1, level)
+        p = self._ig_prec(prec, p)
         self._check(lib.mrhs_restrict(self._h, level, C.c_void_p(coarse.data_ptr()), C.c_void_p(fine.data_ptr()), n,
-                                      prec))
+                                      p))
         return coarse
 
-    def prolong(self, level: int, fine, coarse):
-        n, prec = self._pair(fine, coarse, level, level + 1)
+    def prolong(self, level: int, fine, coarse, prec=None):
+        """fine = P coarse; prec "bf16" runs on the matrix cores (FP32 fields)."""
+        n, p = self._pair(fine, coarse, level, level + 1)
+        p = self._ig_prec(prec, p)
         self._check(lib.mrhs_prolong(self._h, level, C.c_void_p(fine.data_ptr()), C.c_void_p(coarse.data_ptr()), n,
-                                     prec))
+                                     p))
         return fine
 
     def block_normalise(self, level: int, fields, norms=None):
@@ -364,10 +375,14 @@ class Multigrid:
         v.coarse_prec = _PREC_NAMES[coarse_prec]
         return v
 
-    def setup(self, setup_iters: int = 3, smooth_steps: int = 8):
-        """Refine the basis vectors already set on every step (inverse-iteration-like
-        smoothing of D x = 0), block-orthonormalise them and build all coarse operators."""
-        self._check(lib.mrhs_mg_setup(self._h, int(setup_iters), int(smooth_steps)))
+    def setup(self, setup_iters: int = 3, smooth_steps: int = 8, adapt_iters: int = 0, **vc):
+        """Refine the basis vectors already set on every step (smoothing of D x = 0),
+        block-orthonormalise them and build all coarse operators; then adapt_iters
+        passes of inverse iteration v <- K v with K the hierarchy's own V-cycle (vc options)."""
+        p = _lib.SetupParams()
+        p.setup_iters, p.smooth_steps, p.adapt_iters = int(setup_iters), int(smooth_steps), int(adapt_iters)
+        p.vc = self._vc(**vc)
+        self._check(lib.mrhs_mg_setup(self._h, C.byref(p)))
 
     def precondition(self, z, v, **vc):
         """z = V-cycle(v) for FP32 fine fields (V, 12, N)."""

@@ -62,7 +62,7 @@ SIGNATURES = {
     "mrhs_mg_build_coarse": (_i32, [_vp, _i32]),
     "mrhs_coarse_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
     "mrhs_mg_precondition": (_i32, [_vp, _vp, _vp, _i32, _vp]),
-    "mrhs_mg_setup": (_i32, [_vp, _i32, _i32]),
+    "mrhs_mg_setup": (_i32, [_vp, _vp]),
     "mrhs_mg_solve": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mrhs_tune": (_i32, [_vp, C.POINTER(_i32), _i32, C.c_char_p]),
     "mrhs_get_tuning": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(C.c_float)]),
@@ -71,6 +71,10 @@ SIGNATURES = {
 
 class VcycleParams(C.Structure):
     _fields_ = [("nu_pre", _i32), ("nu_post", _i32), ("coarsest_iters", _i32), ("coarse_prec", _i32)]
+
+
+class SetupParams(C.Structure):
+    _fields_ = [("setup_iters", _i32), ("smooth_steps", _i32), ("adapt_iters", _i32), ("vc", VcycleParams)]
 
 
 class SolveParams(C.Structure):

@@ -1,0 +1,225 @@
+// Restriction and prolongation on the matrix cores (paper Sec. 5, with
+// n_v = 16 basis vectors per chirality): with Nrhs right-hand sides both are,
+// per (aggregate A, chirality chi), complex GEMMs
+//
+//   restrict:  Y = W^dag F     (16 x R) = (16 x R_A)^dag (R_A x Nrhs)
+//   prolong:   F = W Y         (R_A x Nrhs) = (R_A x 16) (16 x Nrhs)
+//
+// where R_A = (sites of A) x (h components of chi) and W holds the 16 basis
+// vectors restricted to (A, chi).  They run as v_mfma_f32_32x32x16_bf16 with
+// FP32 accumulation on the real form of the complex product:
+//
+//   restrict: rows 0..15 of the 32 x 32 output are Re y_i, rows 16..31 Im y_i,
+//             A'[i][(r, re)] = Re w_ri, A'[i][(r, im)] = Im w_ri,
+//             A'[16 + i][(r, re)] = -Im w_ri, A'[16 + i][(r, im)] = Re w_ri,
+//             B'[(r, re|im)][k] = Re|Im f_rk;
+//   prolong:  rows 0..15 are Re f_r, rows 16..31 Im f_r of 16 consecutive r,
+//             A'[r][(i, re)] = Re w_ri, A'[r][(i, im)] = -Im w_ri,
+//             A'[16 + r][(i, re)] = Im w_ri, A'[16 + r][(i, im)] = Re w_ri,
+//             B'[(i, re|im)][k] = Re|Im y_ik.
+//
+// With the MFMA layouts A[l % 32][8 (l / 32) + q], B[8 (l / 32) + q][l % 32]
+// and D[8 (p / 4) + 4 (l / 32) + p % 4][l % 32] (accumulator p), the real and
+// imaginary part of one output sit in accumulators p and p + 8 of the same
+// lane, so every store is one complex value and 32 lanes write 256
+// contiguous bytes.  Rows r of (A, chi) are ordered component-major,
+// r = c * (sites of A) + l, so a lane's consecutive rows are consecutive
+// sites of one component.
+//
+// The basis is a BF16 copy of the FP32 basis (round to nearest even, one
+// 32-bit word per complex value, re in the low half); the fine and coarse
+// fields stay FP32 in memory and are rounded to BF16 on the fly by the
+// hardware conversion (round to nearest even).  Products of BF16 values are
+// exact in FP32, so the only other rounding is the FP32 accumulation.
+#include "agg.h"
+#include "internal.h"
+#include "rounding.h"
+
+namespace mrhs {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
+
+constexpr int kNV = 16;
+
+// Site of offset l + j inside aggregate A (consecutive offsets are consecutive
+// x when the aggregate's x-extent is a multiple of 4 and l is too).
+__device__ __forceinline__ int agg_site_j(const AggGeom& a, int A, int l, int j, int s0, bool fast) {
+  return fast ? s0 + j : agg_site(a, A, l + j);
+}
+
+__device__ __forceinline__ bf16x8 to_bf16(const float (&x)[8]) {
+  bf16x8 v;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = (__bf16)x[q];
+  return v;
+}
+
+// One workgroup per (aggregate, chirality, 32-column tile); its four
+// wavefronts take a quarter of the rows each and are summed through LDS in a
+// fixed order.
+__global__ __launch_bounds__(256) void restrict_bf16_kernel(AggGeom a, int h, int nrhs, int ntile,
+                                                            const unsigned* __restrict__ W,
+                                                            const float2* __restrict__ f, float2* __restrict__ y) {
+  __shared__ float red[3][64][16];
+  const int bid = blockIdx.x;
+  const int tile = bid % ntile;
+  const int chi = (bid / ntile) & 1;
+  const int A = bid / ntile >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 31, g = lane >> 5;
+  const int ncomp = 2 * h;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  const int per_c = nsa / 8;  // MFMA steps per component
+  const int steps = h * per_c;
+  const int s0 = wave * steps / 4, s1 = (wave + 1) * steps / 4;
+  const int k = tile * 32 + m;
+  const bool kin = k < nrhs;
+  const int i = m & 15;
+  const bool imrow = m >= 16;
+  const bool fast = (a.b[0] & 3) == 0;
+  f32x16 acc = {};
+  for (int s = s0; s < s1; ++s) {
+    const int c = s / per_c;
+    const int l0 = (s - c * per_c) * 8 + 4 * g;
+    const int site0 = agg_site(a, A, l0);
+    u32x4 av;
+    float bv[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int site = agg_site_j(a, A, l0, j, site0, fast);
+      const size_t row = (size_t)site * ncomp + chi * h + c;
+      const unsigned w = W[row * kNV + i];
+      av[j] = imrow ? (((w >> 16) ^ 0x8000u) | (w << 16)) : w;
+      const float2 v = kin ? f[row * nrhs + k] : make_float2(0.f, 0.f);
+      bv[2 * j] = v.x;
+      bv[2 * j + 1] = v.y;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), to_bf16(bv), acc, 0, 0, 0);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int p = 0; p < 16; ++p) red[wave - 1][lane][p] = acc[p];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int p = 0; p < 16; ++p) acc[p] += red[w][lane][p];
+    if (kin) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int row = 8 * (p / 4) + 4 * g + (p % 4);
+        y[((size_t)A * 2 * kNV + chi * kNV + row) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
+      }
+    }
+  }
+}
+
+// One workgroup per (aggregate, chirality, 32-column tile); the coarse
+// values are loaded once, and the four wavefronts walk the 16-row tiles of
+// the aggregate in turn.
+__global__ __launch_bounds__(256) void prolong_bf16_kernel(AggGeom a, int h, int nrhs, int ntile,
+                                                           const unsigned* __restrict__ W,
+                                                           const float2* __restrict__ y, float2* __restrict__ f) {
+  const int bid = blockIdx.x;
+  const int tile = bid % ntile;
+  const int chi = (bid / ntile) & 1;
+  const int A = bid / ntile >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 31, g = lane >> 5;
+  const int ncomp = 2 * h;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  const int k = tile * 32 + m;
+  const bool kin = k < nrhs;
+  const bool imrow = m >= 16;
+  const bool fast = (a.b[0] & 3) == 0;
+  bf16x8 B[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    float bv[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = st * 8 + 4 * g + j;
+      const float2 v = kin ? y[((size_t)A * 2 * kNV + chi * kNV + i) * nrhs + k] : make_float2(0.f, 0.f);
+      bv[2 * j] = v.x;
+      bv[2 * j + 1] = v.y;
+    }
+    B[st] = to_bf16(bv);
+  }
+  const int ntr = h * nsa / 16;
+  for (int t = wave; t < ntr; t += 4) {
+    const int r0 = t * 16;
+    const int c = r0 / nsa;
+    const int l0 = r0 - c * nsa;
+    // A operand: row r0 + (m & 15)
+    const int lr = l0 + (m & 15);
+    const size_t arow = (size_t)agg_site(a, A, lr) * ncomp + chi * h + c;
+    f32x16 acc = {};
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      u32x4 w = *reinterpret_cast<const u32x4*>(W + arow * kNV + st * 8 + 4 * g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = imrow ? ((w[j] >> 16) | (w[j] << 16)) : (w[j] ^ 0x80000000u);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[st], acc, 0, 0, 0);
+    }
+    if (kin) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int lb = l0 + 8 * half + 4 * g;
+        const int sb = agg_site(a, A, lb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int site = agg_site_j(a, A, lb, j, sb, fast);
+          const int p = 4 * half + j;
+          f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
+        }
+      }
+    }
+  }
+}
+
+// FP32 basis [site][ncomp][16] complex -> BF16 pairs (round to nearest even).
+__global__ __launch_bounds__(256) void pack_basis_bf16_kernel(const float2* __restrict__ in, unsigned* __restrict__ out,
+                                                              long n) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const float2 v = in[e];
+  out[e] = (unsigned)bf16_rne_bits(__float_as_uint(v.x)) | ((unsigned)bf16_rne_bits(__float_as_uint(v.y)) << 16);
+}
+
+}  // namespace
+
+bool intergrid_mfma_supported(const AggGeom& a, int h, int nv) {
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  return nv == kNV && h >= 1 && nsa % 16 == 0;
+}
+
+hipError_t launch_pack_basis_bf16(const void* basis32, void* out, long ncomplex, hipStream_t s) {
+  hipLaunchKernelGGL(pack_basis_bf16_kernel, dim3((unsigned)((ncomplex + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const float2*>(basis32), static_cast<unsigned*>(out), ncomplex);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_bf16(const AggGeom& a, int h, int nrhs, const void* Wbf16, const void* f, void* y,
+                                hipStream_t s) {
+  if (!intergrid_mfma_supported(a, h, kNV)) return hipErrorInvalidValue;
+  const int ntile = (nrhs + 31) / 32;
+  hipLaunchKernelGGL(restrict_bf16_kernel, dim3((unsigned)(a.Vc * 2 * ntile)), dim3(256), 0, s, a, h, nrhs, ntile,
+                     static_cast<const unsigned*>(Wbf16), static_cast<const float2*>(f), static_cast<float2*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_bf16(const AggGeom& a, int h, int nrhs, const void* Wbf16, const void* y, void* f,
+                               hipStream_t s) {
+  if (!intergrid_mfma_supported(a, h, kNV)) return hipErrorInvalidValue;
+  const int ntile = (nrhs + 31) / 32;
+  hipLaunchKernelGGL(prolong_bf16_kernel, dim3((unsigned)(a.Vc * 2 * ntile)), dim3(256), 0, s, a, h, nrhs, ntile,
+                     static_cast<const unsigned*>(Wbf16), static_cast<const float2*>(y), static_cast<float2*>(f));
+  return hipGetLastError();
+}
+
+}  // namespace mrhs

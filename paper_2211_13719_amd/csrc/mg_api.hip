@@ -2,6 +2,7 @@
 // orthonormalisation, restriction / prolongation / block normalisation
 // (paper Sec. 5), coarse stencil blocks by Galerkin projection and the coarse
 // operator apply (paper Sec. 6).
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -102,6 +103,24 @@ mrhs_status refresh_basis32(mrhs_mg mg, int level) {
   if (st != MRHS_OK) return st;
   MRHS_HIP(ctx, launch_convert_f64_to_f32(static_cast<const double*>(L.basis64.p), static_cast<float*>(L.basis32.p),
                                           2 * n, ctx->stream));
+  L.bf16_ok = false;
+  return MRHS_OK;
+}
+
+mrhs_status ensure_basis_bf16(mrhs_mg mg, int from) {
+  mrhs_ctx ctx = mg->ctx;
+  bool packed = false;
+  for (int l = std::max(from, 0); l + 1 < mg->nlevels; ++l) {
+    LevelData& L = mg->lv[l];
+    if (L.bf16_ok || !L.have_basis || !intergrid_mfma_supported(L.agg, L.ncomp / 2, L.nv)) continue;
+    const long n = (long)L.g.V * L.ncomp * L.nv;
+    mrhs_status st = ensure(ctx, L.Wbf16, (size_t)n * 4);
+    if (st != MRHS_OK) return st;
+    MRHS_HIP(ctx, launch_pack_basis_bf16(L.basis32.p, L.Wbf16.p, n, ctx->stream));
+    L.bf16_ok = true;
+    packed = true;
+  }
+  if (packed) MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return MRHS_OK;
 }
 
@@ -166,7 +185,7 @@ void mrhs_mg_destroy(mrhs_mg mg) {
   DevGuard dg(mg->ctx->device);
   (void)hipStreamSynchronize(mg->ctx->stream);
   for (auto& L : mg->lv) {
-    Buffer* bufs[] = {&L.basis64, &L.basis32, &L.B64, &L.BT32, &L.BT64, &L.Bbf16, &L.Bf16, &L.Bf32p};
+    Buffer* bufs[] = {&L.basis64, &L.basis32, &L.Wbf16, &L.B64, &L.BT32, &L.BT64, &L.Bbf16, &L.Bf16, &L.Bf32p};
     for (Buffer* b : bufs) release(*b);
   }
   release(mg->tmpA);
@@ -265,11 +284,19 @@ mrhs_status mrhs_restrict(mrhs_mg mg, int32_t level, void* coarse, const void* f
   if (st != MRHS_OK) return st;
   st = check_fields(ctx, coarse, fine, nrhs);
   if (st != MRHS_OK) return st;
-  if (prec != MRHS_F64 && prec != MRHS_F32)
-    return fail(ctx, MRHS_ERR_UNSUPPORTED, "restrict precision %s not supported", prec_str(prec));
   LevelData& L = mg->lv[level];
+  if (prec == MRHS_BF16 && !intergrid_mfma_supported(L.agg, L.ncomp / 2, L.nv))
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "BF16 restrict needs n_v = 16 and aggregates of a multiple of 16 sites");
+  if (prec != MRHS_F64 && prec != MRHS_F32 && prec != MRHS_BF16)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "restrict precision %s not supported", prec_str(prec));
   if (!L.have_basis) return fail(ctx, MRHS_ERR_STATE, "basis of level %d not set", level);
   DevGuard dg(ctx->device);
+  if (prec == MRHS_BF16) {
+    st = ensure_basis_bf16(mg, level);
+    if (st != MRHS_OK) return st;
+    MRHS_HIP(ctx, launch_restrict_bf16(L.agg, L.ncomp / 2, nrhs, L.Wbf16.p, fine, coarse, ctx->stream));
+    return MRHS_OK;
+  }
   MRHS_HIP(ctx, launch_restrict(prec == MRHS_F64, L.agg, L.ncomp / 2, L.nv, nrhs,
                                 prec == MRHS_F64 ? L.basis64.p : L.basis32.p, fine, coarse, ctx->stream));
   return MRHS_OK;
@@ -282,11 +309,19 @@ mrhs_status mrhs_prolong(mrhs_mg mg, int32_t level, void* fine, const void* coar
   if (st != MRHS_OK) return st;
   st = check_fields(ctx, fine, coarse, nrhs);
   if (st != MRHS_OK) return st;
-  if (prec != MRHS_F64 && prec != MRHS_F32)
-    return fail(ctx, MRHS_ERR_UNSUPPORTED, "prolong precision %s not supported", prec_str(prec));
   LevelData& L = mg->lv[level];
+  if (prec == MRHS_BF16 && !intergrid_mfma_supported(L.agg, L.ncomp / 2, L.nv))
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "BF16 prolong needs n_v = 16 and aggregates of a multiple of 16 sites");
+  if (prec != MRHS_F64 && prec != MRHS_F32 && prec != MRHS_BF16)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "prolong precision %s not supported", prec_str(prec));
   if (!L.have_basis) return fail(ctx, MRHS_ERR_STATE, "basis of level %d not set", level);
   DevGuard dg(ctx->device);
+  if (prec == MRHS_BF16) {
+    st = ensure_basis_bf16(mg, level);
+    if (st != MRHS_OK) return st;
+    MRHS_HIP(ctx, launch_prolong_bf16(L.agg, L.ncomp / 2, nrhs, L.Wbf16.p, coarse, fine, ctx->stream));
+    return MRHS_OK;
+  }
   MRHS_HIP(ctx, launch_prolong(prec == MRHS_F64, L.agg, L.ncomp / 2, L.nv, nrhs,
                                prec == MRHS_F64 ? L.basis64.p : L.basis32.p, coarse, fine, ctx->stream));
   return MRHS_OK;

@@ -15,6 +15,10 @@ struct LevelData {
   AggGeom agg{};
   Buffer basis64, basis32;
   bool have_basis = false;
+  // BF16 copy of basis32 for the matrix-core intergrid kernels (n_v = 16),
+  // built on demand and dropped whenever basis32 changes
+  Buffer Wbf16;
+  bool bf16_ok = false;
   // stencil blocks (levels >= 1): FP64 master [site][9][i][j], transposed
   // copies [site][9][j][i] for the vector-ALU kernels, MFMA packs
   Buffer B64, BT32, BT64, Bbf16, Bf16, Bf32p;
@@ -41,6 +45,19 @@ mrhs_status refresh_blocks(mrhs_mg mg, int level);
 // per-RHS FP16 scales and their reduction words (zeroed when first allocated)
 mrhs_status ensure_colscale(mrhs_mg mg);
 mrhs_status refresh_basis32(mrhs_mg mg, int level);
+// Builds the BF16 basis copy of every level >= from (where the matrix-core
+// intergrid kernels apply) unless current; synchronises the context stream.
+mrhs_status ensure_basis_bf16(mrhs_mg mg, int from);
+// basis32 of `level` was modified in place: drop its BF16 copy
+inline void basis32_changed(mrhs_mg mg, int level) { mg->lv[level].bf16_ok = false; }
+
+// intergrid_mfma.hip (n_v = 16, FP32 fields, BF16 basis and operands, FP32 accumulation)
+bool intergrid_mfma_supported(const AggGeom& a, int h, int nv);
+hipError_t launch_pack_basis_bf16(const void* basis32, void* out, long ncomplex, hipStream_t s);
+hipError_t launch_restrict_bf16(const AggGeom& a, int h, int nrhs, const void* Wbf16, const void* f, void* y,
+                                hipStream_t s);
+hipError_t launch_prolong_bf16(const AggGeom& a, int h, int nrhs, const void* Wbf16, const void* y, void* f,
+                               hipStream_t s);
 
 // coarse_mfma.hip
 bool mfma_supported(int nb);

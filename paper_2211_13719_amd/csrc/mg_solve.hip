@@ -54,6 +54,9 @@ hipError_t launch_inv_sqrt(const double* q, double* sdev, int nrhs, double f, hi
 hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long n, hipStream_t s);
 hipError_t launch_add_f32(void* y, const void* x, long n, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+size_t col_gram_scratch_bytes();
+hipError_t launch_col_gram(const void* v, long rows, int nv, void* scratch, void* g, hipStream_t s);
+hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipStream_t s);
 
 enum Phase { kFine = 0, kRestrict, kProlong, kCoarse, kPhases };
 
@@ -71,6 +74,7 @@ struct SolverState {
   int n = 0;                     // right-hand sides the level buffers hold
   Buffer lb[MRHS_MAX_LEVELS], lx[MRHS_MAX_LEVELS], lr[MRHS_MAX_LEVELS], lp[MRHS_MAX_LEVELS];
   Buffer alpha, part, scl, coef, qn;
+  Buffer gpart, gmat, gT;  // column Gram matrix (setup)
   // outer Krylov
   int m = 0, on = 0;
   Buffer V64, Z32, w64, t64, r64;
@@ -93,7 +97,8 @@ void mg_solver_release(mrhs_mg mg) {
     release(st->lr[l]);
     release(st->lp[l]);
   }
-  Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->V64, &st->Z32, &st->w64, &st->t64, &st->r64};
+  Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->gpart, &st->gmat, &st->gT,
+                 &st->V64, &st->Z32, &st->w64, &st->t64, &st->r64};
   for (Buffer* x : b) release(*x);
   for (auto& gs : st->graphs)
     if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
@@ -235,16 +240,20 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
     if (e != hipSuccess) return e;
   }
   LevelData& L = mg->lv[l];
+  // BF16 coarse levels take the BF16 matrix-core intergrid kernels where they apply
+  const bool ig16 = cp == MRHS_BF16 && L.bf16_ok;
   {
     PhaseMark pm(st, kRestrict);
-    e = launch_restrict(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, r, st->lb[l + 1].p, st->stream);
+    e = ig16 ? launch_restrict_bf16(L.agg, L.ncomp / 2, n, L.Wbf16.p, r, st->lb[l + 1].p, st->stream)
+             : launch_restrict(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, r, st->lb[l + 1].p, st->stream);
     if (e != hipSuccess) return e;
   }
   e = vcycle(mg, st, l + 1, n, vc);
   if (e != hipSuccess) return e;
   {
     PhaseMark pm(st, kProlong);
-    e = launch_prolong(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, st->lx[l + 1].p, p, st->stream);
+    e = ig16 ? launch_prolong_bf16(L.agg, L.ncomp / 2, n, L.Wbf16.p, st->lx[l + 1].p, p, st->stream)
+             : launch_prolong(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, st->lx[l + 1].p, p, st->stream);
     if (e != hipSuccess) return e;
   }
   PhaseMark pm(st, ph);
@@ -332,6 +341,82 @@ mrhs_status join_ctx_stream(mrhs_mg mg, SolverState* st) {
   return MRHS_OK;
 }
 
+// Orthonormalises the n <= 16 columns of an FP32 field [rows][n] as a whole
+// (Cholesky QR applied twice: Gram matrix in FP64 on the device, Cholesky
+// and triangular inverse on the host, v <- v R^-1 on the device), so that
+// repeated smoothing or inverse iteration of a set of test vectors is a
+// subspace iteration and the set keeps n independent directions.  Falls back
+// to normalising each column when the Gram matrix is numerically singular.
+mrhs_status orthonormalise_columns(mrhs_mg mg, SolverState* st, void* v, long rows, int n) {
+  mrhs_ctx ctx = mg->ctx;
+  hipStream_t ss = st->stream;
+  mrhs_status s = ensure(ctx, st->gpart, col_gram_scratch_bytes());
+  if (s == MRHS_OK) s = ensure(ctx, st->gmat, 256 * sizeof(double2));
+  if (s == MRHS_OK) s = ensure(ctx, st->gT, 256 * sizeof(float2));
+  if (s != MRHS_OK) return s;
+  for (int pass = 0; pass < 2; ++pass) {
+    double2 G[256];
+    SOLVER_HIP(launch_col_gram(v, rows, n, st->gpart.p, st->gmat.p, ss));
+    SOLVER_HIP(hipMemcpyAsync(G, st->gmat.p, sizeof(G), hipMemcpyDeviceToHost, ss));
+    SOLVER_HIP(hipStreamSynchronize(ss));
+    // G = R^dag R, R upper triangular with real positive diagonal
+    std::complex<double> R[16][16] = {}, Ri[16][16] = {};
+    auto g = [&](int a, int b) { return std::complex<double>(G[16 * a + b].x, G[16 * a + b].y); };
+    bool ok = true;
+    for (int j = 0; j < n && ok; ++j) {
+      double d = g(j, j).real();
+      for (int k = 0; k < j; ++k) d -= std::norm(R[k][j]);
+      if (!(d > 1e-20 * g(j, j).real()) || !(d > 0.0)) {
+        ok = false;
+        break;
+      }
+      R[j][j] = std::sqrt(d);
+      for (int i = j + 1; i < n; ++i) {
+        std::complex<double> z = g(j, i);
+        for (int k = 0; k < j; ++k) z -= std::conj(R[k][j]) * R[k][i];
+        R[j][i] = z / R[j][j];
+      }
+    }
+    if (!ok) {
+      SOLVER_HIP(launch_dot(0, 1, v, v, rows, n, st->qn.p, st->part.p, ss));
+      SOLVER_HIP(launch_inv_sqrt(static_cast<const double*>(st->qn.p), static_cast<double*>(st->scl.p), n, 1.0, ss));
+      SOLVER_HIP(launch_scale_cols(0, v, v, static_cast<const double*>(st->scl.p), rows, n, ss));
+      return MRHS_OK;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      Ri[i][i] = 1.0 / R[i][i];
+      for (int j = i + 1; j < n; ++j) {
+        std::complex<double> z = 0.0;
+        for (int k = i; k < j; ++k) z += Ri[i][k] * R[k][j];
+        Ri[i][j] = -z / R[j][j];
+      }
+    }
+    float2 T[256];
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b)
+        T[16 * a + b] = (a < n && b < n) ? make_float2((float)Ri[a][b].real(), (float)Ri[a][b].imag())
+                                         : make_float2(0.f, 0.f);
+    SOLVER_HIP(hipMemcpyAsync(st->gT.p, T, sizeof(T), hipMemcpyHostToDevice, ss));
+    SOLVER_HIP(launch_col_transform(v, rows, n, st->gT.p, ss));
+    SOLVER_HIP(hipStreamSynchronize(ss));  // T lives on this stack frame
+  }
+  return MRHS_OK;
+}
+
+// FP64 copy of level l's FP32 basis, block orthonormalisation and the
+// Galerkin operator of level l + 1.
+mrhs_status rebuild_next(mrhs_mg mg, SolverState* st, int l) {
+  mrhs_ctx ctx = mg->ctx;
+  LevelData& L = mg->lv[l];
+  const size_t cnt = (size_t)L.g.V * L.ncomp * L.nv;
+  SOLVER_HIP(launch_convert_f32_to_f64(static_cast<const float*>(L.basis32.p), static_cast<double*>(L.basis64.p),
+                                       2 * cnt, st->stream));
+  SOLVER_HIP(hipStreamSynchronize(st->stream));
+  mrhs_status s = mrhs_mg_block_orthonormalise(mg, l);
+  if (s != MRHS_OK) return s;
+  return mrhs_mg_build_coarse(mg, l + 1);
+}
+
 }  // namespace
 }  // namespace mrhs
 
@@ -353,7 +438,8 @@ mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrh
   if (s != MRHS_OK) return s;
   st->timing = false;
   st->evused = 0;
-  s = join_ctx_stream(mg, st);
+  if (vc->coarse_prec == MRHS_BF16) s = ensure_basis_bf16(mg, 0);
+  if (s == MRHS_OK) s = join_ctx_stream(mg, st);
   if (s != MRHS_OK) return s;
   const size_t bytes = (size_t)level_rows(mg, 0) * nrhs * 8;
   SOLVER_HIP(hipMemcpyAsync(st->lb[0].p, v, bytes, hipMemcpyDeviceToDevice, st->stream));
@@ -364,12 +450,19 @@ mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrh
   return MRHS_OK;
 }
 
-mrhs_status mrhs_mg_setup(mrhs_mg mg, int32_t setup_iters, int32_t smooth_steps) {
+mrhs_status mrhs_mg_setup(mrhs_mg mg, const mrhs_setup_params* prm) {
   if (!mg) return MRHS_ERR_INVALID_ARG;
   mrhs_ctx ctx = mg->ctx;
+  if (!prm) return fail(ctx, MRHS_ERR_INVALID_ARG, "null parameters");
+  const int setup_iters = prm->setup_iters, smooth_steps = prm->smooth_steps, adapt_iters = prm->adapt_iters;
   if (!ctx->have_gauge || !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "fine operator not set");
-  if (setup_iters < 0 || smooth_steps < 0 || setup_iters > 100 || smooth_steps > 1000)
+  if (setup_iters < 0 || smooth_steps < 0 || setup_iters > 100 || smooth_steps > 1000 || adapt_iters < 0 ||
+      adapt_iters > 50)
     return fail(ctx, MRHS_ERR_INVALID_ARG, "setup iteration counts out of range");
+  if (adapt_iters > 0) {
+    mrhs_status sv = check_vc(mg, &prm->vc);
+    if (sv != MRHS_OK) return sv;
+  }
   for (int l = 0; l + 1 < mg->nlevels; ++l)
     if (!mg->lv[l].have_basis) return fail(ctx, MRHS_ERR_STATE, "starting vectors of level %d not set", l);
   SolverState* st;
@@ -398,19 +491,33 @@ mrhs_status mrhs_mg_setup(mrhs_mg mg, int32_t setup_iters, int32_t smooth_steps)
       SOLVER_HIP(hipMemcpyAsync(st->scl.p, minus.data(), n * 8, hipMemcpyHostToDevice, ss));
       SOLVER_HIP(launch_scale_cols(0, r, r, static_cast<const double*>(st->scl.p), rows, n, ss));
       SOLVER_HIP(mr_steps(mg, st, l, v, r, p, n, smooth_steps, MRHS_F32));
-      SOLVER_HIP(launch_dot(0, 1, v, v, rows, n, st->qn.p, st->part.p, ss));
-      SOLVER_HIP(launch_inv_sqrt(static_cast<const double*>(st->qn.p), static_cast<double*>(st->scl.p), n, 1.0, ss));
-      SOLVER_HIP(launch_scale_cols(0, v, v, static_cast<const double*>(st->scl.p), rows, n, ss));
       SOLVER_HIP(hipStreamSynchronize(ss));  // the host array `minus` is reused next sweep
+      s = orthonormalise_columns(mg, st, v, rows, n);
+      if (s != MRHS_OK) return s;
     }
-    const size_t cnt = (size_t)L.g.V * L.ncomp * L.nv;
-    SOLVER_HIP(launch_convert_f32_to_f64(static_cast<const float*>(L.basis32.p), static_cast<double*>(L.basis64.p),
-                                         2 * cnt, ss));
-    SOLVER_HIP(hipStreamSynchronize(ss));
-    s = mrhs_mg_block_orthonormalise(mg, l);
+    s = rebuild_next(mg, st, l);
     if (s != MRHS_OK) return s;
-    s = mrhs_mg_build_coarse(mg, l + 1);
-    if (s != MRHS_OK) return s;
+  }
+  // adaptive passes: inverse iteration v <- K v on every level, K the V-cycle
+  // from that level down (an approximate inverse of D, so the low modes grow)
+  for (int a = 0; a < adapt_iters; ++a) {
+    for (int l = 0; l + 1 < mg->nlevels; ++l) {
+      LevelData& L = mg->lv[l];
+      const int n = L.nv;
+      const long rows = level_rows(mg, l);
+      void* v = L.basis32.p;
+      if (prm->vc.coarse_prec == MRHS_BF16) {
+        s = ensure_basis_bf16(mg, l);
+        if (s != MRHS_OK) return s;
+      }
+      SOLVER_HIP(hipMemcpyAsync(st->lb[l].p, v, (size_t)rows * n * 8, hipMemcpyDeviceToDevice, ss));
+      SOLVER_HIP(vcycle(mg, st, l, n, prm->vc));
+      SOLVER_HIP(hipMemcpyAsync(v, st->lx[l].p, (size_t)rows * n * 8, hipMemcpyDeviceToDevice, ss));
+      s = orthonormalise_columns(mg, st, v, rows, n);
+      if (s != MRHS_OK) return s;
+      s = rebuild_next(mg, st, l);
+      if (s != MRHS_OK) return s;
+    }
   }
   drop_graphs(st);  // the graphs only hold pointers into rebuilt operators, but keep it simple
   return MRHS_OK;
@@ -463,7 +570,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   st->timing = prm->timers != 0;
   st->evused = 0;
   st->marks.clear();
-  s = join_ctx_stream(mg, st);
+  if (prm->precondition && prm->vc.coarse_prec == MRHS_BF16) s = ensure_basis_bf16(mg, 0);
+  if (s == MRHS_OK) s = join_ctx_stream(mg, st);
   if (s != MRHS_OK) return s;
   hipStream_t ss = st->stream;
   const auto t0 = std::chrono::steady_clock::now();

@@ -186,6 +186,71 @@ __global__ __launch_bounds__(kB) void zero_words(uint4* __restrict__ p, long n16
 
 int grid_of(long n) { return (int)((n + kB - 1) / kB); }
 
+// Gram matrix of the nv <= 16 columns of one field, G[a][b] = sum_rows
+// conj(v_a) v_b: workgroup partials over row ranges (rows staged in LDS,
+// thread (a, b) accumulates one entry in FP64), then a fixed-order sum.
+constexpr int kGramRows = 64;
+
+__global__ __launch_bounds__(kB) void col_gram_partial(const float2* __restrict__ v, long rows, int nv, long per,
+                                                       double2* __restrict__ part) {
+  __shared__ float2 tile[kGramRows * 16];
+  const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
+  const long r0 = (long)blockIdx.x * per, r1 = min(rows, r0 + per);
+  double re = 0.0, im = 0.0;
+  for (long base = r0; base < r1; base += kGramRows) {
+    const int nr = (int)min((long)kGramRows, r1 - base);
+    for (int e = threadIdx.x; e < nr * nv; e += kB) tile[(e / nv) * 16 + e % nv] = v[base * nv + e];
+    __syncthreads();
+    if (a < nv && b < nv) {
+      for (int r = 0; r < nr; ++r) {
+        const float2 x = tile[r * 16 + a], y = tile[r * 16 + b];
+        re += (double)x.x * y.x + (double)x.y * y.y;
+        im += (double)x.x * y.y - (double)x.y * y.x;
+      }
+    }
+    __syncthreads();
+  }
+  part[(size_t)blockIdx.x * 256 + threadIdx.x] = make_double2(re, im);
+}
+
+__global__ __launch_bounds__(kB) void col_gram_final(const double2* __restrict__ part, int nblk,
+                                                     double2* __restrict__ g) {
+  double re = 0.0, im = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    const double2 p = part[(size_t)i * 256 + threadIdx.x];
+    re += p.x;
+    im += p.y;
+  }
+  g[threadIdx.x] = make_double2(re, im);
+}
+
+// v <- v T for an upper-triangular nv x nv matrix T (row a, column b at 16 a + b).
+__global__ __launch_bounds__(kB) void col_transform(float2* __restrict__ v, long rows, int nv,
+                                                    const float2* __restrict__ T) {
+  __shared__ float2 t[256];
+  t[threadIdx.x] = T[threadIdx.x];
+  __syncthreads();
+  const long r = (long)blockIdx.x * kB + threadIdx.x;
+  if (r >= rows) return;
+  float2 x[16], y[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) x[a] = a < nv ? v[r * nv + a] : make_float2(0.f, 0.f);
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int a = 0; a <= b; ++a) {
+      const float2 c = t[16 * a + b];
+      re = fmaf(x[a].x, c.x, fmaf(-x[a].y, c.y, re));
+      im = fmaf(x[a].x, c.y, fmaf(x[a].y, c.x, im));
+    }
+    y[b] = make_float2(re, im);
+  }
+#pragma unroll
+  for (int b = 0; b < 16; ++b)
+    if (b < nv) v[r * nv + b] = y[b];
+}
+
 }  // namespace
 
 size_t solver_scratch_bytes(int nrhs) { return (size_t)kMaxPart * nrhs * sizeof(double4); }
@@ -259,6 +324,34 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes % 16) return hipErrorInvalidValue;
   const long n16 = (long)(bytes / 16);
   hipLaunchKernelGGL(zero_words, dim3(grid_of(n16)), dim3(kB), 0, s, static_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
+
+}  // namespace mrhs
+
+namespace mrhs {
+
+size_t col_gram_scratch_bytes() { return (size_t)kMaxPart * 256 * sizeof(double2); }
+
+hipError_t launch_col_gram(const void* v, long rows, int nv, void* scratch, void* g, hipStream_t s) {
+  if (nv < 1 || nv > 16) return hipErrorInvalidValue;
+  long nb = (rows + kGramRows - 1) / kGramRows;
+  if (nb > kMaxPart) nb = kMaxPart;
+  if (nb < 1) nb = 1;
+  const long per = ((rows + nb - 1) / nb + kGramRows - 1) / kGramRows * kGramRows;
+  nb = (rows + per - 1) / per;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(col_gram_partial, dim3((unsigned)nb), dim3(kB), 0, s, static_cast<const float2*>(v), rows, nv,
+                     per, static_cast<double2*>(scratch));
+  hipLaunchKernelGGL(col_gram_final, dim3(1), dim3(kB), 0, s, static_cast<const double2*>(scratch), (int)nb,
+                     static_cast<double2*>(g));
+  return hipGetLastError();
+}
+
+hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipStream_t s) {
+  if (nv < 1 || nv > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(col_transform, dim3((unsigned)((rows + kB - 1) / kB)), dim3(kB), 0, s, static_cast<float2*>(v),
+                     rows, nv, static_cast<const float2*>(T));
   return hipGetLastError();
 }
 

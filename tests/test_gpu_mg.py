@@ -123,6 +123,53 @@ def test_restrict_prolong_coarse_level(gpu_lib):
     assert rel(host(fo), O.prolong(basis, yc, d1, (2, 1, 2, 1))) < 1e-12
 
 
+@pytest.mark.parametrize("nrhs", [1, 7, 24, 33, 64])
+def test_restrict_prolong_bf16(gpu_lib, nrhs):
+    """Matrix-core BF16 restrict/prolong (FP32 fields, FP32 accumulation) on
+    both steps of an 8^4 -> 2^4 -> 1^4 hierarchy: against the oracle on the
+    same BF16-rounded operands (exact products, so only the FP32
+    accumulation differs) and against the exact FP32-basis result within the
+    BF16 bar.  Nrhs covers a partial 32-column tile, several tiles and a
+    ragged tail."""
+    import torch
+
+    dims = (8, 8, 8, 8)
+    blocks = [(4, 4, 4, 4), (2, 2, 2, 2)]
+    ctx, mg = make_mg(gpu_lib, dims, blocks, [16, 16])
+    for lev in (0, 1):
+        d = mg.dims[lev]
+        V = mg.volume[lev]
+        nc = mg.ncomp[lev]
+        basis = O.block_orthonormalise(synth.gaussian_vectors(V, 16, nc, 60 + lev), d, blocks[lev])
+        mg.set_basis(lev, basis)
+        b32 = basis.astype(np.complex64)
+        f = synth.coarse_source(V, nc, nrhs, 61 + lev, np.complex64)
+        y = torch.empty((mg.volume[lev + 1], 32, nrhs), dtype=torch.complex64, device="cuda")
+        mg.restrict(lev, y, dev(f), prec="bf16")
+        got = host(y)
+        assert rel(got, O.restrict_lowprec(b32, f, d, blocks[lev])) < 2e-6
+        assert rel(got, O.restrict(b32, f, d, blocks[lev])) < 2e-2
+        yc = synth.coarse_source(mg.volume[lev + 1], 32, nrhs, 62 + lev, np.complex64)
+        fo = torch.empty((V, nc, nrhs), dtype=torch.complex64, device="cuda")
+        mg.prolong(lev, fo, dev(yc), prec="bf16")
+        got = host(fo)
+        assert rel(got, O.prolong_lowprec(b32, yc, d, blocks[lev])) < 2e-6
+        assert rel(got, O.prolong(b32, yc, d, blocks[lev])) < 2e-2
+
+
+def test_restrict_prolong_bf16_unsupported(gpu_lib):
+    """n_v = 8 has no matrix-core intergrid path: a clear UNSUPPORTED error."""
+    import torch
+
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    ctx, mg = make_mg(gpu_lib, dims, [block], [8])
+    mg.set_basis(0, O.block_orthonormalise(synth.gaussian_vectors(256, 8, 12, 1), dims, block))
+    y = torch.empty((16, 16, 4), dtype=torch.complex64, device="cuda")
+    f = torch.zeros((256, 12, 4), dtype=torch.complex64, device="cuda")
+    with pytest.raises(gpu_lib.MrhsError, match="UNSUPPORTED"):
+        mg.restrict(0, y, f, prec="bf16")
+
+
 def test_intergrid_config4_full(gpu_lib):
     """24^4 fine lattice, 4^4 aggregates, 16 Gaussian vectors block-orthonormalised
     in FP64 on the GPU, restrict / prolong / block-normalise of Nrhs = 24 FP32 fields."""
@@ -145,6 +192,13 @@ def test_intergrid_config4_full(gpu_lib):
     fo = torch.empty_like(tf)
     mg.prolong(0, fo, y)
     assert rel(host(fo), O.prolong(b32, host(y), dims, block)) < 1e-6
+    # the matrix-core BF16 path at the same size, against the rounded-operand oracle
+    yb = torch.empty_like(y)
+    mg.restrict(0, yb, tf, prec="bf16")
+    assert rel(host(yb), O.restrict_lowprec(b32, f, dims, block)) < 2e-6
+    fb = torch.empty_like(tf)
+    mg.prolong(0, fb, y, prec="bf16")
+    assert rel(host(fb), O.prolong_lowprec(b32, host(y), dims, block)) < 2e-6
     norms = torch.empty((mg.volume[1], 2, nrhs), dtype=torch.float64, device="cuda")
     mg.block_normalise(0, tf, norms)
     want, want_n = O.block_normalise(f, dims, block)

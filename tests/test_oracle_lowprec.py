@@ -57,3 +57,27 @@ def test_lowprec_apply_close_to_exact():
         got = O.coarse_apply_lowprec(B, e, dims, fmt)
         rel = np.linalg.norm(got - exact) / np.linalg.norm(exact)
         assert u / 20 < rel < 2 * u, (fmt, rel)
+
+
+def test_lowprec_intergrid_exact_on_representable_and_close_otherwise():
+    """BF16 restrict/prolong emulation: with operands already exactly
+    representable in BF16 it equals the plain restrict/prolong; with generic
+    operands it moves the result by about the BF16 unit roundoff 2^-8, and
+    P^dag P = 1 holds to that accuracy."""
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    V = synth.volume(dims)
+    basis = O.block_orthonormalise(synth.gaussian_vectors(V, 4, 12, 3), dims, block)
+    f = synth.spinor_source(dims, 3, 4, np.complex64)
+    bq = O.round_bf16(basis.real) + 1j * O.round_bf16(basis.imag)
+    fq = O.round_bf16(f.real) + 1j * O.round_bf16(f.imag)
+    np.testing.assert_array_equal(O.restrict_lowprec(bq, fq, dims, block), O.restrict(bq, fq, dims, block))
+    y = synth.coarse_source(16, 8, 3, 5, np.complex64)
+    yq = O.round_bf16(y.real) + 1j * O.round_bf16(y.imag)
+    np.testing.assert_array_equal(O.prolong_lowprec(bq, yq, dims, block), O.prolong(bq, yq, dims, block))
+    u = 2.0 ** -8
+    for got, exact in ((O.restrict_lowprec(basis, f, dims, block), O.restrict(basis, f, dims, block)),
+                       (O.prolong_lowprec(basis, y, dims, block), O.prolong(basis, y, dims, block))):
+        rel = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+        assert u / 20 < rel < 2 * u, rel
+    back = O.restrict_lowprec(basis, O.prolong(basis, y, dims, block), dims, block)
+    assert np.linalg.norm(back - y) / np.linalg.norm(y) < 2 * u
