@@ -55,7 +55,7 @@ HBM_PEAK_GBS = 8000.0
 FLOPS_DWC = 1920          # per site per RHS: hop 1320 + clover 552 + combine 48
 SOLVE_DIMS = (24, 24, 24, 128)
 # multigrid set-up and V-cycle of the solve workload (hyper-parameters, not from the paper)
-SOLVE_SETUP = dict(setup_iters=6, smooth_steps=20, adapt_iters=0)
+SOLVE_SETUP = dict(setup_iters=10, smooth_steps=30, adapt_iters=0)
 SOLVE_VC = dict(nu_pre=0, nu_post=6, coarsest_iters=64)
 SOLVE_RESTART, SOLVE_MAXIT = 8, 1000
 TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solve-nrhs", type=int, default=12)
+    ap.add_argument("--m0", type=float, default=None,
+                    help="bare mass of the solve workload (default: the tuned value in tests/golden)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner text cache (read, appended)")
     ap.add_argument("--retune", action="store_true", help="tune the fine kernel afresh, ignoring the cache")
     ap.add_argument("--calib-copy", action="store_true",
@@ -414,7 +416,9 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_solve:
         mpath = os.path.join(HERE, "tests", "golden", "smooth_links_mass.json")
-        if os.path.exists(mpath):
+        if a.m0 is not None:
+            mass = {"m0": a.m0, "kappa": 1.0 / (2.0 * (4.0 + a.m0)), "sigma_min": None}
+        elif os.path.exists(mpath):
             with open(mpath) as fh:
                 mass = json.load(fh)
         else:

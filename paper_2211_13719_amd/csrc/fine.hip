@@ -17,6 +17,8 @@
 // gamma_4 = [[0, 1], [1, 0]].  Writing psi = (u0, u1, l0, l1) in spin, the
 // projection (1 -+ gamma_mu) psi has upper half h = (h0, h1) and lower half a
 // fixed multiple of h, listed per direction in project()/reconstruct().
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mrhs {
@@ -90,6 +92,21 @@ __device__ __forceinline__ void load_r(const cplx<T>* __restrict__ p, cplx<T> (&
   } else {
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j] = p[j];
+  }
+}
+
+// Load R consecutive input values stored as P (the compute type's complex,
+// or FP32 complex widened exactly to FP64 for the mixed-precision FP64 apply).
+template <typename T, int R, typename P>
+__device__ __forceinline__ void load_in(const P* __restrict__ p, cplx<T> (&v)[R]) {
+  if constexpr (std::is_same<P, cplx<T>>::value) {
+    load_r<T, R>(p, v);
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const P w = p[j];
+      v[j] = mk<T>((T)w.x, (T)w.y);
+    }
   }
 }
 
@@ -190,16 +207,16 @@ __device__ __forceinline__ void project_half(const cplx<T> (&u)[3][R], const cpl
 // Half spinor h of the neighbour at site nb, loading only the two spin
 // components each half needs (keeps half as many values live as loading the
 // whole spinor first).
-template <typename T, int R, int MU, int S>
-__device__ __forceinline__ void load_project(const cplx<T>* __restrict__ in, int nb, int nrhs, int k0,
+template <typename T, int R, int MU, int S, typename P>
+__device__ __forceinline__ void load_project(const P* __restrict__ in, int nb, int nrhs, int k0,
                                              cplx<T> (&h)[2][3][R]) {
-  const cplx<T>* base = in + (size_t)nb * 12 * nrhs + k0;
+  const P* base = in + (size_t)nb * 12 * nrhs + k0;
   {
     cplx<T> u[3][R], l[3][R];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      load_r<T, R>(base + (0 * 3 + c) * nrhs, u[c]);
-      load_r<T, R>(base + (HalfPair<MU>::lo0 * 3 + c) * nrhs, l[c]);
+      load_in<T, R>(base + (0 * 3 + c) * nrhs, u[c]);
+      load_in<T, R>(base + (HalfPair<MU>::lo0 * 3 + c) * nrhs, l[c]);
     }
     project_half<T, R, MU, S, 0>(u, l, h[0]);
   }
@@ -207,8 +224,8 @@ __device__ __forceinline__ void load_project(const cplx<T>* __restrict__ in, int
     cplx<T> u[3][R], l[3][R];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      load_r<T, R>(base + (1 * 3 + c) * nrhs, u[c]);
-      load_r<T, R>(base + (HalfPair<MU>::lo1 * 3 + c) * nrhs, l[c]);
+      load_in<T, R>(base + (1 * 3 + c) * nrhs, u[c]);
+      load_in<T, R>(base + (HalfPair<MU>::lo1 * 3 + c) * nrhs, l[c]);
     }
     project_half<T, R, MU, S, 1>(u, l, h[1]);
   }
@@ -253,11 +270,11 @@ __device__ __forceinline__ void pin(cplx<T> (&acc)[4][3][R]) {
       for (int j = 0; j < R; ++j) asm volatile("" : "+v"(acc[sp][c][j].x), "+v"(acc[sp][c][j].y));
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void load_spinor(const cplx<T>* __restrict__ in, int site, int nrhs, int k0,
+template <typename T, int R, typename P>
+__device__ __forceinline__ void load_spinor(const P* __restrict__ in, int site, int nrhs, int k0,
                                             cplx<T> (&p)[4][3][R]) {
-  const cplx<T>* base = in + (size_t)site * 12 * nrhs + k0;
-  if constexpr (R == 1 && sizeof(T) == 4) {
+  const P* base = in + (size_t)site * 12 * nrhs + k0;
+  if constexpr (R == 1 && sizeof(T) == 4 && std::is_same<P, cplx<T>>::value) {
     if (nrhs == 1) {  // the whole 96-byte spinor is contiguous: six 16-byte loads
       const float4* q = reinterpret_cast<const float4*>(base);
 #pragma unroll
@@ -272,15 +289,15 @@ __device__ __forceinline__ void load_spinor(const cplx<T>* __restrict__ in, int 
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) load_r<T, R>(base + (3 * sp + c) * nrhs, p[sp][c]);
+    for (int c = 0; c < 3; ++c) load_in<T, R>(base + (3 * sp + c) * nrhs, p[sp][c]);
 }
 
 // One direction mu, both hops, accumulated into acc.  nbf / nbb are the
 // sites x + mu and x - mu.  The fermion boundary factor is already folded
 // into the links (see fold_boundary_phase), so no hop needs a phase here.
-template <typename T, int R, int MU, bool SPLIT>
+template <typename T, int R, int MU, bool SPLIT, typename P>
 __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, int k0, const cplx<T>* __restrict__ U,
-                                        const cplx<T>* __restrict__ in, cplx<T> (&acc)[4][3][R], bool inc_f = true,
+                                        const P* __restrict__ in, cplx<T> (&acc)[4][3][R], bool inc_f = true,
                                         bool inc_b = true) {
   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
   if (inc_f) {
@@ -410,11 +427,11 @@ __device__ __forceinline__ void galerkin_keep(const DirFilter& f, int mu, int c,
 // OCC > 0 asks the compiler for at least OCC wavefronts per SIMD (it then
 // keeps the register count at or below 512 / OCC, spilling if it must); the
 // autotuner measures whether that pays.
-template <typename T, int R, int MODE, bool XCD, bool SPLIT, int OCC>
+template <typename T, int R, int MODE, bool XCD, bool SPLIT, int OCC, typename P = cplx<T>>
 __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, int nrhs, T kappa, const int* __restrict__ order,
                                                    const cplx<T>* __restrict__ U,
                                                    const T* __restrict__ A,
-                                                   const cplx<T>* __restrict__ in,
+                                                   const P* __restrict__ in,
                                                    cplx<T>* __restrict__ out, int nblocks, DirFilter filt,
                                                    int nt_out, int nc) {
   int b = blockIdx.x;
@@ -482,12 +499,12 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
 #pragma unroll
       for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c], nt_out);
   } else {
-    const cplx<T>* base = in + (size_t)site * 12 * nrhs + k0;
+    const P* base = in + (size_t)site * 12 * nrhs + k0;
 #pragma unroll
     for (int chi = 0; chi < 2; ++chi) {
       cplx<T> xin[6][R], yout[6][R];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) load_r<T, R>(base + (6 * chi + i) * nrhs, xin[i]);
+      for (int i = 0; i < 6; ++i) load_in<T, R>(base + (6 * chi + i) * nrhs, xin[i]);
       if (MODE != 3 || filt.sign == 0) {
         clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
       } else {
@@ -515,7 +532,7 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
 // chunks: RHS chunks swept in turn (nrhs / chunks must be a multiple of R);
 // lds: dynamic LDS reserved per workgroup (unused by the kernel) to cap the
 // number of workgroups resident on one CU.
-template <typename T, int R, int MODE, int OCC = 0>
+template <typename T, int R, int MODE, int OCC = 0, typename P = cplx<T>>
 hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, const void* A, const void* in,
                     void* out, int nrhs, hipStream_t s, const DirFilter& f = DirFilter{}, int nt = 0,
                     int chunks = 1, unsigned lds = 0) {
@@ -526,9 +543,9 @@ hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, con
   const int nblocks = (int)((threads + 255) / 256);
   const long grid = (long)((nblocks + 7) / 8) * 8 * chunks;
   if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true, true, OCC>), dim3((unsigned)grid), dim3(256), lds, s, g, nrhs,
+  hipLaunchKernelGGL((fine_kernel<T, R, MODE, true, true, OCC, P>), dim3((unsigned)grid), dim3(256), lds, s, g, nrhs,
                      kappa, order, reinterpret_cast<const cplx<T>*>(U), reinterpret_cast<const T*>(A),
-                     reinterpret_cast<const cplx<T>*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f, nt, nc);
+                     reinterpret_cast<const P*>(in), reinterpret_cast<cplx<T>*>(out), nblocks, f, nt, nc);
   return hipGetLastError();
 }
 
@@ -588,6 +605,11 @@ hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U, const void* A,
                            const void* in, void* out, int nrhs, hipStream_t s) {
   return launch_fine<double>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s, nullptr);
+}
+
+hipError_t launch_fine_f64_in32(const Geom& g, double kappa, const void* U, const void* A, const void* in, void* out,
+                                int nrhs, hipStream_t s) {
+  return launch_r<double, 1, 0, 0, float2>(g, g.order, kappa, U, A, in, out, nrhs, s);
 }
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,

@@ -269,54 +269,70 @@ __global__ __launch_bounds__(256) void block_gs_kernel(AggGeom a, int h, int nv,
 // One workgroup per aggregate; thread t accumulates |f|^2 for one (chirality,
 // RHS) pair over a slice of sites, the slices are summed in LDS in a fixed
 // order, and the same workgroup then scales the block.
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(256) void block_norm_kernel(AggGeom a, int h, int nrhs, cplx<T>* __restrict__ f,
                                                          double* __restrict__ norms) {
-  __shared__ double part[256];
+  // Thread (slice, chi, g) owns right-hand sides g W .. g W + W - 1 of one
+  // chirality on the sites l = slice, slice + S, ... of the aggregate: it
+  // sums their squares (FP64), the slices are combined in a fixed order,
+  // and then the same thread rescales the same elements.
+  __shared__ double part[256 * W];
   __shared__ double inv[2 * 64];
   const int A = blockIdx.x;
   const int ncomp = 2 * h;
-  const int np = 2 * nrhs;
+  const int G = nrhs / W;
+  const int np = 2 * G;
   const int S = 256 / np;
   const int t = threadIdx.x;
   const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
-  double acc = 0.0;
   const int pair = t % np, slice = t / np;
-  const int chi = pair / nrhs, k = pair % nrhs;
+  const int chi = pair / G, k0 = (pair % G) * W;
+  double acc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = 0.0;
   if (slice < S) {
     for (int l = slice; l < nsa; l += S) {
-      const int s = agg_site(a, A, l);
-      const cplx<T>* fb = f + ((size_t)s * ncomp + chi * h) * nrhs + k;
+      const cplx<T>* fb = f + ((size_t)agg_site(a, A, l) * ncomp + chi * h) * nrhs + k0;
       for (int c = 0; c < h; ++c) {
-        const cplx<T> v = fb[(size_t)c * nrhs];
-        acc = fma((double)v.x, (double)v.x, acc);
-        acc = fma((double)v.y, (double)v.y, acc);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const cplx<T> v = fb[(size_t)c * nrhs + w];
+          acc[w] = fma((double)v.x, (double)v.x, acc[w]);
+          acc[w] = fma((double)v.y, (double)v.y, acc[w]);
+        }
       }
     }
   }
-  part[t] = acc;
+#pragma unroll
+  for (int w = 0; w < W; ++w) part[t * W + w] = acc[w];
   __syncthreads();
   if (t < np) {
-    double s2 = 0.0;
-    for (int q = 0; q < S; ++q) s2 += part[q * np + t];
-    const double n = sqrt(s2);
-    inv[t] = n > 0.0 ? 1.0 / n : 0.0;
-    if (norms) norms[((size_t)A * 2 + chi) * nrhs + k] = n;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      double s2 = 0.0;
+      for (int q = 0; q < S; ++q) s2 += part[(q * np + t) * W + w];
+      const double n = sqrt(s2);
+      inv[chi * nrhs + k0 + w] = n > 0.0 ? 1.0 / n : 0.0;
+      if (norms) norms[((size_t)A * 2 + chi) * nrhs + k0 + w] = n;
+    }
   }
   __syncthreads();
-  // scale: every thread walks (site, component, rhs) elements of the aggregate
-  const int tot = nsa * ncomp * nrhs;
-  for (int e = t; e < tot; e += 256) {
-    const int kk = e % nrhs;
-    const int c = (e / nrhs) % ncomp;
-    const int l = e / (nrhs * ncomp);
-    const int s = agg_site(a, A, l);
-    cplx<T>* p = f + ((size_t)s * ncomp + c) * nrhs + kk;
-    const T sc = (T)inv[(c / h) * nrhs + kk];
-    cplx<T> v = *p;
-    v.x *= sc;
-    v.y *= sc;
-    *p = v;
+  if (slice < S) {
+    T sc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) sc[w] = (T)inv[chi * nrhs + k0 + w];
+    for (int l = slice; l < nsa; l += S) {
+      cplx<T>* fb = f + ((size_t)agg_site(a, A, l) * ncomp + chi * h) * nrhs + k0;
+      for (int c = 0; c < h; ++c) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          cplx<T> v = fb[(size_t)c * nrhs + w];
+          v.x *= sc[w];
+          v.y *= sc[w];
+          fb[(size_t)c * nrhs + w] = v;
+        }
+      }
+    }
   }
 }
 
@@ -446,11 +462,14 @@ hipError_t launch_block_normalise(int prec64, const AggGeom& a, int h, int nrhs,
                                   hipStream_t s) {
   if (2 * nrhs > 256) return hipErrorInvalidValue;
   if (prec64)
-    hipLaunchKernelGGL((block_norm_kernel<double>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
+    hipLaunchKernelGGL((block_norm_kernel<double, 1>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
                        static_cast<double2*>(f), norms);
+  else if (nrhs % 2 == 0)
+    hipLaunchKernelGGL((block_norm_kernel<float, 2>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
+                       static_cast<float2*>(f), norms);
   else
-    hipLaunchKernelGGL((block_norm_kernel<float>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs, static_cast<float2*>(f),
-                       norms);
+    hipLaunchKernelGGL((block_norm_kernel<float, 1>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
+                       static_cast<float2*>(f), norms);
   return hipGetLastError();
 }
 

@@ -57,6 +57,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 size_t col_gram_scratch_bytes();
 hipError_t launch_col_gram(const void* v, long rows, int nv, void* scratch, void* g, hipStream_t s);
 hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipStream_t s);
+hipError_t launch_multi_axpy_norm(void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
+                                 int nrhs, void* norms, void* scratch, hipStream_t s);
+hipError_t launch_scale_cols_dual(void* y, void* y32, const void* x, const double* sdev, long rows, int nrhs,
+                                  hipStream_t s);
 
 enum Phase { kFine = 0, kRestrict, kProlong, kCoarse, kPhases };
 
@@ -77,7 +81,7 @@ struct SolverState {
   Buffer gpart, gmat, gT;  // column Gram matrix (setup)
   // outer Krylov
   int m = 0, on = 0;
-  Buffer V64, Z32, w64, t64, r64;
+  Buffer V64, Z32, w64, r64;
   // captured V-cycles, one per destination slot
   GraphSlot graphs[kGraphSlots];
   // phase timers
@@ -98,7 +102,7 @@ void mg_solver_release(mrhs_mg mg) {
     release(st->lp[l]);
   }
   Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->gpart, &st->gmat, &st->gT,
-                 &st->V64, &st->Z32, &st->w64, &st->t64, &st->r64};
+                 &st->V64, &st->Z32, &st->w64, &st->r64};
   for (Buffer* x : b) release(*x);
   for (auto& gs : st->graphs)
     if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
@@ -561,7 +565,6 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
     s = ensure(ctx, st->V64, (size_t)(m + 1) * f64);
     if (s == MRHS_OK) s = ensure(ctx, st->Z32, (size_t)m * f32);
     if (s == MRHS_OK) s = ensure(ctx, st->w64, f64);
-    if (s == MRHS_OK) s = ensure(ctx, st->t64, f64);
     if (s == MRHS_OK) s = ensure(ctx, st->r64, f64);
     if (s != MRHS_OK) return s;
     st->m = m;
@@ -588,10 +591,23 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
     SOLVER_HIP(hipStreamSynchronize(ss));
     return MRHS_OK;
   };
+  // y = diag(sc) x in FP64; with preconditioning also FP32(y) into the
+  // V-cycle's input buffer (the next direction to precondition is y)
   auto scale_by = [&](void* y, const void* xx, const std::vector<double>& sc) -> mrhs_status {
     SOLVER_HIP(hipMemcpyAsync(st->scl.p, sc.data(), n * 8, hipMemcpyHostToDevice, ss));
-    SOLVER_HIP(launch_scale_cols(1, y, xx, static_cast<const double*>(st->scl.p), rows, n, ss));
+    SOLVER_HIP(launch_scale_cols_dual(y, prm->precondition ? st->lb[0].p : nullptr, xx,
+                                      static_cast<const double*>(st->scl.p), rows, n, ss));
     SOLVER_HIP(hipStreamSynchronize(ss));  // sc is host memory the caller may change
+    return MRHS_OK;
+  };
+  // w -= sum_i c_i V_i (c from the last multi-dot) and q = ||w||^2 per RHS, one pass
+  // (the first nprod products of the multi-dot are copied to hout)
+  auto project_out = [&](const std::vector<const void*>& vs, int cnt, int nprod, std::vector<std::complex<double>>& hout,
+                         std::vector<double>& qout) -> mrhs_status {
+    SOLVER_HIP(launch_multi_axpy_norm(st->w64.p, st->coef.p, vs.data(), cnt, -1.0, rows, n, st->qn.p, st->part.p, ss));
+    SOLVER_HIP(hipMemcpyAsync(hout.data(), st->coef.p, (size_t)nprod * n * 16, hipMemcpyDeviceToHost, ss));
+    SOLVER_HIP(hipMemcpyAsync(qout.data(), st->qn.p, n * 8, hipMemcpyDeviceToHost, ss));
+    SOLVER_HIP(hipStreamSynchronize(ss));
     return MRHS_OK;
   };
 
@@ -633,9 +649,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       // z_j = M v_j
       {
         auto tp = std::chrono::steady_clock::now();
-        if (prm->precondition) {
-          SOLVER_HIP(launch_convert_f64_to_f32(static_cast<const double*>(Vj(j)), static_cast<float*>(st->lb[0].p),
-                                               2 * rows * n, ss));
+        if (prm->precondition) {  // lb[0] already holds FP32(v_j), written with v_j
           s = run_vcycle(mg, st, n, prm->vc, prm->use_graph != 0, Zj(j), j);
           if (s != MRHS_OK) return s;
         } else {
@@ -647,10 +661,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
           t_pre += std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
         }
       }
-      // w = D z_j in FP64
-      SOLVER_HIP(launch_convert_f32_to_f64(static_cast<const float*>(Zj(j)), static_cast<double*>(st->t64.p),
-                                           2 * rows * n, ss));
-      SOLVER_HIP(D64(st->w64.p, st->t64.p));
+      // w = D z_j in FP64, reading the FP32 direction directly (exact widening)
+      SOLVER_HIP(launch_fine_f64_in32(ctx->g, ctx->kappa, ctx->U64.p, ctx->A64.p, Zj(j), st->w64.p, n, ss));
       // classical Gram-Schmidt; the first pass also yields ||w||^2 (w is the
       // last vector of the multi-dot), and a second pass is made only when
       // the projection removed more than half of ||w||^2 for some
@@ -659,9 +671,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       for (int i = 0; i <= j; ++i) vs[i] = Vj(i);
       vs[j + 1] = st->w64.p;
       SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 2, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
-      SOLVER_HIP(launch_multi_axpy(1, st->w64.p, st->coef.p, vs.data(), j + 1, -1.0, rows, n, ss));
-      SOLVER_HIP(hipMemcpyAsync(hc.data(), st->coef.p, (size_t)(j + 2) * n * 16, hipMemcpyDeviceToHost, ss));
-      s = norms(st->w64.p, q);  // synchronises, so hc is complete
+      s = project_out(vs, j + 1, j + 2, hc, q);  // the last of the j + 2 products is ||w||^2
       if (s != MRHS_OK) return s;
       bool again = false;
       for (int k = 0; k < n; ++k)
@@ -669,9 +679,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       std::fill(hc2.begin(), hc2.end(), cd(0.0));
       if (again) {
         SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
-        SOLVER_HIP(launch_multi_axpy(1, st->w64.p, st->coef.p, vs.data(), j + 1, -1.0, rows, n, ss));
-        SOLVER_HIP(hipMemcpyAsync(hc2.data(), st->coef.p, (size_t)(j + 1) * n * 16, hipMemcpyDeviceToHost, ss));
-        s = norms(st->w64.p, q);
+        s = project_out(vs, j + 1, j + 1, hc2, q);
         if (s != MRHS_OK) return s;
         ++reorth;
       }

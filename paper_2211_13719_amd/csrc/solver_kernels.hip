@@ -137,6 +137,71 @@ __global__ __launch_bounds__(kB) void multi_axpy(double2* __restrict__ y, const 
   y[e] = acc;
 }
 
+// y_k += s sum_i c[i][k] x_i (y, x_i FP64) and, in the same pass, the
+// partial sums of ||y_k||^2 of the updated y: partial[b][k], fixed order.
+__global__ __launch_bounds__(kB) void multi_axpy_norm(double2* __restrict__ y, const double2* __restrict__ c,
+                                                      Ptrs xs, int m, double s, long rows, int nrhs, int tpb,
+                                                      double* __restrict__ part) {
+  __shared__ double red[kB];
+  const int t = threadIdx.x;
+  double acc2 = 0.0;
+  if (t < tpb) {
+    const int k = t % nrhs;
+    const int rpb = tpb / nrhs;
+    const long step = (long)gridDim.x * rpb;
+    for (long row = (long)blockIdx.x * rpb + t / nrhs; row < rows; row += step) {
+      const long e = row * nrhs + k;
+      double2 acc = y[e];
+#pragma unroll 4
+      for (int i = 0; i < m; ++i) {
+        const double2 xv = static_cast<const double2*>(xs.p[i])[e];
+        const double2 ci = c[i * nrhs + k];
+        const double cr = s * ci.x, cim = s * ci.y;
+        acc.x = fma(cr, xv.x, fma(-cim, xv.y, acc.x));
+        acc.y = fma(cr, xv.y, fma(cim, xv.x, acc.y));
+      }
+      y[e] = acc;
+      acc2 = fma(acc.x, acc.x, fma(acc.y, acc.y, acc2));
+    }
+  }
+  red[t] = acc2;
+  __syncthreads();
+  if (t < nrhs) {
+    double v = red[t];
+    for (int j = t + nrhs; j < tpb; j += nrhs) v += red[j];
+    part[(long)blockIdx.x * nrhs + t] = v;
+  }
+}
+
+__global__ __launch_bounds__(kB) void col_sum_final(const double* __restrict__ part, int nblk, int nrhs,
+                                                    double* __restrict__ out) {
+  __shared__ double red[kB];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double v = 0.0;
+  for (int j = t; j < nblk; j += kB) v += part[(long)j * nrhs + k];
+  red[t] = v;
+  __syncthreads();
+  for (int w = kB / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[k] = red[0];
+}
+
+// y_k = s_k x_k in FP64 and, if y32 is given, its FP32 rounding too
+__global__ __launch_bounds__(kB) void scale_cols_dual(double2* __restrict__ y, float2* __restrict__ y32,
+                                                      const double2* __restrict__ x, const double* __restrict__ s,
+                                                      long n, int nrhs) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  const double f = s[e % nrhs];
+  double2 v = x[e];
+  v.x *= f;
+  v.y *= f;
+  y[e] = v;
+  if (y32) y32[e] = make_float2((float)v.x, (float)v.y);
+}
+
 // y_k = s_k x_k, s real per column (device array)
 template <typename T>
 __global__ __launch_bounds__(kB) void scale_cols(typename c2<T>::type* __restrict__ y,
@@ -352,6 +417,27 @@ hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipSt
   if (nv < 1 || nv > 16) return hipErrorInvalidValue;
   hipLaunchKernelGGL(col_transform, dim3((unsigned)((rows + kB - 1) / kB)), dim3(kB), 0, s, static_cast<float2*>(v),
                      rows, nv, static_cast<const float2*>(T));
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy_norm(void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
+                                 int nrhs, void* norms, void* scratch, hipStream_t s) {
+  if (m < 1 || m > kMaxMultiDot || nrhs < 1 || nrhs > kB) return hipErrorInvalidValue;
+  Ptrs p{};
+  for (int i = 0; i < m; ++i) p.p[i] = xs[i];
+  const int tpb = tpb_of(nrhs), nb = nblk_of(rows, nrhs);
+  hipLaunchKernelGGL(multi_axpy_norm, dim3(nb), dim3(kB), 0, s, static_cast<double2*>(y),
+                     static_cast<const double2*>(coef), p, m, sgn, rows, nrhs, tpb, static_cast<double*>(scratch));
+  hipLaunchKernelGGL(col_sum_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double*>(scratch), nb, nrhs,
+                     static_cast<double*>(norms));
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols_dual(void* y, void* y32, const void* x, const double* sdev, long rows, int nrhs,
+                                  hipStream_t s) {
+  const long n = rows * nrhs;
+  hipLaunchKernelGGL(scale_cols_dual, dim3((unsigned)((n + kB - 1) / kB)), dim3(kB), 0, s, static_cast<double2*>(y),
+                     static_cast<float2*>(y32), static_cast<const double2*>(x), sdev, n, nrhs);
   return hipGetLastError();
 }
 
