@@ -273,6 +273,10 @@ typedef struct {
   int32_t use_graph;    /* 1: replay the V-cycle from a captured HIP graph */
   int32_t timers;       /* 1: per-phase device timers (no graph; slower) */
   mrhs_vcycle_params vc;
+  double reorth_eta;    /* second Gram-Schmidt pass when the first left less than reorth_eta times
+                           ||w||^2 for some RHS: 0.5 is the classical "twice is enough" test, 0 never;
+                           one FP64 pass loses about eps / sqrt(reorth_eta) of orthogonality, so 1e-2
+                           (the Python default) costs nothing in convergence at FP64 */
 } mrhs_solve_params;
 
 typedef struct {

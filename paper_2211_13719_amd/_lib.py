@@ -79,7 +79,7 @@ class SetupParams(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", _f64), ("restart", _i32), ("max_iters", _i32), ("precondition", _i32), ("use_graph", _i32),
-                ("timers", _i32), ("vc", VcycleParams)]
+                ("timers", _i32), ("vc", VcycleParams), ("reorth_eta", _f64)]
 
 
 class SolveStats(C.Structure):

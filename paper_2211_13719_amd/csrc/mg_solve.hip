@@ -537,6 +537,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   const int m = prm->restart;
   if (m < 1 || m >= kMaxMultiDot) return fail(ctx, MRHS_ERR_INVALID_ARG, "restart %d outside [1, %d]", m, kMaxMultiDot - 1);
   if (!(prm->tol > 0.0) || prm->max_iters < 1) return fail(ctx, MRHS_ERR_INVALID_ARG, "bad tol or max_iters");
+  if (!(prm->reorth_eta >= 0.0 && prm->reorth_eta <= 1.0))
+    return fail(ctx, MRHS_ERR_INVALID_ARG, "reorth_eta must lie in [0, 1]");
   mrhs_status s = MRHS_OK;
   if (prm->precondition) {
     s = check_vc(mg, &prm->vc);
@@ -675,7 +677,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       if (s != MRHS_OK) return s;
       bool again = false;
       for (int k = 0; k < n; ++k)
-        if (!done[k] && q[k] < 0.5 * hc[(size_t)(j + 1) * n + k].real()) again = true;
+        if (!done[k] && q[k] < prm->reorth_eta * hc[(size_t)(j + 1) * n + k].real()) again = true;
       std::fill(hc2.begin(), hc2.end(), cd(0.0));
       if (again) {
         SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
