@@ -176,3 +176,31 @@ def test_adaptive_setup_keeps_basis_orthonormal_and_solves(gpu_lib):
     st = mg.solve(x, dev(b), tol=1e-10, restart=8, max_iters=300, nu_post=4, coarsest_iters=32, coarse_prec="bf16")
     assert all(st["converged"])
     assert np.all(O.true_residual(U, A, kappa, x.cpu().numpy(), b, dims) <= 1e-10)
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.01, 1.0])
+def test_reorth_threshold_any_value_converges(small, eta):
+    """The second Gram-Schmidt pass (never, on large cancellation, always) does
+    not change what is computed: every setting reaches the true residual."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = synth.spinor_source(dims, 3, 4321)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    st = mg.solve(x, dev(b), reorth_eta=eta, coarse_prec="bf16")
+    assert all(st["converged"])
+    if eta == 0.0:
+        assert st["reorth"] == 0
+    if eta == 1.0:
+        assert st["reorth"] == st["iters"]
+    assert np.all(O.true_residual(U, A, KAPPA, x.cpu().numpy(), b, dims) <= 1e-10)
+
+
+def test_reorth_threshold_out_of_range(small, gpu_lib):
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = dev(synth.spinor_source(dims, 1, 1))
+    x = torch.zeros_like(b)
+    with pytest.raises(gpu_lib.MrhsError, match="INVALID_ARG"):
+        mg.solve(x, b, reorth_eta=1.5)
