@@ -6,9 +6,12 @@
 // Complex arithmetic is split into real products,
 //   Re O += Re B Re E - Im B Im E,   Im O += Re B Im E + Im B Re E,
 // four v_mfma_f32_32x32x16 per 16-wide slice of the contraction index j.
-// One wavefront owns one site and a 32-column tile of right-hand sides and
-// walks the nine directions; rows of the 32 x 32 output are the 32 coarse
-// components i, columns the right-hand sides.
+// One workgroup owns one site and a 32-column tile of right-hand sides; its
+// four wavefronts take the nine directions in turn (d = w, w + 4, w + 8) and
+// their partial sums are added through LDS in a fixed order, which gives the
+// latency-bound small coarse lattices four times the wavefronts in flight.
+// Rows of the 32 x 32 output are the 32 coarse components i, columns the
+// right-hand sides.
 //
 // Operand layouts of v_mfma_f32_32x32x16_{bf16,f16} (lane l, 8 values each):
 //   A (blocks):  A[i = l % 32][j = 8 (l / 32) + q], q = 0..7
@@ -79,6 +82,45 @@ __device__ __forceinline__ int xcd_block(int nblocks) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Adds the partial accumulators of the four wavefronts as (0 + 2) + (1 + 3),
+// through 16 KiB of LDS.  Returns false on the wavefronts that have nothing
+// left to do.
+__device__ __forceinline__ bool reduce_waves(f32x16& accR, f32x16& accI) {
+  __shared__ float red[2][64][32];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv >= 2) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      red[wv - 2][l][r] = accR[r];
+      red[wv - 2][l][16 + r] = accI[r];
+    }
+  }
+  __syncthreads();
+  if (wv < 2) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accR[r] += red[wv][l][r];
+      accI[r] += red[wv][l][16 + r];
+    }
+  }
+  __syncthreads();
+  if (wv == 1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      red[0][l][r] = accR[r];
+      red[0][l][16 + r] = accI[r];
+    }
+  }
+  __syncthreads();
+  if (wv != 0) return false;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accR[r] += red[0][l][r];
+    accI[r] += red[0][l][16 + r];
+  }
+  return true;
+}
+
 template <bool F16>
 __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
                                                           const float2* __restrict__ in, float2* __restrict__ out,
@@ -87,8 +129,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
   using vec = typename O::vec;
   const int l = threadIdx.x & 63;
   const int ntiles = (nrhs + 31) >> 5;
-  const long w = (long)xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
-  if (w >= (long)g.V * ntiles) return;
+  const long w = xcd_block(nblocks);
+  if (w >= (long)g.V * ntiles) return;  // whole workgroup
   const int s = (int)(w / ntiles);
   const int col = (int)(w % ntiles) * 32 + (l & 31);
   const bool colok = col < nrhs;
@@ -106,7 +148,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
     x[3] = r / g.L[2];
   }
   f32x16 accR = {}, accI = {};
-  for (int d = 0; d < 9; ++d) {
+  for (int d = threadIdx.x >> 6; d < 9; d += 4) {
     int nbr = s;
     if (d > 0) {
       const int mu = (d - 1) >> 1;
@@ -138,7 +180,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
       accI = O::mma(ai, vr, accI);
     }
   }
-  if (!colok) return;
+  if (!reduce_waves(accR, accI) || !colok) return;
   const float inv = F16 ? 1.0f / sc : 1.0f;  // exact: sc is a power of two
   float2* o = out + (size_t)s * kNb * nrhs + col;
 #pragma unroll
@@ -158,8 +200,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
                                                               float2* __restrict__ out, int nblocks) {
   const int l = threadIdx.x & 63;
   const int ntiles = (nrhs + 31) >> 5;
-  const long w = (long)xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
-  if (w >= (long)g.V * ntiles) return;
+  const long w = xcd_block(nblocks);
+  if (w >= (long)g.V * ntiles) return;  // whole workgroup
   const int s = (int)(w / ntiles);
   const int col = (int)(w % ntiles) * 32 + (l & 31);
   const bool colok = col < nrhs;
@@ -175,7 +217,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
     x[3] = r / g.L[2];
   }
   f32x16 accR = {}, accI = {};
-  for (int d = 0; d < 9; ++d) {
+  for (int d = threadIdx.x >> 6; d < 9; d += 4) {
     int nbr = s;
     if (d > 0) {
       const int mu = (d - 1) >> 1;
@@ -207,7 +249,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(bi[kc], v.x, accI, 0, 0, 0);
     }
   }
-  if (!colok) return;
+  if (!reduce_waves(accR, accI) || !colok) return;
   float2* o = out + (size_t)s * kNb * nrhs + col;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -314,8 +356,7 @@ hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, 
 hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
                               const float* scale, hipStream_t s) {
   if (nb != kNb) return hipErrorInvalidValue;
-  const long waves = (long)g.V * ((nrhs + 31) / 32);
-  const int blocks = (int)((waves + 3) / 4);
+  const int blocks = (int)((long)g.V * ((nrhs + 31) / 32));  // one workgroup per (site, 32-column tile)
   const int grid = ((blocks + 7) / 8) * 8;
   if (f16)
     hipLaunchKernelGGL((coarse_mfma_kernel<true>), dim3(grid), dim3(256), 0, s, g, nrhs,
@@ -331,8 +372,7 @@ hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const vo
 hipError_t launch_coarse_mfma_f32(const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
                                   hipStream_t s) {
   if (nb != kNb) return hipErrorInvalidValue;
-  const long waves = (long)g.V * ((nrhs + 31) / 32);
-  const int blocks = (int)((waves + 3) / 4);
+  const int blocks = (int)((long)g.V * ((nrhs + 31) / 32));  // one workgroup per (site, 32-column tile)
   const int grid = ((blocks + 7) / 8) * 8;
   hipLaunchKernelGGL(coarse_mfma_f32_kernel, dim3(grid), dim3(256), 0, s, g, nrhs, static_cast<const float4*>(packed),
                      static_cast<const float2*>(in), static_cast<float2*>(out), blocks);
