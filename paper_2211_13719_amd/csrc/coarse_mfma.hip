@@ -309,7 +309,16 @@ __global__ void colmax_kernel(const float2* __restrict__ in, long rows, int nrhs
     const float2 v = in[e];
     mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
   }
-  if (e0 < n) atomicMax(m + k, __float_as_uint(mx));
+  // one atomic per (workgroup, column): thread j < nrhs combines the threads
+  // t = j, j + nrhs, ... of the workgroup, which all hold column k(j)
+  __shared__ float smax[256];
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  if ((int)threadIdx.x < nrhs) {
+    float c = 0.f;
+    for (int t = threadIdx.x; t < 256; t += nrhs) c = fmaxf(c, smax[t]);
+    atomicMax(m + k, __float_as_uint(c));  // non-negative floats order as their bit patterns
+  }
 }
 // Also clears the reduction words, so that the next call starts from zero
 // without a separate launch.
