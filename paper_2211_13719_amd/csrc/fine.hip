@@ -231,6 +231,52 @@ __device__ __forceinline__ void load_project(const P* __restrict__ in, int nb, i
   }
 }
 
+// One link U_mu(x) (3 x 3 complex, 72 bytes at [site][mu]).  In FP32 the
+// matrix starts on a 16-byte boundary for even mu and 8 bytes past one for
+// odd mu, so it is read as four 16-byte loads and one 8-byte load.
+template <typename T, int MU>
+__device__ __forceinline__ void load_link(const cplx<T>* __restrict__ u, cplx<T> (&uu)[3][3]) {
+  if constexpr (sizeof(T) == 4) {
+    float v[18];
+    if constexpr (MU % 2 == 0) {
+      const float4* q = reinterpret_cast<const float4*>(u);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float4 w = q[i];
+        v[4 * i] = w.x;
+        v[4 * i + 1] = w.y;
+        v[4 * i + 2] = w.z;
+        v[4 * i + 3] = w.w;
+      }
+      const cplx<T> t = u[8];
+      v[16] = t.x;
+      v[17] = t.y;
+    } else {
+      const cplx<T> t = u[0];
+      v[0] = t.x;
+      v[1] = t.y;
+      const float4* q = reinterpret_cast<const float4*>(u + 1);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float4 w = q[i];
+        v[2 + 4 * i] = w.x;
+        v[3 + 4 * i] = w.y;
+        v[4 + 4 * i] = w.z;
+        v[5 + 4 * i] = w.w;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) uu[a][b] = mk<T>(v[2 * (3 * a + b)], v[2 * (3 * a + b) + 1]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) uu[a][b] = u[3 * a + b];
+  }
+}
+
 // acc += (1 - s*gamma_mu)-reconstruction of the transported half spinor w.
 template <typename T, int R, int MU, int S>
 __device__ __forceinline__ void reconstruct(cplx<T> (&acc)[4][3][R], const cplx<T> (&w)[2][3][R]) {
@@ -309,12 +355,8 @@ __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, in
       load_spinor<T, R>(in, nbf, nrhs, k0, p);
       project<T, R, MU, +1>(p, h);
     }
-    const cplx<T>* u = U + ((size_t)site * 4 + MU) * 9;
     cplx<T> uu[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) uu[a][b] = u[3 * a + b];
+    load_link<T, MU>(U + ((size_t)site * 4 + MU) * 9, uu);
     cplx<T> w[2][3][R];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -340,12 +382,8 @@ __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, in
       load_spinor<T, R>(in, nbb, nrhs, k0, p);
       project<T, R, MU, -1>(p, h);
     }
-    const cplx<T>* u = U + ((size_t)nbb * 4 + MU) * 9;
     cplx<T> uu[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) uu[a][b] = u[3 * a + b];
+    load_link<T, MU>(U + ((size_t)nbb * 4 + MU) * 9, uu);
     cplx<T> w[2][3][R];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
