@@ -207,11 +207,15 @@ mrhs_status mrhs_mg_block_orthonormalise(mrhs_mg mg, int32_t level);
 
 /* mrhs_restrict ("project", Sec. 5): coarse = P^dag fine for nrhs fields,
  *   coarse(A, chi n_v + i, k) = sum_{x in A} sum_{c in chi} conj(v_i(x)_c) fine(x, c, k),
- * fine on level `level`, coarse on level + 1; prec MRHS_F32 or MRHS_F64
- * (both fields in that precision, sums in that precision). */
+ * fine on level `level`, coarse on level + 1.  prec MRHS_F32 or MRHS_F64:
+ * both fields and the sums in that precision (vector ALU).  prec MRHS_BF16:
+ * FP32 fields, the basis and the input rounded to BF16 (nearest even) and
+ * multiplied on the matrix cores with FP32 accumulation; needs n_v = 16 and
+ * aggregates of a multiple of 16 sites, else MRHS_ERR_UNSUPPORTED. */
 mrhs_status mrhs_restrict(mrhs_mg mg, int32_t level, void* coarse, const void* fine, int32_t nrhs, mrhs_prec prec);
 /* mrhs_prolong ("promote", Sec. 5): fine = P coarse,
- *   fine(x, c, k) = sum_i v_i(x)_c coarse(A(x), chi(c) n_v + i, k). */
+ *   fine(x, c, k) = sum_i v_i(x)_c coarse(A(x), chi(c) n_v + i, k);
+ * precisions as for mrhs_restrict. */
 mrhs_status mrhs_prolong(mrhs_mg mg, int32_t level, void* fine, const void* coarse, int32_t nrhs, mrhs_prec prec);
 /* mrhs_block_normalise: for every RHS k, aggregate A of step `level` and
  * chirality chi, divides the (A, chi) block of field k by its 2-norm (a zero
@@ -256,8 +260,10 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
  * a = <D r, r> / ||D r||^2 per column, the coarse-grid correction
  * x += P V(R r), the residual r = b - D x and nu_post MR steps; on the
  * coarsest level coarsest_iters MR steps from x = 0.  The fine operator runs
- * in FP32; coarse levels in coarse_prec (MRHS_F32 vector ALU, MRHS_BF16 or
- * MRHS_F16 matrix cores with FP32 accumulation, Nb = 32). */
+ * in FP32; coarse levels in coarse_prec (MRHS_F32 vector ALU or FP32 matrix
+ * cores, MRHS_BF16 or MRHS_F16 matrix cores with FP32 accumulation,
+ * Nb = 32).  With MRHS_BF16 the restriction and prolongation of a step with
+ * n_v = 16 run on the BF16 matrix cores too, otherwise in FP32. */
 typedef struct {
   int32_t nu_pre;
   int32_t nu_post;
