@@ -336,7 +336,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * traversal tiles that divide the lattice (including slabs of Lt / 8 time
  * slices, one per XCD, and columns of the full time extent), two tile orders
  * (lexicographic, Morton), the right-hand sides split into 1, 2 or 4 chunks
- * swept one after the other, at most 1 or 2 workgroups per CU or no limit,
+ * swept one after the other, at most 1, 2 or 3 workgroups per CU or no limit,
  * two register budgets (the compiler's, and one that admits 4 wavefronts per
  * SIMD) and ordinary or non-temporal output stores -- on
  * scratch fields, and keeps the

@@ -51,11 +51,10 @@ __global__ __launch_bounds__(kBlock) void dot_partial(const typename c2<T>::type
     const int k = t % nrhs;
     const long r0 = (long)blockIdx.x * rpb + t / nrhs;
     const long step = (long)gridDim.x * rpb;
-    for (long r = r0; r < rows; r += step) {
-      const long e = r * nrhs + k;
-      const double2 x = widen<T>(a[e]);
+    auto add = [&](const typename c2<T>::type& av, const typename c2<T>::type& bv) {
+      const double2 x = widen<T>(av);
       if constexpr (MODE == 0) {
-        const double2 y = widen<T>(b[e]);
+        const double2 y = widen<T>(bv);
         acc.x = fma(x.x, y.x, acc.x);
         acc.x = fma(x.y, y.y, acc.x);
         acc.y = fma(x.x, y.y, acc.y);
@@ -64,6 +63,25 @@ __global__ __launch_bounds__(kBlock) void dot_partial(const typename c2<T>::type
         acc.x = fma(x.x, x.x, acc.x);
         acc.x = fma(x.y, x.y, acc.x);
       }
+    };
+    long r = r0;
+    // several rows' loads in flight at once (four for one input, two for
+    // two inputs); the sums keep the row order
+    constexpr int UN = MODE == 0 ? 2 : 4;
+    for (; r + (UN - 1) * step < rows; r += UN * step) {
+      typename c2<T>::type av[UN], bv[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const long e = (r + u * step) * nrhs + k;
+        av[u] = a[e];
+        bv[u] = MODE == 0 ? b[e] : av[u];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) add(av[u], bv[u]);
+    }
+    for (; r < rows; r += step) {
+      const long e = r * nrhs + k;
+      add(a[e], MODE == 0 ? b[e] : a[e]);
     }
   }
   red[t] = acc;

@@ -106,7 +106,7 @@ bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int 
     if (arch == a && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] && L[3] == g.L[3] &&
         (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1) &&
         (occ == 0 || occ == 4) && (nt == 0 || nt == 1) && (ch == 1 || ch == 2 || ch == 4) && nrhs % ch == 0 &&
-        (nrhs / ch) % R == 0 && cap >= 0 && cap <= 2) {
+        (nrhs / ch) % R == 0 && cap >= 0 && cap <= 3) {
       out.R = R;
       for (int m = 0; m < 4; ++m) out.T[m] = T[m];
       out.curve = curve;
@@ -225,7 +225,7 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
       std::vector<int> opts;
       if (stage == 0) opts = {1, 2, 4};
       if (stage == 1) opts = {1, 2, 4};
-      if (stage == 2) opts = {0, 1, 2};
+      if (stage == 2) opts = {0, 1, 2, 3};
       if (stage == 3) opts = {0, 4};
       if (stage == 4) opts = {0, 1};
       for (int v : opts) {
