@@ -2,7 +2,7 @@
 """Benchmark of the MRHS Wilson-clover multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu-baseline]
-                    [--tune-cache PATH | --retune]
+                    [--tune-cache PATH | --retune] [--solve-nrhs 12,24] [--m0 M]
 
 One step is one pass over every operator of the hot path, each on its
 workload shape (inputs resident in device memory, all synthetic and seeded):
@@ -22,10 +22,12 @@ The timed region holds exactly K steps, bracketed by device synchronisation.
 `per_op` gives per-operator times, GFLOP/s and algorithmic GB/s from HIP
 events on the stream the kernels run on; `roofline` is for the dominant
 kernel.  After the timed region (not part of `value`), `solve` times the
-mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels,
-graph-replayed V-cycle) on 24^3 x 128 smooth links for a batch of RHS and the
-same solver on one RHS with FP32 coarse levels, in seconds per RHS to a true
-residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on a sample.
+mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels
+and intergrid, graph-replayed V-cycle) on 24^3 x 128 smooth links at the bare
+mass stored in tests/golden/smooth_links_mass.json, for batches of 12 and 24
+RHS, and the same solver on one RHS with FP32 coarse levels, in seconds per
+RHS to a true residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on
+a sample.
 
 Fine-kernel launch configurations come from the autotuner's text cache
 (paper_2211_13719_amd/tuning/fine.txt, tuned on an MI355X); lattices or Nrhs
