@@ -19,7 +19,7 @@ def test_stored_mass_is_consistent():
     assert abs(g["sigma_min"] - 0.01) <= 0.05 * 0.01
     assert m0 > g["m_c_estimate"]
     scan = sorted((float(k), v) for k, v in g["scan"].items())
-    assert any(abs(m - m0) < 1e-9 for m, _ in scan)
+    assert any(abs(m - m0) < 6e-6 for m, _ in scan)  # scan keys carry five decimals
     above = [(m, v) for m, v in scan if m > g["m_c_estimate"]]
     below = [(m, v) for m, v in scan if m < g["m_c_estimate"]]
     assert all(v2 > v1 for (_, v1), (_, v2) in zip(above, above[1:]))
