@@ -69,11 +69,11 @@ FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 # the launch configurations it was counted under.  `roofline.traffic` carries
 # it only while the kernel name, sources and configurations still match.
 FINE_TRAFFIC = {
-    "kernel": "fine_kernel<float, 2, 0, true, true, 0>",
-    "sources": "2b6a54d4e2f02f8b",
-    "configs": {"6": [2, [12, 4, 4, 3], 32], "12": [2, [8, 8, 2, 3], 64], "24": [2, [8, 8, 2, 3], 68],
+    "kernel": "fine_kernel<float, 2, 0, true, true, 0, HIP_vector_type<float, 2u> >",
+    "sources": "aa51ff6b32629ee1",
+    "configs": {"6": [2, [12, 4, 4, 3], 32], "12": [2, [8, 8, 2, 3], 65], "24": [2, [8, 8, 2, 3], 68],
                 "48": [2, [8, 4, 4, 3], 68], "64": [2, [8, 4, 4, 3], 5]},
-    "bytes_per_launch": 5.527e9,
+    "bytes_per_launch": 5.51e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
@@ -105,7 +105,7 @@ def fine_kernel_name(ctx, n):
     R, _, variant, _ = ctx.get_tuning(n)
     R = R or (2 if n % 2 == 0 else 1)
     occ = 4 if variant & 2 else 0
-    return f"fine_kernel<float, {R}, 0, true, true, {occ}>"
+    return f"fine_kernel<float, {R}, 0, true, true, {occ}, HIP_vector_type<float, 2u> >"
 
 
 def cpu_baseline(nrhs_sample=8):
