@@ -242,8 +242,7 @@ mrhs_status mrhs_coarse_get_blocks(mrhs_mg mg, int32_t level, void* blocks, mrhs
 mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
 /* mrhs_coarse_apply (Sec. 6): out = D_c in on coarse level `level`.
  * prec MRHS_F64: FP64 fields and arithmetic; MRHS_F32: FP32 fields and
- * arithmetic (on the FP32 matrix cores for Nb = 32 and nrhs >= 8, else the
- * vector ALU); MRHS_BF16 / MRHS_F16: FP32 fields, blocks and vectors rounded
+ * arithmetic (on the FP32 matrix cores for Nb = 32, else the vector ALU); MRHS_BF16 / MRHS_F16: FP32 fields, blocks and vectors rounded
  * to BF16 / FP16 (nearest even; blocks via FP32) and multiplied on the
  * matrix cores with FP32 accumulation (Nb = 32 only; FP16 vectors are scaled
  * per RHS by a power of two first, exactly undone on output). */

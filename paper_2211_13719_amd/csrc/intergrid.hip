@@ -168,6 +168,42 @@ __global__ __launch_bounds__(256) void prolong_kernel(AggGeom a, int nrhs, const
       if (k0 + k < nrhs) fb[(size_t)c * nrhs + k] = acc[c][k];
 }
 
+// Few right-hand sides (nrhs <= 2): one thread per fine row (site, component),
+// so that a wavefront reads 64 consecutive basis rows (n_v contiguous values
+// each) instead of 64 rows' worth of scattered single values; the coarse
+// values of the aggregate are shared through the cache.  Same arithmetic and
+// order per output as prolong_kernel.
+template <typename T, int NV, int NR>
+__global__ __launch_bounds__(256) void prolong_row_kernel(AggGeom a, int h, const cplx<T>* __restrict__ basis,
+                                                          const cplx<T>* __restrict__ y, cplx<T>* __restrict__ f) {
+  const int ncomp = 2 * h;
+  const long row = (long)blockIdx.x * 256 + threadIdx.x;
+  if (row >= (long)a.V * ncomp) return;
+  const int s = (int)(row / ncomp);
+  const int c = (int)(row - (long)s * ncomp);
+  const int chi = c / h;
+  const int A = site_agg(a, s);
+  const cplx<T>* bb = basis + row * NV;
+  const cplx<T>* yb = y + ((size_t)A * 2 * NV + chi * NV) * NR;
+  cplx<T> acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const cplx<T> b = bb[i];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const cplx<T> yv = yb[(size_t)i * NR + k];
+      acc[k].x = fma(b.x, yv.x, acc[k].x);
+      acc[k].x = fma(-b.y, yv.y, acc[k].x);
+      acc[k].y = fma(b.x, yv.y, acc[k].y);
+      acc[k].y = fma(b.y, yv.x, acc[k].y);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) f[row * NR + k] = acc[k];
+}
+
 // ---- block orthonormalisation (FP64) --------------------------------------------------
 // A (aggregate, chirality) block is rank-deficient when the part of v_i left
 // after projecting out v_0..v_{i-1} is below kRankTol times |v_i|.
@@ -373,6 +409,19 @@ hipError_t restrict_nv(const AggGeom& a, int h, int nrhs, const void* basis, con
 
 template <typename T, int NV, int H>
 hipError_t prolong_nvh(const AggGeom& a, int nrhs, const void* basis, const void* y, void* f, hipStream_t s) {
+  if (nrhs <= 2) {
+    const long rows = (long)a.V * 2 * H;
+    const int nb = (int)((rows + 255) / 256);
+    if (nrhs == 1)
+      hipLaunchKernelGGL((prolong_row_kernel<T, NV, 1>), dim3(nb), dim3(256), 0, s, a, H,
+                         static_cast<const cplx<T>*>(basis), static_cast<const cplx<T>*>(y),
+                         static_cast<cplx<T>*>(f));
+    else
+      hipLaunchKernelGGL((prolong_row_kernel<T, NV, 2>), dim3(nb), dim3(256), 0, s, a, H,
+                         static_cast<const cplx<T>*>(basis), static_cast<const cplx<T>*>(y),
+                         static_cast<cplx<T>*>(f));
+    return hipGetLastError();
+  }
   constexpr int R = (H > 8) ? 2 : 4;
   const long threads = (long)a.V * 2 * ((nrhs + R - 1) / R);
   const int nb = (int)((threads + 255) / 256);

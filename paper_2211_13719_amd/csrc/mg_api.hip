@@ -464,9 +464,10 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
       e = launch_coarse_valu(1, L.g, L.ncomp, nrhs, L.BT64.p, in, out, DirFilter{}, ctx->stream);
       break;
     case MRHS_F32:
-      // matrix cores from 8 right-hand sides on (a 32-column tile would idle
-      // below that); the vector-ALU kernel, bound by the block bytes, below
-      if (mfma_supported(L.ncomp) && nrhs >= 8)
+      // FP32 matrix cores whenever Nb = 32: with few right-hand sides most of
+      // the 32-column tile idles, but the stencil is bound by block bytes and
+      // latency, where the direction-split matrix-core kernel does better
+      if (mfma_supported(L.ncomp))
         e = launch_coarse_mfma_f32(L.g, L.ncomp, nrhs, L.Bf32p.p, in, out, ctx->stream);
       else
         e = launch_coarse_valu(0, L.g, L.ncomp, nrhs, L.BT32.p, in, out, DirFilter{}, ctx->stream);
