@@ -7,8 +7,8 @@
 // right-hand side (batched, not block Krylov): per-RHS Hessenberg matrices
 // and Givens rotations live on the host, the vectors on the device, and all
 // inner products of one Gram-Schmidt step are computed in one pass (classical
-// Gram-Schmidt, repeated once when the first pass lost more than half of the
-// vector's norm).  The preconditioned directions Z are stored in
+// Gram-Schmidt, repeated once when the first pass left less than reorth_eta
+// of the vector's squared norm for some RHS).  The preconditioned directions Z are stored in
 // FP32; since the same FP32 values enter both D Z and the update x += Z y, the
 // Arnoldi relation holds to FP64 rounding and the FP64 true residual can reach
 // 1e-10 although the preconditioner works in lower precision.
@@ -18,16 +18,19 @@
 // coarse-grid correction x += P V(R r), the residual r = b - D x, nu_post MR
 // steps.  On the coarsest level: coarsest_iters MR steps from zero.  The fine
 // operator is the FP32 Wilson-clover kernel, coarse operators the stencil in
-// the requested arithmetic (FP32 vector ALU, or BF16/FP16 matrix cores with
-// FP32 accumulation).  The MR step sizes alpha_k = <D r_k, r_k> / ||D r_k||^2
+// the requested arithmetic (FP32, or BF16/FP16 matrix cores with FP32
+// accumulation; with BF16 coarse levels the intergrid operators of n_v = 16
+// steps run on the BF16 matrix cores as well).  The MR step sizes alpha_k = <D r_k, r_k> / ||D r_k||^2
 // are computed and consumed on the device, so one V-cycle is a fixed sequence
 // of kernel launches that can be captured once into a HIP graph and replayed.
 //
 // Setup (the paper does not describe one): starting from the caller's basis
 // vectors on each level, setup_iters sweeps of MR on the homogeneous system
 // D x = 0 (each sweep multiplies the vectors by prod_i (1 - alpha_i D), which
-// damps the high modes and keeps the near-null space), column normalisation,
-// block orthonormalisation in FP64 and the Galerkin coarse operator.
+// damps the high modes and keeps the near-null space), a Cholesky-QR of the
+// test vectors after every sweep (so that they stay independent), block
+// orthonormalisation in FP64 and the Galerkin coarse operator; optionally
+// passes of inverse iteration with the hierarchy's own V-cycle.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
