@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
   const int s = (int)(w / ntiles);
   const int col = (int)(w % ntiles) * 32 + (l & 31);
   const bool colok = col < nrhs;
+  const int colc = colok ? col : nrhs - 1;
   const int jh = 8 * (l >> 5);
   const float sc = (F16 && colok) ? scale[col] : 1.0f;
 
@@ -157,17 +158,27 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
       nbr = s + (cw - x[mu]) * g.stride[mu];
     }
     const uint4* bp = Bp + ((size_t)s * 9 + d) * 256;
-    const float2* e = in + (size_t)nbr * kNb * nrhs + col;
+    // every load of the direction first, from a clamped column (no branch
+    // around the loads); columns past nrhs are zeroed and never stored
+    const float2* e = in + (size_t)nbr * kNb * nrhs + colc;
+    uint4 bl[4];
+    float2 ev[2][8];
 #pragma unroll
     for (int kc = 0; kc < 2; ++kc) {
-      const uint4 br = bp[(kc * 2 + 0) * 64 + l];
-      const uint4 bi = bp[(kc * 2 + 1) * 64 + l];
+      bl[2 * kc] = bp[(kc * 2 + 0) * 64 + l];
+      bl[2 * kc + 1] = bp[(kc * 2 + 1) * 64 + l];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ev[kc][q] = e[(size_t)(kc * 16 + jh + q) * nrhs];
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const uint4 br = bl[2 * kc];
+      const uint4 bi = bl[2 * kc + 1];
       float er[8], ei[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const float2 v = colok ? e[(size_t)(kc * 16 + jh + q) * nrhs] : make_float2(0.f, 0.f);
-        er[q] = v.x * sc;
-        ei[q] = v.y * sc;
+        er[q] = colok ? ev[kc][q].x * sc : 0.f;
+        ei[q] = colok ? ev[kc][q].y * sc : 0.f;
       }
       const vec vr = O::cvt(er), vi = O::cvt(ei);
       const uint4 nbi = make_uint4(bi.x ^ 0x80008000u, bi.y ^ 0x80008000u, bi.z ^ 0x80008000u, bi.w ^ 0x80008000u);
@@ -205,6 +216,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
   const int s = (int)(w / ntiles);
   const int col = (int)(w % ntiles) * 32 + (l & 31);
   const bool colok = col < nrhs;
+  const int colc = colok ? col : nrhs - 1;
   const int jh = l >> 5;
   int x[4];
   {
@@ -239,10 +251,15 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
       bi[4 * q + 2] = b.z;
       bi[4 * q + 3] = b.w;
     }
-    const float2* e = in + (size_t)nbr * kNb * nrhs + col;
+    // all vector loads first, from a clamped column (no branch around the
+    // loads); columns past nrhs are zeroed and never stored
+    const float2* e = in + (size_t)nbr * kNb * nrhs + colc;
+    float2 ev[16];
+#pragma unroll
+    for (int kc = 0; kc < 16; ++kc) ev[kc] = e[(size_t)(2 * kc + jh) * nrhs];
 #pragma unroll
     for (int kc = 0; kc < 16; ++kc) {
-      const float2 v = colok ? e[(size_t)(2 * kc + jh) * nrhs] : make_float2(0.f, 0.f);
+      const float2 v = colok ? ev[kc] : make_float2(0.f, 0.f);
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(br[kc], v.x, accR, 0, 0, 0);
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-bi[kc], v.y, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(br[kc], v.y, accI, 0, 0, 0);

@@ -464,6 +464,9 @@ hipError_t launch_restrict(int prec64, const AggGeom& a, int h, int nv, int nrhs
         return restrict_nv<double, 16>(a, h, nrhs, basis, f, y, s);
     }
   } else {
+    // from 4 right-hand sides on, n_v = 16 goes to the FP32 matrix cores
+    if (nv == 16 && nrhs >= 4 && intergrid_mfma_supported(a, h, nv))
+      return launch_restrict_f32mfma(a, h, nrhs, basis, f, y, s);
     switch (nv) {
       case 4:
         return restrict_nv<float, 4>(a, h, nrhs, basis, f, y, s);
@@ -488,6 +491,8 @@ hipError_t launch_prolong(int prec64, const AggGeom& a, int h, int nv, int nrhs,
         return prolong_nv<double, 16>(a, h, nrhs, basis, y, f, s);
     }
   } else {
+    if (nv == 16 && nrhs >= 4 && intergrid_mfma_supported(a, h, nv))
+      return launch_prolong_f32mfma(a, h, nrhs, basis, y, f, s);
     switch (nv) {
       case 4:
         return prolong_nv<float, 4>(a, h, nrhs, basis, y, f, s);

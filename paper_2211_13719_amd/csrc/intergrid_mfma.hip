@@ -31,6 +31,11 @@
 // fields stay FP32 in memory and are rounded to BF16 on the fly by the
 // hardware conversion (round to nearest even).  Products of BF16 values are
 // exact in FP32, so the only other rounding is the FP32 accumulation.
+//
+// The FP32 variants use v_mfma_f32_32x32x2_f32 on the FP32 basis with the
+// same real form: one contraction step is one row r (restrict) or one basis
+// index i (prolong) with its real and imaginary part as the two k values,
+// A[l % 32][k = l / 32], B[k = l / 32][l % 32].
 #include "agg.h"
 #include "internal.h"
 #include "rounding.h"
@@ -81,23 +86,36 @@ __global__ __launch_bounds__(256) void restrict_bf16_kernel(AggGeom a, int h, in
   const bool imrow = m >= 16;
   const bool fast = (a.b[0] & 3) == 0;
   f32x16 acc = {};
-  for (int s = s0; s < s1; ++s) {
-    const int c = s / per_c;
-    const int l0 = (s - c * per_c) * 8 + 4 * g;
-    const int site0 = agg_site(a, A, l0);
-    u32x4 av;
-    float bv[8];
+  // four MFMA steps' loads in flight together, from clamped addresses with
+  // the operands zeroed instead of branching (steps past the end and
+  // columns past nrhs add zero products)
+  constexpr int U = 4;
+  const int kc = kin ? k : nrhs - 1;
+  for (int s = s0; s < s1; s += U) {
+    u32x4 av[U];
+    float bv[U][8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int site = agg_site_j(a, A, l0, j, site0, fast);
-      const size_t row = (size_t)site * ncomp + chi * h + c;
-      const unsigned w = W[row * kNV + i];
-      av[j] = imrow ? (((w >> 16) ^ 0x8000u) | (w << 16)) : w;
-      const float2 v = kin ? f[row * nrhs + k] : make_float2(0.f, 0.f);
-      bv[2 * j] = v.x;
-      bv[2 * j + 1] = v.y;
+    for (int u = 0; u < U; ++u) {
+      const bool in = s + u < s1;
+      const int su = in ? s + u : s0;
+      const int c = su / per_c;
+      const int l0 = (su - c * per_c) * 8 + 4 * g;
+      const int site0 = agg_site(a, A, l0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int site = agg_site_j(a, A, l0, j, site0, fast);
+        const size_t row = (size_t)site * ncomp + chi * h + c;
+        const unsigned w = W[row * kNV + i];
+        const float2 v = f[row * nrhs + kc];
+        const unsigned x = imrow ? (((w >> 16) ^ 0x8000u) | (w << 16)) : w;
+        av[u][j] = in ? x : 0u;
+        bv[u][2 * j] = (in && kin) ? v.x : 0.f;
+        bv[u][2 * j + 1] = (in && kin) ? v.y : 0.f;
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), to_bf16(bv), acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[u]), to_bf16(bv[u]), acc, 0, 0, 0);
   }
   if (wave > 0) {
 #pragma unroll
@@ -151,31 +169,204 @@ __global__ __launch_bounds__(256) void prolong_bf16_kernel(AggGeom a, int h, int
     B[st] = to_bf16(bv);
   }
   const int ntr = h * nsa / 16;
-  for (int t = wave; t < ntr; t += 4) {
-    const int r0 = t * 16;
-    const int c = r0 / nsa;
-    const int l0 = r0 - c * nsa;
-    // A operand: row r0 + (m & 15)
-    const int lr = l0 + (m & 15);
-    const size_t arow = (size_t)agg_site(a, A, lr) * ncomp + chi * h + c;
-    f32x16 acc = {};
+  // two row tiles (t and t + 4) per pass, their basis loads in flight
+  // together (a missing second tile loads the first one's rows again and
+  // writes nothing)
+  for (int t0 = wave; t0 < ntr; t0 += 8) {
+    u32x4 wt[2][2];
 #pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      u32x4 w = *reinterpret_cast<const u32x4*>(W + arow * kNV + st * 8 + 4 * g);
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + 4 * u < ntr ? t0 + 4 * u : t0;
+      const int r0 = t * 16;
+      const int c = r0 / nsa;
+      const int l0 = r0 - c * nsa;
+      // A operand: row r0 + (m & 15)
+      const size_t arow = (size_t)agg_site(a, A, l0 + (m & 15)) * ncomp + chi * h + c;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) w[j] = imrow ? ((w[j] >> 16) | (w[j] << 16)) : (w[j] ^ 0x80000000u);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[st], acc, 0, 0, 0);
+      for (int st = 0; st < 2; ++st) wt[u][st] = *reinterpret_cast<const u32x4*>(W + arow * kNV + st * 8 + 4 * g);
     }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + 4 * u;
+      const int r0 = t * 16;
+      const int c = r0 / nsa;
+      const int l0 = r0 - c * nsa;
+      f32x16 acc = {};
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        u32x4 w = wt[u][st];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = imrow ? ((w[j] >> 16) | (w[j] << 16)) : (w[j] ^ 0x80000000u);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[st], acc, 0, 0, 0);
+      }
+      if (kin && t < ntr) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const int lb = l0 + 8 * half + 4 * g;
+          const int sb = agg_site(a, A, lb);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int site = agg_site_j(a, A, lb, j, sb, fast);
+            const int p = 4 * half + j;
+            f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// FP32 restrict on the FP32 matrix cores; workgroup and wavefront split as
+// in restrict_bf16_kernel, the rows of (A, chi) taken site by site (all h
+// components of a site in turn).  H > 0 fixes h at compile time, so that the
+// loads of a site are issued together (H = 0: any h).
+template <int H>
+__global__ __launch_bounds__(256) void restrict_f32_kernel(AggGeom a, int h, int nrhs, int ntile,
+                                                           const float2* __restrict__ W,
+                                                           const float2* __restrict__ f, float2* __restrict__ y) {
+  __shared__ float red[3][64][16];
+  const int bid = blockIdx.x;
+  const int tile = bid % ntile;
+  const int chi = (bid / ntile) & 1;
+  const int A = bid / ntile >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 31, g = lane >> 5;
+  const int ncomp = 2 * h;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  const int l0 = wave * nsa / 4, l1 = (wave + 1) * nsa / 4;
+  const int k = tile * 32 + m;
+  const bool kin = k < nrhs;
+  const int i = m & 15;
+  const bool imrow = m >= 16;
+  f32x16 acc = {};
+  if constexpr (H > 0) {
+    // the loads of US sites in flight together (the compiler does not
+    // unroll a loop around the matrix instruction by itself).  Addresses are
+    // clamped to valid ones and the operands zeroed instead of branching, so
+    // that the loads stay one straight block: a site past the end and a
+    // column past nrhs add zero products.
+    constexpr int US = H <= 8 ? 4 : 1;
+    const int kc = kin ? k : nrhs - 1;
+    for (int l = l0; l < l1; l += US) {
+      float av[US][H], bv[US][H];
+#pragma unroll
+      for (int u = 0; u < US; ++u) {
+        const bool in = l + u < l1;
+        const size_t row0 = (size_t)agg_site(a, A, in ? l + u : l0) * ncomp + chi * H;
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+          const float2 w = W[(row0 + c) * kNV + i];
+          const float2 v = f[(row0 + c) * nrhs + kc];
+          // g = 0: coefficient of Re f, g = 1: of Im f
+          const float x = imrow ? (g ? w.x : -w.y) : (g ? w.y : w.x);
+          av[u][c] = in ? x : 0.f;
+          bv[u][c] = (in && kin) ? (g ? v.y : v.x) : 0.f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < US; ++u)
+#pragma unroll
+        for (int c = 0; c < H; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u][c], bv[u][c], acc, 0, 0, 0);
+    }
+  } else {
+    for (int l = l0; l < l1; ++l) {
+      const size_t row0 = (size_t)agg_site(a, A, l) * ncomp + chi * h;
+      for (int c = 0; c < h; ++c) {
+        const float2 wc = W[(row0 + c) * kNV + i];
+        const float2 vc = kin ? f[(row0 + c) * nrhs + k] : make_float2(0.f, 0.f);
+        const float av = imrow ? (g ? wc.x : -wc.y) : (g ? wc.y : wc.x);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g ? vc.y : vc.x, acc, 0, 0, 0);
+      }
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int p = 0; p < 16; ++p) red[wave - 1][lane][p] = acc[p];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int p = 0; p < 16; ++p) acc[p] += red[w][lane][p];
     if (kin) {
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int lb = l0 + 8 * half + 4 * g;
-        const int sb = agg_site(a, A, lb);
+      for (int p = 0; p < 8; ++p) {
+        const int r = 8 * (p / 4) + 4 * g + (p % 4);
+        y[((size_t)A * 2 * kNV + chi * kNV + r) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
+      }
+    }
+  }
+}
+
+// FP32 prolong on the FP32 matrix cores: as prolong_bf16_kernel, sixteen
+// contraction steps (one per basis index) per 16-row tile.
+__global__ __launch_bounds__(256) void prolong_f32_kernel(AggGeom a, int h, int nrhs, int ntile,
+                                                          const float2* __restrict__ W,
+                                                          const float2* __restrict__ y, float2* __restrict__ f) {
+  const int bid = blockIdx.x;
+  const int tile = bid % ntile;
+  const int chi = (bid / ntile) & 1;
+  const int A = bid / ntile >> 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 31, g = lane >> 5;
+  const int ncomp = 2 * h;
+  const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  const int k = tile * 32 + m;
+  const bool kin = k < nrhs;
+  const bool imrow = m >= 16;
+  const bool fast = (a.b[0] & 3) == 0;
+  float bv[kNV];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int site = agg_site_j(a, A, lb, j, sb, fast);
-          const int p = 4 * half + j;
-          f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
+  for (int i = 0; i < kNV; ++i) {
+    const float2 v = kin ? y[((size_t)A * 2 * kNV + chi * kNV + i) * nrhs + k] : make_float2(0.f, 0.f);
+    bv[i] = g ? v.y : v.x;
+  }
+  const int ntr = h * nsa / 16;
+  // two row tiles (t and t + 4) per pass with their basis loads in flight
+  // together (a missing second tile loads the first one's rows again and
+  // writes nothing)
+  for (int t0 = wave; t0 < ntr; t0 += 8) {
+    float4 wt[2][kNV / 2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + 4 * u < ntr ? t0 + 4 * u : t0;
+      const int r0 = t * 16;
+      const int c = r0 / nsa;
+      const int lb0 = r0 - c * nsa;
+      const size_t arow = (size_t)agg_site(a, A, lb0 + (m & 15)) * ncomp + chi * h + c;
+      const float4* wr = reinterpret_cast<const float4*>(W + arow * kNV);
+#pragma unroll
+      for (int q = 0; q < kNV / 2; ++q) wt[u][q] = wr[q];  // basis values i = 2q and 2q + 1
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + 4 * u;
+      const int r0 = t * 16;
+      const int c = r0 / nsa;
+      const int lb0 = r0 - c * nsa;
+      f32x16 acc = {};
+#pragma unroll
+      for (int q = 0; q < kNV / 2; ++q) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float wre = e ? wt[u][q].z : wt[u][q].x, wim = e ? wt[u][q].w : wt[u][q].y;
+          // g = 0: coefficient of Re y, g = 1: of Im y
+          const float av = imrow ? (g ? wre : wim) : (g ? -wim : wre);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[2 * q + e], acc, 0, 0, 0);
+        }
+      }
+      if (kin && t < ntr) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const int lb = lb0 + 8 * half + 4 * g;
+          const int sb = agg_site(a, A, lb);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int site = agg_site_j(a, A, lb, j, sb, fast);
+            const int p = 4 * half + j;
+            f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
+          }
         }
       }
     }
@@ -219,6 +410,32 @@ hipError_t launch_prolong_bf16(const AggGeom& a, int h, int nrhs, const void* Wb
   const int ntile = (nrhs + 31) / 32;
   hipLaunchKernelGGL(prolong_bf16_kernel, dim3((unsigned)(a.Vc * 2 * ntile)), dim3(256), 0, s, a, h, nrhs, ntile,
                      static_cast<const unsigned*>(Wbf16), static_cast<const float2*>(y), static_cast<float2*>(f));
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_f32mfma(const AggGeom& a, int h, int nrhs, const void* W32, const void* f, void* y,
+                                   hipStream_t s) {
+  if (!intergrid_mfma_supported(a, h, kNV)) return hipErrorInvalidValue;
+  const int ntile = (nrhs + 31) / 32;
+  const dim3 grid((unsigned)(a.Vc * 2 * ntile));
+  const auto* w = static_cast<const float2*>(W32);
+  const auto* fi = static_cast<const float2*>(f);
+  auto* yo = static_cast<float2*>(y);
+  if (h == 6)
+    hipLaunchKernelGGL(restrict_f32_kernel<6>, grid, dim3(256), 0, s, a, h, nrhs, ntile, w, fi, yo);
+  else if (h == 16)
+    hipLaunchKernelGGL(restrict_f32_kernel<16>, grid, dim3(256), 0, s, a, h, nrhs, ntile, w, fi, yo);
+  else
+    hipLaunchKernelGGL(restrict_f32_kernel<0>, grid, dim3(256), 0, s, a, h, nrhs, ntile, w, fi, yo);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_f32mfma(const AggGeom& a, int h, int nrhs, const void* W32, const void* y, void* f,
+                                  hipStream_t s) {
+  if (!intergrid_mfma_supported(a, h, kNV)) return hipErrorInvalidValue;
+  const int ntile = (nrhs + 31) / 32;
+  hipLaunchKernelGGL(prolong_f32_kernel, dim3((unsigned)(a.Vc * 2 * ntile)), dim3(256), 0, s, a, h, nrhs, ntile,
+                     static_cast<const float2*>(W32), static_cast<const float2*>(y), static_cast<float2*>(f));
   return hipGetLastError();
 }
 

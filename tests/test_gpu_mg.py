@@ -123,6 +123,29 @@ def test_restrict_prolong_coarse_level(gpu_lib):
     assert rel(host(fo), O.prolong(basis, yc, d1, (2, 1, 2, 1))) < 1e-12
 
 
+@pytest.mark.parametrize("nrhs", [3, 4, 33])
+def test_restrict_prolong_coarse_level_f32(gpu_lib, nrhs):
+    """FP32 step 1 with n_v = 16 on 16-site aggregates (the matrix-core intergrid from 4 RHS on)."""
+    import torch
+
+    dims = (8, 8, 8, 8)
+    blocks = [(2, 2, 2, 2), (2, 2, 2, 2)]
+    ctx, mg = make_mg(gpu_lib, dims, blocks, [16, 16])
+    d1 = mg.dims[1]
+    V1 = mg.volume[1]
+    basis = O.block_orthonormalise(synth.gaussian_vectors(V1, 16, 32, 12), d1, blocks[1])
+    mg.set_basis(1, basis)
+    b_used = basis.astype(np.complex64).astype(np.complex128)
+    f = synth.coarse_source(V1, 32, nrhs, 13, np.complex64)
+    y = torch.empty((mg.volume[2], 32, nrhs), dtype=torch.complex64, device="cuda")
+    mg.restrict(1, y, dev(f))
+    assert rel(host(y), O.restrict(b_used, f, d1, blocks[1])) < 1e-6
+    yc = synth.coarse_source(mg.volume[2], 32, nrhs, 14, np.complex64)
+    fo = torch.empty((V1, 32, nrhs), dtype=torch.complex64, device="cuda")
+    mg.prolong(1, fo, dev(yc))
+    assert rel(host(fo), O.prolong(b_used, yc, d1, blocks[1])) < 1e-6
+
+
 @pytest.mark.parametrize("nrhs", [1, 7, 24, 33, 64])
 def test_restrict_prolong_bf16(gpu_lib, nrhs):
     """Matrix-core BF16 restrict/prolong (FP32 fields, FP32 accumulation) on
