@@ -162,57 +162,61 @@ __global__ __launch_bounds__(256) void prolong_bf16_kernel(AggGeom a, int h, int
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = st * 8 + 4 * g + j;
-      const float2 v = kin ? y[((size_t)A * 2 * kNV + chi * kNV + i) * nrhs + k] : make_float2(0.f, 0.f);
-      bv[2 * j] = v.x;
-      bv[2 * j + 1] = v.y;
+      // clamped column, zeroed past nrhs (no branch around the loads)
+      const float2 v = y[((size_t)A * 2 * kNV + chi * kNV + i) * nrhs + (kin ? k : nrhs - 1)];
+      bv[2 * j] = kin ? v.x : 0.f;
+      bv[2 * j + 1] = kin ? v.y : 0.f;
     }
     B[st] = to_bf16(bv);
   }
   const int ntr = h * nsa / 16;
-  // two row tiles (t and t + 4) per pass, their basis loads in flight
-  // together (a missing second tile loads the first one's rows again and
-  // writes nothing)
-  for (int t0 = wave; t0 < ntr; t0 += 8) {
-    u32x4 wt[2][2];
+  // Software pipeline over the row tiles of the wavefront (t, t + 4, ...):
+  // the basis loads of the next tile are issued before the matrix
+  // instructions of the current one.  A tile past the end loads the first
+  // tile's rows again and writes nothing.
+  auto load = [&](int t, u32x4 (&wt)[2]) {
+    const int tc = t < ntr ? t : wave;
+    const int r0 = tc * 16;
+    const int c = r0 / nsa;
+    const int l0 = r0 - c * nsa;
+    // A operand: row r0 + (m & 15)
+    const size_t arow = (size_t)agg_site(a, A, l0 + (m & 15)) * ncomp + chi * h + c;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + 4 * u < ntr ? t0 + 4 * u : t0;
-      const int r0 = t * 16;
-      const int c = r0 / nsa;
-      const int l0 = r0 - c * nsa;
-      // A operand: row r0 + (m & 15)
-      const size_t arow = (size_t)agg_site(a, A, l0 + (m & 15)) * ncomp + chi * h + c;
+    for (int st = 0; st < 2; ++st) wt[st] = *reinterpret_cast<const u32x4*>(W + arow * kNV + st * 8 + 4 * g);
+  };
+  auto row_tile = [&](int t, const u32x4 (&wt)[2]) {
+    const int r0 = t * 16;
+    const int c = r0 / nsa;
+    const int l0 = r0 - c * nsa;
+    f32x16 acc = {};
 #pragma unroll
-      for (int st = 0; st < 2; ++st) wt[u][st] = *reinterpret_cast<const u32x4*>(W + arow * kNV + st * 8 + 4 * g);
+    for (int st = 0; st < 2; ++st) {
+      u32x4 w = wt[st];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = imrow ? ((w[j] >> 16) | (w[j] << 16)) : (w[j] ^ 0x80000000u);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[st], acc, 0, 0, 0);
     }
+    if (kin && t < ntr) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + 4 * u;
-      const int r0 = t * 16;
-      const int c = r0 / nsa;
-      const int l0 = r0 - c * nsa;
-      f32x16 acc = {};
+      for (int half = 0; half < 2; ++half) {
+        const int lb = l0 + 8 * half + 4 * g;
+        const int sb = agg_site(a, A, lb);
 #pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        u32x4 w = wt[u][st];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = imrow ? ((w[j] >> 16) | (w[j] << 16)) : (w[j] ^ 0x80000000u);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[st], acc, 0, 0, 0);
-      }
-      if (kin && t < ntr) {
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const int lb = l0 + 8 * half + 4 * g;
-          const int sb = agg_site(a, A, lb);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int site = agg_site_j(a, A, lb, j, sb, fast);
-            const int p = 4 * half + j;
-            f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
-          }
+        for (int j = 0; j < 4; ++j) {
+          const int site = agg_site_j(a, A, lb, j, sb, fast);
+          const int p = 4 * half + j;
+          f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
         }
       }
     }
+  };
+  u32x4 wA[2], wB[2];
+  if (wave < ntr) load(wave, wA);
+  for (int t = wave; t < ntr; t += 8) {
+    load(t + 4, wB);
+    row_tile(t, wA);
+    load(t + 8, wA);
+    row_tile(t + 4, wB);
   }
 }
 
@@ -240,33 +244,46 @@ __global__ __launch_bounds__(256) void restrict_f32_kernel(AggGeom a, int h, int
   const bool imrow = m >= 16;
   f32x16 acc = {};
   if constexpr (H > 0) {
-    // the loads of US sites in flight together (the compiler does not
-    // unroll a loop around the matrix instruction by itself).  Addresses are
-    // clamped to valid ones and the operands zeroed instead of branching, so
-    // that the loads stay one straight block: a site past the end and a
+    // Software pipeline over the sites of the wavefront: the loads of the
+    // next US sites are issued before the matrix instructions of the current
+    // ones (the compiler does not unroll a loop around the matrix
+    // instruction by itself).  Addresses are clamped to valid ones and the
+    // operands zeroed instead of branching, so a site past the end and a
     // column past nrhs add zero products.
-    constexpr int US = H <= 8 ? 4 : 1;
+    constexpr int US = H <= 8 ? 2 : 1;
     const int kc = kin ? k : nrhs - 1;
-    for (int l = l0; l < l1; l += US) {
-      float av[US][H], bv[US][H];
+    auto load = [&](int lb, float2 (&w)[US][H], float2 (&v)[US][H]) {
 #pragma unroll
       for (int u = 0; u < US; ++u) {
-        const bool in = l + u < l1;
-        const size_t row0 = (size_t)agg_site(a, A, in ? l + u : l0) * ncomp + chi * H;
+        const size_t row0 = (size_t)agg_site(a, A, lb + u < l1 ? lb + u : l0) * ncomp + chi * H;
 #pragma unroll
         for (int c = 0; c < H; ++c) {
-          const float2 w = W[(row0 + c) * kNV + i];
-          const float2 v = f[(row0 + c) * nrhs + kc];
-          // g = 0: coefficient of Re f, g = 1: of Im f
-          const float x = imrow ? (g ? w.x : -w.y) : (g ? w.y : w.x);
-          av[u][c] = in ? x : 0.f;
-          bv[u][c] = (in && kin) ? (g ? v.y : v.x) : 0.f;
+          w[u][c] = W[(row0 + c) * kNV + i];
+          v[u][c] = f[(row0 + c) * nrhs + kc];
         }
       }
+    };
+    auto mma = [&](int lb, const float2 (&w)[US][H], const float2 (&v)[US][H]) {
 #pragma unroll
-      for (int u = 0; u < US; ++u)
+      for (int u = 0; u < US; ++u) {
+        const bool in = lb + u < l1;
 #pragma unroll
-        for (int c = 0; c < H; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u][c], bv[u][c], acc, 0, 0, 0);
+        for (int c = 0; c < H; ++c) {
+          // g = 0: coefficient of Re f, g = 1: of Im f
+          const float x = imrow ? (g ? w[u][c].x : -w[u][c].y) : (g ? w[u][c].y : w[u][c].x);
+          const float av = in ? x : 0.f;
+          const float bv = (in && kin) ? (g ? v[u][c].y : v[u][c].x) : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+      }
+    };
+    float2 wA[US][H], vA[US][H], wB[US][H], vB[US][H];
+    if (l0 < l1) load(l0, wA, vA);
+    for (int l = l0; l < l1; l += 2 * US) {
+      load(l + US, wB, vB);
+      mma(l, wA, vA);
+      load(l + 2 * US, wA, vA);
+      mma(l + US, wB, vB);
     }
   } else {
     for (int l = l0; l < l1; ++l) {
@@ -319,57 +336,63 @@ __global__ __launch_bounds__(256) void prolong_f32_kernel(AggGeom a, int h, int 
   float bv[kNV];
 #pragma unroll
   for (int i = 0; i < kNV; ++i) {
-    const float2 v = kin ? y[((size_t)A * 2 * kNV + chi * kNV + i) * nrhs + k] : make_float2(0.f, 0.f);
+    // a column past nrhs reads column nrhs - 1: B column k feeds only output
+    // column k, which is not stored (and a select here would let the
+    // compiler put each load behind a branch of its own)
+    const float2 v = y[((size_t)A * 2 * kNV + chi * kNV + i) * nrhs + (kin ? k : nrhs - 1)];
     bv[i] = g ? v.y : v.x;
   }
   const int ntr = h * nsa / 16;
-  // two row tiles (t and t + 4) per pass with their basis loads in flight
-  // together (a missing second tile loads the first one's rows again and
-  // writes nothing)
-  for (int t0 = wave; t0 < ntr; t0 += 8) {
-    float4 wt[2][kNV / 2];
+  // Software pipeline over the row tiles of the wavefront (t, t + 4, ...):
+  // the basis loads of the next tile are issued before the matrix
+  // instructions of the current one.  A tile past the end loads the first
+  // tile's rows again and writes nothing.
+  auto load = [&](int t, float4 (&wt)[kNV / 2]) {
+    const int tc = t < ntr ? t : wave;
+    const int r0 = tc * 16;
+    const int c = r0 / nsa;
+    const int lb0 = r0 - c * nsa;
+    const size_t arow = (size_t)agg_site(a, A, lb0 + (m & 15)) * ncomp + chi * h + c;
+    const float4* wr = reinterpret_cast<const float4*>(W + arow * kNV);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + 4 * u < ntr ? t0 + 4 * u : t0;
-      const int r0 = t * 16;
-      const int c = r0 / nsa;
-      const int lb0 = r0 - c * nsa;
-      const size_t arow = (size_t)agg_site(a, A, lb0 + (m & 15)) * ncomp + chi * h + c;
-      const float4* wr = reinterpret_cast<const float4*>(W + arow * kNV);
+    for (int q = 0; q < kNV / 2; ++q) wt[q] = wr[q];  // basis values i = 2q and 2q + 1
+  };
+  auto row_tile = [&](int t, const float4 (&wt)[kNV / 2]) {
+    const int r0 = t * 16;
+    const int c = r0 / nsa;
+    const int lb0 = r0 - c * nsa;
+    f32x16 acc = {};
 #pragma unroll
-      for (int q = 0; q < kNV / 2; ++q) wt[u][q] = wr[q];  // basis values i = 2q and 2q + 1
-    }
+    for (int q = 0; q < kNV / 2; ++q) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + 4 * u;
-      const int r0 = t * 16;
-      const int c = r0 / nsa;
-      const int lb0 = r0 - c * nsa;
-      f32x16 acc = {};
-#pragma unroll
-      for (int q = 0; q < kNV / 2; ++q) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const float wre = e ? wt[u][q].z : wt[u][q].x, wim = e ? wt[u][q].w : wt[u][q].y;
-          // g = 0: coefficient of Re y, g = 1: of Im y
-          const float av = imrow ? (g ? wre : wim) : (g ? -wim : wre);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[2 * q + e], acc, 0, 0, 0);
-        }
+      for (int e = 0; e < 2; ++e) {
+        const float wre = e ? wt[q].z : wt[q].x, wim = e ? wt[q].w : wt[q].y;
+        // g = 0: coefficient of Re y, g = 1: of Im y
+        const float av = imrow ? (g ? wre : wim) : (g ? -wim : wre);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[2 * q + e], acc, 0, 0, 0);
       }
-      if (kin && t < ntr) {
+    }
+    if (kin && t < ntr) {
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const int lb = lb0 + 8 * half + 4 * g;
-          const int sb = agg_site(a, A, lb);
+      for (int half = 0; half < 2; ++half) {
+        const int lb = lb0 + 8 * half + 4 * g;
+        const int sb = agg_site(a, A, lb);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int site = agg_site_j(a, A, lb, j, sb, fast);
-            const int p = 4 * half + j;
-            f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
-          }
+        for (int j = 0; j < 4; ++j) {
+          const int site = agg_site_j(a, A, lb, j, sb, fast);
+          const int p = 4 * half + j;
+          f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
         }
       }
     }
+  };
+  float4 wA[kNV / 2], wB[kNV / 2];
+  if (wave < ntr) load(wave, wA);
+  for (int t = wave; t < ntr; t += 8) {
+    load(t + 4, wB);
+    row_tile(t, wA);
+    load(t + 8, wA);
+    row_tile(t + 4, wB);
   }
 }
 
