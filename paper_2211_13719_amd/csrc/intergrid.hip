@@ -372,6 +372,74 @@ __global__ __launch_bounds__(256) void block_norm_kernel(AggGeom a, int h, int n
   }
 }
 
+// Single-pass variant for FP32 fields with an even number of RHS: one
+// workgroup of 1024 threads per (aggregate, chirality) keeps the whole block
+// in registers, so the field is read once and written once (the kernel above
+// reads it twice).  Thread (slice, g) holds RHS 2g, 2g + 1 of the rows
+// r = slice, slice + S, ... (r = l h + c: site offset l, component c), at most
+// MAXR of them; the squares are summed in FP64 per thread and over the
+// slices in a fixed order.
+template <int MAXR>
+__global__ __launch_bounds__(1024) void block_norm_reg_kernel(AggGeom a, int h, int nrhs, float2* __restrict__ f,
+                                                              double* __restrict__ norms) {
+  __shared__ double part[1024 * 2];
+  __shared__ double inv[64];
+  const int A = blockIdx.x >> 1, chi = blockIdx.x & 1;
+  const int ncomp = 2 * h;
+  const int G = nrhs / 2;
+  const int S = 1024 / G;
+  const int t = threadIdx.x;
+  const int g = t % G, slice = t / G;
+  const int k0 = 2 * g;
+  const int nrow = a.b[0] * a.b[1] * a.b[2] * a.b[3] * h;
+  auto offset = [&](int r) {
+    const int l = r / h, c = r - (r / h) * h;
+    return ((size_t)agg_site(a, A, l) * ncomp + chi * h + c) * nrhs + k0;
+  };
+  float4 v[MAXR];
+  // all loads first: a row past the end reads row 0 (a valid address) and
+  // counts zero; the value is used either way, so no load sits in a branch
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q) {
+    const int r = slice + q * S;
+    v[q] = *reinterpret_cast<const float4*>(f + offset(slice < S && r < nrow ? r : 0));
+  }
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q) {
+    const int r = slice + q * S;
+    const double m = (slice < S && r < nrow) ? 1.0 : 0.0;
+    acc0 = fma(m * (double)v[q].x, (double)v[q].x, acc0);
+    acc0 = fma(m * (double)v[q].y, (double)v[q].y, acc0);
+    acc1 = fma(m * (double)v[q].z, (double)v[q].z, acc1);
+    acc1 = fma(m * (double)v[q].w, (double)v[q].w, acc1);
+  }
+  part[2 * t] = acc0;
+  part[2 * t + 1] = acc1;
+  __syncthreads();
+  if (t < G) {
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      double s2 = 0.0;
+      for (int q = 0; q < S; ++q) s2 += part[2 * (q * G + t) + w];
+      const double n = sqrt(s2);
+      inv[2 * t + w] = n > 0.0 ? 1.0 / n : 0.0;
+      if (norms) norms[((size_t)A * 2 + chi) * nrhs + 2 * t + w] = n;
+    }
+  }
+  __syncthreads();
+  const float sc0 = (float)inv[k0], sc1 = (float)inv[k0 + 1];
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q) {
+    const int r = slice + q * S;
+    if (slice < S && r < nrow)
+      *reinterpret_cast<float4*>(f + offset(r)) =
+          make_float4(v[q].x * sc0, v[q].y * sc0, v[q].z * sc1, v[q].w * sc1);
+  }
+}
+
+constexpr int kNormRegRows = 20;
+
 // ---- layout conversion between [site][n_v][ncomp] (interface) and [site][ncomp][n_v] --------
 template <typename Tin, typename Tout>
 __global__ void basis_transpose(const cplx<Tin>* __restrict__ in, cplx<Tout>* __restrict__ out, long nsite, int nv,
@@ -518,6 +586,9 @@ hipError_t launch_block_normalise(int prec64, const AggGeom& a, int h, int nrhs,
   if (prec64)
     hipLaunchKernelGGL((block_norm_kernel<double, 1>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
                        static_cast<double2*>(f), norms);
+  else if (nrhs % 2 == 0 && (long)a.b[0] * a.b[1] * a.b[2] * a.b[3] * h <= (long)kNormRegRows * (1024 / (nrhs / 2)))
+    hipLaunchKernelGGL((block_norm_reg_kernel<kNormRegRows>), dim3(2 * a.Vc), dim3(1024), 0, s, a, h, nrhs,
+                       static_cast<float2*>(f), norms);
   else if (nrhs % 2 == 0)
     hipLaunchKernelGGL((block_norm_kernel<float, 2>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
                        static_cast<float2*>(f), norms);

@@ -245,6 +245,25 @@ def test_block_normalise_small(gpu_lib, dt):
     np.testing.assert_allclose(host(norms), want_n, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("nrhs", [2, 12, 26, 28])
+def test_block_normalise_even_nrhs(gpu_lib, nrhs):
+    """FP32, even Nrhs on 4^4 aggregates: the single-pass kernel up to 20 rows per
+    thread (Nrhs <= 26 here, ragged last rows), the two-pass one beyond (28)."""
+    import torch
+
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    ctx, mg = make_mg(gpu_lib, dims, [block], [4])
+    f = synth.spinor_source(dims, nrhs, 77, np.complex64)
+    f[:4] = 0  # sites 0..3 lie in aggregate 0: their rows are zero, the block is not
+    f[synth.volume(dims) // 2:] = 0  # whole aggregates of zeros stay zero
+    t = dev(f)
+    norms = torch.empty((mg.volume[1], 2, nrhs), dtype=torch.float64, device="cuda")
+    mg.block_normalise(0, t, norms)
+    want, want_n = O.block_normalise(f, dims, block)
+    assert rel(host(t), want) < 1e-6
+    np.testing.assert_allclose(host(norms), want_n, rtol=1e-12, atol=0)
+
+
 # ---- coarse stencil --------------------------------------------------------------------
 
 def coarse_mg(mrhs, cdims, nb):
