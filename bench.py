@@ -70,10 +70,10 @@ FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 # it only while the kernel name, sources and configurations still match.
 FINE_TRAFFIC = {
     "kernel": "fine_kernel<float, 2, 0, true, true, 0, HIP_vector_type<float, 2u> >",
-    "sources": "aa51ff6b32629ee1",
+    "sources": "0e9254220a875fda",
     "configs": {"6": [2, [12, 4, 4, 3], 32], "12": [2, [8, 8, 2, 3], 65], "24": [2, [8, 8, 2, 3], 68],
                 "48": [2, [8, 4, 4, 3], 68], "64": [2, [8, 4, 4, 3], 5]},
-    "bytes_per_launch": 5.499e9,
+    "bytes_per_launch": 5.525e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
@@ -149,6 +149,47 @@ class Timer:
         for key, e0, e1 in self.ev:
             out.setdefault(key, []).append(e0.elapsed_time(e1))
         return out
+
+
+def bench_evenodd(ctx, torch, stream, fine, V, warmup, steps):
+    """The checkerboarded pieces on the same 24^4 lattice, FP32, outside the step:
+    M_eooe (hop between the parities), M_ooee and its inverse on one parity, per
+    Nrhs, with the MRHS speedup N t(1) / t(N).  Bytes and flops per output site:
+    M_eooe 576 + 192 N bytes (all eight links of the site, in and out rows) and
+    1320 N flops; M_ooee 288 + 192 N bytes and 552 N flops."""
+    nh = V // 2
+    ops = []
+    for n in sorted(fine):
+        x, y = fine[n][0][:nh], fine[n][1][:nh]
+        ops.append((("meooe", n), 1320 * nh * n, nh * (576 + 192 * n), lambda x=x, y=y: ctx.hop_eo(y, x, 0)))
+        ops.append((("mooee", n), 552 * nh * n, nh * (288 + 192 * n), lambda x=x, y=y: ctx.clover_eo(y, x, 1)))
+        ops.append((("mooee_inv", n), 552 * nh * n, nh * (288 + 192 * n),
+                    lambda x=x, y=y: ctx.clover_eo(y, x, 1, inverse=True)))
+    for _ in range(max(warmup, 1)):
+        for _, _, _, fn in ops:
+            fn()
+    torch.cuda.synchronize()
+    timer = Timer(torch, stream)
+    for _ in range(steps):
+        for key, _, _, fn in ops:
+            timer(key, fn)
+    torch.cuda.synchronize()
+    times = timer.times()
+    out = {}
+    for key, flops, nbytes, _ in ops:
+        ms = float(np.median(times[key]))
+        out[f"{key[0]}@{key[1]}"] = {
+            "ms": round(ms, 5),
+            "gflops": round(flops / ms / 1e6, 1),
+            "alg_gbs": round(nbytes / ms / 1e6, 1),
+            "hbm_frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+        }
+    for kind in ("meooe", "mooee", "mooee_inv"):
+        if (kind, 1) in times:
+            t1 = float(np.median(times[(kind, 1)]))
+            for n in sorted(fine):
+                out[f"{kind}@{n}"]["mrhs_speedup"] = round(n * t1 / float(np.median(times[(kind, n)])), 3)
+    return out
 
 
 def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
@@ -380,6 +421,9 @@ def main():
 
     total_flops = sum(f for _, f, _, _ in ops)
     ms_per_step = wall * 1e3 / a.steps
+
+    evenodd = bench_evenodd(ctx, torch, stream, fine, V, a.warmup, a.steps)
+
     value = total_flops / (ms_per_step * 1e-3) / 1e9
 
     result = {
@@ -419,6 +463,7 @@ def main():
             "launches_per_step": len(share[dom]),
         },
         "per_op": per_op,
+        "evenodd": evenodd,
         "fine_tuning": tuning,
         "fine_sources": fine_sources_digest(),
         "solve": None,

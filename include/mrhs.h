@@ -131,6 +131,36 @@ mrhs_status mrhs_hop_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs
 mrhs_status mrhs_clover_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs,
                               mrhs_prec prec);
 
+/* Even-odd (checkerboard) pieces of the fine operator, Sec. 4: M_eooe (the
+ * hopping term between the checkerboarded lattices) and M_ooee (the clover
+ * term on one checkerboard) with its inverse.  Parity p(x) = (x+y+z+t) mod 2;
+ * every lattice extent must be even (MRHS_ERR_SHAPE otherwise), so that each
+ * hop joins the two parities.  A field on one parity is a device array
+ * [V/2][12][nrhs] in prec (MRHS_F32 or MRHS_F64) whose entry i is the site
+ * of that parity among the lattice sites 2i and 2i + 1.  in and out must not
+ * overlap.  Index tables (and, for the inverse, the inverted blocks) are
+ * built on the first call and kept by the context. */
+/* mrhs_hop_eo_apply: out (parity out_parity) = H in (parity 1 - out_parity),
+ * H the hopping term of mrhs_hop_apply restricted to those two parities.
+ * MRHS_ERR_STATE before the links are set. */
+mrhs_status mrhs_hop_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, int32_t out_parity,
+                              mrhs_prec prec);
+/* mrhs_clover_eo_apply: out = A_p in (inverse = 0) or out = A_p^-1 in
+ * (inverse = 1) on parity p, A_p the chiral 6x6 clover blocks of the parity-p
+ * sites.  The inverse blocks are computed once per clover term in FP64
+ * (Gauss-Jordan with partial pivoting); MRHS_ERR_STATE before the clover
+ * term is set or when a block is singular.  Synchronises on the first
+ * inverse call after a new clover term. */
+mrhs_status mrhs_clover_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, int32_t parity,
+                                 int32_t inverse, mrhs_prec prec);
+/* mrhs_schur_apply: out = (A_e - kappa^2 H_eo A_o^-1 H_oe) in on the even
+ * sites, the Schur complement of D = A - kappa H with respect to the odd
+ * sites (D x = b is equivalent to applying it to x_e with right-hand side
+ * b_e + kappa H_eo A_o^-1 b_o).  in and out are even-parity fields; the
+ * odd-parity intermediates live in a context-owned workspace of two odd
+ * fields, grown on demand. */
+mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
+
 /* ---- batched level-1 operations (paper Sec. 7) ---------------------------
  * A field here is any [nsites][ncomp][nrhs] complex array in device memory,
  * prec MRHS_F32 or MRHS_F64 (fine spinors have ncomp = 12, coarse vectors

@@ -150,6 +150,36 @@ class Context:
         """out = A inp."""
         return self._fine(lib.mrhs_clover_apply, out, inp)
 
+    # -- even-odd (checkerboard) pieces ----------------------------------------------------
+    def _half(self, out, inp):
+        if inp.dim() != 3 or inp.shape[0] != self.V // 2 or inp.shape[1] != 12:
+            raise ValueError(f"checkerboard field shape {tuple(inp.shape)} is not (V/2={self.V // 2}, 12, N)")
+        if out.shape != inp.shape or out.dtype != inp.dtype:
+            raise ValueError("out must match in (shape and dtype)")
+        if not (inp.is_cuda and out.is_cuda):
+            raise ValueError("fields must be device tensors")
+        pi, prec, _ = _ptr_of(inp)
+        po, _, _ = _ptr_of(out)
+        return C.c_void_p(po), C.c_void_p(pi), int(inp.shape[2]), prec
+
+    def hop_eo(self, out, inp, out_parity: int):
+        """M_eooe: out (parity out_parity) = H inp (the other parity); fields (V/2, 12, N)."""
+        po, pi, n, prec = self._half(out, inp)
+        self._check(lib.mrhs_hop_eo_apply(self._h, po, pi, n, int(out_parity), prec))
+        return out
+
+    def clover_eo(self, out, inp, parity: int, inverse: bool = False):
+        """M_ooee on one parity: out = A_p inp, or A_p^-1 inp with inverse=True."""
+        po, pi, n, prec = self._half(out, inp)
+        self._check(lib.mrhs_clover_eo_apply(self._h, po, pi, n, int(parity), int(bool(inverse)), prec))
+        return out
+
+    def schur(self, out, inp):
+        """out = (A_e - kappa^2 H_eo A_o^-1 H_oe) inp on the even sites."""
+        po, pi, n, prec = self._half(out, inp)
+        self._check(lib.mrhs_schur_apply(self._h, po, pi, n, prec))
+        return out
+
     # -- autotuning ------------------------------------------------------------------------
     def tune(self, nrhs_list, cache_path=None):
         """Pick the fastest FP32 fine-kernel launch configuration for each nrhs."""

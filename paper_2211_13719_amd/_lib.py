@@ -44,6 +44,9 @@ SIGNATURES = {
     "mrhs_dwc_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
     "mrhs_hop_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
     "mrhs_clover_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
+    "mrhs_hop_eo_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32]),
+    "mrhs_clover_eo_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _i32]),
+    "mrhs_schur_apply": (_i32, [_vp, _vp, _vp, _i32, _i32]),
     "mrhs_dot": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32]),
     "mrhs_norm2": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32]),
     "mrhs_multi_dot": (_i32, [_vp, _vp, C.POINTER(_vp), _i32, _vp, _i64, _i32, _i32, _i32, _i32]),

@@ -100,6 +100,66 @@ mrhs_status check_field_args(mrhs_ctx ctx, const void* out, const void* in, int3
   return MRHS_OK;
 }
 
+// Checkerboard tables (see fine.hip): built on first use; every extent must
+// be even, so that each hop joins the two parities and s = 2i, 2i + 1 always
+// hold one site of each.
+mrhs_status ensure_eo_tables(mrhs_ctx ctx) {
+  if (ctx->eo_tab[0].p && ctx->eo_tab[1].p) return MRHS_OK;
+  const Geom& g = ctx->g;
+  for (int m = 0; m < 4; ++m)
+    if (g.L[m] % 2)
+      return fail(ctx, MRHS_ERR_SHAPE, "the even-odd operators need even extents (L[%d] = %d)", m, g.L[m]);
+  const int nhalf = g.V / 2;
+  for (int p = 0; p < 2; ++p) {
+    std::vector<int> t((size_t)nhalf * 16, 0);
+    for (int i = 0; i < nhalf; ++i) {
+      int c[4], r = 2 * i;
+      for (int m = 0; m < 4; ++m) {
+        c[m] = r % g.L[m];
+        r /= g.L[m];
+      }
+      const int s = 2 * i + (((c[0] + c[1] + c[2] + c[3]) & 1) == p ? 0 : 1);
+      if (s != 2 * i) c[0] += 1;
+      int* e = &t[(size_t)i * 16];
+      for (int m = 0; m < 4; ++m) {
+        const int up = c[m] == g.L[m] - 1 ? -(g.L[m] - 1) : 1;
+        const int dn = c[m] == 0 ? g.L[m] - 1 : -1;
+        const int sf = s + up * g.stride[m], sb = s + dn * g.stride[m];
+        e[2 * m] = sf / 2;  // checkerboard index of a neighbour (other parity)
+        e[2 * m + 1] = sb / 2;
+        e[9 + m] = sb;  // lattice site of the backward neighbour
+      }
+      e[8] = s;
+    }
+    mrhs_status st = ensure(ctx, ctx->eo_tab[p], t.size() * 4);
+    if (st != MRHS_OK) return st;
+    MRHS_HIP(ctx, hipMemcpy(ctx->eo_tab[p].p, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+  }
+  return MRHS_OK;
+}
+
+mrhs_status ensure_clover_inverse(mrhs_ctx ctx) {
+  if (ctx->have_clover_inv) return MRHS_OK;
+  const size_t n = (size_t)ctx->g.V * 2 * 36;
+  mrhs_status st = ensure(ctx, ctx->Ainv64, n * 8);
+  if (st == MRHS_OK) st = ensure(ctx, ctx->Ainv32, n * 4);
+  Buffer flag;
+  if (st == MRHS_OK) st = ensure(ctx, flag, sizeof(int));
+  if (st != MRHS_OK) return st;
+  int h = 0;
+  hipError_t e = hipMemsetAsync(flag.p, 0, sizeof(int), ctx->stream);
+  if (e == hipSuccess)
+    e = launch_clover_invert((long)ctx->g.V * 2, ctx->A64.p, ctx->Ainv64.p, ctx->Ainv32.p, static_cast<int*>(flag.p),
+                             ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release(flag);
+  if (e != hipSuccess) return hip_fail(ctx, e, "clover inversion");
+  if (h) return fail(ctx, MRHS_ERR_STATE, "a clover block is singular");
+  ctx->have_clover_inv = true;
+  return MRHS_OK;
+}
+
 mrhs_status fine_apply(mrhs_ctx ctx, int mode, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
   if (!ctx) return MRHS_ERR_INVALID_ARG;
   mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V);
@@ -270,6 +330,11 @@ void mrhs_destroy(mrhs_ctx ctx) {
   release(ctx->scal);
   release(ctx->nbr);
   for (auto& o : ctx->orders) release(o.second);
+  release(ctx->eo_tab[0]);
+  release(ctx->eo_tab[1]);
+  release(ctx->Ainv64);
+  release(ctx->Ainv32);
+  release(ctx->eo_work);
   delete ctx;
 }
 
@@ -305,6 +370,7 @@ mrhs_status mrhs_set_gauge(mrhs_ctx ctx, const void* U, mrhs_prec prec, int32_t 
   MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->have_gauge = true;
   ctx->have_clover = false;  // a clover term built from old links is stale
+  ctx->have_clover_inv = false;
   return MRHS_OK;
 }
 
@@ -326,6 +392,7 @@ mrhs_status mrhs_build_clover(mrhs_ctx ctx, double csw, double kappa) {
   if (e != hipSuccess) return hip_fail(ctx, e, "clover build");
   ctx->kappa = kappa;
   ctx->have_clover = true;
+  ctx->have_clover_inv = false;
   return MRHS_OK;
 }
 
@@ -340,6 +407,7 @@ mrhs_status mrhs_set_clover(mrhs_ctx ctx, const void* A, mrhs_prec prec, int32_t
   if (st != MRHS_OK) return st;
   ctx->kappa = kappa;
   ctx->have_clover = true;
+  ctx->have_clover_inv = false;
   return MRHS_OK;
 }
 
@@ -369,6 +437,68 @@ mrhs_status mrhs_hop_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs
 
 mrhs_status mrhs_clover_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
   return fine_apply(ctx, 2, out, in, nrhs, prec);
+}
+
+mrhs_status mrhs_hop_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, int32_t out_parity,
+                              mrhs_prec prec) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (out_parity != 0 && out_parity != 1) return fail(ctx, MRHS_ERR_INVALID_ARG, "parity must be 0 or 1");
+  mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V / 2);
+  if (st != MRHS_OK) return st;
+  if (!ctx->have_gauge) return fail(ctx, MRHS_ERR_STATE, "gauge field not set");
+  DeviceGuard dg(ctx->device);
+  st = ensure_eo_tables(ctx);
+  if (st != MRHS_OK) return st;
+  const int p64 = prec == MRHS_F64;
+  MRHS_HIP(ctx, launch_hop_eo(p64, ctx->g.V / 2, static_cast<const int4*>(ctx->eo_tab[out_parity].p),
+                              p64 ? ctx->U64.p : ctx->U32.p, in, out, nrhs, ctx->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_clover_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, int32_t parity,
+                                 int32_t inverse, mrhs_prec prec) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (parity != 0 && parity != 1) return fail(ctx, MRHS_ERR_INVALID_ARG, "parity must be 0 or 1");
+  mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V / 2);
+  if (st != MRHS_OK) return st;
+  if (!ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "clover term not set");
+  DeviceGuard dg(ctx->device);
+  st = ensure_eo_tables(ctx);
+  if (st == MRHS_OK && inverse) st = ensure_clover_inverse(ctx);
+  if (st != MRHS_OK) return st;
+  const int p64 = prec == MRHS_F64;
+  const void* A = inverse ? (p64 ? ctx->Ainv64.p : ctx->Ainv32.p) : (p64 ? ctx->A64.p : ctx->A32.p);
+  MRHS_HIP(ctx, launch_clover_eo(p64, ctx->g.V / 2, static_cast<const int4*>(ctx->eo_tab[parity].p), A, in,
+                                 nullptr, 0.0, out, nrhs, ctx->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V / 2);
+  if (st != MRHS_OK) return st;
+  if (!ctx->have_gauge || !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "fine operator not set");
+  DeviceGuard dg(ctx->device);
+  st = ensure_eo_tables(ctx);
+  if (st == MRHS_OK) st = ensure_clover_inverse(ctx);
+  const int p64 = prec == MRHS_F64;
+  const size_t half = (size_t)(ctx->g.V / 2) * 12 * nrhs * (p64 ? 16 : 8);
+  if (st == MRHS_OK) st = ensure(ctx, ctx->eo_work, 2 * half);
+  if (st != MRHS_OK) return st;
+  void* t1 = ctx->eo_work.p;
+  void* t2 = static_cast<char*>(ctx->eo_work.p) + half;
+  const int nh = ctx->g.V / 2;
+  const auto* te = static_cast<const int4*>(ctx->eo_tab[0].p);
+  const auto* to = static_cast<const int4*>(ctx->eo_tab[1].p);
+  const void* U = p64 ? ctx->U64.p : ctx->U32.p;
+  // t1 = H_oe in, t2 = A_o^-1 t1, t1 = H_eo t2, out = A_e in - kappa^2 t1
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, U, in, t1, nrhs, ctx->stream));
+  MRHS_HIP(ctx, launch_clover_eo(p64, nh, to, p64 ? ctx->Ainv64.p : ctx->Ainv32.p, t1, nullptr, 0.0, t2, nrhs,
+                                 ctx->stream));
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, U, t2, t1, nrhs, ctx->stream));
+  MRHS_HIP(ctx, launch_clover_eo(p64, nh, te, p64 ? ctx->A64.p : ctx->A32.p, in, t1, -ctx->kappa * ctx->kappa, out,
+                                 nrhs, ctx->stream));
+  return MRHS_OK;
 }
 
 }  // extern "C"

@@ -341,10 +341,12 @@ __device__ __forceinline__ void load_spinor(const P* __restrict__ in, int site, 
 // One direction mu, both hops, accumulated into acc.  nbf / nbb are the
 // sites x + mu and x - mu.  The fermion boundary factor is already folded
 // into the links (see fold_boundary_phase), so no hop needs a phase here.
+// lbb, when given, is the site whose link U_mu carries the backward hop (on a
+// checkerboarded field the spinor index nbb and the lattice site differ).
 template <typename T, int R, int MU, bool SPLIT, typename P>
 __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, int k0, const cplx<T>* __restrict__ U,
                                         const P* __restrict__ in, cplx<T> (&acc)[4][3][R], bool inc_f = true,
-                                        bool inc_b = true) {
+                                        bool inc_b = true, int lbb = -1) {
   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
   if (inc_f) {
     cplx<T> h[2][3][R];
@@ -383,7 +385,7 @@ __device__ __forceinline__ void hop_dir(int site, int nbf, int nbb, int nrhs, in
       project<T, R, MU, -1>(p, h);
     }
     cplx<T> uu[3][3];
-    load_link<T, MU>(U + ((size_t)nbb * 4 + MU) * 9, uu);
+    load_link<T, MU>(U + ((size_t)(lbb < 0 ? nbb : lbb) * 4 + MU) * 9, uu);
     cplx<T> w[2][3][R];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -633,6 +635,184 @@ hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U
   }
 }
 
+// ---- checkerboarded pieces (paper Sec. 4: M_eooe and M_ooee) ----------------------------
+// A field on one parity is [V/2][12][nrhs]; entry i is the site of that parity
+// among s = 2i, 2i + 1.  Per checkerboard index the table holds four int4:
+// the checkerboard indices of the neighbours (+x, -x, +y, -y), (+z, -z, +t,
+// -t) on the other parity, then the lattice site of i itself and of its
+// backward neighbours (self, -x, -y, -z), (-t, -, -, -), which index the links
+// and clover blocks.
+
+// M_eooe: out (parity p) = H in (parity 1 - p), R right-hand sides per thread.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
+                                                     const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
+                                                     cplx<T>* __restrict__ out) {
+  const int groups = nrhs / R;
+  const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (long)nhalf * groups) return;
+  const int i = (int)(gid / groups);
+  const int k0 = (int)(gid - (long)i * groups) * R;
+  const int4 n0 = tab[4 * i], n1 = tab[4 * i + 1], s0 = tab[4 * i + 2], s1 = tab[4 * i + 3];
+  cplx<T> acc[4][3][R];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
+  hop_dir<T, R, 0, true>(s0.x, n0.x, n0.y, nrhs, k0, U, in, acc, true, true, s0.y);
+  hop_dir<T, R, 1, true>(s0.x, n0.z, n0.w, nrhs, k0, U, in, acc, true, true, s0.z);
+  hop_dir<T, R, 2, true>(s0.x, n1.x, n1.y, nrhs, k0, U, in, acc, true, true, s0.w);
+  hop_dir<T, R, 3, true>(s0.x, n1.z, n1.w, nrhs, k0, U, in, acc, true, true, s1.x);
+  cplx<T>* o = out + (size_t)i * 12 * nrhs + k0;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c]);
+}
+
+// M_ooee (or its inverse, given the inverse blocks): out = A in + coef add on
+// one parity (add may be null).
+template <typename T, int R>
+__global__ __launch_bounds__(256) void clover_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
+                                                        const T* __restrict__ A, const cplx<T>* __restrict__ in,
+                                                        const cplx<T>* __restrict__ add, T coef,
+                                                        cplx<T>* __restrict__ out) {
+  const int groups = nrhs / R;
+  const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (long)nhalf * groups) return;
+  const int i = (int)(gid / groups);
+  const int k0 = (int)(gid - (long)i * groups) * R;
+  const int site = tab[4 * i + 2].x;
+  const size_t base = (size_t)i * 12 * nrhs + k0;
+#pragma unroll
+  for (int chi = 0; chi < 2; ++chi) {
+    cplx<T> xin[6][R], yout[6][R];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) load_r<T, R>(in + base + (6 * chi + r) * nrhs, xin[r]);
+    clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
+    if (add) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        cplx<T> a[R];
+        load_r<T, R>(add + base + (6 * chi + r) * nrhs, a);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          yout[r][j].x = fma(coef, a[j].x, yout[r][j].x);
+          yout[r][j].y = fma(coef, a[j].y, yout[r][j].y);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) store_r<T, R>(out + base + (6 * chi + r) * nrhs, yout[r]);
+  }
+}
+
+// Inverse of every Hermitian 6x6 chiral clover block (FP64, Gauss-Jordan
+// elimination with partial pivoting), packed like the blocks: six real
+// diagonal entries, then the strictly lower triangle row by row as (re, im).
+// A block whose pivot vanishes sets *flag.
+__global__ __launch_bounds__(256) void clover_invert_kernel(long nblk, const double* __restrict__ A,
+                                                            double* __restrict__ Ai64, float* __restrict__ Ai32,
+                                                            int* __restrict__ flag) {
+  const long b = (long)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nblk) return;
+  const double* a = A + b * 36;
+  double2 M[6][6], X[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) X[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  for (int r = 0; r < 6; ++r) M[r][r] = make_double2(a[r], 0.0);
+  int k = 6;
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < r; ++c) {
+      M[r][c] = make_double2(a[k], a[k + 1]);
+      M[c][r] = make_double2(a[k], -a[k + 1]);
+      k += 2;
+    }
+  bool ok = true;
+  for (int col = 0; col < 6; ++col) {
+    int piv = col;
+    double best = -1.0;
+    for (int r = col; r < 6; ++r) {
+      const double m = M[r][col].x * M[r][col].x + M[r][col].y * M[r][col].y;
+      if (m > best) {
+        best = m;
+        piv = r;
+      }
+    }
+    if (!(best > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (piv != col)
+      for (int c = 0; c < 6; ++c) {
+        const double2 t = M[col][c];
+        M[col][c] = M[piv][c];
+        M[piv][c] = t;
+        const double2 u = X[col][c];
+        X[col][c] = X[piv][c];
+        X[piv][c] = u;
+      }
+    // 1 / pivot
+    const double2 p = M[col][col];
+    const double2 ip = make_double2(p.x / best, -p.y / best);
+    for (int c = 0; c < 6; ++c) {
+      const double2 m = M[col][c], x = X[col][c];
+      M[col][c] = make_double2(m.x * ip.x - m.y * ip.y, m.x * ip.y + m.y * ip.x);
+      X[col][c] = make_double2(x.x * ip.x - x.y * ip.y, x.x * ip.y + x.y * ip.x);
+    }
+    for (int r = 0; r < 6; ++r) {
+      if (r == col) continue;
+      const double2 f = M[r][col];
+      for (int c = 0; c < 6; ++c) {
+        const double2 m = M[col][c], x = X[col][c];
+        M[r][c] = make_double2(M[r][c].x - (f.x * m.x - f.y * m.y), M[r][c].y - (f.x * m.y + f.y * m.x));
+        X[r][c] = make_double2(X[r][c].x - (f.x * x.x - f.y * x.y), X[r][c].y - (f.x * x.y + f.y * x.x));
+      }
+    }
+  }
+  if (!ok) {
+    atomicOr(flag, 1);
+    return;
+  }
+  double* o64 = Ai64 + b * 36;
+  float* o32 = Ai32 + b * 36;
+  for (int r = 0; r < 6; ++r) {
+    o64[r] = X[r][r].x;
+    o32[r] = (float)X[r][r].x;
+  }
+  k = 6;
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < r; ++c) {
+      o64[k] = X[r][c].x;
+      o64[k + 1] = X[r][c].y;
+      o32[k] = (float)X[r][c].x;
+      o32[k + 1] = (float)X[r][c].y;
+      k += 2;
+    }
+}
+
+template <typename T, int R>
+hipError_t launch_hop_eo_r(int nhalf, int nrhs, const int4* tab, const void* U, const void* in, void* out,
+                           hipStream_t s) {
+  const long threads = (long)nhalf * (nrhs / R);
+  hipLaunchKernelGGL((hop_eo_kernel<T, R>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nhalf, nrhs,
+                     tab, static_cast<const cplx<T>*>(U), static_cast<const cplx<T>*>(in),
+                     static_cast<cplx<T>*>(out));
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t launch_clover_eo_r(int nhalf, int nrhs, const int4* tab, const void* A, const void* in, const void* add,
+                              double coef, void* out, hipStream_t s) {
+  const long threads = (long)nhalf * (nrhs / R);
+  hipLaunchKernelGGL((clover_eo_kernel<T, R>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nhalf,
+                     nrhs, tab, static_cast<const T*>(A), static_cast<const cplx<T>*>(in),
+                     static_cast<const cplx<T>*>(add), (T)coef, static_cast<cplx<T>*>(out));
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U, const void* A,
@@ -654,6 +834,27 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
                                void* out, int nrhs, const DirFilter& f, hipStream_t s) {
   (void)t_bc;  // folded into the links
   return launch_r<double, 1, 3>(g, g.order, kappa, U, A, in, out, nrhs, s, f);
+}
+
+// FP32: two right-hand sides per thread for even nrhs; FP64: one.
+hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const void* U, const void* in, void* out, int nrhs,
+                         hipStream_t s) {
+  if (prec64) return launch_hop_eo_r<double, 1>(nhalf, nrhs, tab, U, in, out, s);
+  if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(nhalf, nrhs, tab, U, in, out, s);
+  return launch_hop_eo_r<float, 1>(nhalf, nrhs, tab, U, in, out, s);
+}
+
+hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
+                            double coef, void* out, int nrhs, hipStream_t s) {
+  if (prec64) return launch_clover_eo_r<double, 1>(nhalf, nrhs, tab, A, in, add, coef, out, s);
+  if (nrhs % 2 == 0) return launch_clover_eo_r<float, 2>(nhalf, nrhs, tab, A, in, add, coef, out, s);
+  return launch_clover_eo_r<float, 1>(nhalf, nrhs, tab, A, in, add, coef, out, s);
+}
+
+hipError_t launch_clover_invert(long nblk, const void* A64, void* Ai64, void* Ai32, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(clover_invert_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, nblk,
+                     static_cast<const double*>(A64), static_cast<double*>(Ai64), static_cast<float*>(Ai32), flag);
+  return hipGetLastError();
 }
 
 }  // namespace mrhs

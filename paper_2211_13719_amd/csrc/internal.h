@@ -106,6 +106,13 @@ struct mrhs_ctx_s {
   // autotuned launch configurations of the FP32 fine kernel, by nrhs
   mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
 
+  // checkerboard tables (per parity, four int4 per site) and the inverse
+  // clover blocks, built on first use; a workspace for the Schur operator
+  mrhs::Buffer eo_tab[2];
+  mrhs::Buffer Ainv64, Ainv32;
+  bool have_clover_inv = false;
+  mrhs::Buffer eo_work;
+
   // fine-lattice index tables: neighbours, and one traversal order per tile
   mrhs::Buffer nbr;
   std::vector<std::pair<std::array<int, 5>, mrhs::Buffer>> orders;
@@ -148,6 +155,13 @@ hipError_t launch_fine_f64_in32(const Geom& g, double kappa, const void* U, cons
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,
                                void* out, int nrhs, const DirFilter& f, hipStream_t s);
+// checkerboarded fine pieces (fine.hip): nhalf = V / 2 sites per parity,
+// tab = that parity's table (four int4 per site)
+hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const void* U, const void* in, void* out, int nrhs,
+                         hipStream_t s);
+hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
+                            double coef, void* out, int nrhs, hipStream_t s);
+hipError_t launch_clover_invert(long nblk, const void* A64, void* Ai64, void* Ai32, int* flag, hipStream_t s);
 
 // ---- launchers (clover_build.hip) -------------------------------------------
 hipError_t launch_clover_build(const Geom& g, double csw, double kappa, const void* U64,

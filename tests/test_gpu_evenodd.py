@@ -1,0 +1,141 @@
+"""GPU parity of the even-odd pieces (M_eooe, M_ooee and its inverse, the Schur
+complement) against the FP64 oracle, and against the full-lattice kernels.
+
+Tolerances as for the full operator: 1e-12 relative L2 in FP64, 1e-6 in FP32.
+The checkerboard hop must also equal the full-lattice hop of a field that is
+zero on the output parity, bit for bit in FP32 (same per-site arithmetic).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import evenodd as EO
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KAPPA, CSW = 0.13, 1.0
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def lat(gpu_lib):
+    dims = (4, 6, 4, 8)  # non-cubic, all extents even
+    U = synth.gauge_haar(dims, 4001)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx = gpu_lib.Context(dims, t_bc=-1)
+    ctx.set_gauge(U)
+    ctx.build_clover(CSW, KAPPA)
+    return dims, U, A, ctx
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("nrhs", [1, 5, 24])
+@pytest.mark.parametrize("p", [0, 1])
+def test_hop_eo(lat, dt, nrhs, p):
+    import torch
+
+    dims, U, A, ctx = lat
+    psi = EO.to_cb(synth.spinor_source(dims, nrhs, 50, dt), dims, 1 - p)
+    out = torch.empty(psi.shape, dtype=torch.complex128 if dt == np.complex128 else torch.complex64, device="cuda")
+    ctx.hop_eo(out, dev(psi), p)
+    tol = 1e-12 if dt == np.complex128 else 1e-6
+    assert rel(out.cpu().numpy(), EO.hop_eo(U, psi, dims, p)) < tol
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("inverse", [False, True])
+@pytest.mark.parametrize("p", [0, 1])
+def test_clover_eo(lat, dt, inverse, p):
+    import torch
+
+    dims, U, A, ctx = lat
+    psi = EO.to_cb(synth.spinor_source(dims, 6, 60, dt), dims, p)
+    out = torch.empty(psi.shape, dtype=torch.complex128 if dt == np.complex128 else torch.complex64, device="cuda")
+    ctx.clover_eo(out, dev(psi), p, inverse=inverse)
+    blocks = EO.clover_inverse(A) if inverse else A
+    tol = 1e-12 if dt == np.complex128 else 1e-6
+    assert rel(out.cpu().numpy(), EO.clover_cb(blocks, psi, dims, p)) < tol
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_schur(lat, dt, nrhs):
+    import torch
+
+    dims, U, A, ctx = lat
+    psi = EO.to_cb(synth.spinor_source(dims, nrhs, 70, dt), dims, 0)
+    out = torch.empty(psi.shape, dtype=torch.complex128 if dt == np.complex128 else torch.complex64, device="cuda")
+    ctx.schur(out, dev(psi))
+    tol = 1e-12 if dt == np.complex128 else 1e-6
+    assert rel(out.cpu().numpy(), EO.schur_ee(U, A, KAPPA, psi, dims)) < tol
+
+
+def _full_vs_eo(gpu_lib, dims, seed, nrhs):
+    """FP32: hop_eo of an odd field equals the full-lattice hop of the field placed on
+    the odd sites (zero on the even ones), read on the even sites, bit for bit."""
+    import torch
+
+    U = synth.gauge_haar(dims, seed)
+    ctx = gpu_lib.Context(dims, t_bc=-1)
+    ctx.set_gauge(U)
+    ctx.build_clover(CSW, KAPPA)
+    f = synth.spinor_source(dims, nrhs, seed + 1, np.complex64)
+    f_odd = EO.to_cb(f, dims, 1)
+    full = EO.from_cb(np.zeros_like(f_odd), f_odd, dims)
+    h = torch.empty(full.shape, dtype=torch.complex64, device="cuda")
+    ctx.hop(h, dev(full))
+    he = torch.empty(f_odd.shape, dtype=torch.complex64, device="cuda")
+    ctx.hop_eo(he, dev(f_odd), 0)
+    np.testing.assert_array_equal(he.cpu().numpy(), EO.to_cb(h.cpu().numpy(), dims, 0))
+
+
+def test_hop_eo_equals_full_hop(gpu_lib):
+    _full_vs_eo(gpu_lib, (4, 6, 4, 8), 4101, 6)
+
+
+def test_hop_eo_equals_full_hop_24(gpu_lib):
+    """The 24^4 benchmark lattice at Nrhs = 24, the size the benchmark times."""
+    _full_vs_eo(gpu_lib, (24, 24, 24, 24), 4201, 24)
+
+
+def test_odd_extent_rejected(gpu_lib):
+    import torch
+
+    dims = (4, 4, 4, 3)
+    ctx = gpu_lib.Context(dims, t_bc=-1)
+    ctx.set_gauge(synth.gauge_unit(dims))
+    V2 = synth.volume(dims) // 2
+    a = torch.zeros((V2, 12, 2), dtype=torch.complex64, device="cuda")
+    b = torch.zeros_like(a)
+    with pytest.raises(gpu_lib.MrhsError, match="SHAPE"):
+        ctx.hop_eo(b, a, 0)
+
+
+def test_singular_clover_rejected(gpu_lib):
+    import torch
+
+    dims = (2, 2, 2, 2)
+    ctx = gpu_lib.Context(dims, t_bc=-1)
+    ctx.set_gauge(synth.gauge_unit(dims))
+    A = np.zeros((synth.volume(dims), 2, 36))
+    A[:, :, :6] = 1.0
+    A[3, 1, 2] = 0.0  # one block with a zero row and column
+    ctx.set_clover(A, KAPPA)
+    a = torch.ones((8, 12, 2), dtype=torch.complex64, device="cuda")
+    b = torch.zeros_like(a)
+    ctx.clover_eo(b, a, 0)  # the blocks themselves are fine
+    with pytest.raises(gpu_lib.MrhsError, match="STATE"):
+        ctx.clover_eo(b, a, 1, inverse=True)
