@@ -104,7 +104,7 @@ mrhs_status check_field_args(mrhs_ctx ctx, const void* out, const void* in, int3
 // be even, so that each hop joins the two parities and s = 2i, 2i + 1 always
 // hold one site of each.
 mrhs_status ensure_eo_tables(mrhs_ctx ctx) {
-  if (ctx->eo_tab[0].p && ctx->eo_tab[1].p) return MRHS_OK;
+  if (ctx->eo_tab[0].p && ctx->eo_tab[1].p && ctx->eo_order[0].p && ctx->eo_order[1].p) return MRHS_OK;
   const Geom& g = ctx->g;
   for (int m = 0; m < 4; ++m)
     if (g.L[m] % 2)
@@ -134,6 +134,26 @@ mrhs_status ensure_eo_tables(mrhs_ctx ctx) {
     mrhs_status st = ensure(ctx, ctx->eo_tab[p], t.size() * 4);
     if (st != MRHS_OK) return st;
     MRHS_HIP(ctx, hipMemcpy(ctx->eo_tab[p].p, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+  }
+  // traversal: the full kernel's default tiled order, keeping the sites of
+  // each parity (as checkerboard indices s / 2)
+  std::vector<int> full((size_t)g.V);
+  MRHS_HIP(ctx, hipMemcpy(full.data(), g.order, full.size() * 4, hipMemcpyDeviceToHost));
+  for (int p = 0; p < 2; ++p) {
+    std::vector<int> ord;
+    ord.reserve(nhalf);
+    for (int s : full) {
+      int c[4], r = s;
+      for (int m = 0; m < 4; ++m) {
+        c[m] = r % g.L[m];
+        r /= g.L[m];
+      }
+      if (((c[0] + c[1] + c[2] + c[3]) & 1) == p) ord.push_back(s / 2);
+    }
+    if ((int)ord.size() != nhalf) return fail(ctx, MRHS_ERR_SHAPE, "checkerboard traversal is incomplete");
+    mrhs_status st = ensure(ctx, ctx->eo_order[p], ord.size() * 4);
+    if (st != MRHS_OK) return st;
+    MRHS_HIP(ctx, hipMemcpy(ctx->eo_order[p].p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice));
   }
   return MRHS_OK;
 }
@@ -330,8 +350,10 @@ void mrhs_destroy(mrhs_ctx ctx) {
   release(ctx->scal);
   release(ctx->nbr);
   for (auto& o : ctx->orders) release(o.second);
-  release(ctx->eo_tab[0]);
-  release(ctx->eo_tab[1]);
+  for (int p = 0; p < 2; ++p) {
+    release(ctx->eo_tab[p]);
+    release(ctx->eo_order[p]);
+  }
   release(ctx->Ainv64);
   release(ctx->Ainv32);
   release(ctx->eo_work);
@@ -451,7 +473,8 @@ mrhs_status mrhs_hop_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t n
   if (st != MRHS_OK) return st;
   const int p64 = prec == MRHS_F64;
   MRHS_HIP(ctx, launch_hop_eo(p64, ctx->g.V / 2, static_cast<const int4*>(ctx->eo_tab[out_parity].p),
-                              p64 ? ctx->U64.p : ctx->U32.p, in, out, nrhs, ctx->stream));
+                              static_cast<const int*>(ctx->eo_order[out_parity].p), p64 ? ctx->U64.p : ctx->U32.p,
+                              in, out, nrhs, ctx->stream));
   return MRHS_OK;
 }
 
@@ -492,10 +515,12 @@ mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nr
   const auto* to = static_cast<const int4*>(ctx->eo_tab[1].p);
   const void* U = p64 ? ctx->U64.p : ctx->U32.p;
   // t1 = H_oe in, t2 = A_o^-1 t1, t1 = H_eo t2, out = A_e in - kappa^2 t1
-  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, U, in, t1, nrhs, ctx->stream));
+  const auto* oe = static_cast<const int*>(ctx->eo_order[0].p);
+  const auto* oo = static_cast<const int*>(ctx->eo_order[1].p);
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, oo, U, in, t1, nrhs, ctx->stream));
   MRHS_HIP(ctx, launch_clover_eo(p64, nh, to, p64 ? ctx->Ainv64.p : ctx->Ainv32.p, t1, nullptr, 0.0, t2, nrhs,
                                  ctx->stream));
-  MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, U, t2, t1, nrhs, ctx->stream));
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, oe, U, t2, t1, nrhs, ctx->stream));
   MRHS_HIP(ctx, launch_clover_eo(p64, nh, te, p64 ? ctx->A64.p : ctx->A32.p, in, t1, -ctx->kappa * ctx->kappa, out,
                                  nrhs, ctx->stream));
   return MRHS_OK;

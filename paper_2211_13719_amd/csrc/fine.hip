@@ -644,15 +644,23 @@ hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U
 // and clover blocks.
 
 // M_eooe: out (parity p) = H in (parity 1 - p), R right-hand sides per thread.
+// Sites are visited in the order of a traversal table (the parity-p sites of
+// the full kernel's tiled order), each XCD taking one contiguous range of it,
+// so that neighbour rows are re-read from its own L2 as in fine_kernel.
 template <typename T, int R>
 __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
+                                                     const int* __restrict__ order, int nblocks,
                                                      const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
                                                      cplx<T>* __restrict__ out) {
+  const int per = (nblocks + 7) >> 3;
+  const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (b >= nblocks) return;
   const int groups = nrhs / R;
-  const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+  const long gid = (long)b * 256 + threadIdx.x;
   if (gid >= (long)nhalf * groups) return;
-  const int i = (int)(gid / groups);
-  const int k0 = (int)(gid - (long)i * groups) * R;
+  const int pidx = (int)(gid / groups);
+  const int k0 = (int)(gid - (long)pidx * groups) * R;
+  const int i = order[pidx];
   const int4 n0 = tab[4 * i], n1 = tab[4 * i + 1], s0 = tab[4 * i + 2], s1 = tab[4 * i + 3];
   cplx<T> acc[4][3][R];
 #pragma unroll
@@ -794,12 +802,13 @@ __global__ __launch_bounds__(256) void clover_invert_kernel(long nblk, const dou
 }
 
 template <typename T, int R>
-hipError_t launch_hop_eo_r(int nhalf, int nrhs, const int4* tab, const void* U, const void* in, void* out,
-                           hipStream_t s) {
+hipError_t launch_hop_eo_r(int nhalf, int nrhs, const int4* tab, const int* order, const void* U, const void* in,
+                           void* out, hipStream_t s) {
   const long threads = (long)nhalf * (nrhs / R);
-  hipLaunchKernelGGL((hop_eo_kernel<T, R>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nhalf, nrhs,
-                     tab, static_cast<const cplx<T>*>(U), static_cast<const cplx<T>*>(in),
-                     static_cast<cplx<T>*>(out));
+  const int nblocks = (int)((threads + 255) / 256);
+  const int grid = ((nblocks + 7) / 8) * 8;
+  hipLaunchKernelGGL((hop_eo_kernel<T, R>), dim3((unsigned)grid), dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks,
+                     static_cast<const cplx<T>*>(U), static_cast<const cplx<T>*>(in), static_cast<cplx<T>*>(out));
   return hipGetLastError();
 }
 
@@ -837,11 +846,12 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
 }
 
 // FP32: two right-hand sides per thread for even nrhs; FP64: one.
-hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const void* U, const void* in, void* out, int nrhs,
-                         hipStream_t s) {
-  if (prec64) return launch_hop_eo_r<double, 1>(nhalf, nrhs, tab, U, in, out, s);
-  if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(nhalf, nrhs, tab, U, in, out, s);
-  return launch_hop_eo_r<float, 1>(nhalf, nrhs, tab, U, in, out, s);
+hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
+                         void* out, int nrhs, hipStream_t s) {
+  if (!tab || !order) return hipErrorInvalidValue;
+  if (prec64) return launch_hop_eo_r<double, 1>(nhalf, nrhs, tab, order, U, in, out, s);
+  if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(nhalf, nrhs, tab, order, U, in, out, s);
+  return launch_hop_eo_r<float, 1>(nhalf, nrhs, tab, order, U, in, out, s);
 }
 
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,

@@ -106,9 +106,10 @@ struct mrhs_ctx_s {
   // autotuned launch configurations of the FP32 fine kernel, by nrhs
   mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
 
-  // checkerboard tables (per parity, four int4 per site) and the inverse
-  // clover blocks, built on first use; a workspace for the Schur operator
-  mrhs::Buffer eo_tab[2];
+  // checkerboard tables (per parity, four int4 per site, and the traversal
+  // order of its sites) and the inverse clover blocks, built on first use; a
+  // workspace for the Schur operator
+  mrhs::Buffer eo_tab[2], eo_order[2];
   mrhs::Buffer Ainv64, Ainv32;
   bool have_clover_inv = false;
   mrhs::Buffer eo_work;
@@ -157,8 +158,8 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
                                void* out, int nrhs, const DirFilter& f, hipStream_t s);
 // checkerboarded fine pieces (fine.hip): nhalf = V / 2 sites per parity,
 // tab = that parity's table (four int4 per site)
-hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const void* U, const void* in, void* out, int nrhs,
-                         hipStream_t s);
+hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
+                         void* out, int nrhs, hipStream_t s);
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
                             double coef, void* out, int nrhs, hipStream_t s);
 hipError_t launch_clover_invert(long nblk, const void* A64, void* Ai64, void* Ai32, int* flag, hipStream_t s);
