@@ -292,12 +292,19 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
  * in FP32; coarse levels in coarse_prec (MRHS_F32 vector ALU or FP32 matrix
  * cores, MRHS_BF16 or MRHS_F16 matrix cores with FP32 accumulation,
  * Nb = 32).  With MRHS_BF16 the restriction and prolongation of a step with
- * n_v = 16 run on the BF16 matrix cores too, otherwise in FP32. */
+ * n_v = 16 run on the BF16 matrix cores too, otherwise in FP32.
+ * With fine_eo = 1 (every extent even) a fine-level smoothing pass of nu
+ * steps computes its correction e ~ D^-1 r from the Schur complement
+ * Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe (see mrhs_schur_apply): nu MR steps
+ * on Dhat e_e = r_e + kappa H_eo A_o^-1 r_o from e_e = 0, then
+ * e_o = A_o^-1 (r_o + kappa H_oe e_e), x += e and r = b - D x. */
 typedef struct {
   int32_t nu_pre;
   int32_t nu_post;
   int32_t coarsest_iters;
   mrhs_prec coarse_prec;
+  int32_t fine_eo; /* 1: the fine-level smoothing steps run on the even-odd
+                      Schur complement (see below); 0: on D */
 } mrhs_vcycle_params;
 
 typedef struct {

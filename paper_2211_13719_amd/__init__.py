@@ -399,10 +399,11 @@ class Multigrid:
 
     # -- solver ---------------------------------------------------------------------------
     @staticmethod
-    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16"):
+    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16", fine_eo=False):
         v = _lib.VcycleParams()
         v.nu_pre, v.nu_post, v.coarsest_iters = int(nu_pre), int(nu_post), int(coarsest_iters)
         v.coarse_prec = _PREC_NAMES[coarse_prec]
+        v.fine_eo = int(bool(fine_eo))
         return v
 
     def setup(self, setup_iters: int = 3, smooth_steps: int = 8, adapt_iters: int = 0, **vc):

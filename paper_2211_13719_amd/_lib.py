@@ -73,7 +73,8 @@ SIGNATURES = {
 
 
 class VcycleParams(C.Structure):
-    _fields_ = [("nu_pre", _i32), ("nu_post", _i32), ("coarsest_iters", _i32), ("coarse_prec", _i32)]
+    _fields_ = [("nu_pre", _i32), ("nu_post", _i32), ("coarsest_iters", _i32), ("coarse_prec", _i32),
+                ("fine_eo", _i32)]
 
 
 class SetupParams(C.Structure):

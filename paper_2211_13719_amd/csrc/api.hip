@@ -100,6 +100,49 @@ mrhs_status check_field_args(mrhs_ctx ctx, const void* out, const void* in, int3
   return MRHS_OK;
 }
 
+mrhs_status fine_apply(mrhs_ctx ctx, int mode, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V);
+  if (st != MRHS_OK) return st;
+  if (mode != 2 && !ctx->have_gauge) return fail(ctx, MRHS_ERR_STATE, "gauge field not set");
+  if (mode != 1 && !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "clover term not set");
+  DeviceGuard dg(ctx->device);
+  hipError_t e;
+  if (prec == MRHS_F32)
+    e = launch_fine_f32(ctx->g, ctx->t_bc, mode, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, nrhs,
+                        ctx->stream, &ctx->fine_cfg[nrhs]);
+  else
+    e = launch_fine_f64(ctx->g, ctx->t_bc, mode, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, nrhs, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fine operator launch");
+  return MRHS_OK;
+}
+
+// Copy n doubles or floats (given prec) from a host or device pointer into
+// the FP64 and FP32 library buffers.
+mrhs_status import_real_array(mrhs_ctx ctx, const void* src, mrhs_prec prec, int on_device, size_t n,
+                              Buffer& b64, Buffer& b32) {
+  mrhs_status st = ensure(ctx, b64, n * 8);
+  if (st != MRHS_OK) return st;
+  st = ensure(ctx, b32, n * 4);
+  if (st != MRHS_OK) return st;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (prec == MRHS_F64) {
+    MRHS_HIP(ctx, hipMemcpyAsync(b64.p, src, n * 8, kind, ctx->stream));
+    MRHS_HIP(ctx, launch_convert_f64_to_f32(static_cast<const double*>(b64.p), static_cast<float*>(b32.p), n,
+                                            ctx->stream));
+  } else {
+    MRHS_HIP(ctx, hipMemcpyAsync(b32.p, src, n * 4, kind, ctx->stream));
+    MRHS_HIP(ctx, launch_convert_f32_to_f64(static_cast<const float*>(b32.p), static_cast<double*>(b64.p), n,
+                                            ctx->stream));
+  }
+  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return MRHS_OK;
+}
+
+}  // namespace
+
+namespace mrhs {
+
 // Checkerboard tables (see fine.hip): built on first use; every extent must
 // be even, so that each hop joins the two parities and s = 2i, 2i + 1 always
 // hold one site of each.
@@ -179,49 +222,6 @@ mrhs_status ensure_clover_inverse(mrhs_ctx ctx) {
   ctx->have_clover_inv = true;
   return MRHS_OK;
 }
-
-mrhs_status fine_apply(mrhs_ctx ctx, int mode, void* out, const void* in, int32_t nrhs, mrhs_prec prec) {
-  if (!ctx) return MRHS_ERR_INVALID_ARG;
-  mrhs_status st = check_field_args(ctx, out, in, nrhs, prec, 12, ctx->g.V);
-  if (st != MRHS_OK) return st;
-  if (mode != 2 && !ctx->have_gauge) return fail(ctx, MRHS_ERR_STATE, "gauge field not set");
-  if (mode != 1 && !ctx->have_clover) return fail(ctx, MRHS_ERR_STATE, "clover term not set");
-  DeviceGuard dg(ctx->device);
-  hipError_t e;
-  if (prec == MRHS_F32)
-    e = launch_fine_f32(ctx->g, ctx->t_bc, mode, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, nrhs,
-                        ctx->stream, &ctx->fine_cfg[nrhs]);
-  else
-    e = launch_fine_f64(ctx->g, ctx->t_bc, mode, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, nrhs, ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "fine operator launch");
-  return MRHS_OK;
-}
-
-// Copy n doubles or floats (given prec) from a host or device pointer into
-// the FP64 and FP32 library buffers.
-mrhs_status import_real_array(mrhs_ctx ctx, const void* src, mrhs_prec prec, int on_device, size_t n,
-                              Buffer& b64, Buffer& b32) {
-  mrhs_status st = ensure(ctx, b64, n * 8);
-  if (st != MRHS_OK) return st;
-  st = ensure(ctx, b32, n * 4);
-  if (st != MRHS_OK) return st;
-  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  if (prec == MRHS_F64) {
-    MRHS_HIP(ctx, hipMemcpyAsync(b64.p, src, n * 8, kind, ctx->stream));
-    MRHS_HIP(ctx, launch_convert_f64_to_f32(static_cast<const double*>(b64.p), static_cast<float*>(b32.p), n,
-                                            ctx->stream));
-  } else {
-    MRHS_HIP(ctx, hipMemcpyAsync(b32.p, src, n * 4, kind, ctx->stream));
-    MRHS_HIP(ctx, launch_convert_f32_to_f64(static_cast<const float*>(b32.p), static_cast<double*>(b64.p), n,
-                                            ctx->stream));
-  }
-  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return MRHS_OK;
-}
-
-}  // namespace
-
-namespace mrhs {
 
 // Site traversal of the fine kernels.  Sites are grouped in tiles of extent
 // T; tiles are visited t-row by t-row (the tile index along t outermost, so

@@ -801,6 +801,25 @@ __global__ __launch_bounds__(256) void clover_invert_kernel(long nblk, const dou
     }
 }
 
+// Row copies between a full-lattice FP32 field and one parity's checkerboard
+// field: one thread per (checkerboard site, component, pair of RHS values).
+template <bool ADD>
+__global__ __launch_bounds__(256) void eo_rows_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
+                                                      float2* __restrict__ full, float2* __restrict__ half) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long per = 12L * nrhs;
+  if (e >= (long)nhalf * per) return;
+  const int i = (int)(e / per);
+  const long r = e - (long)i * per;
+  const size_t f = (size_t)tab[4 * i + 2].x * per + r;
+  if (ADD) {
+    const float2 a = full[f], b = half[e];
+    full[f] = make_float2(a.x + b.x, a.y + b.y);
+  } else {
+    half[e] = full[f];
+  }
+}
+
 template <typename T, int R>
 hipError_t launch_hop_eo_r(int nhalf, int nrhs, const int4* tab, const int* order, const void* U, const void* in,
                            void* out, hipStream_t s) {
@@ -859,6 +878,20 @@ hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* 
   if (prec64) return launch_clover_eo_r<double, 1>(nhalf, nrhs, tab, A, in, add, coef, out, s);
   if (nrhs % 2 == 0) return launch_clover_eo_r<float, 2>(nhalf, nrhs, tab, A, in, add, coef, out, s);
   return launch_clover_eo_r<float, 1>(nhalf, nrhs, tab, A, in, add, coef, out, s);
+}
+
+hipError_t launch_eo_gather(int nhalf, const int4* tab, const void* full, void* half, int nrhs, hipStream_t s) {
+  const long n = (long)nhalf * 12 * nrhs;
+  hipLaunchKernelGGL(eo_rows_kernel<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nhalf, nrhs, tab,
+                     const_cast<float2*>(static_cast<const float2*>(full)), static_cast<float2*>(half));
+  return hipGetLastError();
+}
+
+hipError_t launch_eo_scatter_add(int nhalf, const int4* tab, void* full, const void* half, int nrhs, hipStream_t s) {
+  const long n = (long)nhalf * 12 * nrhs;
+  hipLaunchKernelGGL(eo_rows_kernel<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nhalf, nrhs, tab,
+                     static_cast<float2*>(full), const_cast<float2*>(static_cast<const float2*>(half)));
+  return hipGetLastError();
 }
 
 hipError_t launch_clover_invert(long nblk, const void* A64, void* Ai64, void* Ai32, int* flag, hipStream_t s) {

@@ -163,6 +163,10 @@ hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* orde
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
                             double coef, void* out, int nrhs, hipStream_t s);
 hipError_t launch_clover_invert(long nblk, const void* A64, void* Ai64, void* Ai32, int* flag, hipStream_t s);
+// FP32 rows of one parity between a full-lattice field and a checkerboard one:
+// half[i] = full[site(i)], or full[site(i)] += half[i]
+hipError_t launch_eo_gather(int nhalf, const int4* tab, const void* full, void* half, int nrhs, hipStream_t s);
+hipError_t launch_eo_scatter_add(int nhalf, const int4* tab, void* full, const void* half, int nrhs, hipStream_t s);
 
 // ---- launchers (clover_build.hip) -------------------------------------------
 hipError_t launch_clover_build(const Geom& g, double csw, double kappa, const void* U64,
@@ -204,6 +208,9 @@ hipError_t launch_basis_columns(int prec64, const void* basis, void* W, long nsi
 // Traversal table of the fine lattice for tile T (built and cached on first
 // use); null on failure.
 const int* fine_order_table(mrhs_ctx ctx, const int T[4], int curve = 0);
+// checkerboard tables and traversal orders, inverse clover blocks (api.hip)
+mrhs_status ensure_eo_tables(mrhs_ctx ctx);
+mrhs_status ensure_clover_inverse(mrhs_ctx ctx);
 // Multiplies the t-links of the last time slice by t_bc (FP64 and FP32 copies).
 hipError_t launch_fold_boundary_phase(const Geom& g, int t_bc, void* U64, void* U32, hipStream_t s);
 

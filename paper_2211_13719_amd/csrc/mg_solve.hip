@@ -56,6 +56,7 @@ hipError_t launch_scale_cols(int prec64, void* y, const void* x, const double* s
 hipError_t launch_inv_sqrt(const double* q, double* sdev, int nrhs, double f, hipStream_t s);
 hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long n, hipStream_t s);
 hipError_t launch_add_f32(void* y, const void* x, long n, hipStream_t s);
+hipError_t launch_axpy_f32(void* y, const void* x, double c, long n, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 size_t col_gram_scratch_bytes();
 hipError_t launch_col_gram(const void* v, long rows, int nv, void* scratch, void* g, hipStream_t s);
@@ -82,6 +83,9 @@ struct SolverState {
   Buffer lb[MRHS_MAX_LEVELS], lx[MRHS_MAX_LEVELS], lr[MRHS_MAX_LEVELS], lp[MRHS_MAX_LEVELS];
   Buffer alpha, part, scl, coef, qn;
   Buffer gpart, gmat, gT;  // column Gram matrix (setup)
+  // even-odd fine smoother: eight checkerboard fields of eo_n columns
+  Buffer eo;
+  int eo_n = 0;
   // outer Krylov
   int m = 0, on = 0;
   Buffer V64, Z32, w64, r64;
@@ -105,7 +109,7 @@ void mg_solver_release(mrhs_mg mg) {
     release(st->lp[l]);
   }
   Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->gpart, &st->gmat, &st->gT,
-                 &st->V64, &st->Z32, &st->w64, &st->r64};
+                 &st->V64, &st->Z32, &st->w64, &st->r64, &st->eo};
   for (Buffer* x : b) release(*x);
   for (auto& gs : st->graphs)
     if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
@@ -226,6 +230,65 @@ hipError_t mr_steps(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* 
   return hipSuccess;
 }
 
+// Fine-level smoothing on the even-odd Schur complement: with r = b - D x,
+//   rhat = r_e + kappa H_eo A_o^-1 r_o,  nu MR steps on Dhat e_e = rhat from 0,
+//   e_o = A_o^-1 (r_o + kappa H_oe e_e),  x += e,  r = b - D x.
+// Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe.  Checkerboard work fields live in
+// st->eo: r_e, r_o, rho, q, e_e, t_o, t_o2, t_e.
+hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* b, void* p, int n, int nu) {
+  mrhs_ctx ctx = mg->ctx;
+  if (nu <= 0) return hipSuccess;
+  const int nh = ctx->g.V / 2;
+  const long hrows = (long)nh * 12;
+  const size_t hb = (size_t)hrows * n * 8;
+  char* w = static_cast<char*>(st->eo.p);
+  void *re = w, *ro = w + hb, *rho = w + 2 * hb, *q = w + 3 * hb, *ee = w + 4 * hb, *to = w + 5 * hb,
+       *to2 = w + 6 * hb, *te = w + 7 * hb;
+  const auto* tabe = static_cast<const int4*>(ctx->eo_tab[0].p);
+  const auto* tabo = static_cast<const int4*>(ctx->eo_tab[1].p);
+  const auto* orde = static_cast<const int*>(ctx->eo_order[0].p);
+  const auto* ordo = static_cast<const int*>(ctx->eo_order[1].p);
+  const void* U = ctx->U32.p;
+  const void* A = ctx->A32.p;
+  const void* Ai = ctx->Ainv32.p;
+  const double k = ctx->kappa;
+  hipStream_t s = st->stream;
+  hipError_t e = launch_eo_gather(nh, tabe, r, re, n, s);
+  if (e == hipSuccess) e = launch_eo_gather(nh, tabo, r, ro, n, s);
+  // rhat = r_e + kappa H_eo A_o^-1 r_o
+  if (e == hipSuccess) e = launch_clover_eo(0, nh, tabo, Ai, ro, nullptr, 0.0, to, n, s);
+  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to, te, n, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(rho, re, hb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_axpy_f32(rho, te, k, hrows * n, s);
+  if (e == hipSuccess) e = launch_zero(ee, hb, s);
+  for (int i = 0; i < nu && e == hipSuccess; ++i) {
+    // q = Dhat rho
+    e = launch_hop_eo(0, nh, tabo, ordo, U, rho, to, n, s);
+    if (e == hipSuccess) e = launch_clover_eo(0, nh, tabo, Ai, to, nullptr, 0.0, to2, n, s);
+    if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to2, te, n, s);
+    if (e == hipSuccess) e = launch_clover_eo(0, nh, tabe, A, rho, te, -k * k, q, n, s);
+    if (e == hipSuccess) e = launch_mr_alpha(q, rho, hrows, n, st->alpha.p, st->part.p, s);
+    if (e == hipSuccess) e = launch_mr_update(ee, rho, q, st->alpha.p, hrows, n, s);
+  }
+  // e_o = A_o^-1 (r_o + kappa H_oe e_e), written over r_o's copy
+  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabo, ordo, U, ee, to, n, s);
+  if (e == hipSuccess) e = launch_axpy_f32(ro, to, k, hrows * n, s);
+  if (e == hipSuccess) e = launch_clover_eo(0, nh, tabo, Ai, ro, nullptr, 0.0, to2, n, s);
+  if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabe, x, ee, n, s);
+  if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabo, x, to2, n, s);
+  // r = b - D x
+  if (e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
+  if (e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, 0) * n, s);
+  return e;
+}
+
+// The smoothing pass of the V-cycle on level l.
+hipError_t smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r, const void* b, void* p, int n, int nu,
+                  const mrhs_vcycle_params& vc) {
+  if (l == 0 && vc.fine_eo) return eo_smooth(mg, st, x, r, b, p, n, nu);
+  return mr_steps(mg, st, l, x, r, p, n, nu, vc.coarse_prec);
+}
+
 // x_l ~ D_l^{-1} b_l (buffers lb[l] -> lx[l]).
 hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_params& vc, void* xout = nullptr) {
   const long rows = level_rows(mg, l);
@@ -243,7 +306,7 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
     if (e == hipSuccess) e = hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st->stream);
     if (e != hipSuccess) return e;
     if (l == mg->nlevels - 1) return mr_steps(mg, st, l, x, r, p, n, vc.coarsest_iters, cp);
-    e = mr_steps(mg, st, l, x, r, p, n, vc.nu_pre, cp);
+    e = smooth(mg, st, l, x, r, b, p, n, vc.nu_pre, vc);
     if (e != hipSuccess) return e;
   }
   LevelData& L = mg->lv[l];
@@ -267,7 +330,7 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   e = launch_add_f32(x, p, rows * n, st->stream);
   if (e == hipSuccess) e = apply_level(mg, l, p, x, n, cp, st->stream);
   if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, st->stream);
-  if (e == hipSuccess) e = mr_steps(mg, st, l, x, r, p, n, vc.nu_post, cp);
+  if (e == hipSuccess) e = smooth(mg, st, l, x, r, b, p, n, vc.nu_post, vc);
   return e;
 }
 
@@ -285,7 +348,7 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
   GraphSlot& gs = st->graphs[slot];
   const bool same = gs.exec && gs.n == n && gs.out == xout && gs.vc.nu_pre == vc.nu_pre &&
                     gs.vc.nu_post == vc.nu_post && gs.vc.coarsest_iters == vc.coarsest_iters &&
-                    gs.vc.coarse_prec == vc.coarse_prec;
+                    gs.vc.coarse_prec == vc.coarse_prec && gs.vc.fine_eo == vc.fine_eo;
   if (!same) {
     if (gs.exec) {
       (void)hipGraphExecDestroy(gs.exec);
@@ -325,6 +388,28 @@ mrhs_status check_vc(mrhs_mg mg, const mrhs_vcycle_params* vc) {
     return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "V-cycle iteration counts out of range");
   if (vc->coarse_prec != MRHS_F32 && vc->coarse_prec != MRHS_BF16 && vc->coarse_prec != MRHS_F16)
     return fail(mg->ctx, MRHS_ERR_UNSUPPORTED, "coarse precision must be f32, bf16 or f16");
+  if (vc->fine_eo != 0 && vc->fine_eo != 1) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "fine_eo must be 0 or 1");
+  return MRHS_OK;
+}
+
+// Index tables, inverse clover blocks and checkerboard work fields of the
+// even-odd fine smoother (outside any graph capture).
+mrhs_status prepare_eo(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_params& vc) {
+  if (!vc.fine_eo) return MRHS_OK;
+  mrhs_ctx ctx = mg->ctx;
+  mrhs_status s = ensure_eo_tables(ctx);
+  if (s == MRHS_OK) s = ensure_clover_inverse(ctx);
+  if (s != MRHS_OK) return s;
+  if (n > st->eo_n) {
+    for (auto& gs : st->graphs) {
+      if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
+      gs = GraphSlot{};
+    }
+    release(st->eo);
+    s = ensure(ctx, st->eo, (size_t)8 * (ctx->g.V / 2) * 12 * n * 8);
+    if (s != MRHS_OK) return s;
+    st->eo_n = n;
+  }
   return MRHS_OK;
 }
 
@@ -442,6 +527,7 @@ mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrh
   SolverState* st;
   s = state_of(mg, &st);
   if (s == MRHS_OK) s = ensure_levels(mg, st, nrhs);
+  if (s == MRHS_OK) s = prepare_eo(mg, st, nrhs, *vc);
   if (s != MRHS_OK) return s;
   st->timing = false;
   st->evused = 0;
@@ -478,6 +564,7 @@ mrhs_status mrhs_mg_setup(mrhs_mg mg, const mrhs_setup_params* prm) {
   int nmax = 0;
   for (int l = 0; l + 1 < mg->nlevels; ++l) nmax = std::max(nmax, mg->lv[l].nv);
   s = ensure_levels(mg, st, nmax);
+  if (s == MRHS_OK && adapt_iters > 0) s = prepare_eo(mg, st, nmax, prm->vc);
   if (s != MRHS_OK) return s;
   st->timing = false;
   st->evused = 0;
@@ -560,6 +647,7 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   SolverState* st;
   s = state_of(mg, &st);
   if (s == MRHS_OK) s = ensure_levels(mg, st, nrhs);
+  if (s == MRHS_OK && prm->precondition) s = prepare_eo(mg, st, nrhs, prm->vc);
   if (s != MRHS_OK) return s;
   const int n = nrhs;
   const size_t f64 = (size_t)rows * n * 16, f32 = (size_t)rows * n * 8;

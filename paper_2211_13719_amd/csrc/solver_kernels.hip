@@ -244,6 +244,14 @@ __global__ __launch_bounds__(kB) void add_f32(float2* __restrict__ y, const floa
   y[e] = u;
 }
 
+// y += c x for n complex FP32 values (real c).
+__global__ __launch_bounds__(kB) void axpy_f32(float2* __restrict__ y, const float2* __restrict__ x, float c, long n) {
+  for (long e = (long)blockIdx.x * kB + threadIdx.x; e < n; e += (long)gridDim.x * kB) {
+    const float2 a = y[e], b = x[e];
+    y[e] = make_float2(fmaf(c, b.x, a.x), fmaf(c, b.y, a.y));
+  }
+}
+
 __global__ __launch_bounds__(kB) void zero_words(uint4* __restrict__ p, long n16) {
   const long e = (long)blockIdx.x * kB + threadIdx.x;
   if (e < n16) p[e] = make_uint4(0, 0, 0, 0);
@@ -382,6 +390,12 @@ hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long 
 hipError_t launch_add_f32(void* y, const void* x, long n, hipStream_t s) {
   hipLaunchKernelGGL(add_f32, dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(y), static_cast<const float2*>(x),
                      n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_f32(void* y, const void* x, double c, long n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_f32, dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(y), static_cast<const float2*>(x),
+                     (float)c, n);
   return hipGetLastError();
 }
 

@@ -204,3 +204,30 @@ def test_reorth_threshold_out_of_range(small, gpu_lib):
     x = torch.zeros_like(b)
     with pytest.raises(gpu_lib.MrhsError, match="INVALID_ARG"):
         mg.solve(x, b, reorth_eta=1.5)
+
+
+@pytest.mark.parametrize("nrhs", [1, 12])
+def test_solve_even_odd_smoother(small, nrhs):
+    """Fine smoothing on the even-odd Schur complement: same 1e-10 true residual."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = synth.spinor_source(dims, nrhs, 9100)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    st = mg.solve(x, dev(b), tol=1e-10, restart=8, max_iters=400, nu_pre=1, nu_post=3, coarsest_iters=16,
+                  coarse_prec="bf16", fine_eo=True)
+    assert all(st["converged"]) and max(st["rel_resid"]) <= 1e-10
+    assert np.all(O.true_residual(U, A, KAPPA, x.cpu().numpy(), b, dims) <= 1e-10)
+
+
+def test_even_odd_smoother_graph_replay_is_bitwise_equal(small):
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = dev(synth.spinor_source(dims, 4, 9200))
+    x1 = torch.zeros_like(b)
+    x2 = torch.zeros_like(b)
+    s1 = mg.solve(x1, b, use_graph=True, coarse_prec="bf16", fine_eo=True)
+    s2 = mg.solve(x2, b, use_graph=False, coarse_prec="bf16", fine_eo=True)
+    assert s1["iters"] == s2["iters"]
+    assert torch.equal(x1, x2)
