@@ -60,6 +60,7 @@ SOLVE_DIMS = (24, 24, 24, 128)
 SOLVE_SETUP = dict(setup_iters=10, smooth_steps=30, adapt_iters=0)
 SOLVE_VC = dict(nu_pre=0, nu_post=6, coarsest_iters=64)
 SOLVE_RESTART, SOLVE_MAXIT = 8, 1000
+SOLVE_MRHS_FINE_EO = True  # 24^3x128, 12 / 24 RHS: 24 instead of 28 outer steps, 10-13 % less time
 TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
 FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 
@@ -210,7 +211,7 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] solve setup {setup_s:.1f} s", file=sys.stderr, flush=True)
-    vc = SOLVE_VC
+    vc = dict(SOLVE_VC, fine_eo=SOLVE_MRHS_FINE_EO)
     kw = dict(tol=1e-10, restart=SOLVE_RESTART, max_iters=SOLVE_MAXIT, check=False)
     mrhs_res, phases = {}, None
     for n in nrhs_list:
@@ -234,10 +235,16 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
             print(f"[bench] timed MRHS solve {stt['seconds_total']:.2f} s", file=sys.stderr, flush=True)
         del b, x
         torch.cuda.empty_cache()
+    # the comparator is the faster of the two fine smoothers on one RHS
     b1 = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, 1, 4000)).cuda()
-    x1 = torch.zeros_like(b1)
-    s1 = mg.solve(x1, b1, use_graph=True, coarse_prec="f32", **kw, **vc)
-    print(f"[bench] SRHS solve {s1['seconds_total']:.2f} s, {s1['iters']} iterations", file=sys.stderr, flush=True)
+    srhs = {}
+    for eo in (False, True):
+        x1 = torch.zeros_like(b1)
+        srhs[eo] = mg.solve(x1, b1, use_graph=True, coarse_prec="f32", **kw, **dict(SOLVE_VC, fine_eo=eo))
+        print(f"[bench] SRHS solve (fine_eo={int(eo)}) {srhs[eo]['seconds_total']:.2f} s, {srhs[eo]['iters']} "
+              "iterations", file=sys.stderr, flush=True)
+    srhs_eo = min(srhs, key=lambda e: srhs[e]["seconds_total"] if srhs[e]["converged"][0] else 1e30)
+    s1 = srhs[srhs_eo]
     ok = [k for k, v in mrhs_res.items() if v["converged"] == int(k)]
     best = min(ok, key=lambda k: mrhs_res[k]["s_per_rhs"]) if ok else None
     out = {
@@ -252,11 +259,14 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "srhs_iters": s1["iters"],
         "srhs_true_resid": s1["rel_resid"][0],
         "srhs_converged": int(s1["converged"][0]),
+        "srhs_fine_eo": int(srhs_eo),
+        "srhs_s_by_fine_eo": {str(int(e)): round(v["seconds_total"], 4) for e, v in srhs.items()},
         "speedup": round(s1["seconds_total"] / mrhs_res[best]["s_per_rhs"], 3) if best else None,
         "mrhs_phase_s": phases,
         "config": f"FP64 FGMRES({SOLVE_RESTART}), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
-                  "levels and BF16 matrix-core restrict/prolong, graph replay; SRHS comparator: same solver, one "
-                  "RHS, FP32 coarse levels and FP32 intergrid",
+                  f"levels and BF16 matrix-core restrict/prolong, fine_eo {int(SOLVE_MRHS_FINE_EO)} (fine smoothing "
+                  "on the even-odd Schur complement), graph replay; SRHS comparator: same solver, one RHS, FP32 "
+                  "coarse levels and FP32 intergrid, the faster of the two fine smoothers",
         "mass_tuning": {k: mass.get(k) for k in ("sigma_min", "t_bc_for_sigma_min", "target_sigma_min")},
     }
     mg.close()

@@ -297,7 +297,8 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
  * steps computes its correction e ~ D^-1 r from the Schur complement
  * Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe (see mrhs_schur_apply): nu MR steps
  * on Dhat e_e = r_e + kappa H_eo A_o^-1 r_o from e_e = 0, then
- * e_o = A_o^-1 (r_o + kappa H_oe e_e), x += e and r = b - D x. */
+ * e_o = A_o^-1 (r_o + kappa H_oe e_e) and x += e (then r = b - D x when the
+ * residual is still needed, i.e. after the pre-smoothing pass). */
 typedef struct {
   int32_t nu_pre;
   int32_t nu_post;

@@ -514,15 +514,13 @@ mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nr
   const auto* te = static_cast<const int4*>(ctx->eo_tab[0].p);
   const auto* to = static_cast<const int4*>(ctx->eo_tab[1].p);
   const void* U = p64 ? ctx->U64.p : ctx->U32.p;
-  // t1 = H_oe in, t2 = A_o^-1 t1, t1 = H_eo t2, out = A_e in - kappa^2 t1
+  // t2 = A_o^-1 (H_oe in), out = A_e in - kappa^2 (H_eo t2): two fused launches
   const auto* oe = static_cast<const int*>(ctx->eo_order[0].p);
   const auto* oo = static_cast<const int*>(ctx->eo_order[1].p);
-  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, oo, U, in, t1, nrhs, ctx->stream));
-  MRHS_HIP(ctx, launch_clover_eo(p64, nh, to, p64 ? ctx->Ainv64.p : ctx->Ainv32.p, t1, nullptr, 0.0, t2, nrhs,
-                                 ctx->stream));
-  MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, oe, U, t2, t1, nrhs, ctx->stream));
-  MRHS_HIP(ctx, launch_clover_eo(p64, nh, te, p64 ? ctx->A64.p : ctx->A32.p, in, t1, -ctx->kappa * ctx->kappa, out,
-                                 nrhs, ctx->stream));
+  (void)t1;
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, oo, U, in, t2, nrhs, ctx->stream, 1, p64 ? ctx->Ainv64.p : ctx->Ainv32.p));
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, oe, U, t2, out, nrhs, ctx->stream, 2, p64 ? ctx->A64.p : ctx->A32.p, in,
+                              -ctx->kappa * ctx->kappa));
   return MRHS_OK;
 }
 

@@ -647,11 +647,16 @@ hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U
 // Sites are visited in the order of a traversal table (the parity-p sites of
 // the full kernel's tiled order), each XCD taking one contiguous range of it,
 // so that neighbour rows are re-read from its own L2 as in fine_kernel.
-template <typename T, int R>
+// EPI selects what is stored: 0 the hop itself; 1 Ablk (H in), Ablk the
+// clover blocks (or their inverses) of the output sites; 2 Ablk in2 + coef
+// (H in), in2 a field on the output parity.  1 and 2 fuse the Schur
+// complement's clover factors into the hops.
+template <typename T, int R, int EPI>
 __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
                                                      const int* __restrict__ order, int nblocks,
                                                      const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
-                                                     cplx<T>* __restrict__ out) {
+                                                     cplx<T>* __restrict__ out, const T* __restrict__ Ablk,
+                                                     const cplx<T>* __restrict__ in2, T coef) {
   const int per = (nblocks + 7) >> 3;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (b >= nblocks) return;
@@ -674,10 +679,39 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
   hop_dir<T, R, 2, true>(s0.x, n1.x, n1.y, nrhs, k0, U, in, acc, true, true, s0.w);
   hop_dir<T, R, 3, true>(s0.x, n1.z, n1.w, nrhs, k0, U, in, acc, true, true, s1.x);
   cplx<T>* o = out + (size_t)i * 12 * nrhs + k0;
+  if constexpr (EPI == 0) {
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
+    for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c]);
+      for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c]);
+  } else {
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      cplx<T> xin[6][R], yout[6][R];
+      if constexpr (EPI == 1) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int j = 0; j < R; ++j) xin[r][j] = acc[2 * chi + r / 3][r % 3][j];
+      } else {
+        const cplx<T>* q = in2 + (size_t)i * 12 * nrhs + k0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) load_r<T, R>(q + (6 * chi + r) * nrhs, xin[r]);
+      }
+      clover_block<T, R>(Ablk + ((size_t)s0.x * 2 + chi) * 36, xin, yout);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        if constexpr (EPI == 2) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            yout[r][j].x = fma(coef, acc[2 * chi + r / 3][r % 3][j].x, yout[r][j].x);
+            yout[r][j].y = fma(coef, acc[2 * chi + r / 3][r % 3][j].y, yout[r][j].y);
+          }
+        }
+        store_r<T, R>(o + (6 * chi + r) * nrhs, yout[r]);
+      }
+    }
+  }
 }
 
 // M_ooee (or its inverse, given the inverse blocks): out = A in + coef add on
@@ -821,13 +855,25 @@ __global__ __launch_bounds__(256) void eo_rows_kernel(int nhalf, int nrhs, const
 }
 
 template <typename T, int R>
-hipError_t launch_hop_eo_r(int nhalf, int nrhs, const int4* tab, const int* order, const void* U, const void* in,
-                           void* out, hipStream_t s) {
+hipError_t launch_hop_eo_r(int epi, int nhalf, int nrhs, const int4* tab, const int* order, const void* U,
+                           const void* in, void* out, const void* Ablk, const void* in2, double coef, hipStream_t s) {
   const long threads = (long)nhalf * (nrhs / R);
   const int nblocks = (int)((threads + 255) / 256);
-  const int grid = ((nblocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((hop_eo_kernel<T, R>), dim3((unsigned)grid), dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks,
-                     static_cast<const cplx<T>*>(U), static_cast<const cplx<T>*>(in), static_cast<cplx<T>*>(out));
+  const dim3 grid((unsigned)(((nblocks + 7) / 8) * 8));
+  const auto* u = static_cast<const cplx<T>*>(U);
+  const auto* x = static_cast<const cplx<T>*>(in);
+  auto* y = static_cast<cplx<T>*>(out);
+  const auto* a = static_cast<const T*>(Ablk);
+  const auto* x2 = static_cast<const cplx<T>*>(in2);
+  if (epi == 1)
+    hipLaunchKernelGGL((hop_eo_kernel<T, R, 1>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks, u, x, y, a,
+                       x2, (T)coef);
+  else if (epi == 2)
+    hipLaunchKernelGGL((hop_eo_kernel<T, R, 2>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks, u, x, y, a,
+                       x2, (T)coef);
+  else
+    hipLaunchKernelGGL((hop_eo_kernel<T, R, 0>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks, u, x, y, a,
+                       x2, (T)coef);
   return hipGetLastError();
 }
 
@@ -866,11 +912,12 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
 
 // FP32: two right-hand sides per thread for even nrhs; FP64: one.
 hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
-                         void* out, int nrhs, hipStream_t s) {
-  if (!tab || !order) return hipErrorInvalidValue;
-  if (prec64) return launch_hop_eo_r<double, 1>(nhalf, nrhs, tab, order, U, in, out, s);
-  if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(nhalf, nrhs, tab, order, U, in, out, s);
-  return launch_hop_eo_r<float, 1>(nhalf, nrhs, tab, order, U, in, out, s);
+                         void* out, int nrhs, hipStream_t s, int epi, const void* Ablk, const void* in2,
+                         double coef) {
+  if (!tab || !order || (epi && !Ablk) || (epi == 2 && !in2)) return hipErrorInvalidValue;
+  if (prec64) return launch_hop_eo_r<double, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+  if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+  return launch_hop_eo_r<float, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
 }
 
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,

@@ -232,10 +232,12 @@ hipError_t mr_steps(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* 
 
 // Fine-level smoothing on the even-odd Schur complement: with r = b - D x,
 //   rhat = r_e + kappa H_eo A_o^-1 r_o,  nu MR steps on Dhat e_e = rhat from 0,
-//   e_o = A_o^-1 (r_o + kappa H_oe e_e),  x += e,  r = b - D x.
+//   e_o = A_o^-1 (r_o + kappa H_oe e_e),  x += e,  and r = b - D x when the
+// caller still needs the residual (not after the last smoothing pass).
 // Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe.  Checkerboard work fields live in
 // st->eo: r_e, r_o, rho, q, e_e, t_o, t_o2, t_e.
-hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* b, void* p, int n, int nu) {
+hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* b, void* p, int n, int nu,
+                     bool need_r) {
   mrhs_ctx ctx = mg->ctx;
   if (nu <= 0) return hipSuccess;
   const int nh = ctx->g.V / 2;
@@ -262,11 +264,9 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   if (e == hipSuccess) e = launch_axpy_f32(rho, te, k, hrows * n, s);
   if (e == hipSuccess) e = launch_zero(ee, hb, s);
   for (int i = 0; i < nu && e == hipSuccess; ++i) {
-    // q = Dhat rho
-    e = launch_hop_eo(0, nh, tabo, ordo, U, rho, to, n, s);
-    if (e == hipSuccess) e = launch_clover_eo(0, nh, tabo, Ai, to, nullptr, 0.0, to2, n, s);
-    if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to2, te, n, s);
-    if (e == hipSuccess) e = launch_clover_eo(0, nh, tabe, A, rho, te, -k * k, q, n, s);
+    // q = Dhat rho: to2 = A_o^-1 (H_oe rho), q = A_e rho - kappa^2 (H_eo to2), fused launches
+    e = launch_hop_eo(0, nh, tabo, ordo, U, rho, to2, n, s, 1, Ai);
+    if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to2, q, n, s, 2, A, rho, -k * k);
     if (e == hipSuccess) e = launch_mr_alpha(q, rho, hrows, n, st->alpha.p, st->part.p, s);
     if (e == hipSuccess) e = launch_mr_update(ee, rho, q, st->alpha.p, hrows, n, s);
   }
@@ -277,15 +277,15 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabe, x, ee, n, s);
   if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabo, x, to2, n, s);
   // r = b - D x
-  if (e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
-  if (e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, 0) * n, s);
+  if (need_r && e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
+  if (need_r && e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, 0) * n, s);
   return e;
 }
 
 // The smoothing pass of the V-cycle on level l.
 hipError_t smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r, const void* b, void* p, int n, int nu,
-                  const mrhs_vcycle_params& vc) {
-  if (l == 0 && vc.fine_eo) return eo_smooth(mg, st, x, r, b, p, n, nu);
+                  const mrhs_vcycle_params& vc, bool need_r) {
+  if (l == 0 && vc.fine_eo) return eo_smooth(mg, st, x, r, b, p, n, nu, need_r);
   return mr_steps(mg, st, l, x, r, p, n, nu, vc.coarse_prec);
 }
 
@@ -306,7 +306,7 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
     if (e == hipSuccess) e = hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st->stream);
     if (e != hipSuccess) return e;
     if (l == mg->nlevels - 1) return mr_steps(mg, st, l, x, r, p, n, vc.coarsest_iters, cp);
-    e = smooth(mg, st, l, x, r, b, p, n, vc.nu_pre, vc);
+    e = smooth(mg, st, l, x, r, b, p, n, vc.nu_pre, vc, true);
     if (e != hipSuccess) return e;
   }
   LevelData& L = mg->lv[l];
@@ -330,7 +330,7 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   e = launch_add_f32(x, p, rows * n, st->stream);
   if (e == hipSuccess) e = apply_level(mg, l, p, x, n, cp, st->stream);
   if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, st->stream);
-  if (e == hipSuccess) e = smooth(mg, st, l, x, r, b, p, n, vc.nu_post, vc);
+  if (e == hipSuccess) e = smooth(mg, st, l, x, r, b, p, n, vc.nu_post, vc, false);
   return e;
 }
 
