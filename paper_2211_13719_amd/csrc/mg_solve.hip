@@ -23,6 +23,9 @@
 // steps run on the BF16 matrix cores as well).  The MR step sizes alpha_k = <D r_k, r_k> / ||D r_k||^2
 // are computed and consumed on the device, so one V-cycle is a fixed sequence
 // of kernel launches that can be captured once into a HIP graph and replayed.
+// With fine_eo the fine-level smoothing passes run their MR steps on the
+// even-odd Schur complement A_e - kappa^2 H_eo A_o^-1 H_oe (Sec. 4's M_eooe
+// and M_ooee pieces) and reconstruct the odd sites afterwards.
 //
 // Setup (the paper does not describe one): starting from the caller's basis
 // vectors on each level, setup_iters sweeps of MR on the homogeneous system
