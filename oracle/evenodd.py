@@ -103,3 +103,53 @@ def schur_rhs(U, Apacked, kappa: float, b, dims, t_bc: float = -1.0) -> np.ndarr
     Ainv = clover_inverse(Apacked)
     b_o = to_cb(b, dims, 1)
     return to_cb(b, dims, 0) + kappa * hop_eo(U, clover_cb(Ainv, b_o, dims, 1), dims, 0, t_bc)
+
+
+# ---- coarse level (paper Sec. 6: the coarse-level M_eooe) ------------------------------
+# With all coarse extents even the 9-point stencil splits the same way,
+#     D_c = [[ S_e , H_eo ],
+#            [ H_oe, S_o  ]],
+# S the self blocks B_self of one parity and H the eight hop directions; the
+# Schur complement on the even sites is S_e - H_eo S_o^-1 H_oe, and D_c x = b
+# is equivalent to (S_e - H_eo S_o^-1 H_oe) x_e = b_e - H_eo S_o^-1 b_o,
+# x_o = S_o^-1 (b_o - H_oe x_e).
+
+
+def coarse_hop_eo(B, e_cb, dims, out_parity: int) -> np.ndarray:
+    """The eight hop directions of the coarse stencil B (Vc, 9, Nb, Nb) from parity
+    1 - p to parity p: place e on its sites, apply the stencil without its self
+    blocks, keep the parity-p sites."""
+    from .mg import coarse_apply
+
+    Bh = np.array(B, dtype=np.complex128, copy=True)
+    Bh[:, 0] = 0.0
+    V = int(np.prod(dims))
+    e_cb = np.asarray(e_cb, dtype=np.complex128)
+    full = np.zeros((V,) + e_cb.shape[1:], dtype=np.complex128)
+    full[cb_sites(dims, 1 - out_parity)] = e_cb
+    return coarse_apply(Bh, full, dims)[cb_sites(dims, out_parity)]
+
+
+def coarse_self_inverse(B) -> np.ndarray:
+    """Inverses (Vc, Nb, Nb) of the self blocks B[:, 0], by numpy's dense inverse."""
+    return np.linalg.inv(np.asarray(B, dtype=np.complex128)[:, 0])
+
+
+def coarse_self_cb(S, e_cb, dims, p: int) -> np.ndarray:
+    """Per-site blocks S (Vc, Nb, Nb) of the parity-p sites applied to e on parity p."""
+    return np.einsum("vij,vjn->vin", np.asarray(S)[cb_sites(dims, p)], np.asarray(e_cb, dtype=np.complex128))
+
+
+def coarse_schur_ee(B, e_e, dims) -> np.ndarray:
+    """(S_e - H_eo S_o^-1 H_oe) e_e on the even coarse sites."""
+    B = np.asarray(B, dtype=np.complex128)
+    Sinv = coarse_self_inverse(B)
+    g = coarse_self_cb(Sinv, coarse_hop_eo(B, e_e, dims, 1), dims, 1)
+    return coarse_self_cb(B[:, 0], e_e, dims, 0) - coarse_hop_eo(B, g, dims, 0)
+
+
+def coarse_schur_rhs(B, b, dims) -> np.ndarray:
+    """b_e - H_eo S_o^-1 b_o."""
+    B = np.asarray(B, dtype=np.complex128)
+    g = coarse_self_cb(coarse_self_inverse(B), to_cb(b, dims, 1), dims, 1)
+    return to_cb(b, dims, 0) - coarse_hop_eo(B, g, dims, 0)
