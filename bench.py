@@ -152,14 +152,26 @@ class Timer:
         return out
 
 
-def bench_evenodd(ctx, torch, stream, fine, V, warmup, steps):
-    """The checkerboarded pieces on the same 24^4 lattice, FP32, outside the step:
+def bench_evenodd(ctx, mg, torch, stream, fine, coarse, V, warmup, steps):
+    """The checkerboarded pieces, outside the step: on the 24^4 lattice in FP32,
     M_eooe (hop between the parities), M_ooee and its inverse on one parity, per
-    Nrhs, with the MRHS speedup N t(1) / t(N).  Bytes and flops per output site:
-    M_eooe 576 + 192 N bytes (all eight links of the site, in and out rows) and
-    1320 N flops; M_ooee 288 + 192 N bytes and 552 N flops."""
+    Nrhs, with the MRHS speedup N t(1) / t(N); on the 6^4 coarse level (Nb 32)
+    the coarse M_eooe (eight hop directions into one parity) in FP32 and BF16
+    and the inverse self blocks.  Bytes and flops per output site: M_eooe 576 +
+    192 N bytes (all eight links of the site, in and out rows) and 1320 N
+    flops; M_ooee 288 + 192 N bytes and 552 N flops; coarse M_eooe 8 Nb^2
+    block entries (8 or 4 bytes) + 16 Nb N bytes and 64 Nb^2 N flops; inverse
+    self blocks Nb^2 entries + 16 Nb N bytes and 8 Nb^2 N flops."""
     nh = V // 2
     ops = []
+    vch = mg.volume[1] // 2
+    for n in sorted(n for (lev, n) in coarse if lev == 1):
+        e, o = coarse[(1, n)][0][:vch], coarse[(1, n)][1][:vch]
+        for prec, bs in (("f32", 8), ("bf16", 4)):
+            ops.append(((f"coarse_meooe_{prec}", n), 64 * NB * NB * vch * n, vch * (8 * NB * NB * bs + 16 * NB * n),
+                        lambda e=e, o=o, p=prec: mg.coarse_hop_eo(1, o, e, 0, prec=p)))
+        ops.append((("coarse_sinv_bf16", n), 8 * NB * NB * vch * n, vch * (NB * NB * 4 + 16 * NB * n),
+                    lambda e=e, o=o: mg.coarse_self_eo(1, o, e, 1, inverse=True, prec="bf16")))
     for n in sorted(fine):
         x, y = fine[n][0][:nh], fine[n][1][:nh]
         ops.append((("meooe", n), 1320 * nh * n, nh * (576 + 192 * n), lambda x=x, y=y: ctx.hop_eo(y, x, 0)))
@@ -185,7 +197,7 @@ def bench_evenodd(ctx, torch, stream, fine, V, warmup, steps):
             "alg_gbs": round(nbytes / ms / 1e6, 1),
             "hbm_frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4),
         }
-    for kind in ("meooe", "mooee", "mooee_inv"):
+    for kind in ("meooe", "mooee", "mooee_inv"):  # the coarse ops start at Nrhs 12: no t(1)
         if (kind, 1) in times:
             t1 = float(np.median(times[(kind, 1)]))
             for n in sorted(fine):
@@ -432,7 +444,7 @@ def main():
     total_flops = sum(f for _, f, _, _ in ops)
     ms_per_step = wall * 1e3 / a.steps
 
-    evenodd = bench_evenodd(ctx, torch, stream, fine, V, a.warmup, a.steps)
+    evenodd = bench_evenodd(ctx, mg, torch, stream, fine, coarse, V, a.warmup, a.steps)
 
     value = total_flops / (ms_per_step * 1e-3) / 1e9
 

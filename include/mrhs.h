@@ -278,6 +278,25 @@ mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
  * per RHS by a power of two first, exactly undone on output). */
 mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 
+/* Even-odd pieces of the coarse stencil, Sec. 6 (the coarse-level M_eooe):
+ * on a level whose extents are all even, with the checkerboard layout of the
+ * fine even-odd calls ([V/2][Nb][nrhs], entry i the site of that parity among
+ * 2i, 2i + 1), and Nb = 32.  prec MRHS_F32 (FP32 matrix cores), MRHS_BF16 or
+ * MRHS_F16 (matrix cores, FP32 accumulation, FP16 with a per-RHS power-of-two
+ * scale as in mrhs_coarse_apply).  MRHS_ERR_SHAPE for odd extents,
+ * MRHS_ERR_STATE before the level's blocks exist. */
+/* mrhs_coarse_hop_eo_apply: out (parity out_parity) = the eight hop directions
+ * of D_c applied to in (parity 1 - out_parity); the self blocks do not enter. */
+mrhs_status mrhs_coarse_hop_eo_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs,
+                                     int32_t out_parity, mrhs_prec prec);
+/* mrhs_coarse_self_eo_apply: out = S_p in (inverse = 0) or S_p^-1 in
+ * (inverse = 1) on parity p, S the self blocks B_self.  The inverses are
+ * computed once per set of blocks in FP64 (Gauss-Jordan with partial
+ * pivoting, one workgroup per site) and rounded to the operand precision;
+ * the first inverse call synchronises, MRHS_ERR_STATE for a singular block. */
+mrhs_status mrhs_coarse_self_eo_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs,
+                                      int32_t parity, int32_t inverse, mrhs_prec prec);
+
 /* ---- multigrid-preconditioned solve (paper Sec. 8) -----------------------
  * The paper solves with FGMRES preconditioned by multigrid, on many RHS at
  * once; it does not describe its smoother, cycle or setup, so the ones below

@@ -397,6 +397,36 @@ class Multigrid:
                                           p))
         return out
 
+    def _half_pair(self, a, b, level):
+        for t in (a, b):
+            if t.dim() != 3 or t.shape[0] != self.volume[level] // 2 or t.shape[1] != self.ncomp[level]:
+                raise ValueError(f"field {tuple(t.shape)} is not (V/2={self.volume[level] // 2}, "
+                                 f"{self.ncomp[level]}, N) on level {level}")
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("fields must be contiguous device tensors")
+        if a.shape[2] != b.shape[2] or a.dtype != b.dtype:
+            raise ValueError("fields must share nrhs and dtype")
+        if _prec_of(a) != F32:
+            raise ValueError("the even-odd stencil calls take FP32 fields")
+        return int(a.shape[2])
+
+    def coarse_hop_eo(self, level: int, out, inp, out_parity: int, prec="f32"):
+        """Coarse M_eooe: the eight hop directions of D_c from parity 1 - out_parity to
+        out_parity; checkerboard fields (V/2, Nb, N) in FP32, arithmetic prec."""
+        n = self._half_pair(out, inp, level)
+        self._check(lib.mrhs_coarse_hop_eo_apply(self._h, level, C.c_void_p(out.data_ptr()),
+                                                 C.c_void_p(inp.data_ptr()), n, int(out_parity),
+                                                 _PREC_NAMES[prec]))
+        return out
+
+    def coarse_self_eo(self, level: int, out, inp, parity: int, inverse: bool = False, prec="f32"):
+        """Self blocks (or their inverses) of the parity-p coarse sites applied to inp."""
+        n = self._half_pair(out, inp, level)
+        self._check(lib.mrhs_coarse_self_eo_apply(self._h, level, C.c_void_p(out.data_ptr()),
+                                                  C.c_void_p(inp.data_ptr()), n, int(parity), int(bool(inverse)),
+                                                  _PREC_NAMES[prec]))
+        return out
+
     # -- solver ---------------------------------------------------------------------------
     @staticmethod
     def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16", fine_eo=False):

@@ -121,17 +121,36 @@ __device__ __forceinline__ bool reduce_waves(f32x16& accR, f32x16& accI) {
   return true;
 }
 
-template <bool F16>
+// Even-odd modes of the stencil kernels (all coarse extents even; a field on
+// one parity is [V/2][Nb][nrhs], entry i the site of that parity among 2i,
+// 2i + 1): EO = 1 applies the eight hop directions from parity 1 - p to p,
+// EO = 2 the self blocks (or the packed blocks bstride = 1 of their
+// inverses) on parity p.  EO = 0 is the full stencil.
+__device__ __forceinline__ int cb_site(const Geom& g, int i, int p) {
+  const int s2 = 2 * i;
+  int r = s2;
+  int sum = 0;
+  for (int m = 0; m < 4; ++m) {
+    sum += r % g.L[m];
+    r /= g.L[m];
+  }
+  return (sum & 1) == p ? s2 : s2 + 1;
+}
+
+template <bool F16, int EO>
 __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
                                                           const float2* __restrict__ in, float2* __restrict__ out,
-                                                          const float* __restrict__ scale, int nblocks) {
+                                                          const float* __restrict__ scale, int nblocks, int parity,
+                                                          int bstride) {
   using O = Op<F16>;
   using vec = typename O::vec;
   const int l = threadIdx.x & 63;
   const int ntiles = (nrhs + 31) >> 5;
   const long w = xcd_block(nblocks);
-  if (w >= (long)g.V * ntiles) return;  // whole workgroup
-  const int s = (int)(w / ntiles);
+  const int nsite = EO ? g.V / 2 : g.V;
+  if (w >= (long)nsite * ntiles) return;  // whole workgroup
+  const int io = (int)(w / ntiles);  // output row
+  const int s = EO ? cb_site(g, io, parity) : io;
   const int col = (int)(w % ntiles) * 32 + (l & 31);
   const bool colok = col < nrhs;
   const int colc = colok ? col : nrhs - 1;
@@ -149,7 +168,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
     x[3] = r / g.L[2];
   }
   f32x16 accR = {}, accI = {};
-  for (int d = threadIdx.x >> 6; d < 9; d += 4) {
+  const int d0 = EO == 1 ? 1 : 0, d1 = EO == 2 ? 1 : 9;
+  for (int d = d0 + (threadIdx.x >> 6); d < d1; d += 4) {
     int nbr = s;
     if (d > 0) {
       const int mu = (d - 1) >> 1;
@@ -157,10 +177,11 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
       const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
       nbr = s + (cw - x[mu]) * g.stride[mu];
     }
-    const uint4* bp = Bp + ((size_t)s * 9 + d) * 256;
+    const int ii = EO == 1 ? nbr / 2 : (EO == 2 ? io : nbr);  // input row
+    const uint4* bp = Bp + ((size_t)s * bstride + d) * 256;
     // every load of the direction first, from a clamped column (no branch
     // around the loads); columns past nrhs are zeroed and never stored
-    const float2* e = in + (size_t)nbr * kNb * nrhs + colc;
+    const float2* e = in + (size_t)ii * kNb * nrhs + colc;
     uint4 bl[4];
     float2 ev[2][8];
 #pragma unroll
@@ -193,7 +214,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
   }
   if (!reduce_waves(accR, accI) || !colok) return;
   const float inv = F16 ? 1.0f / sc : 1.0f;  // exact: sc is a power of two
-  float2* o = out + (size_t)s * kNb * nrhs + col;
+  float2* o = out + (size_t)io * kNb * nrhs + col;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
@@ -206,14 +227,18 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
 // so one instruction contracts two values of j.  Blocks are packed
 // [site][d][re|im][lane][16] with element q of lane l holding
 // B[i = l % 32][j = 2 q + l / 32]: four 16-byte loads per lane per part.
+template <int EO>
 __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, const float4* __restrict__ Bp,
                                                               const float2* __restrict__ in,
-                                                              float2* __restrict__ out, int nblocks) {
+                                                              float2* __restrict__ out, int nblocks, int parity,
+                                                              int bstride) {
   const int l = threadIdx.x & 63;
   const int ntiles = (nrhs + 31) >> 5;
   const long w = xcd_block(nblocks);
-  if (w >= (long)g.V * ntiles) return;  // whole workgroup
-  const int s = (int)(w / ntiles);
+  const int nsite = EO ? g.V / 2 : g.V;
+  if (w >= (long)nsite * ntiles) return;  // whole workgroup
+  const int io = (int)(w / ntiles);  // output row
+  const int s = EO ? cb_site(g, io, parity) : io;
   const int col = (int)(w % ntiles) * 32 + (l & 31);
   const bool colok = col < nrhs;
   const int colc = colok ? col : nrhs - 1;
@@ -229,7 +254,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
     x[3] = r / g.L[2];
   }
   f32x16 accR = {}, accI = {};
-  for (int d = threadIdx.x >> 6; d < 9; d += 4) {
+  const int d0 = EO == 1 ? 1 : 0, d1 = EO == 2 ? 1 : 9;
+  for (int d = d0 + (threadIdx.x >> 6); d < d1; d += 4) {
     int nbr = s;
     if (d > 0) {
       const int mu = (d - 1) >> 1;
@@ -237,7 +263,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
       const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
       nbr = s + (cw - x[mu]) * g.stride[mu];
     }
-    const float4* bp = Bp + ((size_t)s * 9 + d) * 2 * 64 * 4;
+    const int ii = EO == 1 ? nbr / 2 : (EO == 2 ? io : nbr);  // input row
+    const float4* bp = Bp + ((size_t)s * bstride + d) * 2 * 64 * 4;
     float br[16], bi[16];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -253,7 +280,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
     }
     // all vector loads first, from a clamped column (no branch around the
     // loads); columns past nrhs are zeroed and never stored
-    const float2* e = in + (size_t)nbr * kNb * nrhs + colc;
+    const float2* e = in + (size_t)ii * kNb * nrhs + colc;
     float2 ev[16];
 #pragma unroll
     for (int kc = 0; kc < 16; ++kc) ev[kc] = e[(size_t)(2 * kc + jh) * nrhs];
@@ -267,7 +294,7 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
     }
   }
   if (!reduce_waves(accR, accI) || !colok) return;
-  float2* o = out + (size_t)s * kNb * nrhs + col;
+  float2* o = out + (size_t)io * kNb * nrhs + col;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
@@ -385,13 +412,137 @@ hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const vo
   const int blocks = (int)((long)g.V * ((nrhs + 31) / 32));  // one workgroup per (site, 32-column tile)
   const int grid = ((blocks + 7) / 8) * 8;
   if (f16)
-    hipLaunchKernelGGL((coarse_mfma_kernel<true>), dim3(grid), dim3(256), 0, s, g, nrhs,
+    hipLaunchKernelGGL((coarse_mfma_kernel<true, 0>), dim3(grid), dim3(256), 0, s, g, nrhs,
                        static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
-                       scale, blocks);
+                       scale, blocks, 0, 9);
   else
-    hipLaunchKernelGGL((coarse_mfma_kernel<false>), dim3(grid), dim3(256), 0, s, g, nrhs,
+    hipLaunchKernelGGL((coarse_mfma_kernel<false, 0>), dim3(grid), dim3(256), 0, s, g, nrhs,
                        static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
-                       scale, blocks);
+                       scale, blocks, 0, 9);
+  return hipGetLastError();
+}
+
+// Even-odd modes (see cb_site): prec 0 FP32, 1 BF16, 2 FP16 (scale needed);
+// eo 1 hop to parity p, eo 2 per-site blocks (bstride 9: the self blocks of
+// the stencil pack, 1: a pack of single blocks per site).
+hipError_t launch_coarse_mfma_eo(int prec, int eo, int parity, const Geom& g, int nb, int nrhs, const void* packed,
+                                 int bstride, const void* in, void* out, const float* scale, hipStream_t s) {
+  if (nb != kNb || (eo != 1 && eo != 2) || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
+  for (int m = 0; m < 4; ++m)
+    if (g.L[m] % 2) return hipErrorInvalidValue;
+  const int blocks = (int)((long)(g.V / 2) * ((nrhs + 31) / 32));
+  const dim3 grid((unsigned)(((blocks + 7) / 8) * 8));
+  const auto* x = static_cast<const float2*>(in);
+  auto* y = static_cast<float2*>(out);
+  if (prec == 0) {
+    const auto* b = static_cast<const float4*>(packed);
+    if (eo == 1)
+      hipLaunchKernelGGL((coarse_mfma_f32_kernel<1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, blocks, parity,
+                         bstride);
+    else
+      hipLaunchKernelGGL((coarse_mfma_f32_kernel<2>), grid, dim3(256), 0, s, g, nrhs, b, x, y, blocks, parity,
+                         bstride);
+  } else {
+    const auto* b = static_cast<const uint4*>(packed);
+    if (prec == 2 && eo == 1)
+      hipLaunchKernelGGL((coarse_mfma_kernel<true, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride);
+    else if (prec == 2)
+      hipLaunchKernelGGL((coarse_mfma_kernel<true, 2>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride);
+    else if (eo == 1)
+      hipLaunchKernelGGL((coarse_mfma_kernel<false, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride);
+    else
+      hipLaunchKernelGGL((coarse_mfma_kernel<false, 2>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride);
+  }
+  return hipGetLastError();
+}
+
+// Inverse of every Nb x Nb self block (FP64 Gauss-Jordan with partial
+// pivoting, one workgroup per site, [M | 1] in LDS).  B64 is the stencil
+// master [site][9][Nb][Nb]; out [site][Nb][Nb]; a vanishing pivot sets *flag.
+__global__ __launch_bounds__(256) void self_invert_kernel(const double2* __restrict__ B64,
+                                                          double2* __restrict__ out, int* __restrict__ flag) {
+  __shared__ double2 M[kNb][2 * kNb];
+  __shared__ int piv;
+  const int site = blockIdx.x;
+  const double2* b = B64 + (size_t)site * 9 * kNb * kNb;  // direction 0
+  for (int e = threadIdx.x; e < kNb * 2 * kNb; e += 256) {
+    const int r = e / (2 * kNb), c = e % (2 * kNb);
+    M[r][c] = c < kNb ? b[r * kNb + c] : make_double2(c - kNb == r ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < kNb; ++k) {
+    if (threadIdx.x == 0) {
+      int p = k;
+      double best = -1.0;
+      for (int r = k; r < kNb; ++r) {
+        const double m = M[r][k].x * M[r][k].x + M[r][k].y * M[r][k].y;
+        if (m > best) {
+          best = m;
+          p = r;
+        }
+      }
+      piv = best > 0.0 ? p : -1;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p < 0) {
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+      return;  // uniform across the workgroup
+    }
+    if (p != k && threadIdx.x < 2 * kNb) {
+      const double2 t = M[k][threadIdx.x];
+      M[k][threadIdx.x] = M[p][threadIdx.x];
+      M[p][threadIdx.x] = t;
+    }
+    __syncthreads();
+    const double2 a = M[k][k];
+    const double n2 = a.x * a.x + a.y * a.y;
+    const double2 ia = make_double2(a.x / n2, -a.y / n2);
+    __syncthreads();
+    if (threadIdx.x < 2 * kNb) {
+      const double2 v = M[k][threadIdx.x];
+      M[k][threadIdx.x] = make_double2(v.x * ia.x - v.y * ia.y, v.x * ia.y + v.y * ia.x);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNb * 2 * kNb; e += 256) {
+      const int r = e / (2 * kNb), c = e % (2 * kNb);
+      if (r == k) continue;
+      const double2 f = M[r][k], v = M[k][c];
+      // M[r][k] itself is read by every column of row r: update it last
+      if (c == k) continue;
+      M[r][c] = make_double2(M[r][c].x - (f.x * v.x - f.y * v.y), M[r][c].y - (f.x * v.y + f.y * v.x));
+    }
+    __syncthreads();
+    if (threadIdx.x < kNb && threadIdx.x != k) M[threadIdx.x][k] = make_double2(0.0, 0.0);
+    __syncthreads();
+  }
+  double2* o = out + (size_t)site * kNb * kNb;
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) o[e] = M[e / kNb][kNb + e % kNb];
+}
+
+hipError_t launch_self_invert(long nsite, const void* B64, void* out, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(self_invert_kernel, dim3((unsigned)nsite), dim3(256), 0, s, static_cast<const double2*>(B64),
+                     static_cast<double2*>(out), flag);
+  return hipGetLastError();
+}
+
+// Packs nblk FP64 Nb x Nb blocks into the BF16 / FP16 (f16) or FP32 operand orders.
+hipError_t launch_pack_block_list(int kind, const void* B64, void* packed, long nblk, hipStream_t s) {
+  const long n = nblk * kNb * kNb;
+  const int blocks = (int)((n + 255) / 256);
+  if (kind == 0)
+    hipLaunchKernelGGL(pack_f32_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(B64),
+                       static_cast<float*>(packed), nblk);
+  else if (kind == 2)
+    hipLaunchKernelGGL((pack_kernel<true>), dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(B64),
+                       static_cast<unsigned short*>(packed), nblk);
+  else
+    hipLaunchKernelGGL((pack_kernel<false>), dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(B64),
+                       static_cast<unsigned short*>(packed), nblk);
   return hipGetLastError();
 }
 
@@ -400,8 +551,9 @@ hipError_t launch_coarse_mfma_f32(const Geom& g, int nb, int nrhs, const void* p
   if (nb != kNb) return hipErrorInvalidValue;
   const int blocks = (int)((long)g.V * ((nrhs + 31) / 32));  // one workgroup per (site, 32-column tile)
   const int grid = ((blocks + 7) / 8) * 8;
-  hipLaunchKernelGGL(coarse_mfma_f32_kernel, dim3(grid), dim3(256), 0, s, g, nrhs, static_cast<const float4*>(packed),
-                     static_cast<const float2*>(in), static_cast<float2*>(out), blocks);
+  hipLaunchKernelGGL((coarse_mfma_f32_kernel<0>), dim3(grid), dim3(256), 0, s, g, nrhs,
+                     static_cast<const float4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
+                     blocks, 0, 9);
   return hipGetLastError();
 }
 

@@ -83,6 +83,32 @@ mrhs_status refresh_blocks(mrhs_mg mg, int level) {
   st = pack_blocks_mfma(mg, level);
   if (st != MRHS_OK) return st;
   L.have_blocks = true;
+  L.have_sinv = false;
+  return MRHS_OK;
+}
+
+// Inverted self blocks of a level and their three MFMA packs (synchronises).
+mrhs_status ensure_self_inverse(mrhs_mg mg, int level) {
+  mrhs_ctx ctx = mg->ctx;
+  LevelData& L = mg->lv[level];
+  if (L.have_sinv) return MRHS_OK;
+  const long V = L.g.V;
+  const size_t blk = (size_t)L.ncomp * L.ncomp;
+  mrhs_status st = ensure(ctx, L.Sinv64, V * blk * 16);
+  if (st == MRHS_OK) st = ensure(ctx, L.SinvF32p, V * blk * 8);
+  if (st == MRHS_OK) st = ensure(ctx, L.SinvBf16, V * blk * 4);
+  if (st == MRHS_OK) st = ensure(ctx, L.SinvF16, V * blk * 4);
+  if (st != MRHS_OK) return st;
+  MRHS_HIP(ctx, hipMemsetAsync(mg->flag, 0, sizeof(int), ctx->stream));
+  MRHS_HIP(ctx, launch_self_invert(V, L.B64.p, L.Sinv64.p, mg->flag, ctx->stream));
+  int h = 0;
+  MRHS_HIP(ctx, hipMemcpyAsync(&h, mg->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h) return fail(ctx, MRHS_ERR_STATE, "a self block of level %d is singular", level);
+  MRHS_HIP(ctx, launch_pack_block_list(0, L.Sinv64.p, L.SinvF32p.p, V, ctx->stream));
+  MRHS_HIP(ctx, launch_pack_block_list(1, L.Sinv64.p, L.SinvBf16.p, V, ctx->stream));
+  MRHS_HIP(ctx, launch_pack_block_list(2, L.Sinv64.p, L.SinvF16.p, V, ctx->stream));
+  L.have_sinv = true;
   return MRHS_OK;
 }
 
@@ -185,7 +211,8 @@ void mrhs_mg_destroy(mrhs_mg mg) {
   DevGuard dg(mg->ctx->device);
   (void)hipStreamSynchronize(mg->ctx->stream);
   for (auto& L : mg->lv) {
-    Buffer* bufs[] = {&L.basis64, &L.basis32, &L.Wbf16, &L.B64, &L.BT32, &L.BT64, &L.Bbf16, &L.Bf16, &L.Bf32p};
+    Buffer* bufs[] = {&L.basis64, &L.basis32, &L.Wbf16, &L.B64,      &L.BT32,     &L.BT64,   &L.Bbf16,
+                      &L.Bf16,    &L.Bf32p,   &L.Sinv64, &L.SinvF32p, &L.SinvBf16, &L.SinvF16};
     for (Buffer* b : bufs) release(*b);
   }
   release(mg->tmpA);
@@ -494,6 +521,67 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "coarse stencil launch");
   return MRHS_OK;
+}
+
+// Shared checks and launch of the two even-odd coarse calls.
+static mrhs_status coarse_eo(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs, int32_t parity,
+                             int eo, int inverse, mrhs_prec prec) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_ctx ctx = mg->ctx;
+  mrhs_status st = check_level(mg, level, 1, MRHS_MAX_LEVELS - 1);
+  if (st != MRHS_OK) return st;
+  st = check_fields(ctx, out, in, nrhs);
+  if (st != MRHS_OK) return st;
+  if (parity != 0 && parity != 1) return fail(ctx, MRHS_ERR_INVALID_ARG, "parity must be 0 or 1");
+  LevelData& L = mg->lv[level];
+  if (!L.have_blocks) return fail(ctx, MRHS_ERR_STATE, "blocks of level %d not set", level);
+  if (!mfma_supported(L.ncomp))
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "even-odd stencil calls need Nb = 32, got %d", L.ncomp);
+  for (int m = 0; m < 4; ++m)
+    if (L.g.L[m] % 2)
+      return fail(ctx, MRHS_ERR_SHAPE, "even-odd calls need even extents (level %d: L[%d] = %d)", level, m,
+                  L.g.L[m]);
+  if (prec != MRHS_F32 && prec != MRHS_BF16 && prec != MRHS_F16)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "precision must be f32, bf16 or f16");
+  const size_t bytes = (size_t)(L.g.V / 2) * L.ncomp * nrhs * 8;
+  const char* a = static_cast<const char*>(in);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return fail(ctx, MRHS_ERR_INVALID_ARG, "in and out overlap");
+  DevGuard dg(ctx->device);
+  if (inverse) {
+    st = ensure_self_inverse(mg, level);
+    if (st != MRHS_OK) return st;
+  }
+  const int pk = prec == MRHS_F32 ? 0 : (prec == MRHS_BF16 ? 1 : 2);
+  const void* pack;
+  int bstride = 9;
+  if (inverse) {
+    pack = pk == 0 ? L.SinvF32p.p : (pk == 1 ? L.SinvBf16.p : L.SinvF16.p);
+    bstride = 1;
+  } else {
+    pack = pk == 0 ? L.Bf32p.p : (pk == 1 ? L.Bbf16.p : L.Bf16.p);
+  }
+  const float* scale = nullptr;
+  if (pk == 2) {
+    st = ensure_colscale(mg);
+    if (st != MRHS_OK) return st;
+    float* sc = static_cast<float*>(mg->colscale.p);
+    MRHS_HIP(ctx, launch_column_scale(in, (long)(L.g.V / 2) * L.ncomp, nrhs, sc + MRHS_MAX_NRHS, sc, ctx->stream));
+    scale = sc;
+  }
+  MRHS_HIP(ctx, launch_coarse_mfma_eo(pk, eo, parity, L.g, L.ncomp, nrhs, pack, bstride, in, out, scale,
+                                      ctx->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_coarse_hop_eo_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs,
+                                     int32_t out_parity, mrhs_prec prec) {
+  return coarse_eo(mg, level, out, in, nrhs, out_parity, 1, 0, prec);
+}
+
+mrhs_status mrhs_coarse_self_eo_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs,
+                                      int32_t parity, int32_t inverse, mrhs_prec prec) {
+  return coarse_eo(mg, level, out, in, nrhs, parity, 2, inverse ? 1 : 0, prec);
 }
 
 }  // extern "C"

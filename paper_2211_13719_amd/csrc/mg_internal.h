@@ -23,6 +23,10 @@ struct LevelData {
   // copies [site][9][j][i] for the vector-ALU kernels, MFMA packs
   Buffer B64, BT32, BT64, Bbf16, Bf16, Bf32p;
   bool have_blocks = false;
+  // inverses of the self blocks (FP64 [site][Nb][Nb]) and their MFMA packs,
+  // built on first use by the even-odd calls, dropped when the blocks change
+  Buffer Sinv64, SinvBf16, SinvF16, SinvF32p;
+  bool have_sinv = false;
 };
 
 struct SolverState;
@@ -71,6 +75,15 @@ hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const vo
 // FP32 operands on the FP32 matrix cores (Nb = 32)
 hipError_t launch_coarse_mfma_f32(const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
                                   hipStream_t s);
+
+// even-odd modes of the stencil (coarse_mfma.hip): prec 0 FP32, 1 BF16, 2 FP16;
+// eo 1 the eight hop directions into parity p, eo 2 per-site blocks on parity p
+// (bstride 9: the stencil pack's self blocks, 1: a pack of one block per site)
+hipError_t launch_coarse_mfma_eo(int prec, int eo, int parity, const Geom& g, int nb, int nrhs, const void* packed,
+                                 int bstride, const void* in, void* out, const float* scale, hipStream_t s);
+hipError_t launch_self_invert(long nsite, const void* B64, void* out, int* flag, hipStream_t s);
+// kind 0 FP32 pack, 1 BF16, 2 FP16, of nblk FP64 Nb x Nb blocks
+hipError_t launch_pack_block_list(int kind, const void* B64, void* packed, long nblk, hipStream_t s);
 
 // solver (mg_solve.hip)
 void mg_solver_release(mrhs_mg mg);

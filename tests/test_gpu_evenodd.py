@@ -139,3 +139,85 @@ def test_singular_clover_rejected(gpu_lib):
     ctx.clover_eo(b, a, 0)  # the blocks themselves are fine
     with pytest.raises(gpu_lib.MrhsError, match="STATE"):
         ctx.clover_eo(b, a, 1, inverse=True)
+
+
+# ---- coarse level ---------------------------------------------------------------------
+
+def _coarse(gpu_lib, cdims, seed, shift=4.0):
+    """A hierarchy whose level 1 is cdims with Nb = 32 and Gaussian blocks (+shift I
+    on the self blocks; 12 keeps every self block's condition number near 10 or below,
+    so the rounding of its inverse to FP32 / BF16 stays within the usual tolerances)."""
+    ctx = gpu_lib.Context(tuple(2 * c for c in cdims), t_bc=-1)
+    ctx.set_gauge(synth.gauge_unit(tuple(2 * c for c in cdims)))
+    ctx.build_clover(CSW, KAPPA)
+    mg = gpu_lib.Multigrid(ctx, [(2, 2, 2, 2)], [16])
+    B = synth.gaussian_blocks(synth.volume(cdims), 32, seed, shift=shift)
+    mg.set_blocks(1, B)
+    return ctx, mg, B
+
+
+@pytest.mark.parametrize("cdims", [(4, 6, 2, 4), (6, 6, 6, 6)])
+@pytest.mark.parametrize("nrhs", [1, 12, 33])
+@pytest.mark.parametrize("p", [0, 1])
+def test_coarse_hop_eo(gpu_lib, cdims, nrhs, p):
+    import torch
+
+    ctx, mg, B = _coarse(gpu_lib, cdims, 5000 + nrhs)
+    Vh = synth.volume(cdims) // 2
+    e = EO.to_cb(synth.coarse_source(synth.volume(cdims), 32, nrhs, 5100, np.complex64), cdims, 1 - p)
+    want = EO.coarse_hop_eo(B, e, cdims, p)
+    for prec, tol in (("f32", 1e-6), ("bf16", 2e-2), ("f16", 2e-2)):
+        out = torch.empty((Vh, 32, nrhs), dtype=torch.complex64, device="cuda")
+        mg.coarse_hop_eo(1, out, dev(e), p, prec=prec)
+        Bp = B.astype(np.complex64) if prec == "f32" else B
+        w = EO.coarse_hop_eo(Bp, e, cdims, p) if prec == "f32" else want
+        assert rel(out.cpu().numpy(), w) < tol, prec
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+@pytest.mark.parametrize("p", [0, 1])
+def test_coarse_self_eo(gpu_lib, inverse, p):
+    import torch
+
+    cdims, nrhs = (4, 6, 2, 4), 24
+    ctx, mg, B = _coarse(gpu_lib, cdims, 5200, shift=12.0)
+    Vh = synth.volume(cdims) // 2
+    e = EO.to_cb(synth.coarse_source(synth.volume(cdims), 32, nrhs, 5300, np.complex64), cdims, p)
+    S = EO.coarse_self_inverse(B) if inverse else B[:, 0]
+    want = EO.coarse_self_cb(S, e, cdims, p)
+    for prec, tol in (("f32", 1e-6), ("bf16", 2e-2), ("f16", 2e-2)):
+        out = torch.empty((Vh, 32, nrhs), dtype=torch.complex64, device="cuda")
+        mg.coarse_self_eo(1, out, dev(e), p, inverse=inverse, prec=prec)
+        assert rel(out.cpu().numpy(), want) < tol, prec
+
+
+def test_coarse_schur_composed(gpu_lib):
+    """S_e x - H_eo S_o^-1 H_oe x from the three GPU calls (FP32) against the oracle."""
+    import torch
+
+    cdims, nrhs = (6, 6, 6, 6), 12
+    ctx, mg, B = _coarse(gpu_lib, cdims, 5400, shift=12.0)
+    Vh = synth.volume(cdims) // 2
+    x = EO.to_cb(synth.coarse_source(synth.volume(cdims), 32, nrhs, 5500, np.complex64), cdims, 0)
+    t1 = torch.empty((Vh, 32, nrhs), dtype=torch.complex64, device="cuda")
+    t2 = torch.empty_like(t1)
+    t3 = torch.empty_like(t1)
+    t4 = torch.empty_like(t1)
+    xd = dev(x)
+    mg.coarse_hop_eo(1, t1, xd, 1)
+    mg.coarse_self_eo(1, t2, t1, 1, inverse=True)
+    mg.coarse_hop_eo(1, t3, t2, 0)
+    mg.coarse_self_eo(1, t4, xd, 0)
+    got = (t4 - t3).cpu().numpy()
+    assert rel(got, EO.coarse_schur_ee(B, x, cdims)) < 1e-5
+
+
+def test_coarse_eo_odd_extent_rejected(gpu_lib):
+    import torch
+
+    cdims = (3, 3, 3, 3)
+    ctx, mg, B = _coarse(gpu_lib, cdims, 5600)
+    a = torch.zeros((40, 32, 2), dtype=torch.complex64, device="cuda")
+    b = torch.zeros_like(a)
+    with pytest.raises((gpu_lib.MrhsError, ValueError)):
+        mg.coarse_hop_eo(1, b, a, 0)
