@@ -74,7 +74,7 @@ FINE_TRAFFIC = {
     "sources": "e11d200eeecd4d6b",
     "configs": {"6": [2, [12, 4, 4, 3], 32], "12": [2, [8, 8, 2, 3], 65], "24": [2, [8, 8, 2, 3], 68],
                 "48": [2, [8, 4, 4, 3], 68], "64": [2, [8, 4, 4, 3], 5]},
-    "bytes_per_launch": 5.501e9,
+    "bytes_per_launch": 5.498e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
