@@ -157,8 +157,8 @@ mrhs_status mrhs_clover_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_
  * sites, the Schur complement of D = A - kappa H with respect to the odd
  * sites (D x = b is equivalent to applying it to x_e with right-hand side
  * b_e + kappa H_eo A_o^-1 b_o).  in and out are even-parity fields; the
- * odd-parity intermediates live in a context-owned workspace of two odd
- * fields, grown on demand. */
+ * odd-parity intermediate A_o^-1 H_oe in lives in a context-owned workspace
+ * field, grown on demand. */
 mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 
 /* ---- batched level-1 operations (paper Sec. 7) ---------------------------

@@ -506,10 +506,9 @@ mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nr
   if (st == MRHS_OK) st = ensure_clover_inverse(ctx);
   const int p64 = prec == MRHS_F64;
   const size_t half = (size_t)(ctx->g.V / 2) * 12 * nrhs * (p64 ? 16 : 8);
-  if (st == MRHS_OK) st = ensure(ctx, ctx->eo_work, 2 * half);
+  if (st == MRHS_OK) st = ensure(ctx, ctx->eo_work, half);
   if (st != MRHS_OK) return st;
-  void* t1 = ctx->eo_work.p;
-  void* t2 = static_cast<char*>(ctx->eo_work.p) + half;
+  void* t2 = ctx->eo_work.p;
   const int nh = ctx->g.V / 2;
   const auto* te = static_cast<const int4*>(ctx->eo_tab[0].p);
   const auto* to = static_cast<const int4*>(ctx->eo_tab[1].p);
@@ -517,7 +516,6 @@ mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nr
   // t2 = A_o^-1 (H_oe in), out = A_e in - kappa^2 (H_eo t2): two fused launches
   const auto* oe = static_cast<const int*>(ctx->eo_order[0].p);
   const auto* oo = static_cast<const int*>(ctx->eo_order[1].p);
-  (void)t1;
   MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, oo, U, in, t2, nrhs, ctx->stream, 1, p64 ? ctx->Ainv64.p : ctx->Ainv32.p));
   MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, oe, U, t2, out, nrhs, ctx->stream, 2, p64 ? ctx->A64.p : ctx->A32.p, in,
                               -ctx->kappa * ctx->kappa));

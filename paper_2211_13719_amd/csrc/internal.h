@@ -107,8 +107,8 @@ struct mrhs_ctx_s {
   mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
 
   // checkerboard tables (per parity, four int4 per site, and the traversal
-  // order of its sites) and the inverse clover blocks, built on first use; a
-  // workspace for the Schur operator
+  // order of its sites) and the inverse clover blocks, built on first use; an
+  // odd-parity workspace field for the Schur operator
   mrhs::Buffer eo_tab[2], eo_order[2];
   mrhs::Buffer Ainv64, Ainv32;
   bool have_clover_inv = false;
