@@ -280,8 +280,9 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
 
 /* Even-odd pieces of the coarse stencil, Sec. 6 (the coarse-level M_eooe):
  * on a level whose extents are all even, with the checkerboard layout of the
- * fine even-odd calls ([V/2][Nb][nrhs], entry i the site of that parity among
- * 2i, 2i + 1), and Nb = 32.  prec MRHS_F32 (FP32 matrix cores), MRHS_BF16 or
+ * fine even-odd calls (FP32 complex device fields [V/2][Nb][nrhs], entry i the
+ * site of that parity among 2i, 2i + 1), and Nb = 32.  prec selects the
+ * arithmetic: MRHS_F32 (FP32 matrix cores), MRHS_BF16 or
  * MRHS_F16 (matrix cores, FP32 accumulation, FP16 with a per-RHS power-of-two
  * scale as in mrhs_coarse_apply).  MRHS_ERR_SHAPE for odd extents,
  * MRHS_ERR_STATE before the level's blocks exist. */
