@@ -651,11 +651,15 @@ hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U
 // Sites are visited in the order of a traversal table (the parity-p sites of
 // the full kernel's tiled order), each XCD taking one contiguous range of it,
 // so that neighbour rows are re-read from its own L2 as in fine_kernel.
-// EPI selects what is stored: 0 the hop itself; 1 Ablk (H in), Ablk the
-// clover blocks (or their inverses) of the output sites; 2 Ablk in2 + coef
-// (H in), in2 a field on the output parity.  1 and 2 fuse the Schur
-// complement's clover factors into the hops.
-template <typename T, int R, int EPI>
+// EPI selects what is stored, with h = H in, Ablk the clover blocks (or their
+// inverses) of the output sites and in2 a field on the output parity:
+//   0: h;  1: Ablk h;  2: Ablk in2 + coef h;  3: in2 + coef h;
+//   4: Ablk (in2 + coef h).
+// 1 and 2 fuse the Schur complement's clover factors into the hops, 3 and 4
+// the even-odd smoother's right-hand side and odd-site reconstruction.  FULL2
+// reads in2 from a full-lattice field (row = lattice site) instead of a
+// checkerboard one; ADDF adds the result into a full-lattice out.
+template <typename T, int R, int EPI, bool FULL2, bool ADDF>
 __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
                                                      const int* __restrict__ order, int nblocks,
                                                      const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
@@ -682,12 +686,39 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
   hop_dir<T, R, 1, true>(s0.x, n0.z, n0.w, nrhs, k0, U, in, acc, true, true, s0.z);
   hop_dir<T, R, 2, true>(s0.x, n1.x, n1.y, nrhs, k0, U, in, acc, true, true, s0.w);
   hop_dir<T, R, 3, true>(s0.x, n1.z, n1.w, nrhs, k0, U, in, acc, true, true, s1.x);
-  cplx<T>* o = out + (size_t)i * 12 * nrhs + k0;
-  if constexpr (EPI == 0) {
+  cplx<T>* o = out + (size_t)(ADDF ? s0.x : i) * 12 * nrhs + k0;
+  const cplx<T>* q = in2 + (size_t)(FULL2 ? s0.x : i) * 12 * nrhs + k0;
+  // y = the stored value of component r of chirality chi
+  auto put = [&](cplx<T>* dst, const cplx<T> (&y)[R]) {
+    if constexpr (ADDF) {
+      cplx<T> a[R], sum[R];
+      load_r<T, R>(dst, a);
+#pragma unroll
+      for (int j = 0; j < R; ++j) sum[j] = add<T>(a[j], y[j]);
+      store_r<T, R>(dst, sum);
+    } else {
+      store_r<T, R>(dst, y);
+    }
+  };
+  if constexpr (EPI == 0 || EPI == 3) {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) store_r<T, R>(o + (3 * sp + c) * nrhs, acc[sp][c]);
+      for (int c = 0; c < 3; ++c) {
+        cplx<T> y[R];
+        if constexpr (EPI == 3) {
+          load_r<T, R>(q + (3 * sp + c) * nrhs, y);
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            y[j].x = fma(coef, acc[sp][c][j].x, y[j].x);
+            y[j].y = fma(coef, acc[sp][c][j].y, y[j].y);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < R; ++j) y[j] = acc[sp][c][j];
+        }
+        put(o + (3 * sp + c) * nrhs, y);
+      }
   } else {
 #pragma unroll
     for (int chi = 0; chi < 2; ++chi) {
@@ -698,9 +729,17 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
 #pragma unroll
           for (int j = 0; j < R; ++j) xin[r][j] = acc[2 * chi + r / 3][r % 3][j];
       } else {
-        const cplx<T>* q = in2 + (size_t)i * 12 * nrhs + k0;
 #pragma unroll
         for (int r = 0; r < 6; ++r) load_r<T, R>(q + (6 * chi + r) * nrhs, xin[r]);
+        if constexpr (EPI == 4) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+              xin[r][j].x = fma(coef, acc[2 * chi + r / 3][r % 3][j].x, xin[r][j].x);
+              xin[r][j].y = fma(coef, acc[2 * chi + r / 3][r % 3][j].y, xin[r][j].y);
+            }
+        }
       }
       clover_block<T, R>(Ablk + ((size_t)s0.x * 2 + chi) * 36, xin, yout);
 #pragma unroll
@@ -712,7 +751,7 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
             yout[r][j].y = fma(coef, acc[2 * chi + r / 3][r % 3][j].y, yout[r][j].y);
           }
         }
-        store_r<T, R>(o + (6 * chi + r) * nrhs, yout[r]);
+        put(o + (6 * chi + r) * nrhs, yout[r]);
       }
     }
   }
@@ -720,7 +759,8 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
 
 // M_ooee (or its inverse, given the inverse blocks): out = A in + coef add on
 // one parity (add may be null).
-template <typename T, int R>
+// FULLIN: in is a full-lattice field (row = lattice site).
+template <typename T, int R, bool FULLIN>
 __global__ __launch_bounds__(256) void clover_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
                                                         const T* __restrict__ A, const cplx<T>* __restrict__ in,
                                                         const cplx<T>* __restrict__ add, T coef,
@@ -732,11 +772,12 @@ __global__ __launch_bounds__(256) void clover_eo_kernel(int nhalf, int nrhs, con
   const int k0 = (int)(gid - (long)i * groups) * R;
   const int site = tab[4 * i + 2].x;
   const size_t base = (size_t)i * 12 * nrhs + k0;
+  const size_t ibase = (size_t)(FULLIN ? site : i) * 12 * nrhs + k0;
 #pragma unroll
   for (int chi = 0; chi < 2; ++chi) {
     cplx<T> xin[6][R], yout[6][R];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) load_r<T, R>(in + base + (6 * chi + r) * nrhs, xin[r]);
+    for (int r = 0; r < 6; ++r) load_r<T, R>(in + ibase + (6 * chi + r) * nrhs, xin[r]);
     clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
     if (add) {
 #pragma unroll
@@ -858,36 +899,56 @@ __global__ __launch_bounds__(256) void eo_rows_kernel(int nhalf, int nrhs, const
   }
 }
 
-template <typename T, int R>
-hipError_t launch_hop_eo_r(int epi, int nhalf, int nrhs, const int4* tab, const int* order, const void* U,
-                           const void* in, void* out, const void* Ablk, const void* in2, double coef, hipStream_t s) {
+template <typename T, int R, int EPI, bool FULL2, bool ADDF>
+hipError_t launch_hop_eo_k(int nhalf, int nrhs, const int4* tab, const int* order, const void* U, const void* in,
+                           void* out, const void* Ablk, const void* in2, double coef, hipStream_t s) {
   const long threads = (long)nhalf * (nrhs / R);
   const int nblocks = (int)((threads + 255) / 256);
   const dim3 grid((unsigned)(((nblocks + 7) / 8) * 8));
-  const auto* u = static_cast<const cplx<T>*>(U);
-  const auto* x = static_cast<const cplx<T>*>(in);
-  auto* y = static_cast<cplx<T>*>(out);
-  const auto* a = static_cast<const T*>(Ablk);
-  const auto* x2 = static_cast<const cplx<T>*>(in2);
-  if (epi == 1)
-    hipLaunchKernelGGL((hop_eo_kernel<T, R, 1>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks, u, x, y, a,
-                       x2, (T)coef);
-  else if (epi == 2)
-    hipLaunchKernelGGL((hop_eo_kernel<T, R, 2>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks, u, x, y, a,
-                       x2, (T)coef);
-  else
-    hipLaunchKernelGGL((hop_eo_kernel<T, R, 0>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks, u, x, y, a,
-                       x2, (T)coef);
+  hipLaunchKernelGGL((hop_eo_kernel<T, R, EPI, FULL2, ADDF>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order, nblocks,
+                     static_cast<const cplx<T>*>(U), static_cast<const cplx<T>*>(in), static_cast<cplx<T>*>(out),
+                     static_cast<const T*>(Ablk), static_cast<const cplx<T>*>(in2), (T)coef);
   return hipGetLastError();
+}
+
+// epi 0..2 on checkerboard fields (FP32 and FP64); the smoother's forms 3
+// (in2 full-lattice) and 4 (in2 full-lattice, added into a full-lattice out)
+// in FP32 only.
+template <typename T, int R>
+hipError_t launch_hop_eo_r(int epi, int nhalf, int nrhs, const int4* tab, const int* order, const void* U,
+                           const void* in, void* out, const void* Ablk, const void* in2, double coef, hipStream_t s) {
+  switch (epi) {
+    case 0:
+      return launch_hop_eo_k<T, R, 0, false, false>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+    case 1:
+      return launch_hop_eo_k<T, R, 1, false, false>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+    case 2:
+      return launch_hop_eo_k<T, R, 2, false, false>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+    default:
+      break;
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (epi == 3)
+      return launch_hop_eo_k<T, R, 3, true, false>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+    if (epi == 4)
+      return launch_hop_eo_k<T, R, 4, true, true>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int R>
 hipError_t launch_clover_eo_r(int nhalf, int nrhs, const int4* tab, const void* A, const void* in, const void* add,
-                              double coef, void* out, hipStream_t s) {
+                              double coef, void* out, bool full_in, hipStream_t s) {
   const long threads = (long)nhalf * (nrhs / R);
-  hipLaunchKernelGGL((clover_eo_kernel<T, R>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nhalf,
-                     nrhs, tab, static_cast<const T*>(A), static_cast<const cplx<T>*>(in),
-                     static_cast<const cplx<T>*>(add), (T)coef, static_cast<cplx<T>*>(out));
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (full_in)
+    hipLaunchKernelGGL((clover_eo_kernel<T, R, true>), grid, dim3(256), 0, s, nhalf, nrhs, tab,
+                       static_cast<const T*>(A), static_cast<const cplx<T>*>(in), static_cast<const cplx<T>*>(add),
+                       (T)coef, static_cast<cplx<T>*>(out));
+  else
+    hipLaunchKernelGGL((clover_eo_kernel<T, R, false>), grid, dim3(256), 0, s, nhalf, nrhs, tab,
+                       static_cast<const T*>(A), static_cast<const cplx<T>*>(in), static_cast<const cplx<T>*>(add),
+                       (T)coef, static_cast<cplx<T>*>(out));
   return hipGetLastError();
 }
 
@@ -918,17 +979,18 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
 hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
                          void* out, int nrhs, hipStream_t s, int epi, const void* Ablk, const void* in2,
                          double coef) {
-  if (!tab || !order || (epi && !Ablk) || (epi == 2 && !in2)) return hipErrorInvalidValue;
+  const bool need_a = epi == 1 || epi == 2 || epi == 4, need_in2 = epi >= 2;
+  if (!tab || !order || epi < 0 || epi > 4 || (need_a && !Ablk) || (need_in2 && !in2)) return hipErrorInvalidValue;
   if (prec64) return launch_hop_eo_r<double, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
   if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
   return launch_hop_eo_r<float, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
 }
 
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
-                            double coef, void* out, int nrhs, hipStream_t s) {
-  if (prec64) return launch_clover_eo_r<double, 1>(nhalf, nrhs, tab, A, in, add, coef, out, s);
-  if (nrhs % 2 == 0) return launch_clover_eo_r<float, 2>(nhalf, nrhs, tab, A, in, add, coef, out, s);
-  return launch_clover_eo_r<float, 1>(nhalf, nrhs, tab, A, in, add, coef, out, s);
+                            double coef, void* out, int nrhs, hipStream_t s, bool full_in) {
+  if (prec64) return launch_clover_eo_r<double, 1>(nhalf, nrhs, tab, A, in, add, coef, out, full_in, s);
+  if (nrhs % 2 == 0) return launch_clover_eo_r<float, 2>(nhalf, nrhs, tab, A, in, add, coef, out, full_in, s);
+  return launch_clover_eo_r<float, 1>(nhalf, nrhs, tab, A, in, add, coef, out, full_in, s);
 }
 
 hipError_t launch_eo_gather(int nhalf, const int4* tab, const void* full, void* half, int nrhs, hipStream_t s) {

@@ -159,12 +159,15 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
 // checkerboarded fine pieces (fine.hip): nhalf = V / 2 sites per parity,
 // tab = that parity's table (four int4 per site)
 // epi 0: out = H in; 1: out = Ablk (H in); 2: out = Ablk in2 + coef (H in)
-// (Ablk: packed clover blocks or their inverses; in2 on the output parity)
+// (Ablk: packed clover blocks or their inverses; in2 on the output parity);
+// FP32 only: 3: out = in2 + coef (H in) and 4: out += Ablk (in2 + coef (H in)),
+// both with in2 a full-lattice field and 4 adding into a full-lattice out
 hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
                          void* out, int nrhs, hipStream_t s, int epi = 0, const void* Ablk = nullptr,
                          const void* in2 = nullptr, double coef = 0.0);
+// full_in: in is a full-lattice field (its parity rows are read)
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
-                            double coef, void* out, int nrhs, hipStream_t s);
+                            double coef, void* out, int nrhs, hipStream_t s, bool full_in = false);
 hipError_t launch_clover_invert(long nblk, const void* A64, void* Ai64, void* Ai32, int* flag, hipStream_t s);
 // FP32 rows of one parity between a full-lattice field and a checkerboard one:
 // half[i] = full[site(i)], or full[site(i)] += half[i]

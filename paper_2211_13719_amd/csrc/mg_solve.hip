@@ -86,7 +86,7 @@ struct SolverState {
   Buffer lb[MRHS_MAX_LEVELS], lx[MRHS_MAX_LEVELS], lr[MRHS_MAX_LEVELS], lp[MRHS_MAX_LEVELS];
   Buffer alpha, part, scl, coef, qn;
   Buffer gpart, gmat, gT;  // column Gram matrix (setup)
-  // even-odd fine smoother: eight checkerboard fields of eo_n columns
+  // even-odd fine smoother: five checkerboard fields of eo_n columns
   Buffer eo;
   int eo_n = 0;
   // outer Krylov
@@ -238,7 +238,8 @@ hipError_t mr_steps(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* 
 //   e_o = A_o^-1 (r_o + kappa H_oe e_e),  x += e,  and r = b - D x when the
 // caller still needs the residual (not after the last smoothing pass).
 // Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe.  Checkerboard work fields live in
-// st->eo: r_e, r_o, rho, q, e_e, t_o, t_o2, t_e.
+// st->eo: rho, q, e_e, t_o, t_o2; r and x stay full-lattice fields whose
+// parity rows the kernels read or update in place.
 hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* b, void* p, int n, int nu,
                      bool need_r) {
   mrhs_ctx ctx = mg->ctx;
@@ -247,8 +248,7 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   const long hrows = (long)nh * 12;
   const size_t hb = (size_t)hrows * n * 8;
   char* w = static_cast<char*>(st->eo.p);
-  void *re = w, *ro = w + hb, *rho = w + 2 * hb, *q = w + 3 * hb, *ee = w + 4 * hb, *to = w + 5 * hb,
-       *to2 = w + 6 * hb, *te = w + 7 * hb;
+  void *rho = w, *q = w + hb, *ee = w + 2 * hb, *to = w + 3 * hb, *to2 = w + 4 * hb;
   const auto* tabe = static_cast<const int4*>(ctx->eo_tab[0].p);
   const auto* tabo = static_cast<const int4*>(ctx->eo_tab[1].p);
   const auto* orde = static_cast<const int*>(ctx->eo_order[0].p);
@@ -258,13 +258,9 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   const void* Ai = ctx->Ainv32.p;
   const double k = ctx->kappa;
   hipStream_t s = st->stream;
-  hipError_t e = launch_eo_gather(nh, tabe, r, re, n, s);
-  if (e == hipSuccess) e = launch_eo_gather(nh, tabo, r, ro, n, s);
-  // rhat = r_e + kappa H_eo A_o^-1 r_o
-  if (e == hipSuccess) e = launch_clover_eo(0, nh, tabo, Ai, ro, nullptr, 0.0, to, n, s);
-  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to, te, n, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(rho, re, hb, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = launch_axpy_f32(rho, te, k, hrows * n, s);
+  // rhat = r_e + kappa H_eo (A_o^-1 r_o), reading r's rows in place
+  hipError_t e = launch_clover_eo(0, nh, tabo, Ai, r, nullptr, 0.0, to, n, s, true);
+  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to, rho, n, s, 3, nullptr, r, k);
   if (e == hipSuccess) e = launch_zero(ee, hb, s);
   for (int i = 0; i < nu && e == hipSuccess; ++i) {
     // q = Dhat rho: to2 = A_o^-1 (H_oe rho), q = A_e rho - kappa^2 (H_eo to2), fused launches
@@ -273,12 +269,9 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
     if (e == hipSuccess) e = launch_mr_alpha(q, rho, hrows, n, st->alpha.p, st->part.p, s);
     if (e == hipSuccess) e = launch_mr_update(ee, rho, q, st->alpha.p, hrows, n, s);
   }
-  // e_o = A_o^-1 (r_o + kappa H_oe e_e), written over r_o's copy
-  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabo, ordo, U, ee, to, n, s);
-  if (e == hipSuccess) e = launch_axpy_f32(ro, to, k, hrows * n, s);
-  if (e == hipSuccess) e = launch_clover_eo(0, nh, tabo, Ai, ro, nullptr, 0.0, to2, n, s);
+  // x_o += A_o^-1 (r_o + kappa H_oe e_e) in one launch, x_e += e_e
+  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabo, ordo, U, ee, x, n, s, 4, Ai, r, k);
   if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabe, x, ee, n, s);
-  if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabo, x, to2, n, s);
   // r = b - D x
   if (need_r && e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
   if (need_r && e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, 0) * n, s);
@@ -409,7 +402,7 @@ mrhs_status prepare_eo(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
       gs = GraphSlot{};
     }
     release(st->eo);
-    s = ensure(ctx, st->eo, (size_t)8 * (ctx->g.V / 2) * 12 * n * 8);
+    s = ensure(ctx, st->eo, (size_t)5 * (ctx->g.V / 2) * 12 * n * 8);
     if (s != MRHS_OK) return s;
     st->eo_n = n;
   }
