@@ -296,12 +296,16 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   const mrhs_prec cp = vc.coarse_prec;
   const int ph = l == 0 ? kFine : kCoarse;
   hipError_t e;
-  {
+  // Without pre-smoothing x stays zero until the coarse-grid correction, so
+  // the correction is prolongated straight into x and restricted from b.
+  const bool coarsest = l == mg->nlevels - 1;
+  const bool pre = coarsest || vc.nu_pre > 0;
+  if (pre) {
     PhaseMark pm(st, ph);
     e = launch_zero(x, bytes, st->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st->stream);
     if (e != hipSuccess) return e;
-    if (l == mg->nlevels - 1) return mr_steps(mg, st, l, x, r, p, n, vc.coarsest_iters, cp);
+    if (coarsest) return mr_steps(mg, st, l, x, r, p, n, vc.coarsest_iters, cp);
     e = smooth(mg, st, l, x, r, b, p, n, vc.nu_pre, vc, true);
     if (e != hipSuccess) return e;
   }
@@ -310,20 +314,22 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   const bool ig16 = cp == MRHS_BF16 && L.bf16_ok;
   {
     PhaseMark pm(st, kRestrict);
-    e = ig16 ? launch_restrict_bf16(L.agg, L.ncomp / 2, n, L.Wbf16.p, r, st->lb[l + 1].p, st->stream)
-             : launch_restrict(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, r, st->lb[l + 1].p, st->stream);
+    const void* rin = pre ? r : b;
+    e = ig16 ? launch_restrict_bf16(L.agg, L.ncomp / 2, n, L.Wbf16.p, rin, st->lb[l + 1].p, st->stream)
+             : launch_restrict(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, rin, st->lb[l + 1].p, st->stream);
     if (e != hipSuccess) return e;
   }
   e = vcycle(mg, st, l + 1, n, vc);
   if (e != hipSuccess) return e;
   {
     PhaseMark pm(st, kProlong);
-    e = ig16 ? launch_prolong_bf16(L.agg, L.ncomp / 2, n, L.Wbf16.p, st->lx[l + 1].p, p, st->stream)
-             : launch_prolong(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, st->lx[l + 1].p, p, st->stream);
+    void* pout = pre ? p : x;
+    e = ig16 ? launch_prolong_bf16(L.agg, L.ncomp / 2, n, L.Wbf16.p, st->lx[l + 1].p, pout, st->stream)
+             : launch_prolong(0, L.agg, L.ncomp / 2, L.nv, n, L.basis32.p, st->lx[l + 1].p, pout, st->stream);
     if (e != hipSuccess) return e;
   }
   PhaseMark pm(st, ph);
-  e = launch_add_f32(x, p, rows * n, st->stream);
+  e = pre ? launch_add_f32(x, p, rows * n, st->stream) : hipSuccess;
   if (e == hipSuccess) e = apply_level(mg, l, p, x, n, cp, st->stream);
   if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, st->stream);
   if (e == hipSuccess) e = smooth(mg, st, l, x, r, b, p, n, vc.nu_post, vc, false);
