@@ -248,7 +248,9 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
             print(f"[bench] timed MRHS solve {stt['seconds_total']:.2f} s", file=sys.stderr, flush=True)
         del b, x
         torch.cuda.empty_cache()
-    # the comparator is the faster of the two fine smoothers on one RHS
+    # the comparator is the faster of the two fine smoothers on one RHS, with
+    # the FP32 coarse stencil kernel tuned for one RHS
+    mg.tune([1])
     b1 = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, 1, 4000)).cuda()
     srhs = {}
     for eo in (False, True):
@@ -273,6 +275,7 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "srhs_true_resid": s1["rel_resid"][0],
         "srhs_converged": int(s1["converged"][0]),
         "srhs_fine_eo": int(srhs_eo),
+        "srhs_coarse_f32_kernel": {str(l): mg.get_tuning(l, 1) for l in (1, 2)},
         "srhs_s_by_fine_eo": {str(int(e)): round(v["seconds_total"], 4) for e, v in srhs.items()},
         "speedup": round(s1["seconds_total"] / mrhs_res[best]["s_per_rhs"], 3) if best else None,
         "mrhs_phase_s": phases,
@@ -343,6 +346,8 @@ def main():
     mg.set_basis(1, synth.gaussian_vectors(mg.volume[1], 16, 32, 400))
     mg.block_orthonormalise(1)
     mg.build_coarse(2)
+    mg.tune(list(NRHS_COARSE))
+    coarse_tuning = {str(l): {str(n): mg.get_tuning(l, n) for n in NRHS_COARSE} for l in (1, 2)}
     src = synth.spinor_source(DIMS, max(NRHS_FINE), 100, np.complex64)
     fine = {}
     for n in NRHS_FINE:
@@ -488,6 +493,7 @@ def main():
         "per_op": per_op,
         "evenodd": evenodd,
         "fine_tuning": tuning,
+        "coarse_f32_tuning": coarse_tuning,
         "fine_sources": fine_sources_digest(),
         "solve": None,
         "cpu_baseline": None,

@@ -278,6 +278,17 @@ mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
  * per RHS by a power of two first, exactly undone on output). */
 mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 
+/* mrhs_mg_tune: for every coarse level with Nb = 32 and blocks set, and each
+ * nrhs in nrhs_list (count entries), times the two FP32 stencil kernels (FP32
+ * matrix cores, vector ALU) on the device and keeps the faster one for
+ * mrhs_coarse_apply with MRHS_F32 and for V-cycles with FP32 coarse levels
+ * (untuned: the matrix cores).  Synchronises; drops the solver's captured
+ * V-cycles and work buffers, which the next solve rebuilds. */
+mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count);
+/* mrhs_mg_get_tuning: *f32_valu = 1 when level uses the vector-ALU FP32
+ * stencil for nrhs (always for Nb != 32), 0 for the FP32 matrix cores. */
+mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu);
+
 /* Even-odd pieces of the coarse stencil, Sec. 6 (the coarse-level M_eooe):
  * on a level whose extents are all even, with the checkerboard layout of the
  * fine even-odd calls (FP32 complex device fields [V/2][Nb][nrhs], entry i the

@@ -397,6 +397,17 @@ class Multigrid:
                                           p))
         return out
 
+    def tune(self, nrhs_list):
+        """Time the FP32 coarse stencil kernels (matrix cores vs vector ALU) per level and nrhs."""
+        arr = (C.c_int32 * len(nrhs_list))(*[int(n) for n in nrhs_list])
+        self._check(lib.mrhs_mg_tune(self._h, arr, len(nrhs_list)))
+
+    def get_tuning(self, level: int, nrhs: int) -> str:
+        """"valu" or "mfma": the FP32 stencil kernel level uses for nrhs."""
+        v = C.c_int32()
+        self._check(lib.mrhs_mg_get_tuning(self._h, int(level), int(nrhs), C.byref(v)))
+        return "valu" if v.value else "mfma"
+
     def _half_pair(self, a, b, level):
         for t in (a, b):
             if t.dim() != 3 or t.shape[0] != self.volume[level] // 2 or t.shape[1] != self.ncomp[level]:

@@ -64,6 +64,8 @@ SIGNATURES = {
     "mrhs_coarse_get_blocks": (_i32, [_vp, _i32, _vp, _i32, _i32]),
     "mrhs_mg_build_coarse": (_i32, [_vp, _i32]),
     "mrhs_coarse_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
+    "mrhs_mg_tune": (_i32, [_vp, _vp, _i32]),
+    "mrhs_mg_get_tuning": (_i32, [_vp, _i32, _i32, _vp]),
     "mrhs_coarse_hop_eo_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32, _i32]),
     "mrhs_coarse_self_eo_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _i32]),
     "mrhs_mg_precondition": (_i32, [_vp, _vp, _vp, _i32, _vp]),

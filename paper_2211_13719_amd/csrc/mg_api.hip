@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "mg_internal.h"
 
@@ -85,6 +86,13 @@ mrhs_status refresh_blocks(mrhs_mg mg, int level) {
   L.have_blocks = true;
   L.have_sinv = false;
   return MRHS_OK;
+}
+
+hipError_t coarse_apply_f32(mrhs_mg mg, int level, const void* in, void* out, int n, hipStream_t s) {
+  LevelData& L = mg->lv[level];
+  if (mfma_supported(L.ncomp) && !L.f32_valu[n])
+    return launch_coarse_mfma_f32(L.g, L.ncomp, n, L.Bf32p.p, in, out, s);
+  return launch_coarse_valu(0, L.g, L.ncomp, n, L.BT32.p, in, out, DirFilter{}, s);
 }
 
 // Inverted self blocks of a level and their three MFMA packs (synchronises).
@@ -491,13 +499,9 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
       e = launch_coarse_valu(1, L.g, L.ncomp, nrhs, L.BT64.p, in, out, DirFilter{}, ctx->stream);
       break;
     case MRHS_F32:
-      // FP32 matrix cores whenever Nb = 32: with few right-hand sides most of
-      // the 32-column tile idles, but the stencil is bound by block bytes and
-      // latency, where the direction-split matrix-core kernel does better
-      if (mfma_supported(L.ncomp))
-        e = launch_coarse_mfma_f32(L.g, L.ncomp, nrhs, L.Bf32p.p, in, out, ctx->stream);
-      else
-        e = launch_coarse_valu(0, L.g, L.ncomp, nrhs, L.BT32.p, in, out, DirFilter{}, ctx->stream);
+      // FP32 matrix cores for Nb = 32 unless mrhs_mg_tune found the
+      // vector-ALU kernel faster for this level and nrhs
+      e = coarse_apply_f32(mg, level, in, out, nrhs, ctx->stream);
       break;
     case MRHS_BF16:
     case MRHS_F16: {
@@ -571,6 +575,72 @@ static mrhs_status coarse_eo(mrhs_mg mg, int32_t level, void* out, const void* i
   }
   MRHS_HIP(ctx, launch_coarse_mfma_eo(pk, eo, parity, L.g, L.ncomp, nrhs, pack, bstride, in, out, scale,
                                       ctx->stream));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_ctx ctx = mg->ctx;
+  if (!nrhs_list || count < 1 || count > 64) return fail(ctx, MRHS_ERR_INVALID_ARG, "bad nrhs list");
+  for (int i = 0; i < count; ++i)
+    if (nrhs_list[i] < 1 || nrhs_list[i] > MRHS_MAX_NRHS)
+      return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs_list[i], MRHS_MAX_NRHS);
+  DevGuard dg(ctx->device);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MRHS_HIP(ctx, hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  for (int l = 1; l < mg->nlevels && e == hipSuccess; ++l) {
+    LevelData& L = mg->lv[l];
+    if (!L.have_blocks || !mfma_supported(L.ncomp)) continue;
+    const int nmax = *std::max_element(nrhs_list, nrhs_list + count);
+    const size_t bytes = (size_t)L.g.V * L.ncomp * nmax * 8;
+    mrhs_status st = ensure(ctx, mg->tmpA, bytes);
+    if (st == MRHS_OK) st = ensure(ctx, mg->tmpB, bytes);
+    if (st != MRHS_OK) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return st;
+    }
+    e = hipMemsetAsync(mg->tmpA.p, 0, bytes, ctx->stream);
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+      const int n = nrhs_list[i];
+      float best[2] = {0.f, 0.f};
+      for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        L.f32_valu[n] = (signed char)k;
+        std::vector<float> t;
+        for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, ctx->stream);
+          if (e == hipSuccess) e = coarse_apply_f32(mg, l, mg->tmpA.p, mg->tmpB.p, n, ctx->stream);
+          if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) t.push_back(ms);  // the first launch is a warm-up
+        }
+        if (e == hipSuccess) {
+          std::sort(t.begin(), t.end());
+          best[k] = t[t.size() / 2];
+        }
+      }
+      L.f32_valu[n] = (signed char)(e == hipSuccess && best[1] < best[0]);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(ctx, e, "coarse tuning");
+  mg_solver_release(mg);  // captured V-cycles hold the previous kernel choice
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_level(mg, level, 1, MRHS_MAX_LEVELS - 1);
+  if (st != MRHS_OK) return st;
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS)
+    return fail(mg->ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  if (!f32_valu) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "null output");
+  const LevelData& L = mg->lv[level];
+  *f32_valu = (!mfma_supported(L.ncomp) || L.f32_valu[nrhs]) ? 1 : 0;
   return MRHS_OK;
 }
 

@@ -27,6 +27,9 @@ struct LevelData {
   // built on first use by the even-odd calls, dropped when the blocks change
   Buffer Sinv64, SinvBf16, SinvF16, SinvF32p;
   bool have_sinv = false;
+  // FP32 stencil kernel per Nrhs, set by mrhs_mg_tune: 0 the FP32 matrix
+  // cores (default for Nb = 32), 1 the vector-ALU kernel
+  signed char f32_valu[MRHS_MAX_NRHS + 1] = {};
 };
 
 struct SolverState;
@@ -46,6 +49,9 @@ struct mrhs_mg_s {
 namespace mrhs {
 
 mrhs_status refresh_blocks(mrhs_mg mg, int level);
+// FP32 stencil D_l in -> out with the kernel mrhs_mg_tune chose for n (Nb = 32:
+// matrix cores unless the vector-ALU kernel measured faster)
+hipError_t coarse_apply_f32(mrhs_mg mg, int level, const void* in, void* out, int n, hipStream_t s);
 // per-RHS FP16 scales and their reduction words (zeroed when first allocated)
 mrhs_status ensure_colscale(mrhs_mg mg);
 mrhs_status refresh_basis32(mrhs_mg mg, int level);

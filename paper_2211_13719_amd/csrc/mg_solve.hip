@@ -208,9 +208,7 @@ hipError_t apply_level(mrhs_mg mg, int l, void* out, const void* in, int n, mrhs
     return launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, n, s,
                            &ctx->fine_cfg[n]);
   LevelData& L = mg->lv[l];
-  if (!mfma_supported(L.ncomp))
-    return launch_coarse_valu(0, L.g, L.ncomp, n, L.BT32.p, in, out, DirFilter{}, s);
-  if (cp == MRHS_F32) return launch_coarse_mfma_f32(L.g, L.ncomp, n, L.Bf32p.p, in, out, s);
+  if (!mfma_supported(L.ncomp) || cp == MRHS_F32) return coarse_apply_f32(mg, l, in, out, n, s);
   const float* scale = nullptr;
   if (cp == MRHS_F16) {
     float* sc = static_cast<float*>(mg->colscale.p);

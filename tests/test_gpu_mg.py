@@ -302,6 +302,28 @@ def test_coarse_apply_all_precisions(gpu_lib, cdims, nrhs):
         assert rel(got, O.coarse_apply_lowprec(B, e32, cdims, fmt)) < 1e-6, fmt
 
 
+@pytest.mark.parametrize("cdims", [(6, 6, 6, 6), (3, 3, 3, 3)])
+def test_coarse_tune_keeps_parity(gpu_lib, cdims):
+    """mrhs_mg_tune picks the FP32 stencil kernel per nrhs; whichever it picks matches
+    the oracle on the FP32-rounded blocks (1e-6)."""
+    import torch
+
+    nb = 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 17)
+    mg.set_blocks(1, B)
+    ns = [1, 12, 33]
+    mg.tune(ns)
+    B32 = B.astype(np.complex64)
+    for n in ns:
+        assert mg.get_tuning(1, n) in ("mfma", "valu")
+        e32 = synth.coarse_source(Vc, nb, n, 19, np.complex64)
+        o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+        mg.coarse_apply(1, o, dev(e32), "f32")
+        assert rel(host(o), O.coarse_apply(B32, e32, cdims)) < 1e-6, (n, mg.get_tuning(1, n))
+
+
 def test_coarse_apply_nb8_valu(gpu_lib):
     import torch
 
