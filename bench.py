@@ -2,7 +2,7 @@
 """Benchmark of the MRHS Wilson-clover multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu-baseline]
-                    [--tune-cache PATH | --retune] [--solve-nrhs 12,24] [--m0 M]
+                    [--tune-cache PATH | --retune] [--solve-nrhs 12,24,48] [--m0 M]
 
 One step is one pass over every operator of the hot path, each on its
 workload shape (inputs resident in device memory, all synthetic and seeded):
@@ -24,9 +24,10 @@ events on the stream the kernels run on; `roofline` is for the dominant
 kernel.  After the timed region (not part of `value`), `solve` times the
 mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels
 and intergrid, graph-replayed V-cycle) on 24^3 x 128 smooth links at the bare
-mass stored in tests/golden/smooth_links_mass.json, for batches of 12 and 24
-RHS, and the same solver on one RHS with FP32 coarse levels, in seconds per
-RHS to a true residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on
+mass stored in tests/golden/smooth_links_mass.json, for batches of 12, 24 and
+48 RHS (FGMRES(8), or the longest restart whose fields fit in the free HBM),
+and the same solver on one RHS with FP32 coarse levels, in seconds per RHS to
+a true residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on
 a sample.
 
 Fine-kernel launch configurations come from the autotuner's text cache
@@ -206,6 +207,20 @@ def bench_evenodd(ctx, mg, torch, stream, fine, coarse, V, warmup, steps):
     return out
 
 
+def solve_restart(elems, free_bytes, reserve=4 << 30):
+    """FGMRES restart length for a batch whose fine fields hold `elems` complex numbers
+    (V x 12 x Nrhs): the largest m <= SOLVE_RESTART whose solver fields fit in the device
+    memory left after the set-up, less a reserve.  Per complex element: m + 1 FP64 basis
+    vectors, m FP32 preconditioned directions, two FP64 work fields, the caller's FP64 x and
+    b, four FP32 V-cycle fields of the fine level and five half-lattice FP32 fields of the
+    even-odd smoother (2.5 full ones)."""
+    for m in range(SOLVE_RESTART, 1, -1):
+        per = 16 * (m + 1) + 8 * m + 2 * 16 + 2 * 16 + 4 * 8 + 20
+        if elems * per <= free_bytes - reserve:
+            return m
+    return 2
+
+
 def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     """MRHS mixed-precision solves (one per batch size) vs the same solver on one RHS
     with FP32 coarse levels and FP32 intergrid."""
@@ -224,25 +239,39 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] solve setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    free0, total = torch.cuda.mem_get_info()
+    print(f"[bench] device memory after set-up: {free0 / 2**30:.1f} GiB free of {total / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
     vc = dict(SOLVE_VC, fine_eo=SOLVE_MRHS_FINE_EO)
-    kw = dict(tol=1e-10, restart=SOLVE_RESTART, max_iters=SOLVE_MAXIT, check=False)
+    kw = dict(tol=1e-10, max_iters=SOLVE_MAXIT, check=False)
     mrhs_res, phases = {}, None
     for n in nrhs_list:
-        b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, n, 4000)).cuda()
-        x = torch.zeros_like(b)
-        st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", **kw, **vc)
+        m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n, free0)
+        try:
+            b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, n, 4000)).cuda()
+            x = torch.zeros_like(b)
+            st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", restart=m, **kw, **vc)
+            if st["status"] not in (0, 7):  # 7: ran to max_iters, reported below as not converged
+                mg._check(st["status"])
+        except Exception as exc:  # e.g. out of memory at the largest batch: keep the other batches
+            mrhs_res[str(n)] = {"restart": m, "error": f"{type(exc).__name__}: {exc}"}
+            print(f"[bench] MRHS solve N={n} failed: {exc}", file=sys.stderr, flush=True)
+            b = x = None
+            torch.cuda.empty_cache()
+            continue
         mrhs_res[str(n)] = {
             "s_per_rhs": round(st["seconds_total"] / n, 4),
             "seconds": round(st["seconds_total"], 3),
             "iters": st["iters"],
+            "restart": m,
             "converged": int(sum(st["converged"])),
             "max_true_resid": max(st["rel_resid"]),
         }
         print(f"[bench] MRHS solve N={n}: {st['seconds_total']:.2f} s, {st['iters']} iterations, "
-              f"{sum(st['converged'])}/{n} converged", file=sys.stderr, flush=True)
+              f"FGMRES({m}), {sum(st['converged'])}/{n} converged", file=sys.stderr, flush=True)
         if phases is None:  # per-phase breakdown from a timed (graph-free) solve of the first batch
             x.zero_()
-            stt = mg.solve(x, b, use_graph=False, timers=True, coarse_prec="bf16", **kw, **vc)
+            stt = mg.solve(x, b, use_graph=False, timers=True, coarse_prec="bf16", restart=m, **kw, **vc)
             phases = {"nrhs": n, "total_s": round(stt["seconds_total"], 4),
                       **{k: round(v, 4) for k, v in stt["seconds_phase"].items()}}
             print(f"[bench] timed MRHS solve {stt['seconds_total']:.2f} s", file=sys.stderr, flush=True)
@@ -255,12 +284,13 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     srhs = {}
     for eo in (False, True):
         x1 = torch.zeros_like(b1)
-        srhs[eo] = mg.solve(x1, b1, use_graph=True, coarse_prec="f32", **kw, **dict(SOLVE_VC, fine_eo=eo))
+        srhs[eo] = mg.solve(x1, b1, use_graph=True, coarse_prec="f32", restart=SOLVE_RESTART, **kw,
+                            **dict(SOLVE_VC, fine_eo=eo))
         print(f"[bench] SRHS solve (fine_eo={int(eo)}) {srhs[eo]['seconds_total']:.2f} s, {srhs[eo]['iters']} "
               "iterations", file=sys.stderr, flush=True)
     srhs_eo = min(srhs, key=lambda e: srhs[e]["seconds_total"] if srhs[e]["converged"][0] else 1e30)
     s1 = srhs[srhs_eo]
-    ok = [k for k, v in mrhs_res.items() if v["converged"] == int(k)]
+    ok = [k for k, v in mrhs_res.items() if v.get("converged") == int(k)]
     best = min(ok, key=lambda k: mrhs_res[k]["s_per_rhs"]) if ok else None
     out = {
         "workload": "24^3x128, smooth links U = exp(0.3 i H), csw 1.0, antiperiodic t, "
@@ -279,7 +309,7 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "srhs_s_by_fine_eo": {str(int(e)): round(v["seconds_total"], 4) for e, v in srhs.items()},
         "speedup": round(s1["seconds_total"] / mrhs_res[best]["s_per_rhs"], 3) if best else None,
         "mrhs_phase_s": phases,
-        "config": f"FP64 FGMRES({SOLVE_RESTART}), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
+        "config": f"FP64 FGMRES({SOLVE_RESTART}, shorter where the batch's fields would not fit in HBM), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
                   f"levels and BF16 matrix-core restrict/prolong, fine_eo {int(SOLVE_MRHS_FINE_EO)} (fine smoothing "
                   "on the even-odd Schur complement), graph replay; SRHS comparator: same solver, one RHS, FP32 "
                   "coarse levels and FP32 intergrid, the faster of the two fine smoothers",
@@ -297,7 +327,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--solve-nrhs", default="12,24", help="comma-separated batch sizes of the MRHS solve")
+    ap.add_argument("--solve-nrhs", default="12,24,48", help="comma-separated batch sizes of the MRHS solve")
     ap.add_argument("--m0", type=float, default=None,
                     help="bare mass of the solve workload (default: the tuned value in tests/golden)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner text cache (read, appended)")
