@@ -349,9 +349,19 @@ __global__ void colmax_kernel(const float2* __restrict__ in, long rows, int nrhs
   // the stride is a multiple of nrhs when launched as below, so the column is fixed
   const int k = (int)(e0 % nrhs);
   float mx = 0.f;
-  for (long e = e0; e < n; e += stride) {
-    const float2 v = in[e];
-    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+  // four loads in flight per thread; an index past the end reads this
+  // thread's own first element (valid, as e0 < n inside the loop) and counts
+  // zero, so no load sits in a branch
+  constexpr int U = 4;
+  for (long e = e0; e < n; e += U * stride) {
+    float2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = in[e + u * stride < n ? e + u * stride : e0];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float a = fmaxf(fabsf(v[u].x), fabsf(v[u].y));
+      mx = fmaxf(mx, e + u * stride < n ? a : 0.f);
+    }
   }
   // one atomic per (workgroup, column): thread j < nrhs combines the threads
   // t = j, j + nrhs, ... of the workgroup, which all hold column k(j)
@@ -398,7 +408,8 @@ hipError_t launch_pack_blocks(int f16, const void* B64, void* packed, long nsite
 hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, float* scale, hipStream_t s) {
   unsigned int* m = static_cast<unsigned int*>(work);
   // workgroup stride must be a multiple of nrhs: use blocks of 256 threads and
-  // a grid such that 256 * grid % nrhs == 0
+  // a grid such that 256 * grid % nrhs == 0 (a few hundred workgroups: every
+  // one ends in nrhs atomics on the same nrhs words)
   int grid = 256;
   while ((256L * grid) % nrhs) ++grid;
   hipLaunchKernelGGL(colmax_kernel, dim3(grid), dim3(256), 0, s, static_cast<const float2*>(in), rows, nrhs, m);

@@ -372,25 +372,39 @@ __global__ __launch_bounds__(256) void block_norm_kernel(AggGeom a, int h, int n
   }
 }
 
-// Single-pass variant for FP32 fields with an even number of RHS: one
-// workgroup of 1024 threads per (aggregate, chirality) keeps the whole block
-// in registers, so the field is read once and written once (the kernel above
-// reads it twice).  Thread (slice, g) holds RHS 2g, 2g + 1 of the rows
-// r = slice, slice + S, ... (r = l h + c: site offset l, component c), at most
-// MAXR of them; the squares are summed in FP64 per thread and over the
-// slices in a fixed order.
-template <int MAXR>
-__global__ __launch_bounds__(1024) void block_norm_reg_kernel(AggGeom a, int h, int nrhs, float2* __restrict__ f,
-                                                              double* __restrict__ norms) {
+// Single-pass variant for FP32 fields with an even number of RHS: workgroups
+// of 1024 threads keep a whole (aggregate, chirality) block, or a range of its
+// RHS columns, in registers, so the field is read once and written once (the
+// kernel above reads it twice).  The norms are per column, so the C = nrhs /
+// parts columns of each part are independent; the parts of one block get
+// workgroup indices 8 apart (workgroups go round-robin over the eight XCDs),
+// which keeps them on one XCD, where they share the L2 lines that their column
+// ranges have in common.  Thread (slice, g) holds columns 2g, 2g + 1 of its
+// part for the rows r = slice, slice + S, ... (r = l h + c: site offset l,
+// component c), at most MAXR of them; with MAXR = 10 and WPE = 8 a workgroup
+// fits in 64 VGPRs per lane and two share a CU, so one's loads overlap the
+// other's reduction and stores.  The squares are summed in FP64 per thread,
+// then over the slices in a fixed order (eight interleaved partial sums, then
+// those eight), so the result does not depend on timing.
+template <int MAXR, int WPE>
+__global__ __launch_bounds__(1024, WPE) void block_norm_reg_kernel(AggGeom a, int h, int nrhs, int parts, int nac,
+                                                                   float2* __restrict__ f,
+                                                                   double* __restrict__ norms) {
   __shared__ double part[1024 * 2];
+  __shared__ double red[8 * 64];
   __shared__ double inv[64];
-  const int A = blockIdx.x >> 1, chi = blockIdx.x & 1;
+  const int q8 = blockIdx.x >> 3;
+  const int ac = (q8 / parts) * 8 + (blockIdx.x & 7);
+  if (ac >= nac) return;  // whole workgroup
+  const int pc = q8 % parts;
+  const int A = ac >> 1, chi = ac & 1;
   const int ncomp = 2 * h;
-  const int G = nrhs / 2;
+  const int C = nrhs / parts;
+  const int G = C / 2;
   const int S = 1024 / G;
   const int t = threadIdx.x;
   const int g = t % G, slice = t / G;
-  const int k0 = 2 * g;
+  const int k0 = pc * C + 2 * g;
   const int nrow = a.b[0] * a.b[1] * a.b[2] * a.b[3] * h;
   auto offset = [&](int r) {
     const int l = r / h, c = r - (r / h) * h;
@@ -414,31 +428,48 @@ __global__ __launch_bounds__(1024) void block_norm_reg_kernel(AggGeom a, int h, 
     acc1 = fma(m * (double)v[q].z, (double)v[q].z, acc1);
     acc1 = fma(m * (double)v[q].w, (double)v[q].w, acc1);
   }
+  // column o = 2 g + w of slice q sits at part[2 q G + o]
   part[2 * t] = acc0;
   part[2 * t + 1] = acc1;
   __syncthreads();
-  if (t < G) {
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-      double s2 = 0.0;
-      for (int q = 0; q < S; ++q) s2 += part[2 * (q * G + t) + w];
-      const double n = sqrt(s2);
-      inv[2 * t + w] = n > 0.0 ? 1.0 / n : 0.0;
-      if (norms) norms[((size_t)A * 2 + chi) * nrhs + 2 * t + w] = n;
-    }
+  if (t < 16 * G) {
+    const int o = t % (2 * G), j = t / (2 * G);
+    double s2 = 0.0;
+    for (int q = j; q < S; q += 8) s2 += part[2 * q * G + o];
+    red[j * 2 * G + o] = s2;
   }
   __syncthreads();
-  const float sc0 = (float)inv[k0], sc1 = (float)inv[k0 + 1];
+  if (t < 2 * G) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s2 += red[j * 2 * G + t];
+    const double n = sqrt(s2);
+    inv[t] = n > 0.0 ? 1.0 / n : 0.0;
+    if (norms) norms[((size_t)A * 2 + chi) * nrhs + pc * C + t] = n;
+  }
+  __syncthreads();
+  const float sc0 = (float)inv[2 * g], sc1 = (float)inv[2 * g + 1];
 #pragma unroll
   for (int q = 0; q < MAXR; ++q) {
     const int r = slice + q * S;
     if (slice < S && r < nrow)
-      *reinterpret_cast<float4*>(f + offset(r)) =
-          make_float4(v[q].x * sc0, v[q].y * sc0, v[q].z * sc1, v[q].w * sc1);
+      *reinterpret_cast<float4*>(f + offset(r)) = make_float4(v[q].x * sc0, v[q].y * sc0, v[q].z * sc1, v[q].w * sc1);
   }
 }
 
-constexpr int kNormRegRows = 20;
+constexpr int kNormRegRows = 20, kNormRegRowsSplit = 6;
+
+// Number of column parts for the MAXR = 10 variant: the fewest that fit, each
+// of at least 8 columns (64-byte row segments) unless the block fits whole.
+int norm_reg_parts(long nrow, int nrhs) {
+  if (nrhs % 2) return 0;
+  for (int p = 1; p <= nrhs / 2; ++p) {
+    if ((nrhs / 2) % p || (p > 1 && nrhs / p < 8)) continue;
+    const int G = nrhs / 2 / p;
+    if (nrow <= (long)kNormRegRowsSplit * (1024 / G)) return p;
+  }
+  return 0;
+}
 
 // ---- layout conversion between [site][n_v][ncomp] (interface) and [site][ncomp][n_v] --------
 template <typename Tin, typename Tout>
@@ -583,12 +614,17 @@ hipError_t launch_block_gs(const AggGeom& a, int h, int nv, void* basis64, int* 
 hipError_t launch_block_normalise(int prec64, const AggGeom& a, int h, int nrhs, void* f, double* norms,
                                   hipStream_t s) {
   if (2 * nrhs > 256) return hipErrorInvalidValue;
+  const long nrow = (long)a.b[0] * a.b[1] * a.b[2] * a.b[3] * h;
+  const int nac = 2 * a.Vc;
   if (prec64)
     hipLaunchKernelGGL((block_norm_kernel<double, 1>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
                        static_cast<double2*>(f), norms);
-  else if (nrhs % 2 == 0 && (long)a.b[0] * a.b[1] * a.b[2] * a.b[3] * h <= (long)kNormRegRows * (1024 / (nrhs / 2)))
-    hipLaunchKernelGGL((block_norm_reg_kernel<kNormRegRows>), dim3(2 * a.Vc), dim3(1024), 0, s, a, h, nrhs,
-                       static_cast<float2*>(f), norms);
+  else if (const int p = norm_reg_parts(nrow, nrhs); p > 0)
+    hipLaunchKernelGGL((block_norm_reg_kernel<kNormRegRowsSplit, 8>), dim3((nac + 7) / 8 * 8 * p), dim3(1024), 0, s,
+                       a, h, nrhs, p, nac, static_cast<float2*>(f), norms);
+  else if (nrhs % 2 == 0 && nrow <= (long)kNormRegRows * (1024 / (nrhs / 2)))
+    hipLaunchKernelGGL((block_norm_reg_kernel<kNormRegRows, 4>), dim3((nac + 7) / 8 * 8), dim3(1024), 0, s, a, h,
+                       nrhs, 1, nac, static_cast<float2*>(f), norms);
   else if (nrhs % 2 == 0)
     hipLaunchKernelGGL((block_norm_kernel<float, 2>), dim3(a.Vc), dim3(256), 0, s, a, h, nrhs,
                        static_cast<float2*>(f), norms);

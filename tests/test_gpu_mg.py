@@ -245,10 +245,12 @@ def test_block_normalise_small(gpu_lib, dt):
     np.testing.assert_allclose(host(norms), want_n, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("nrhs", [2, 12, 26, 28])
+@pytest.mark.parametrize("nrhs", [2, 12, 24, 26, 28, 64])
 def test_block_normalise_even_nrhs(gpu_lib, nrhs):
-    """FP32, even Nrhs on 4^4 aggregates: the single-pass kernel up to 20 rows per
-    thread (Nrhs <= 26 here, ragged last rows), the two-pass one beyond (28)."""
+    """FP32, even Nrhs on 4^4 aggregates (1536 rows of 6 components): the single-pass
+    kernel with the columns split into parts of 8 (24: three parts, 64: eight) or whole
+    (2), the one with up to 20 rows per thread (12, and 26 with ragged last rows), the
+    two-pass one beyond (28)."""
     import torch
 
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
