@@ -42,7 +42,7 @@ def lat(gpu_lib):
 
 
 @pytest.mark.parametrize("dt", [np.complex128, np.complex64])
-@pytest.mark.parametrize("nrhs", [1, 5, 24])
+@pytest.mark.parametrize("nrhs", [1, 5, 24, 64])
 @pytest.mark.parametrize("p", [0, 1])
 def test_hop_eo(lat, dt, nrhs, p):
     import torch
@@ -71,7 +71,7 @@ def test_clover_eo(lat, dt, inverse, p):
 
 
 @pytest.mark.parametrize("dt", [np.complex128, np.complex64])
-@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("nrhs", [1, 3, 64])
 def test_schur(lat, dt, nrhs):
     import torch
 
