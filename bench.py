@@ -59,9 +59,11 @@ FLOPS_DWC = 1920          # per site per RHS: hop 1320 + clover 552 + combine 48
 SOLVE_DIMS = (24, 24, 24, 128)
 # multigrid set-up and V-cycle of the solve workload (hyper-parameters, not from the paper)
 SOLVE_SETUP = dict(setup_iters=10, smooth_steps=30, adapt_iters=0)
-SOLVE_VC = dict(nu_pre=0, nu_post=6, coarsest_iters=64)
+# 24^3x128, 12 RHS, even-odd fine smoother: nu_post 4 with 128 coarsest steps 1.09 s (23 outer steps),
+# nu_post 6 with 64 steps 1.31 s (24); on one RHS 4 / 128 is the fastest setting measured too (0.367 s)
+SOLVE_VC = dict(nu_pre=0, nu_post=4, coarsest_iters=128)
 SOLVE_RESTART, SOLVE_MAXIT = 8, 1000
-SOLVE_MRHS_FINE_EO = True  # 24^3x128, 12 / 24 RHS: 24 instead of 28 outer steps, 10-13 % less time
+SOLVE_MRHS_FINE_EO = True  # 24^3x128, 12 / 24 RHS, nu_post 6: 24 instead of 28 outer steps, 10-13 % less time
 TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
 FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 
