@@ -58,7 +58,9 @@ HBM_PEAK_GBS = 8000.0
 FLOPS_DWC = 1920          # per site per RHS: hop 1320 + clover 552 + combine 48
 SOLVE_DIMS = (24, 24, 24, 128)
 # multigrid set-up and V-cycle of the solve workload (hyper-parameters, not from the paper)
-SOLVE_SETUP = dict(setup_iters=10, smooth_steps=30, adapt_iters=0)
+# 15 set-up sweeps instead of 10: 21 instead of 23 outer steps at 12 RHS (0.98 vs 1.08 s), 0.32 vs 0.36 s on
+# one RHS, for about 1 s more set-up; 20 sweeps or 50 MR steps per sweep gain nothing further
+SOLVE_SETUP = dict(setup_iters=15, smooth_steps=30, adapt_iters=0)
 # 24^3x128, 12 RHS, even-odd fine smoother: nu_post 4 with 128 coarsest steps 1.09 s (23 outer steps),
 # nu_post 6 with 64 steps 1.31 s (24); on one RHS 4 / 128 is the fastest setting measured too (0.367 s)
 SOLVE_VC = dict(nu_pre=0, nu_post=4, coarsest_iters=128)
