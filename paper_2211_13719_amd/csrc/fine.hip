@@ -658,21 +658,34 @@ hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U
 // 1 and 2 fuse the Schur complement's clover factors into the hops, 3 and 4
 // the even-odd smoother's right-hand side and odd-site reconstruction.  FULL2
 // reads in2 from a full-lattice field (row = lattice site) instead of a
-// checkerboard one; ADDF adds the result into a full-lattice out.
-template <typename T, int R, int EPI, bool FULL2, bool ADDF>
+// checkerboard one; ADDF adds the result into a full-lattice out.  DOT (with
+// EPI 2, the minimal-residual step p = Dhat r, in2 = r) also writes per
+// workgroup b and column k the partial sums (Re <p, r>, Im <p, r>, ||p||^2)
+// in FP64 to part[b][k], summed over the workgroup's threads in a fixed order.
+template <typename T, int R, int EPI, bool FULL2, bool ADDF, bool DOT = false>
 __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
                                                      const int* __restrict__ order, int nblocks,
                                                      const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
                                                      cplx<T>* __restrict__ out, const T* __restrict__ Ablk,
-                                                     const cplx<T>* __restrict__ in2, T coef) {
+                                                     const cplx<T>* __restrict__ in2, T coef,
+                                                     double4* __restrict__ part = nullptr) {
+  static_assert(!DOT || (EPI == 2 && !ADDF), "the MR partial sums go with the second Schur hop");
   const int per = (nblocks + 7) >> 3;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (b >= nblocks) return;
+  if (b >= nblocks) return;  // the whole workgroup
   const int groups = nrhs / R;
   const long gid = (long)b * 256 + threadIdx.x;
-  if (gid >= (long)nhalf * groups) return;
-  const int pidx = (int)(gid / groups);
-  const int k0 = (int)(gid - (long)pidx * groups) * R;
+  const long total = (long)nhalf * groups;
+  // with DOT every thread reaches the workgroup's barrier: one past the end
+  // recomputes the last entry, stores nothing and adds zeros
+  const bool valid = gid < total;
+  if (!DOT && !valid) return;
+  const long gv = valid ? gid : total - 1;
+  const int pidx = (int)(gv / groups);
+  const int k0 = (int)(gv - (long)pidx * groups) * R;
+  double dre[R], dim[R], dpp[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) dre[j] = dim[j] = dpp[j] = 0.0;
   const int i = order[pidx];
   const int4 n0 = tab[4 * i], n1 = tab[4 * i + 1], s0 = tab[4 * i + 2], s1 = tab[4 * i + 3];
   cplx<T> acc[4][3][R];
@@ -690,6 +703,9 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
   const cplx<T>* q = in2 + (size_t)(FULL2 ? s0.x : i) * 12 * nrhs + k0;
   // y = the stored value of component r of chirality chi
   auto put = [&](cplx<T>* dst, const cplx<T> (&y)[R]) {
+    if constexpr (DOT) {
+      if (!valid) return;
+    }
     if constexpr (ADDF) {
       cplx<T> a[R], sum[R];
       load_r<T, R>(dst, a);
@@ -751,8 +767,41 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
             yout[r][j].y = fma(coef, acc[2 * chi + r / 3][r % 3][j].y, yout[r][j].y);
           }
         }
+        if constexpr (DOT) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const double px = yout[r][j].x, py = yout[r][j].y, qx = xin[r][j].x, qy = xin[r][j].y;
+            dre[j] = fma(px, qx, fma(py, qy, dre[j]));
+            dim[j] = fma(px, qy, fma(-py, qx, dim[j]));
+            dpp[j] = fma(px, px, fma(py, py, dpp[j]));
+          }
+        }
         put(o + (6 * chi + r) * nrhs, yout[r]);
       }
+    }
+  }
+  if constexpr (DOT) {
+    // thread u of the workgroup holds columns ((b 256 + u) mod groups) R + j
+    __shared__ double red[256 * R * 3];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      red[(t * R + j) * 3 + 0] = valid ? dre[j] : 0.0;
+      red[(t * R + j) * 3 + 1] = valid ? dim[j] : 0.0;
+      red[(t * R + j) * 3 + 2] = valid ? dpp[j] : 0.0;
+    }
+    __syncthreads();
+    if (t < nrhs) {
+      const int gi = t / R, j = t - (t / R) * R;
+      int u = gi - (int)(((long)b * 256) % groups);
+      if (u < 0) u += groups;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (; u < 256; u += groups) {
+        s0 += red[(u * R + j) * 3 + 0];
+        s1 += red[(u * R + j) * 3 + 1];
+        s2 += red[(u * R + j) * 3 + 2];
+      }
+      part[(long)b * nrhs + t] = make_double4(s0, s1, s2, 0.0);
     }
   }
 }
@@ -911,6 +960,21 @@ hipError_t launch_hop_eo_k(int nhalf, int nrhs, const int4* tab, const int* orde
   return hipGetLastError();
 }
 
+template <int R>
+hipError_t launch_hop_eo_dot_r(int nhalf, int nrhs, const int4* tab, const int* order, const void* U, const void* in,
+                               void* out, const void* Ablk, const void* in2, double coef, void* part, int* nblk,
+                               hipStream_t s) {
+  const long threads = (long)nhalf * (nrhs / R);
+  const int nblocks = (int)((threads + 255) / 256);
+  const dim3 grid((unsigned)(((nblocks + 7) / 8) * 8));
+  hipLaunchKernelGGL((hop_eo_kernel<float, R, 2, false, false, true>), grid, dim3(256), 0, s, nhalf, nrhs, tab, order,
+                     nblocks, static_cast<const float2*>(U), static_cast<const float2*>(in),
+                     static_cast<float2*>(out), static_cast<const float*>(Ablk), static_cast<const float2*>(in2),
+                     (float)coef, static_cast<double4*>(part));
+  *nblk = nblocks;
+  return hipGetLastError();
+}
+
 // epi 0..2 on checkerboard fields (FP32 and FP64); the smoother's forms 3
 // (in2 full-lattice) and 4 (in2 full-lattice, added into a full-lattice out)
 // in FP32 only.
@@ -984,6 +1048,23 @@ hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* orde
   if (prec64) return launch_hop_eo_r<double, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
   if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
   return launch_hop_eo_r<float, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
+}
+
+// FP32 epi 2 with the minimal-residual partial sums (see hop_eo_kernel).
+// The partials of one launch: sized for one RHS per thread, which bounds
+// every nrhs' <= nrhs as well.
+size_t hop_eo_dot_scratch_bytes(int nhalf, int nrhs) {
+  const long nblocks = ((long)nhalf * nrhs + 255) / 256;
+  return (size_t)nblocks * nrhs * sizeof(double4);
+}
+
+hipError_t launch_hop_eo_dot(int nhalf, const int4* tab, const int* order, const void* U, const void* in, void* out,
+                             const void* Ablk, const void* in2, double coef, int nrhs, void* part, int* nblk,
+                             hipStream_t s) {
+  if (!tab || !order || !Ablk || !in2 || !part || !nblk || nrhs < 1 || nrhs > 256) return hipErrorInvalidValue;
+  if (nrhs % 2 == 0)
+    return launch_hop_eo_dot_r<2>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, part, nblk, s);
+  return launch_hop_eo_dot_r<1>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, part, nblk, s);
 }
 
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,

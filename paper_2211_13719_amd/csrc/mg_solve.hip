@@ -52,6 +52,11 @@ size_t solver_scratch_bytes(int nrhs);
 hipError_t launch_mr_alpha(const void* p, const void* r, long rows, int nrhs, void* alpha, void* scratch,
                            hipStream_t s);
 hipError_t launch_mr_update(void* x, void* r, const void* p, const void* alpha, long rows, int nrhs, hipStream_t s);
+hipError_t launch_mr_final(const void* part, int nblk, int nrhs, void* alpha, hipStream_t s);
+size_t hop_eo_dot_scratch_bytes(int nhalf, int nrhs);
+hipError_t launch_hop_eo_dot(int nhalf, const int4* tab, const int* order, const void* U, const void* in, void* out,
+                             const void* Ablk, const void* in2, double coef, int nrhs, void* part, int* nblk,
+                             hipStream_t s);
 hipError_t launch_multi_axpy(int x64, void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
                              int nrhs, hipStream_t s);
 hipError_t launch_scale_cols(int prec64, void* y, const void* x, const double* sdev, long rows, int nrhs,
@@ -87,7 +92,7 @@ struct SolverState {
   Buffer alpha, part, scl, coef, qn;
   Buffer gpart, gmat, gT;  // column Gram matrix (setup)
   // even-odd fine smoother: five checkerboard fields of eo_n columns
-  Buffer eo;
+  Buffer eo, eo_part;
   int eo_n = 0;
   // outer Krylov
   int m = 0, on = 0;
@@ -112,7 +117,7 @@ void mg_solver_release(mrhs_mg mg) {
     release(st->lp[l]);
   }
   Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->gpart, &st->gmat, &st->gT,
-                 &st->V64, &st->Z32, &st->w64, &st->r64, &st->eo};
+                 &st->V64, &st->Z32, &st->w64, &st->r64, &st->eo, &st->eo_part};
   for (Buffer* x : b) release(*x);
   for (auto& gs : st->graphs)
     if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
@@ -261,10 +266,12 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to, rho, n, s, 3, nullptr, r, k);
   if (e == hipSuccess) e = launch_zero(ee, hb, s);
   for (int i = 0; i < nu && e == hipSuccess; ++i) {
-    // q = Dhat rho: to2 = A_o^-1 (H_oe rho), q = A_e rho - kappa^2 (H_eo to2), fused launches
+    // q = Dhat rho: to2 = A_o^-1 (H_oe rho), q = A_e rho - kappa^2 (H_eo to2), fused launches;
+    // the second also sums <q, rho> and ||q||^2 per workgroup for the step length
+    int nblk = 0;
     e = launch_hop_eo(0, nh, tabo, ordo, U, rho, to2, n, s, 1, Ai);
-    if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to2, q, n, s, 2, A, rho, -k * k);
-    if (e == hipSuccess) e = launch_mr_alpha(q, rho, hrows, n, st->alpha.p, st->part.p, s);
+    if (e == hipSuccess) e = launch_hop_eo_dot(nh, tabe, orde, U, to2, q, A, rho, -k * k, n, st->eo_part.p, &nblk, s);
+    if (e == hipSuccess) e = launch_mr_final(st->eo_part.p, nblk, n, st->alpha.p, s);
     if (e == hipSuccess) e = launch_mr_update(ee, rho, q, st->alpha.p, hrows, n, s);
   }
   // x_o += A_o^-1 (r_o + kappa H_oe e_e) in one launch, x_e += e_e
@@ -406,7 +413,9 @@ mrhs_status prepare_eo(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
       gs = GraphSlot{};
     }
     release(st->eo);
+    release(st->eo_part);
     s = ensure(ctx, st->eo, (size_t)5 * (ctx->g.V / 2) * 12 * n * 8);
+    if (s == MRHS_OK) s = ensure(ctx, st->eo_part, hop_eo_dot_scratch_bytes(ctx->g.V / 2, n));
     if (s != MRHS_OK) return s;
     st->eo_n = n;
   }

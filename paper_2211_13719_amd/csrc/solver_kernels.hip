@@ -73,12 +73,21 @@ __global__ __launch_bounds__(kB) void mr_final(const double4* __restrict__ part,
   __shared__ double4 red[kB];
   const int k = blockIdx.x, t = threadIdx.x;
   double4 s = make_double4(0, 0, 0, 0);
-  for (int j = t; j < nblk; j += kB) {
-    const double4 v = part[(long)j * nrhs + k];
+  auto add = [&](const double4& v) {
     s.x += v.x;
     s.y += v.y;
     s.z += v.z;
+  };
+  // four loads in flight; the sum keeps the order j = t, t + kB, ...
+  int j = t;
+  for (; j + 3 * kB < nblk; j += 4 * kB) {
+    double4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[(long)(j + u * kB) * nrhs + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(v[u]);
   }
+  for (; j < nblk; j += kB) add(part[(long)j * nrhs + k]);
   red[t] = s;
   __syncthreads();
   for (int w = kB / 2; w > 0; w >>= 1) {
@@ -334,6 +343,12 @@ hipError_t launch_mr_alpha(const void* p, const void* r, long rows, int nrhs, vo
   hipLaunchKernelGGL(mr_partial, dim3(nb), dim3(kB), 0, s, static_cast<const float2*>(p),
                      static_cast<const float2*>(r), rows, nrhs, tpb, static_cast<double4*>(scratch));
   hipLaunchKernelGGL(mr_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double4*>(scratch), nb, nrhs,
+                     static_cast<double2*>(alpha));
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_final(const void* part, int nblk, int nrhs, void* alpha, hipStream_t s) {
+  hipLaunchKernelGGL(mr_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double4*>(part), nblk, nrhs,
                      static_cast<double2*>(alpha));
   return hipGetLastError();
 }
