@@ -393,6 +393,7 @@ mrhs_status mrhs_set_gauge(mrhs_ctx ctx, const void* U, mrhs_prec prec, int32_t 
   ctx->have_gauge = true;
   ctx->have_clover = false;  // a clover term built from old links is stale
   ctx->have_clover_inv = false;
+  ++ctx->op_gen;
   return MRHS_OK;
 }
 
@@ -415,6 +416,7 @@ mrhs_status mrhs_build_clover(mrhs_ctx ctx, double csw, double kappa) {
   ctx->kappa = kappa;
   ctx->have_clover = true;
   ctx->have_clover_inv = false;
+  ++ctx->op_gen;
   return MRHS_OK;
 }
 
@@ -430,6 +432,7 @@ mrhs_status mrhs_set_clover(mrhs_ctx ctx, const void* A, mrhs_prec prec, int32_t
   ctx->kappa = kappa;
   ctx->have_clover = true;
   ctx->have_clover_inv = false;
+  ++ctx->op_gen;
   return MRHS_OK;
 }
 

@@ -98,6 +98,10 @@ struct mrhs_ctx_s {
   bool have_gauge = false;
   bool have_clover = false;
   double kappa = 0.0;
+  // bumped whenever an operator of this context or of a hierarchy on it
+  // changes (links, clover, kappa, basis, coarse blocks): captured V-cycle
+  // graphs hold kappa by value and are replayed only while it is unchanged
+  uint64_t op_gen = 0;
 
   // workspaces: reduction partials, small per-RHS scalar arrays
   mrhs::Buffer work;

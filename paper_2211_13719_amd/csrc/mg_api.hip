@@ -267,6 +267,7 @@ mrhs_status mrhs_mg_set_basis(mrhs_mg mg, int32_t level, const void* vecs, mrhs_
   L.have_basis = true;
   // coarse levels built from an older basis are stale
   for (int l = level + 1; l < mg->nlevels; ++l) mg->lv[l].have_blocks = false;
+  ++ctx->op_gen;
   return MRHS_OK;
 }
 
@@ -308,6 +309,7 @@ mrhs_status mrhs_mg_block_orthonormalise(mrhs_mg mg, int32_t level) {
   MRHS_HIP(ctx, hipMemcpyAsync(&flag, mg->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   for (int l = level + 1; l < mg->nlevels; ++l) mg->lv[l].have_blocks = false;
+  ++ctx->op_gen;
   if (flag) return fail(ctx, MRHS_ERR_STATE, "basis of level %d is rank-deficient on some aggregate", level);
   return MRHS_OK;
 }
@@ -404,6 +406,7 @@ mrhs_status mrhs_coarse_set_blocks(mrhs_mg mg, int32_t level, const void* blocks
   st = refresh_blocks(mg, level);
   if (st != MRHS_OK) return st;
   MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ++ctx->op_gen;
   return MRHS_OK;
 }
 
@@ -475,6 +478,7 @@ mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level) {
   if (st != MRHS_OK) return st;
   for (int l = level + 1; l < mg->nlevels; ++l) mg->lv[l].have_blocks = false;
   MRHS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ++ctx->op_gen;
   return MRHS_OK;
 }
 

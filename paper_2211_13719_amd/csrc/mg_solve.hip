@@ -83,6 +83,7 @@ struct GraphSlot {
   int n = 0;
   void* out = nullptr;
   mrhs_vcycle_params vc{};
+  uint64_t gen = 0;  // the context's operator generation at capture
 };
 
 struct SolverState {
@@ -355,7 +356,8 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
   GraphSlot& gs = st->graphs[slot];
   const bool same = gs.exec && gs.n == n && gs.out == xout && gs.vc.nu_pre == vc.nu_pre &&
                     gs.vc.nu_post == vc.nu_post && gs.vc.coarsest_iters == vc.coarsest_iters &&
-                    gs.vc.coarse_prec == vc.coarse_prec && gs.vc.fine_eo == vc.fine_eo;
+                    gs.vc.coarse_prec == vc.coarse_prec && gs.vc.fine_eo == vc.fine_eo &&
+                    gs.gen == ctx->op_gen;
   if (!same) {
     if (gs.exec) {
       (void)hipGraphExecDestroy(gs.exec);
@@ -376,6 +378,7 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
     gs.n = n;
     gs.vc = vc;
     gs.out = xout;
+    gs.gen = ctx->op_gen;
   }
   SOLVER_HIP(hipGraphLaunch(gs.exec, st->stream));
   return MRHS_OK;

@@ -6,6 +6,9 @@ output is ~1e-7).  The FP32 kernel is also required to give bit-identical
 results for a column whether it is applied alone or inside a batch.
 """
 
+import os
+import shutil
+
 import numpy as np
 import pytest
 
@@ -142,28 +145,66 @@ def test_deterministic_repeat(small):
 
 # ---- config 2: 24^4, FP32, Nrhs in {1, 6, 12, 24, 48, 64} ---------------------------
 
+NRHS_BIG = (1, 6, 12, 24, 48, 64)
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2211_13719_amd",
+                          "tuning", "fine.txt")
+
+
+def _cached_lines(path, arch, dims):
+    """The autotuner cache's configuration per Nrhs for this lattice (the last
+    matching line wins, as in the library)."""
+    out = {}
+    for line in open(path):
+        f = line.split()
+        if len(f) != 17 or f[0] != arch or tuple(map(int, f[1:5])) != tuple(dims):
+            continue
+        n, R = int(f[5]), int(f[6])
+        tile = tuple(map(int, f[7:11]))
+        curve, occ, nt, chunks, cap = map(int, f[11:16])
+        variant = curve + 2 * (occ == 4) + 4 * nt + 8 * {1: 0, 2: 1, 4: 2}[chunks] + 32 * cap
+        out[n] = (R, tile, variant)
+    return out
+
+
 @pytest.fixture(scope="module")
-def big(gpu_lib):
+def big(gpu_lib, tmp_path_factory):
+    """Config 2 on the lattice the benchmark times, in the launch configurations
+    it times: the fine kernel's tuned configuration per Nrhs comes from the
+    committed autotuner cache (read from a copy, so that nothing is appended
+    to the committed file), exactly as bench.py loads it."""
+    import torch
+
     dims = (24, 24, 24, 24)
     U = synth.gauge_haar(dims, 2024)
     A = O.clover_packed_direct(U, dims, CSW, KAPPA)
     ctx = _ctx(gpu_lib, dims, U)
-    return dims, U, A, ctx
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    want = _cached_lines(TUNE_CACHE, arch, dims)
+    assert set(NRHS_BIG) <= set(want), "the committed tuning cache lacks a 24^4 Nrhs"
+    cache = tmp_path_factory.mktemp("tune") / "fine.txt"
+    shutil.copyfile(TUNE_CACHE, cache)
+    before = cache.read_text()
+    ctx.tune(list(NRHS_BIG), str(cache))
+    assert cache.read_text() == before, "a 24^4 configuration was tuned afresh instead of read from the cache"
+    return dims, U, A, ctx, want
 
 
 def test_clover_build_24(big):
-    dims, U, A, ctx = big
+    dims, U, A, ctx, _ = big
     assert np.max(np.abs(ctx.get_clover() - A)) < 1e-14
 
 
-@pytest.mark.parametrize("nrhs", [1, 6, 12, 24, 48, 64])
+@pytest.mark.parametrize("nrhs", NRHS_BIG)
 def test_fp32_24444_sampled(big, nrhs):
-    """Full-size apply in the benchmark's launch configuration, checked on a
+    """Full-size apply in the launch configuration the benchmark times (the
+    cached tuned configuration of this Nrhs, asserted first), checked on a
     sample of sites (all boundary-wrapping directions included) against the
     per-site oracle; N = 1 is also checked on every site."""
     import torch
 
-    dims, U, A, ctx = big
+    dims, U, A, ctx, want = big
+    R, tile, variant, _ = ctx.get_tuning(nrhs)
+    assert (R, tuple(tile), variant) == want[nrhs]
     psi = synth.spinor_source(dims, nrhs, 100, np.complex64)
     x = _dev(torch, psi)
     y = torch.empty_like(x)

@@ -8,6 +8,8 @@ operators is below 10, checked loosely as 1e-8).  Iteration counts, the
 setup and the smoother are not unique and are not compared.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -232,3 +234,142 @@ def test_even_odd_smoother_graph_replay_is_bitwise_equal(small):
     s2 = mg.solve(x2, b, use_graph=False, coarse_prec="bf16", fine_eo=True)
     assert s1["iters"] == s2["iters"]
     assert torch.equal(x1, x2)
+
+
+def _eo_smoother_ref(U, A, kappa, b, dims, nu):
+    """nu minimal-residual steps from zero on the even-odd Schur system
+    Dhat e_e = b_e + kappa H_eo A_o^-1 b_o, step alpha_k = <q_k, rho_k> /
+    ||q_k||^2 per right-hand side with q = Dhat rho, then the odd sites
+    e_o = A_o^-1 (b_o + kappa H_oe e_e); FP64 throughout, from the oracle's
+    even-odd pieces."""
+    from oracle import evenodd as E
+
+    b = np.asarray(b, dtype=np.complex128)
+    rho = E.schur_rhs(U, A, kappa, b, dims)
+    ee = np.zeros_like(rho)
+    for _ in range(nu):
+        q = E.schur_ee(U, A, kappa, rho, dims)
+        N = q.shape[-1]
+        num = np.einsum("sck,sck->k", q.conj(), rho)
+        den = np.einsum("sck,sck->k", q.conj(), q).real
+        alpha = (num / den).reshape(1, 1, N)
+        ee = ee + alpha * rho
+        rho = rho - alpha * q
+    Ainv = E.clover_inverse(A)
+    eo = E.clover_cb(Ainv, E.to_cb(b, dims, 1) + kappa * E.hop_eo(U, ee, dims, 1), dims, 1)
+    return E.from_cb(ee, eo, dims)
+
+
+@pytest.mark.parametrize("dims,block,nv,nrhs", [
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16, 1),
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16, 5),
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16, 12),
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16, 24),
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16, 64),
+    ((4, 6, 4, 6), (2, 2, 2, 2), 4, 12),
+    ((4, 6, 4, 6), (2, 2, 2, 2), 4, 3),
+])
+def test_even_odd_smoother_alone(gpu_lib, dims, block, nv, nrhs):
+    """The fine even-odd smoother by itself: with two levels, no pre-smoothing
+    and no coarsest-level steps the coarse correction is exactly zero, so the
+    V-cycle returns nu_post = 3 even-odd MR steps applied to v.  Its step
+    lengths come from the per-workgroup sums in the checkerboard hop's
+    epilogue; any slip in their column mapping (Nrhs not dividing 256, one
+    RHS per thread, a ragged last workgroup on the 4x6x4x6 lattice) changes
+    alpha and fails the comparison with the FP64 reference at the FP32 bar."""
+    import torch
+
+    U = synth.gauge_haar(dims, 4242)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx, mg = build(gpu_lib, dims, U, [block], [nv], setup_iters=1, smooth_steps=4)
+    v = synth.spinor_source(dims, nrhs, 9300, np.complex64)
+    z = torch.empty(v.shape, dtype=torch.complex64, device="cuda")
+    mg.precondition(z, dev(v), nu_pre=0, nu_post=3, coarsest_iters=0, coarse_prec="bf16", fine_eo=True)
+    want = _eo_smoother_ref(U, A, KAPPA, v, dims, 3)
+    got = z.cpu().numpy()
+    for k in range(nrhs):
+        err = np.linalg.norm(got[:, :, k] - want[:, :, k]) / np.linalg.norm(want[:, :, k])
+        assert err < 1e-5, (k, err)
+    mg.close()
+    ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_solve_24x24x24x128_bench_settings(gpu_lib, capsys, tmp_path):
+    """The solve workload the benchmark times (24^3 x 128 smooth links at the
+    tuned bare mass, three levels, BF16 coarse levels and intergrid, even-odd
+    fine smoother, graph-replayed V-cycle, the benchmark's set-up and V-cycle
+    parameters and its first two right-hand sides): every column's true
+    residual, recomputed by the FP64 oracle on the host, is at most 1e-10."""
+    import json
+    import shutil
+    import time
+
+    import torch
+
+    import bench
+
+    t0 = time.time()
+
+    def say(msg):
+        with capsys.disabled():
+            print(f"  [24^3x128 solve {time.time() - t0:5.0f} s] {msg}", flush=True)
+
+    dims = bench.SOLVE_DIMS
+    mass = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "smooth_links_mass.json")))
+    kappa = mass["kappa"]
+    say("generating links")
+    U = synth.gauge_smooth(dims, 5)
+    ctx = gpu_lib.Context(dims, t_bc=-1)
+    ctx.set_gauge(U)
+    ctx.build_clover(CSW, kappa)
+    cache = tmp_path / "fine.txt"
+    shutil.copyfile(bench.TUNE_CACHE, cache)
+    ctx.tune([2, 16], str(cache))
+    mg = gpu_lib.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
+    for l in range(2):
+        mg.set_basis(l, synth.gaussian_vectors(mg.volume[l], 16, mg.ncomp[l], 600 + l))
+    say("set-up")
+    mg.setup(**bench.SOLVE_SETUP, coarse_prec="bf16", **bench.SOLVE_VC)
+    b = synth.spinor_source(dims, 2, 4000)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    say("solve")
+    st = mg.solve(x, dev(b), tol=1e-10, restart=bench.SOLVE_RESTART, max_iters=bench.SOLVE_MAXIT,
+                  coarse_prec="bf16", use_graph=True, fine_eo=bench.SOLVE_MRHS_FINE_EO, **bench.SOLVE_VC)
+    assert all(st["converged"])
+    xs = x.cpu().numpy()
+    mg.close()
+    ctx.close()
+    del x
+    torch.cuda.empty_cache()
+    say(f"{st['iters']} outer steps; oracle clover and residual")
+    A = O.clover_packed(U, dims, CSW, kappa)
+    res = O.true_residual(U, A, kappa, xs, b, dims)
+    say(f"oracle true residual {res}")
+    assert np.all(res <= 1e-10), res
+
+
+def test_graph_recaptured_after_kappa_change(gpu_lib):
+    """A captured V-cycle holds kappa by value: after the clover term is rebuilt
+    with another kappa (same hierarchy, no new set-up) the graph-replayed solve
+    must still equal the eager one bit for bit and solve the new operator."""
+    import torch
+
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_haar(dims, 818)
+    ctx, mg = build(gpu_lib, dims, U, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
+    b = synth.spinor_source(dims, 3, 9400)
+    x0 = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    mg.solve(x0, dev(b), use_graph=True, coarse_prec="bf16", fine_eo=True)
+    kappa2 = 0.125
+    ctx.build_clover(CSW, kappa2)
+    x1 = torch.zeros_like(x0)
+    x2 = torch.zeros_like(x0)
+    s1 = mg.solve(x1, dev(b), use_graph=True, coarse_prec="bf16", fine_eo=True)
+    s2 = mg.solve(x2, dev(b), use_graph=False, coarse_prec="bf16", fine_eo=True)
+    assert s1["iters"] == s2["iters"]
+    assert torch.equal(x1, x2)
+    A2 = O.clover_packed(U, dims, CSW, kappa2)
+    assert np.all(O.true_residual(U, A2, kappa2, x1.cpu().numpy(), b, dims) <= 1e-10)
+    mg.close()
+    ctx.close()
