@@ -186,6 +186,20 @@ mrhs_status mrhs_norm2(mrhs_ctx ctx, double* out, const void* a, int64_t nsites,
  * w).  out: 2*m*nrhs doubles, host or device as for mrhs_dot. */
 mrhs_status mrhs_multi_dot(mrhs_ctx ctx, double* out, const void* const* v, int32_t m, const void* w,
                            int64_t nsites, int32_t ncomp, int32_t nrhs, mrhs_prec prec, int32_t out_on_device);
+/* mrhs_multi_dot_noalloc: mrhs_multi_dot for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, same kernels and bit-identical
+ * results, but no allocation of any kind.  Its partial sums (and, with
+ * out_on_device = 0, the staged result) live in a fixed device array of
+ * 16 MiB + 16 KiB per device, held until the process ends; its address is
+ * looked up when a context is first created on the device.  Limits: m <= 16
+ * and nrhs <= 64 (the array holds 1024 x m x nrhs partials at the maximum);
+ * larger requests get MRHS_ERR_SHAPE.  Every call on one device shares that
+ * array: calls that overlap in time on one device (other host threads or
+ * streams) race and must be serialised by the caller. */
+mrhs_status mrhs_multi_dot_noalloc(mrhs_ctx ctx, double* out, const void* const* v, int32_t m, const void* w,
+                                   int64_t nsites, int32_t ncomp, int32_t nrhs, mrhs_prec prec,
+                                   int32_t out_on_device);
 /* mrhs_axpy: y_k <- y_k + alpha_k x_k per column, alpha_k = alpha[2k] + i alpha[2k+1]
  * (FP64, host memory if alpha_on_device = 0, else device memory); the update
  * is computed in FP64 and rounded to prec.  x and y must not overlap. */

@@ -233,8 +233,10 @@ class Context:
         self._check(lib.mrhs_norm2(self._h, C.c_void_p(res.ctypes.data), C.c_void_p(pa), ns, nc, n, prec, 0))
         return res
 
-    def multi_dot(self, vs, w):
-        """(m, nrhs) complex128 array of <v_j,k, w_k>."""
+    def multi_dot(self, vs, w, out=None, noalloc=False):
+        """(m, nrhs) complex128 array of <v_j,k, w_k>; into the device tensor
+        `out` (complex128, (m, nrhs)) when given.  noalloc selects the entry
+        point that allocates nothing (fixed device scratch array)."""
         ns, nc, n = self._field_shape(w)
         m = len(vs)
         ptrs = (C.c_void_p * m)()
@@ -243,9 +245,15 @@ class Context:
                 raise ValueError("every v_j must match w")
             ptrs[j] = v.data_ptr()
         pw, prec, _ = _ptr_of(w)
+        fn = lib.mrhs_multi_dot_noalloc if noalloc else lib.mrhs_multi_dot
+        if out is not None:
+            if tuple(out.shape) != (m, n) or not out.is_cuda or not out.is_contiguous() or \
+                    out.dtype != _torch().complex128:
+                raise ValueError(f"out must be a contiguous complex128 device tensor of shape {(m, n)}")
+            self._check(fn(self._h, C.c_void_p(out.data_ptr()), ptrs, m, C.c_void_p(pw), ns, nc, n, prec, 1))
+            return out
         res = np.empty((m, n), dtype=np.complex128)
-        self._check(lib.mrhs_multi_dot(self._h, C.c_void_p(res.ctypes.data), ptrs, m, C.c_void_p(pw), ns, nc, n,
-                                       prec, 0))
+        self._check(fn(self._h, C.c_void_p(res.ctypes.data), ptrs, m, C.c_void_p(pw), ns, nc, n, prec, 0))
         return res
 
     def axpy(self, y, alpha, x):

@@ -333,6 +333,15 @@ mrhs_status mrhs_create(mrhs_ctx* out, const int32_t dims[4], int32_t t_bc, int3
       delete ctx;
       return MRHS_ERR_OOM;
     }
+    // device address of the fixed scratch array of the allocation-free calls
+    e = noalloc_scratch_init(device, nullptr);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e);
+      release(ctx->nbr);
+      for (auto& o : ctx->orders) release(o.second);
+      delete ctx;
+      return MRHS_ERR_HIP;
+    }
   }
   *out = ctx;
   return MRHS_OK;

@@ -215,6 +215,11 @@ hipError_t launch_coarse_valu(int prec64, const Geom& g, int nb, int nrhs, const
 hipError_t launch_block_transpose(const void* in, int in64, void* out, int out64, long nblk, int nb, hipStream_t s);
 hipError_t launch_basis_columns(int prec64, const void* basis, void* W, long nsite, int ncomp, int nv, hipStream_t s);
 
+// Device address of the fixed scratch array of the allocation-free entry
+// points on `device` (which must be current), looked up on first use per
+// device (noalloc.hip).
+hipError_t noalloc_scratch_init(int device, void** out);
+
 // Traversal table of the fine lattice for tile T (built and cached on first
 // use); null on failure.
 const int* fine_order_table(mrhs_ctx ctx, const int T[4], int curve = 0);
