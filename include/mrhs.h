@@ -293,15 +293,27 @@ mrhs_status mrhs_mg_build_coarse(mrhs_mg mg, int32_t level);
 mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 
 /* mrhs_mg_tune: for every coarse level with Nb = 32 and blocks set, and each
- * nrhs in nrhs_list (count entries), times the two FP32 stencil kernels (FP32
- * matrix cores, vector ALU) on the device and keeps the faster one for
+ * nrhs in nrhs_list (count entries), times on the device (a) the two FP32
+ * stencil kernels (FP32 matrix cores, vector ALU) and keeps the faster one for
  * mrhs_coarse_apply with MRHS_F32 and for V-cycles with FP32 coarse levels
- * (untuned: the matrix cores).  Synchronises; drops the solver's captured
- * V-cycles and work buffers, which the next solve rebuilds. */
+ * (untuned: the matrix cores), and (b) the launch shapes of the BF16/FP16
+ * matrix-core stencil (four or eight wavefronts per site, one or two
+ * 32-column tiles of right-hand sides per workgroup; untuned: four and one),
+ * used for BF16 and FP16 applies and V-cycles, and (c) on levels of at most
+ * 1024 sites the same shapes for the fused BF16 minimal-residual step of the
+ * coarsest-level solve.  Synchronises; drops the solver's captured V-cycles
+ * and work buffers, which the next solve rebuilds. */
 mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count);
 /* mrhs_mg_get_tuning: *f32_valu = 1 when level uses the vector-ALU FP32
- * stencil for nrhs (always for Nb != 32), 0 for the FP32 matrix cores. */
-mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu);
+ * stencil for nrhs (always for Nb != 32), 0 for the FP32 matrix cores;
+ * *lowp_cfg (if not NULL) = the BF16/FP16 stencil's launch shape, bit 0 eight
+ * wavefronts per site (else four), bit 1 two 32-column tiles per workgroup. */
+mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu, int32_t* lowp_cfg);
+/* mrhs_mg_set_lowp_cfg: sets the BF16/FP16 stencil's launch shape (and that
+ * of the fused MR step) for level and nrhs by hand (0..3, bits as in
+ * mrhs_mg_get_tuning), e.g. to restore a persisted tuning; every shape
+ * computes the same operator.  Captured V-cycles are recaptured. */
+mrhs_status mrhs_mg_set_lowp_cfg(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t cfg);
 
 /* Even-odd pieces of the coarse stencil, Sec. 6 (the coarse-level M_eooe):
  * on a level whose extents are all even, with the checkerboard layout of the
@@ -343,7 +355,11 @@ mrhs_status mrhs_coarse_self_eo_apply(mrhs_mg mg, int32_t level, void* out, cons
  * Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe (see mrhs_schur_apply): nu MR steps
  * on Dhat e_e = r_e + kappa H_eo A_o^-1 r_o from e_e = 0, then
  * e_o = A_o^-1 (r_o + kappa H_oe e_e) and x += e (then r = b - D x when the
- * residual is still needed, i.e. after the pre-smoothing pass). */
+ * residual is still needed, i.e. after the pre-smoothing pass).
+ * With coarse_eo the same elimination on a coarse level, D_c = [[S_e, H_eo],
+ * [H_oe, S_o]] with S the self blocks and H the eight hop directions: nu MR
+ * steps on (S_e - H_eo S_o^-1 H_oe) e_e = r_e - H_eo S_o^-1 r_o from e_e = 0,
+ * then e_o = S_o^-1 (r_o - H_oe e_e), x += e. */
 typedef struct {
   int32_t nu_pre;
   int32_t nu_post;
@@ -351,6 +367,11 @@ typedef struct {
   mrhs_prec coarse_prec;
   int32_t fine_eo; /* 1: the fine-level smoothing steps run on the even-odd
                       Schur complement (see below); 0: on D */
+  int32_t coarse_eo; /* 1: on every coarse level above the coarsest whose
+                        extents are all even (Nb = 32, BF16 coarse_prec) the
+                        smoothing steps run on the coarse Schur complement
+                        S_e - H_eo S_o^-1 H_oe (Sec. 6, the coarse M_eooe;
+                        see below); 0: on D_c */
 } mrhs_vcycle_params;
 
 typedef struct {
@@ -383,6 +404,16 @@ typedef struct {
  * [V][12][nrhs]).  Needs the bases and coarse operators of every level.
  * Synchronises. */
 mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrhs, const mrhs_vcycle_params* vc);
+/* mrhs_coarse_mr_solve: x ~ D_c^-1 b on coarse level `level` (>= 1) by
+ * `iters` minimal-residual steps from x = 0, alpha_k = <D r_k, r_k> /
+ * ||D r_k||^2 per right-hand side: the coarsest-level solve of the V-cycle
+ * (Sec. 6).  x, b: FP32 device fields [V_level][Nb][nrhs] (x is
+ * overwritten; b is read only).  prec: the stencil's arithmetic, MRHS_F32,
+ * MRHS_BF16 or MRHS_F16; with BF16 on a level of Nb = 32 and at most 1024
+ * sites every step is two launches (stencil fused with the previous step's
+ * update and the per-site inner products; the step length).  Synchronises. */
+mrhs_status mrhs_coarse_mr_solve(mrhs_mg mg, int32_t level, void* x, const void* b, int32_t nrhs, int32_t iters,
+                                 mrhs_prec prec);
 typedef struct {
   int32_t setup_iters;    /* smoothing sweeps per level, 0..100 */
   int32_t smooth_steps;   /* MR steps per sweep, 0..1000 */

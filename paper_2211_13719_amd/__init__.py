@@ -413,8 +413,29 @@ class Multigrid:
     def get_tuning(self, level: int, nrhs: int) -> str:
         """"valu" or "mfma": the FP32 stencil kernel level uses for nrhs."""
         v = C.c_int32()
-        self._check(lib.mrhs_mg_get_tuning(self._h, int(level), int(nrhs), C.byref(v)))
+        self._check(lib.mrhs_mg_get_tuning(self._h, int(level), int(nrhs), C.byref(v), None))
         return "valu" if v.value else "mfma"
+
+    def set_lowp_cfg(self, level: int, nrhs: int, cfg: int):
+        """Launch shape of the BF16/FP16 stencil on level for nrhs, by hand (0..3)."""
+        self._check(lib.mrhs_mg_set_lowp_cfg(self._h, int(level), int(nrhs), int(cfg)))
+
+    def coarse_mr_solve(self, level: int, x, b, iters: int, prec="bf16"):
+        """x ~ D_c^-1 b by `iters` MR steps from zero on coarse level `level`
+        (complex64 fields (V_level, Nb, N))."""
+        n, fprec = self._pair(x, b, level, level)
+        if fprec != F32:
+            raise TypeError("coarse MR works on complex64 fields")
+        self._check(lib.mrhs_coarse_mr_solve(self._h, int(level), C.c_void_p(x.data_ptr()), C.c_void_p(b.data_ptr()),
+                                             n, int(iters), _PREC_NAMES[prec]))
+        return x
+
+    def get_lowp_tuning(self, level: int, nrhs: int) -> dict:
+        """Launch shape of the BF16/FP16 stencil on level for nrhs."""
+        v, c = C.c_int32(), C.c_int32()
+        self._check(lib.mrhs_mg_get_tuning(self._h, int(level), int(nrhs), C.byref(v), C.byref(c)))
+        return {"waves_per_site": 8 if c.value & 1 else 4, "rhs_per_workgroup": 64 if c.value & 2 else 32,
+                "cfg": int(c.value)}
 
     def _half_pair(self, a, b, level):
         for t in (a, b):
@@ -448,11 +469,12 @@ class Multigrid:
 
     # -- solver ---------------------------------------------------------------------------
     @staticmethod
-    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16", fine_eo=False):
+    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16", fine_eo=False, coarse_eo=False):
         v = _lib.VcycleParams()
         v.nu_pre, v.nu_post, v.coarsest_iters = int(nu_pre), int(nu_post), int(coarsest_iters)
         v.coarse_prec = _PREC_NAMES[coarse_prec]
         v.fine_eo = int(bool(fine_eo))
+        v.coarse_eo = int(bool(coarse_eo))
         return v
 
     def setup(self, setup_iters: int = 3, smooth_steps: int = 8, adapt_iters: int = 0, **vc):

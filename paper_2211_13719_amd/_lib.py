@@ -66,7 +66,9 @@ SIGNATURES = {
     "mrhs_mg_build_coarse": (_i32, [_vp, _i32]),
     "mrhs_coarse_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32]),
     "mrhs_mg_tune": (_i32, [_vp, _vp, _i32]),
-    "mrhs_mg_get_tuning": (_i32, [_vp, _i32, _i32, _vp]),
+    "mrhs_mg_get_tuning": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "mrhs_mg_set_lowp_cfg": (_i32, [_vp, _i32, _i32, _i32]),
+    "mrhs_coarse_mr_solve": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32, _i32]),
     "mrhs_coarse_hop_eo_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32, _i32]),
     "mrhs_coarse_self_eo_apply": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _i32]),
     "mrhs_mg_precondition": (_i32, [_vp, _vp, _vp, _i32, _vp]),
@@ -79,7 +81,7 @@ SIGNATURES = {
 
 class VcycleParams(C.Structure):
     _fields_ = [("nu_pre", _i32), ("nu_post", _i32), ("coarsest_iters", _i32), ("coarse_prec", _i32),
-                ("fine_eo", _i32)]
+                ("fine_eo", _i32), ("coarse_eo", _i32)]
 
 
 class SetupParams(C.Structure):

@@ -121,6 +121,34 @@ __device__ __forceinline__ bool reduce_waves(f32x16& accR, f32x16& accI) {
   return true;
 }
 
+// Sum of the WV wavefronts' accumulators into wavefront 0 in a fixed order, a
+// halving tree through LDS (wavefront w + h is added into w for h = WV / 2,
+// WV / 4, ..., 1; for WV = 4 that is (0 + 2) + (1 + 3)).  Every thread of the
+// workgroup must call it.
+template <int WV>
+__device__ __forceinline__ void reduce_waves_t(f32x16& accR, f32x16& accI, float (*red)[64][32]) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int h = WV / 2; h >= 1; h >>= 1) {
+    if (wv >= h && wv < 2 * h) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        red[wv - h][l][r] = accR[r];
+        red[wv - h][l][16 + r] = accI[r];
+      }
+    }
+    __syncthreads();
+    if (wv < h) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[r] += red[wv][l][r];
+        accI[r] += red[wv][l][16 + r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Even-odd modes of the stencil kernels (all coarse extents even; a field on
 // one parity is [V/2][Nb][nrhs], entry i the site of that parity among 2i,
 // 2i + 1): EO = 1 applies the eight hop directions from parity 1 - p to p,
@@ -137,26 +165,34 @@ __device__ __forceinline__ int cb_site(const Geom& g, int i, int p) {
   return (sum & 1) == p ? s2 : s2 + 1;
 }
 
-template <bool F16, int EO>
-__global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
-                                                          const float2* __restrict__ in, float2* __restrict__ out,
-                                                          const float* __restrict__ scale, int nblocks, int parity,
-                                                          int bstride) {
+// Neighbour of site s (coordinates x) in direction d of the stencil
+// (self, +x, -x, +y, -y, +z, -z, +t, -t), periodic.
+__device__ __forceinline__ int stencil_nbr(const Geom& g, int s, const int (&x)[4], int d) {
+  if (d == 0) return s;
+  const int mu = (d - 1) >> 1;
+  const int c = x[mu] + (((d - 1) & 1) ? -1 : 1);
+  const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
+  return s + (cw - x[mu]) * g.stride[mu];
+}
+
+// The stencil's work on one site, split into units (d, kc) = (direction,
+// 16-wide slice of the contraction index): unit u = 2 d + kc.  Wavefront w of
+// WV takes units u0 + w, u0 + w + WV, ... (balanced: 18 units over four
+// wavefronts are 5, 5, 4, 4), each unit four v_mfma_f32_32x32x16 per
+// 32-column tile of the NT tiles the workgroup covers, so a block slice is
+// loaded once for all its right-hand sides.  A unit past the end is computed
+// on a valid unit with zero operands (straight-line loads, no branch).
+// fetch(row, e, t, d) returns the FP32 operand at row `row` (of the input
+// field of direction d), element offset e = j nrhs + column, for tile t.
+template <bool F16, int WV, int NT, class Fetch>
+__device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int EOmode, int nrhs, const uint4* Bp,
+                                              int bstride, const int (&colc)[NT], const bool (&colok)[NT],
+                                              const float (&sc)[NT], Fetch&& fetch, f32x16 (&accR)[NT],
+                                              f32x16 (&accI)[NT]) {
   using O = Op<F16>;
   using vec = typename O::vec;
-  const int l = threadIdx.x & 63;
-  const int ntiles = (nrhs + 31) >> 5;
-  const long w = xcd_block(nblocks);
-  const int nsite = EO ? g.V / 2 : g.V;
-  if (w >= (long)nsite * ntiles) return;  // whole workgroup
-  const int io = (int)(w / ntiles);  // output row
-  const int s = EO ? cb_site(g, io, parity) : io;
-  const int col = (int)(w % ntiles) * 32 + (l & 31);
-  const bool colok = col < nrhs;
-  const int colc = colok ? col : nrhs - 1;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int jh = 8 * (l >> 5);
-  const float sc = (F16 && colok) ? scale[col] : 1.0f;
-
   int x[4];
   {
     int r = s;
@@ -167,59 +203,276 @@ __global__ __launch_bounds__(256) void coarse_mfma_kernel(Geom g, int nrhs, cons
     x[2] = r % g.L[2];
     x[3] = r / g.L[2];
   }
-  f32x16 accR = {}, accI = {};
-  const int d0 = EO == 1 ? 1 : 0, d1 = EO == 2 ? 1 : 9;
-  for (int d = d0 + (threadIdx.x >> 6); d < d1; d += 4) {
-    int nbr = s;
-    if (d > 0) {
-      const int mu = (d - 1) >> 1;
-      const int c = x[mu] + (((d - 1) & 1) ? -1 : 1);
-      const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
-      nbr = s + (cw - x[mu]) * g.stride[mu];
-    }
-    const int ii = EO == 1 ? nbr / 2 : (EO == 2 ? io : nbr);  // input row
+  const int u0 = EOmode == 1 ? 2 : 0, u1 = EOmode == 2 ? 2 : 18;
+  constexpr int KMAX = (18 + WV - 1) / WV;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int u = u0 + wv + k * WV;
+    const bool live = u < u1;
+    const int uc = live ? u : u0;
+    const int d = uc >> 1, kc = uc & 1;
+    const int nbr = stencil_nbr(g, s, x, d);
+    // input row: EO 1 the neighbour's checkerboard index, EO 2 the output row,
+    // EO 3 both (self term on the output row, hops on the neighbours')
+    const int ii = EOmode == 1 ? nbr / 2 : (EOmode == 2 ? io : (EOmode == 3 ? (d == 0 ? io : nbr / 2) : nbr));
     const uint4* bp = Bp + ((size_t)s * bstride + d) * 256;
-    // every load of the direction first, from a clamped column (no branch
-    // around the loads); columns past nrhs are zeroed and never stored
-    const float2* e = in + (size_t)ii * kNb * nrhs + colc;
-    uint4 bl[4];
-    float2 ev[2][8];
+    const uint4 br = bp[(kc * 2 + 0) * 64 + l];
+    const uint4 bi = bp[(kc * 2 + 1) * 64 + l];
+    float2 ev[NT][8];
 #pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      bl[2 * kc] = bp[(kc * 2 + 0) * 64 + l];
-      bl[2 * kc + 1] = bp[(kc * 2 + 1) * 64 + l];
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) ev[kc][q] = e[(size_t)(kc * 16 + jh + q) * nrhs];
-    }
+      for (int q = 0; q < 8; ++q) ev[t][q] = fetch(ii, (size_t)(kc * 16 + jh + q) * nrhs + colc[t], t, d);
+    const uint4 nbi = make_uint4(bi.x ^ 0x80008000u, bi.y ^ 0x80008000u, bi.z ^ 0x80008000u, bi.w ^ 0x80008000u);
+    const vec ar = __builtin_bit_cast(vec, br);
+    const vec ai = __builtin_bit_cast(vec, bi);
+    const vec an = __builtin_bit_cast(vec, nbi);
 #pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      const uint4 br = bl[2 * kc];
-      const uint4 bi = bl[2 * kc + 1];
+    for (int t = 0; t < NT; ++t) {
       float er[8], ei[8];
+      const bool on = live && colok[t];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        er[q] = colok ? ev[kc][q].x * sc : 0.f;
-        ei[q] = colok ? ev[kc][q].y * sc : 0.f;
+        er[q] = on ? ev[t][q].x * sc[t] : 0.f;
+        ei[q] = on ? ev[t][q].y * sc[t] : 0.f;
       }
       const vec vr = O::cvt(er), vi = O::cvt(ei);
-      const uint4 nbi = make_uint4(bi.x ^ 0x80008000u, bi.y ^ 0x80008000u, bi.z ^ 0x80008000u, bi.w ^ 0x80008000u);
-      const vec ar = __builtin_bit_cast(vec, br);
-      const vec ai = __builtin_bit_cast(vec, bi);
-      const vec an = __builtin_bit_cast(vec, nbi);
-      accR = O::mma(ar, vr, accR);
-      accR = O::mma(an, vi, accR);
-      accI = O::mma(ar, vi, accI);
-      accI = O::mma(ai, vr, accI);
+      accR[t] = O::mma(ar, vr, accR[t]);
+      accR[t] = O::mma(an, vi, accR[t]);
+      accI[t] = O::mma(ar, vi, accI[t]);
+      accI[t] = O::mma(ai, vr, accI[t]);
     }
   }
-  if (!reduce_waves(accR, accI) || !colok) return;
-  const float inv = F16 ? 1.0f / sc : 1.0f;  // exact: sc is a power of two
-  float2* o = out + (size_t)io * kNb * nrhs + col;
+}
+
+// One workgroup of WV wavefronts per (output site, group of NT 32-column
+// tiles of right-hand sides).
+// EO = 3 (the coarse Schur complement's outer product, all extents even):
+// out = S_p in - H_{p,1-p} in2 on parity p, in on parity p, in2 on 1 - p.
+template <bool F16, int EO, int WV, int NT>
+__global__ __launch_bounds__(64 * WV) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
+                                                              const float2* __restrict__ in, float2* __restrict__ out,
+                                                              const float* __restrict__ scale, int nblocks,
+                                                              int parity, int bstride,
+                                                              const float2* __restrict__ in2 = nullptr) {
+  __shared__ float red[WV / 2][64][32];
+  const int l = threadIdx.x & 63;
+  const int ngroups = (nrhs + 32 * NT - 1) / (32 * NT);
+  const long w = xcd_block(nblocks);
+  const int nsite = EO ? g.V / 2 : g.V;
+  if (w >= (long)nsite * ngroups) return;  // whole workgroup
+  const int io = (int)(w / ngroups);  // output row
+  const int s = EO ? cb_site(g, io, parity) : io;
+  const int c0 = (int)(w % ngroups) * 32 * NT;
+  int col[NT], colc[NT];
+  bool colok[NT];
+  float sc[NT];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-    o[(size_t)row * nrhs] = make_float2(accR[r] * inv, accI[r] * inv);
+  for (int t = 0; t < NT; ++t) {
+    col[t] = c0 + 32 * t + (l & 31);
+    colok[t] = col[t] < nrhs;
+    colc[t] = colok[t] ? col[t] : nrhs - 1;
+    sc[t] = (F16 && colok[t]) ? scale[col[t]] : 1.0f;
   }
+  f32x16 accR[NT], accI[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    accR[t] = f32x16{};
+    accI[t] = f32x16{};
+  }
+  stencil_units<F16, WV, NT>(g, s, io, EO, nrhs, Bp, bstride, colc, colok, sc,
+                             [&](int ii, size_t e, int, int d) {
+                               if (EO == 3 && d > 0) {  // minus the hop term, read from the second field
+                                 const float2 v = in2[(size_t)ii * kNb * nrhs + e];
+                                 return make_float2(-v.x, -v.y);
+                               }
+                               return in[(size_t)ii * kNb * nrhs + e];
+                             },
+                             accR, accI);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) reduce_waves_t<WV>(accR[t], accI[t], red);
+  if ((threadIdx.x >> 6) != 0) return;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (!colok[t]) continue;
+    const float inv = F16 ? 1.0f / sc[t] : 1.0f;  // exact: sc is a power of two
+    float2* o = out + (size_t)io * kNb * nrhs + col[t];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+      o[(size_t)row * nrhs] = make_float2(accR[t][r] * inv, accI[t][r] * inv);
+    }
+  }
+}
+
+// r_k - a_k p_k in FP32 with the rounding of the separate MR update kernel
+// (a_k rounded to FP32 first).
+__device__ __forceinline__ float2 mr_residual(float2 rv, float2 pv, float ar, float ai) {
+  float2 rn;
+  rn.x = fmaf(-ar, pv.x, fmaf(ai, pv.y, rv.x));
+  rn.y = fmaf(-ar, pv.y, fmaf(-ai, pv.x, rv.y));
+  return rn;
+}
+
+// One minimal-residual step on a coarse level with BF16 operands in two
+// launches (paper Sec. 6: the coarsest level is latency-bound, so a step
+// should be as few kernels as possible, not a stencil, two reductions and an
+// update):
+//   r_i = r_{i-1} - a_{i-1} p_{i-1}   recomputed on the fly wherever the
+//                                     stencil reads it, stored for the own site
+//   x_i = x_{i-1} + a_{i-1} r_{i-1}   own site, in place
+//   p_i = D r_i                       stored
+//   per (site, column): <p_i, r_i> and ||p_i||^2 over the site's Nb rows (FP64),
+//   which a second small launch (mr_site_alpha_kernel) sums over the sites in
+//   a fixed order into a_i = <p_i, r_i> / ||p_i||^2 per column.
+// first: step 0, r_0 = rold as given, x untouched.  Fields [V][Nb][nrhs] FP32;
+// rold / pold and rnew / pnew are different buffers (ping-pong across steps).
+template <int WV, int NT>
+__global__ __launch_bounds__(64 * WV) void coarse_mr_step_kernel(
+    Geom g, int nrhs, const uint4* __restrict__ Bp, const float2* __restrict__ rold, const float2* __restrict__ pold,
+    float2* __restrict__ rnew, float2* __restrict__ pnew, float2* __restrict__ x, const double2* __restrict__ aold,
+    double4* __restrict__ part, int nblocks, int first) {
+  __shared__ float red[WV / 2][64][32];
+  __shared__ double4 dred[64];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ngroups = (nrhs + 32 * NT - 1) / (32 * NT);
+  const long w = xcd_block(nblocks);
+  const long nwork = (long)g.V * ngroups;
+  if (w >= nwork) return;  // whole workgroup
+  const int s = (int)(w / ngroups);
+  const int c0 = (int)(w % ngroups) * 32 * NT;
+  int col[NT], colc[NT];
+  bool colok[NT];
+  float sc[NT], ar[NT], ai[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    col[t] = c0 + 32 * t + (l & 31);
+    colok[t] = col[t] < nrhs;
+    colc[t] = colok[t] ? col[t] : nrhs - 1;
+    sc[t] = 1.0f;
+    const double2 a = first ? make_double2(0.0, 0.0) : aold[colc[t]];
+    ar[t] = (float)a.x;
+    ai[t] = (float)a.y;
+  }
+  f32x16 accR[NT], accI[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    accR[t] = f32x16{};
+    accI[t] = f32x16{};
+  }
+  stencil_units<false, WV, NT>(g, s, s, 0, nrhs, Bp, 9, colc, colok, sc,
+                               [&](int ii, size_t e, int t, int) {
+                                 const size_t o = (size_t)ii * kNb * nrhs + e;
+                                 const float2 rv = rold[o];
+                                 if (first) return rv;
+                                 return mr_residual(rv, pold[o], ar[t], ai[t]);
+                               },
+                               accR, accI);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) reduce_waves_t<WV>(accR[t], accI[t], red);
+  // epilogue on wavefront 0: own-site r_i, x_i, p_i and the partial sums
+  double4 sum[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) sum[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (wv == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (!colok[t]) continue;
+      const size_t base = (size_t)s * kNb * nrhs + col[t];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+        const size_t o = base + (size_t)row * nrhs;
+        const float2 rv = rold[o];
+        float2 ri = rv;
+        if (!first) {
+          ri = mr_residual(rv, pold[o], ar[t], ai[t]);
+          float2 xv = x[o];
+          xv.x = fmaf(ar[t], rv.x, fmaf(-ai[t], rv.y, xv.x));
+          xv.y = fmaf(ar[t], rv.y, fmaf(ai[t], rv.x, xv.y));
+          x[o] = xv;
+          rnew[o] = ri;
+        }
+        const float2 p = make_float2(accR[t][r], accI[t][r]);
+        pnew[o] = p;
+        const double px = p.x, py = p.y, rx = ri.x, ry = ri.y;
+        sum[t].x = fma(px, rx, fma(py, ry, sum[t].x));
+        sum[t].y = fma(px, ry, fma(-py, rx, sum[t].y));
+        sum[t].z = fma(px, px, fma(py, py, sum[t].z));
+      }
+    }
+  }
+  // lanes l and l + 32 of wavefront 0 hold the two row halves of a column
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (wv == 0 && l >= 32) dred[l - 32] = sum[t];
+    __syncthreads();
+    if (wv == 0 && l < 32 && colok[t]) {
+      const double4 o = dred[l];
+      part[(size_t)s * nrhs + col[t]] =
+          make_double4(sum[t].x + o.x, sum[t].y + o.y, sum[t].z + o.z, 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+// Step length of the fused MR step: one workgroup per column sums the
+// per-site partials in a fixed order (strided by thread, then a tree) and
+// writes a = <p, r> / ||p||^2.
+__global__ __launch_bounds__(256) void mr_site_alpha_kernel(const double4* __restrict__ part, int nsite, int nrhs,
+                                                            double2* __restrict__ anew) {
+  __shared__ double4 red[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+  int site = t;
+  for (; site + 3 * 256 < nsite; site += 4 * 256) {
+    double4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(site + u * 256) * nrhs + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc.x += v[u].x;
+      acc.y += v[u].y;
+      acc.z += v[u].z;
+    }
+  }
+  for (; site < nsite; site += 256) {
+    const double4 v = part[(size_t)site * nrhs + k];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      red[t].x += red[t + w].x;
+      red[t].y += red[t + w].y;
+      red[t].z += red[t + w].z;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double4 a = red[0];
+    anew[k] = a.z > 0.0 ? make_double2(a.x / a.z, a.y / a.z) : make_double2(0.0, 0.0);
+  }
+}
+
+// After the last fused step: x += a r and, if rout is given, rout = r - a p
+// (FP32, the separate update kernel's rounding).  rout may be r itself.
+__global__ __launch_bounds__(256) void mr_finish_kernel(float2* __restrict__ x, const float2* r,
+                                                        const float2* __restrict__ p, float2* rout,
+                                                        const double2* __restrict__ alpha, long n, int nrhs) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const double2 a = alpha[e % nrhs];
+  const float ar = (float)a.x, ai = (float)a.y;
+  const float2 rv = r[e];
+  float2 xv = x[e];
+  xv.x = fmaf(ar, rv.x, fmaf(-ai, rv.y, xv.x));
+  xv.y = fmaf(ar, rv.y, fmaf(ai, rv.x, xv.y));
+  x[e] = xv;
+  if (rout) rout[e] = mr_residual(rv, p[e], ar, ai);
 }
 
 // FP32 operands on v_mfma_f32_32x32x2_f32 (full-rate FP32 matrix cores):
@@ -417,19 +670,79 @@ hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, 
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
-                              const float* scale, hipStream_t s) {
-  if (nb != kNb) return hipErrorInvalidValue;
-  const int blocks = (int)((long)g.V * ((nrhs + 31) / 32));  // one workgroup per (site, 32-column tile)
+namespace {
+
+template <bool F16, int WV, int NT>
+hipError_t launch_stencil_t(const Geom& g, int nrhs, const void* packed, const void* in, void* out, const float* scale,
+                            hipStream_t s) {
+  const int blocks = (int)((long)g.V * ((nrhs + 32 * NT - 1) / (32 * NT)));
   const int grid = ((blocks + 7) / 8) * 8;
-  if (f16)
-    hipLaunchKernelGGL((coarse_mfma_kernel<true, 0>), dim3(grid), dim3(256), 0, s, g, nrhs,
-                       static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
-                       scale, blocks, 0, 9);
-  else
-    hipLaunchKernelGGL((coarse_mfma_kernel<false, 0>), dim3(grid), dim3(256), 0, s, g, nrhs,
-                       static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
-                       scale, blocks, 0, 9);
+  hipLaunchKernelGGL((coarse_mfma_kernel<F16, 0, WV, NT>), dim3(grid), dim3(64 * WV), 0, s, g, nrhs,
+                     static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
+                     scale, blocks, 0, 9, nullptr);
+  return hipGetLastError();
+}
+
+template <int WV, int NT>
+hipError_t launch_mr_t(const Geom& g, int nrhs, const void* packed, const void* rold, const void* pold, void* rnew,
+                       void* pnew, void* x, const void* aold, void* anew, void* part, int first, hipStream_t s) {
+  const int blocks = (int)((long)g.V * ((nrhs + 32 * NT - 1) / (32 * NT)));
+  const int grid = ((blocks + 7) / 8) * 8;
+  hipLaunchKernelGGL((coarse_mr_step_kernel<WV, NT>), dim3(grid), dim3(64 * WV), 0, s, g, nrhs,
+                     static_cast<const uint4*>(packed), static_cast<const float2*>(rold),
+                     static_cast<const float2*>(pold), static_cast<float2*>(rnew), static_cast<float2*>(pnew),
+                     static_cast<float2*>(x), static_cast<const double2*>(aold), static_cast<double4*>(part), blocks,
+                     first);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mr_site_alpha_kernel, dim3(nrhs), dim3(256), 0, s, static_cast<const double4*>(part), g.V, nrhs,
+                     static_cast<double2*>(anew));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// cfg: launch shape of the BF16/FP16 stencil, bit 0 eight wavefronts per
+// workgroup (else four), bit 1 two 32-column tiles per workgroup (else one).
+hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
+                              const float* scale, hipStream_t s, int cfg) {
+  if (nb != kNb || cfg < 0 || cfg > 3) return hipErrorInvalidValue;
+  if (f16) {
+    switch (cfg) {
+      case 0: return launch_stencil_t<true, 4, 1>(g, nrhs, packed, in, out, scale, s);
+      case 1: return launch_stencil_t<true, 8, 1>(g, nrhs, packed, in, out, scale, s);
+      case 2: return launch_stencil_t<true, 4, 2>(g, nrhs, packed, in, out, scale, s);
+      default: return launch_stencil_t<true, 8, 2>(g, nrhs, packed, in, out, scale, s);
+    }
+  }
+  switch (cfg) {
+    case 0: return launch_stencil_t<false, 4, 1>(g, nrhs, packed, in, out, scale, s);
+    case 1: return launch_stencil_t<false, 8, 1>(g, nrhs, packed, in, out, scale, s);
+    case 2: return launch_stencil_t<false, 4, 2>(g, nrhs, packed, in, out, scale, s);
+    default: return launch_stencil_t<false, 8, 2>(g, nrhs, packed, in, out, scale, s);
+  }
+}
+
+size_t coarse_mr_part_bytes(long nsite) { return (size_t)nsite * MRHS_MAX_NRHS * sizeof(double4); }
+
+hipError_t launch_coarse_mr_step(const Geom& g, int nb, int nrhs, const void* packed, const void* rold, const void* pold,
+                                 void* rnew, void* pnew, void* x, const void* aold, void* anew, void* part, int first,
+                                 int cfg, hipStream_t s) {
+  if (nb != kNb || cfg < 0 || cfg > 3 || nrhs < 1 || nrhs > MRHS_MAX_NRHS) return hipErrorInvalidValue;
+  switch (cfg) {
+    case 0: return launch_mr_t<4, 1>(g, nrhs, packed, rold, pold, rnew, pnew, x, aold, anew, part, first, s);
+    case 1: return launch_mr_t<8, 1>(g, nrhs, packed, rold, pold, rnew, pnew, x, aold, anew, part, first, s);
+    case 2: return launch_mr_t<4, 2>(g, nrhs, packed, rold, pold, rnew, pnew, x, aold, anew, part, first, s);
+    default: return launch_mr_t<8, 2>(g, nrhs, packed, rold, pold, rnew, pnew, x, aold, anew, part, first, s);
+  }
+}
+
+hipError_t launch_mr_finish(void* x, const void* r, const void* p, void* rout, const void* alpha, long rows, int nrhs,
+                            hipStream_t s) {
+  const long n = rows * nrhs;
+  hipLaunchKernelGGL(mr_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, static_cast<float2*>(x),
+                     static_cast<const float2*>(r), static_cast<const float2*>(p), static_cast<float2*>(rout),
+                     static_cast<const double2*>(alpha), n, nrhs);
   return hipGetLastError();
 }
 
@@ -456,18 +769,62 @@ hipError_t launch_coarse_mfma_eo(int prec, int eo, int parity, const Geom& g, in
   } else {
     const auto* b = static_cast<const uint4*>(packed);
     if (prec == 2 && eo == 1)
-      hipLaunchKernelGGL((coarse_mfma_kernel<true, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
-                         parity, bstride);
+      hipLaunchKernelGGL((coarse_mfma_kernel<true, 1, 4, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride, nullptr);
     else if (prec == 2)
-      hipLaunchKernelGGL((coarse_mfma_kernel<true, 2>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
-                         parity, bstride);
+      hipLaunchKernelGGL((coarse_mfma_kernel<true, 2, 4, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride, nullptr);
     else if (eo == 1)
-      hipLaunchKernelGGL((coarse_mfma_kernel<false, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
-                         parity, bstride);
+      hipLaunchKernelGGL((coarse_mfma_kernel<false, 1, 4, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride, nullptr);
     else
-      hipLaunchKernelGGL((coarse_mfma_kernel<false, 2>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
-                         parity, bstride);
+      hipLaunchKernelGGL((coarse_mfma_kernel<false, 2, 4, 1>), grid, dim3(256), 0, s, g, nrhs, b, x, y, scale, blocks,
+                         parity, bstride, nullptr);
   }
+  return hipGetLastError();
+}
+
+// The coarse Schur complement's outer product on parity p with BF16 operands:
+// out = S_p in - H_{p,1-p} in2 (in, out on parity p; in2 on 1 - p).
+hipError_t launch_coarse_schur(int parity, const Geom& g, int nb, int nrhs, const void* packed, const void* in,
+                               const void* in2, void* out, hipStream_t s) {
+  if (nb != kNb || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
+  for (int m = 0; m < 4; ++m)
+    if (g.L[m] % 2) return hipErrorInvalidValue;
+  const int blocks = (int)((long)(g.V / 2) * ((nrhs + 31) / 32));
+  hipLaunchKernelGGL((coarse_mfma_kernel<false, 3, 4, 1>), dim3((unsigned)(((blocks + 7) / 8) * 8)), dim3(256), 0, s,
+                     g, nrhs, static_cast<const uint4*>(packed), static_cast<const float2*>(in),
+                     static_cast<float2*>(out), nullptr, blocks, parity, 9, static_cast<const float2*>(in2));
+  return hipGetLastError();
+}
+
+// Rows of one parity between a full coarse field [V][Nb][nrhs] and a
+// checkerboard one [V/2][Nb][nrhs] (entry i: the site of that parity among
+// 2i, 2i + 1): half = full rows (gather), or full rows += half (scatter_add).
+__global__ __launch_bounds__(256) void cb_rows_kernel(const Geom g, int parity, long rowlen, const float2* __restrict__ src,
+                                                      float2* __restrict__ dst, int scatter_add) {
+  const int i = blockIdx.y;
+  const int s = cb_site(g, i, parity);
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < rowlen; e += (long)gridDim.x * 256) {
+    if (scatter_add) {
+      float2 v = dst[(size_t)s * rowlen + e];
+      const float2 h = src[(size_t)i * rowlen + e];
+      v.x += h.x;
+      v.y += h.y;
+      dst[(size_t)s * rowlen + e] = v;
+    } else {
+      dst[(size_t)i * rowlen + e] = src[(size_t)s * rowlen + e];
+    }
+  }
+}
+
+hipError_t launch_coarse_cb_rows(int parity, const Geom& g, int nb, int nrhs, const void* src, void* dst, int scatter_add,
+                                 hipStream_t s) {
+  if (g.V / 2 > 65535) return hipErrorInvalidValue;
+  const long rowlen = (long)nb * nrhs;
+  const dim3 grid((unsigned)((rowlen + 255) / 256), (unsigned)(g.V / 2));
+  hipLaunchKernelGGL(cb_rows_kernel, grid, dim3(256), 0, s, g, parity, rowlen, static_cast<const float2*>(src),
+                     static_cast<float2*>(dst), scatter_add);
   return hipGetLastError();
 }
 

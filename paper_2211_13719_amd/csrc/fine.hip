@@ -1029,8 +1029,11 @@ hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, cons
 }
 
 hipError_t launch_fine_f64_in32(const Geom& g, double kappa, const void* U, const void* A, const void* in, void* out,
-                                int nrhs, hipStream_t s) {
-  return launch_r<double, 1, 0, 0, float2>(g, g.order, kappa, U, A, in, out, nrhs, s);
+                                int nrhs, hipStream_t s, const FineCfg* cfg) {
+  // the traversal order (tile) the autotuner chose for the FP32 kernel at
+  // this Nrhs, one RHS per thread
+  const bool tuned = cfg && cfg->R > 0 && cfg->order;
+  return launch_r<double, 1, 0, 0, float2>(g, tuned ? cfg->order : g.order, kappa, U, A, in, out, nrhs, s);
 }
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,

@@ -156,7 +156,7 @@ hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, cons
                            const void* A, const void* in, void* out, int nrhs, hipStream_t s);
 // D = A - kappa H in FP64 on an FP32 input field (widened exactly on load)
 hipError_t launch_fine_f64_in32(const Geom& g, double kappa, const void* U, const void* A, const void* in, void* out,
-                                int nrhs, hipStream_t s);
+                                int nrhs, hipStream_t s, const FineCfg* cfg = nullptr);
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,
                                void* out, int nrhs, const DirFilter& f, hipStream_t s);

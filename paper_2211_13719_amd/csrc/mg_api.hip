@@ -521,7 +521,7 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
         scale = sc;
       }
       e = launch_coarse_mfma(prec == MRHS_F16, L.g, L.ncomp, nrhs, prec == MRHS_F16 ? L.Bf16.p : L.Bbf16.p, in, out,
-                             scale, ctx->stream);
+                             scale, ctx->stream, L.lowp_cfg[nrhs]);
       break;
     }
     default:
@@ -627,6 +627,86 @@ mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count) {
         }
       }
       L.f32_valu[n] = (signed char)(e == hipSuccess && best[1] < best[0]);
+      // launch shape of the BF16 / FP16 stencil: four or eight wavefronts per
+      // site, one or two 32-column tiles per workgroup (timed in BF16; the
+      // FP16 kernel has the same structure)
+      float lbest = 1e30f;
+      int lcfg = 0;
+      for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+        if ((c & 2) && n <= 32) continue;  // a second tile would be empty
+        std::vector<float> t;
+        for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, ctx->stream);
+          if (e == hipSuccess)
+            e = launch_coarse_mfma(0, L.g, L.ncomp, n, L.Bbf16.p, mg->tmpA.p, mg->tmpB.p, nullptr, ctx->stream, c);
+          if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) t.push_back(ms);
+        }
+        if (e == hipSuccess) {
+          std::sort(t.begin(), t.end());
+          if (t[t.size() / 2] < lbest) {
+            lbest = t[t.size() / 2];
+            lcfg = c;
+          }
+        }
+      }
+      L.lowp_cfg[n] = (signed char)lcfg;
+      // launch shape of the fused MR step on small levels (timed on a step
+      // that is not the first, i.e. with the on-the-fly update)
+      if (L.g.V <= kFusedMrMaxSites && e == hipSuccess) {
+        const size_t fb = (size_t)L.g.V * L.ncomp * n * 8;
+        Buffer x, r2, p2, part, al;
+        mrhs_status s2 = ensure(ctx, x, fb);
+        if (s2 == MRHS_OK) s2 = ensure(ctx, r2, fb);
+        if (s2 == MRHS_OK) s2 = ensure(ctx, p2, fb);
+        if (s2 == MRHS_OK) s2 = ensure(ctx, part, coarse_mr_part_bytes(L.g.V));
+        if (s2 == MRHS_OK) s2 = ensure(ctx, al, 2 * MRHS_MAX_NRHS * 16);
+        if (s2 == MRHS_OK) {
+          e = hipMemsetAsync(x.p, 0, fb, ctx->stream);
+          if (e == hipSuccess) e = hipMemsetAsync(al.p, 0, 2 * MRHS_MAX_NRHS * 16, ctx->stream);
+          if (e == hipSuccess) e = hipMemsetAsync(p2.p, 0, fb, ctx->stream);
+          float mbest = 1e30f;
+          int mcfg = 0;
+          char* a = static_cast<char*>(al.p);
+          for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+            if ((c & 2) && n <= 32) continue;
+            std::vector<float> t;
+            for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+              e = hipEventRecord(e0, ctx->stream);
+              if (e == hipSuccess)
+                e = launch_coarse_mr_step(L.g, L.ncomp, n, L.Bbf16.p, mg->tmpA.p, p2.p, r2.p, mg->tmpB.p, x.p, a,
+                                          a + MRHS_MAX_NRHS * 16, part.p, 0, c, ctx->stream);
+              if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+              if (e == hipSuccess) e = hipEventSynchronize(e1);
+              float ms = 0.f;
+              if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+              if (rep > 0) t.push_back(ms);
+            }
+            if (e == hipSuccess) {
+              std::sort(t.begin(), t.end());
+              if (t[t.size() / 2] < mbest) {
+                mbest = t[t.size() / 2];
+                mcfg = c;
+              }
+            }
+          }
+          L.mr_cfg[n] = (signed char)mcfg;
+        }
+        (void)hipStreamSynchronize(ctx->stream);
+        release(x);
+        release(r2);
+        release(p2);
+        release(part);
+        release(al);
+        if (s2 != MRHS_OK) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return s2;
+        }
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -636,7 +716,7 @@ mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count) {
   return MRHS_OK;
 }
 
-mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu) {
+mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu, int32_t* lowp_cfg) {
   if (!mg) return MRHS_ERR_INVALID_ARG;
   mrhs_status st = check_level(mg, level, 1, MRHS_MAX_LEVELS - 1);
   if (st != MRHS_OK) return st;
@@ -645,6 +725,20 @@ mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t*
   if (!f32_valu) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "null output");
   const LevelData& L = mg->lv[level];
   *f32_valu = (!mfma_supported(L.ncomp) || L.f32_valu[nrhs]) ? 1 : 0;
+  if (lowp_cfg) *lowp_cfg = L.lowp_cfg[nrhs];
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_mg_set_lowp_cfg(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t cfg) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_status st = check_level(mg, level, 1, MRHS_MAX_LEVELS - 1);
+  if (st != MRHS_OK) return st;
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS)
+    return fail(mg->ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  if (cfg < 0 || cfg > 3) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "launch shape %d outside [0, 3]", cfg);
+  mg->lv[level].lowp_cfg[nrhs] = (signed char)cfg;
+  mg->lv[level].mr_cfg[nrhs] = (signed char)cfg;
+  ++mg->ctx->op_gen;  // captured V-cycles hold the previous shape
   return MRHS_OK;
 }
 

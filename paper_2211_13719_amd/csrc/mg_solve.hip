@@ -69,10 +69,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 size_t col_gram_scratch_bytes();
 hipError_t launch_col_gram(const void* v, long rows, int nv, void* scratch, void* g, hipStream_t s);
 hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipStream_t s);
-hipError_t launch_multi_axpy_norm(void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
-                                 int nrhs, void* norms, void* scratch, hipStream_t s);
-hipError_t launch_scale_cols_dual(void* y, void* y32, const void* x, const double* sdev, long rows, int nrhs,
-                                  hipStream_t s);
+hipError_t launch_multi_axpy_norm(void* y, void* y32, const void* yin, const void* coef, const void* cscale,
+                                 const void* const* xs, int m, double sgn, long rows, int nrhs, void* norms,
+                                 void* scratch, hipStream_t s);
+hipError_t launch_sub_dual(void* out, void* out32, const void* a, const void* b, long n, hipStream_t s);
+
 
 enum Phase { kFine = 0, kRestrict, kProlong, kCoarse, kPhases };
 
@@ -91,13 +92,20 @@ struct SolverState {
   int n = 0;                     // right-hand sides the level buffers hold
   Buffer lb[MRHS_MAX_LEVELS], lx[MRHS_MAX_LEVELS], lr[MRHS_MAX_LEVELS], lp[MRHS_MAX_LEVELS];
   Buffer alpha, part, scl, coef, qn;
+  // fused MR steps on small coarse levels: second r and p fields per level
+  // (ping-pong), two alpha arrays and the per-(site, column) partial sums
+  Buffer lr2[MRHS_MAX_LEVELS], lp2[MRHS_MAX_LEVELS];
+  Buffer mralpha, mrpart;
   Buffer gpart, gmat, gT;  // column Gram matrix (setup)
   // even-odd fine smoother: five checkerboard fields of eo_n columns
   Buffer eo, eo_part;
   int eo_n = 0;
+  // even-odd coarse smoother: seven checkerboard fields per level of ceo_n columns
+  Buffer ceo[MRHS_MAX_LEVELS];
+  int ceo_n = 0;
   // outer Krylov
   int m = 0, on = 0;
-  Buffer V64, Z32, w64, r64;
+  Buffer V64, Z32, w64;
   // captured V-cycles, one per destination slot
   GraphSlot graphs[kGraphSlots];
   // phase timers
@@ -116,9 +124,12 @@ void mg_solver_release(mrhs_mg mg) {
     release(st->lx[l]);
     release(st->lr[l]);
     release(st->lp[l]);
+    release(st->lr2[l]);
+    release(st->lp2[l]);
+    release(st->ceo[l]);
   }
   Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->gpart, &st->gmat, &st->gT,
-                 &st->V64, &st->Z32, &st->w64, &st->r64, &st->eo, &st->eo_part};
+                 &st->V64, &st->Z32, &st->w64, &st->eo, &st->eo_part, &st->mralpha, &st->mrpart};
   for (Buffer* x : b) release(*x);
   for (auto& gs : st->graphs)
     if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
@@ -137,6 +148,13 @@ namespace {
   } while (0)
 
 long level_rows(mrhs_mg mg, int l) { return (long)mg->lv[l].g.V * mg->lv[l].ncomp; }
+
+// Coarse levels small enough for the fused MR step, whose step-length launch
+// sums one partial per (site, column) with one workgroup per column (the 3^4
+// and 3^3 x 16 levels are 81 and 432 sites).
+bool fused_mr_level(mrhs_mg mg, int l) {
+  return l >= 1 && mfma_supported(mg->lv[l].ncomp) && mg->lv[l].g.V <= kFusedMrMaxSites;
+}
 
 mrhs_status state_of(mrhs_mg mg, SolverState** out) {
   if (!mg->solver) {
@@ -158,19 +176,25 @@ mrhs_status ensure_levels(mrhs_mg mg, SolverState* st, int n) {
     }
     for (int l = 0; l < mg->nlevels; ++l) {
       const size_t bytes = (size_t)level_rows(mg, l) * n * 8;
-      Buffer* bs[] = {&st->lb[l], &st->lx[l], &st->lr[l], &st->lp[l]};
+      Buffer* bs[] = {&st->lb[l], &st->lx[l], &st->lr[l], &st->lp[l], &st->lr2[l], &st->lp2[l]};
       for (Buffer* b : bs) {
         release(*b);
+        if ((b == &st->lr2[l] || b == &st->lp2[l]) && !fused_mr_level(mg, l)) continue;
         mrhs_status s = ensure(ctx, *b, bytes);
         if (s != MRHS_OK) return s;
       }
     }
     st->n = n;
   }
+  if (!st->mrpart.p) {
+    mrhs_status s = ensure(ctx, st->mralpha, 2 * MRHS_MAX_NRHS * 16);
+    if (s == MRHS_OK) s = ensure(ctx, st->mrpart, coarse_mr_part_bytes(kFusedMrMaxSites));
+    if (s != MRHS_OK) return s;
+  }
   mrhs_status s = ensure(ctx, st->alpha, MRHS_MAX_NRHS * 16);
   if (s == MRHS_OK) s = ensure(ctx, st->part, std::max(solver_scratch_bytes(MRHS_MAX_NRHS),
                                                         blas_scratch_bytes(MRHS_MAX_NRHS, kMaxMultiDot)));
-  if (s == MRHS_OK) s = ensure(ctx, st->scl, MRHS_MAX_NRHS * 8);
+  if (s == MRHS_OK) s = ensure(ctx, st->scl, (size_t)kMaxMultiDot * MRHS_MAX_NRHS * 8);
   if (s == MRHS_OK) s = ensure(ctx, st->coef, (size_t)kMaxMultiDot * MRHS_MAX_NRHS * 16);
   if (s == MRHS_OK) s = ensure(ctx, st->qn, MRHS_MAX_NRHS * 8);
   if (s == MRHS_OK) s = ensure_colscale(mg);
@@ -222,11 +246,35 @@ hipError_t apply_level(mrhs_mg mg, int l, void* out, const void* in, int n, mrhs
     if (e != hipSuccess) return e;
     scale = sc;
   }
-  return launch_coarse_mfma(cp == MRHS_F16, L.g, L.ncomp, n, cp == MRHS_F16 ? L.Bf16.p : L.Bbf16.p, in, out, scale, s);
+  return launch_coarse_mfma(cp == MRHS_F16, L.g, L.ncomp, n, cp == MRHS_F16 ? L.Bf16.p : L.Bbf16.p, in, out, scale, s,
+                            L.lowp_cfg[n]);
+}
+
+// nu MR steps on a small coarse level with BF16 operands, two launches each
+// (fused stencil, update and per-site inner products; step length), then one
+// launch for the last update of x and r.  p and the level's second r / p
+// fields are overwritten.
+hipError_t mr_steps_fused(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* p, int n, int nu) {
+  if (nu <= 0) return hipSuccess;
+  LevelData& L = mg->lv[l];
+  void* R[2] = {r, st->lr2[l].p};
+  void* P[2] = {p, st->lp2[l].p};
+  char* a = static_cast<char*>(st->mralpha.p);
+  void* A[2] = {a, a + MRHS_MAX_NRHS * 16};
+  for (int i = 0; i < nu; ++i) {
+    const int cur = i & 1, prv = (i + 1) & 1;
+    hipError_t e = launch_coarse_mr_step(L.g, L.ncomp, n, L.Bbf16.p, i == 0 ? R[0] : R[prv], P[prv], R[cur], P[cur],
+                                         x, A[prv], A[cur], st->mrpart.p, i == 0, L.mr_cfg[n], st->stream);
+    if (e != hipSuccess) return e;
+  }
+  const int last = (nu - 1) & 1;
+  return launch_mr_finish(x, R[last], P[last], r, A[last], level_rows(mg, l), n, st->stream);
 }
 
 // nu MR steps on D_l x = b with x and r = b - D x kept up to date.
 hipError_t mr_steps(mrhs_mg mg, SolverState* st, int l, void* x, void* r, void* p, int n, int nu, mrhs_prec cp) {
+  if (cp == MRHS_BF16 && fused_mr_level(mg, l) && st->lr2[l].p && st->mrpart.p)
+    return mr_steps_fused(mg, st, l, x, r, p, n, nu);
   const long rows = level_rows(mg, l);
   for (int i = 0; i < nu; ++i) {
     hipError_t e = apply_level(mg, l, p, r, n, cp, st->stream);
@@ -284,10 +332,66 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   return e;
 }
 
+// Coarse levels (not the coarsest) where the even-odd smoother applies:
+// Nb = 32 and all extents even.
+bool coarse_eo_level(mrhs_mg mg, int l) {
+  if (l < 1 || l >= mg->nlevels - 1 || !mfma_supported(mg->lv[l].ncomp) || mg->lv[l].g.V / 2 > 65535) return false;
+  for (int m = 0; m < 4; ++m)
+    if (mg->lv[l].g.L[m] % 2) return false;
+  return true;
+}
+
+// Smoothing on a coarse level's even-odd Schur complement with BF16
+// operands (D_c = [[S_e, H_eo], [H_oe, S_o]], S the self blocks, H the hop
+// directions), with r = b - D_c x:
+//   t_o = S_o^-1 r_o,  rhat = r_e - H_eo t_o,
+//   nu MR steps on Shat e_e = rhat from 0, Shat = S_e - H_eo S_o^-1 H_oe,
+//   e_o = S_o^-1 (r_o - H_oe e_e),  x += e,  and r = b - D_c x if needed.
+// One MR step: a_o = H_oe rho, t_o = S_o^-1 a_o, q = S_e rho - H_eo t_o (one
+// launch), then the step length and the update.
+hipError_t coarse_eo_smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r, const void* b, void* p, int n, int nu,
+                            bool need_r) {
+  if (nu <= 0) return hipSuccess;
+  LevelData& L = mg->lv[l];
+  const int nb = L.ncomp;
+  const long hrows = (long)(L.g.V / 2) * nb;
+  const size_t hb = (size_t)hrows * n * 8;
+  char* w = static_cast<char*>(st->ceo[l].p);
+  void *re = w, *ro = w + hb, *f2 = w + 2 * hb, *f3 = w + 3 * hb, *rho = w + 4 * hb, *q = w + 5 * hb, *ee = w + 6 * hb;
+  hipStream_t s = st->stream;
+  const void* B = L.Bbf16.p;
+  const void* Si = L.SinvBf16.p;
+  hipError_t e = launch_coarse_cb_rows(0, L.g, nb, n, r, re, 0, s);
+  if (e == hipSuccess) e = launch_coarse_cb_rows(1, L.g, nb, n, r, ro, 0, s);
+  // rhat = r_e - H_eo S_o^-1 r_o
+  if (e == hipSuccess) e = launch_coarse_mfma_eo(1, 2, 1, L.g, nb, n, Si, 1, ro, f2, nullptr, s);
+  if (e == hipSuccess) e = launch_coarse_mfma_eo(1, 1, 0, L.g, nb, n, B, 9, f2, f3, nullptr, s);
+  if (e == hipSuccess) e = launch_sub(0, rho, re, f3, hrows * n, s);
+  if (e == hipSuccess) e = launch_zero(ee, hb, s);
+  for (int i = 0; i < nu && e == hipSuccess; ++i) {
+    e = launch_coarse_mfma_eo(1, 1, 1, L.g, nb, n, B, 9, rho, f2, nullptr, s);
+    if (e == hipSuccess) e = launch_coarse_mfma_eo(1, 2, 1, L.g, nb, n, Si, 1, f2, f3, nullptr, s);
+    if (e == hipSuccess) e = launch_coarse_schur(0, L.g, nb, n, B, rho, f3, q, s);
+    if (e == hipSuccess) e = launch_mr_alpha(q, rho, hrows, n, st->alpha.p, st->part.p, s);
+    if (e == hipSuccess) e = launch_mr_update(ee, rho, q, st->alpha.p, hrows, n, s);
+  }
+  // e_o = S_o^-1 (r_o - H_oe e_e); x += e
+  if (e == hipSuccess) e = launch_coarse_mfma_eo(1, 1, 1, L.g, nb, n, B, 9, ee, f2, nullptr, s);
+  if (e == hipSuccess) e = launch_sub(0, f3, ro, f2, hrows * n, s);
+  if (e == hipSuccess) e = launch_coarse_mfma_eo(1, 2, 1, L.g, nb, n, Si, 1, f3, f2, nullptr, s);
+  if (e == hipSuccess) e = launch_coarse_cb_rows(0, L.g, nb, n, ee, x, 1, s);
+  if (e == hipSuccess) e = launch_coarse_cb_rows(1, L.g, nb, n, f2, x, 1, s);
+  if (need_r && e == hipSuccess) e = apply_level(mg, l, p, x, n, MRHS_BF16, s);
+  if (need_r && e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, l) * n, s);
+  return e;
+}
+
 // The smoothing pass of the V-cycle on level l.
 hipError_t smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r, const void* b, void* p, int n, int nu,
                   const mrhs_vcycle_params& vc, bool need_r) {
   if (l == 0 && vc.fine_eo) return eo_smooth(mg, st, x, r, b, p, n, nu, need_r);
+  if (vc.coarse_eo && vc.coarse_prec == MRHS_BF16 && coarse_eo_level(mg, l) && st->ceo[l].p)
+    return coarse_eo_smooth(mg, st, l, x, r, b, p, n, nu, need_r);
   return mr_steps(mg, st, l, x, r, p, n, nu, vc.coarse_prec);
 }
 
@@ -357,6 +461,7 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
   const bool same = gs.exec && gs.n == n && gs.out == xout && gs.vc.nu_pre == vc.nu_pre &&
                     gs.vc.nu_post == vc.nu_post && gs.vc.coarsest_iters == vc.coarsest_iters &&
                     gs.vc.coarse_prec == vc.coarse_prec && gs.vc.fine_eo == vc.fine_eo &&
+                    gs.vc.coarse_eo == vc.coarse_eo &&
                     gs.gen == ctx->op_gen;
   if (!same) {
     if (gs.exec) {
@@ -399,14 +504,37 @@ mrhs_status check_vc(mrhs_mg mg, const mrhs_vcycle_params* vc) {
   if (vc->coarse_prec != MRHS_F32 && vc->coarse_prec != MRHS_BF16 && vc->coarse_prec != MRHS_F16)
     return fail(mg->ctx, MRHS_ERR_UNSUPPORTED, "coarse precision must be f32, bf16 or f16");
   if (vc->fine_eo != 0 && vc->fine_eo != 1) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "fine_eo must be 0 or 1");
+  if (vc->coarse_eo != 0 && vc->coarse_eo != 1) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "coarse_eo must be 0 or 1");
   return MRHS_OK;
 }
 
 // Index tables, inverse clover blocks and checkerboard work fields of the
 // even-odd fine smoother (outside any graph capture).
 mrhs_status prepare_eo(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_params& vc) {
-  if (!vc.fine_eo) return MRHS_OK;
   mrhs_ctx ctx = mg->ctx;
+  if (vc.coarse_eo && vc.coarse_prec == MRHS_BF16) {
+    // inverse self blocks and checkerboard work fields of every coarse level
+    // the even-odd smoother runs on
+    const bool grow = n > st->ceo_n;
+    if (grow) {
+      for (auto& gs : st->graphs) {
+        if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
+        gs = GraphSlot{};
+      }
+    }
+    for (int l = 1; l < mg->nlevels; ++l) {
+      if (!coarse_eo_level(mg, l)) continue;
+      mrhs_status s = ensure_self_inverse(mg, l);
+      if (s != MRHS_OK) return s;
+      if (grow || !st->ceo[l].p) {
+        release(st->ceo[l]);
+        s = ensure(ctx, st->ceo[l], (size_t)7 * (mg->lv[l].g.V / 2) * mg->lv[l].ncomp * std::max(n, st->ceo_n) * 8);
+        if (s != MRHS_OK) return s;
+      }
+    }
+    if (grow) st->ceo_n = n;
+  }
+  if (!vc.fine_eo) return MRHS_OK;
   mrhs_status s = ensure_eo_tables(ctx);
   if (s == MRHS_OK) s = ensure_clover_inverse(ctx);
   if (s != MRHS_OK) return s;
@@ -555,6 +683,40 @@ mrhs_status mrhs_mg_precondition(mrhs_mg mg, void* z, const void* v, int32_t nrh
   return MRHS_OK;
 }
 
+mrhs_status mrhs_coarse_mr_solve(mrhs_mg mg, int32_t level, void* x, const void* b, int32_t nrhs, int32_t iters,
+                                 mrhs_prec prec) {
+  if (!mg) return MRHS_ERR_INVALID_ARG;
+  mrhs_ctx ctx = mg->ctx;
+  if (level < 1 || level >= mg->nlevels)
+    return fail(ctx, MRHS_ERR_INVALID_ARG, "level %d outside [1, %d]", level, mg->nlevels - 1);
+  if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(ctx, MRHS_ERR_INVALID_ARG, "null or misaligned field");
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  if (iters < 0 || iters > 100000) return fail(ctx, MRHS_ERR_INVALID_ARG, "iters = %d outside [0, 100000]", iters);
+  if (prec != MRHS_F32 && prec != MRHS_BF16 && prec != MRHS_F16)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "coarse MR precision must be f32, bf16 or f16");
+  LevelData& L = mg->lv[level];
+  if (!L.have_blocks) return fail(ctx, MRHS_ERR_STATE, "blocks of level %d not set", level);
+  if (prec != MRHS_F32 && !mfma_supported(L.ncomp))
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "matrix-core stencil needs Nb = 32, got %d", L.ncomp);
+  const size_t bytes = (size_t)level_rows(mg, level) * nrhs * 8;
+  {
+    const char* xa = static_cast<const char*>(x);
+    const char* ba = static_cast<const char*>(b);
+    if (xa < ba + bytes && ba < xa + bytes) return fail(ctx, MRHS_ERR_INVALID_ARG, "x and b overlap");
+  }
+  SolverState* st;
+  mrhs_status s = state_of(mg, &st);
+  if (s == MRHS_OK) s = ensure_levels(mg, st, nrhs);
+  if (s == MRHS_OK) s = join_ctx_stream(mg, st);
+  if (s != MRHS_OK) return s;
+  st->timing = false;
+  SOLVER_HIP(launch_zero(x, bytes, st->stream));
+  SOLVER_HIP(hipMemcpyAsync(st->lr[level].p, b, bytes, hipMemcpyDeviceToDevice, st->stream));
+  SOLVER_HIP(mr_steps(mg, st, level, x, st->lr[level].p, st->lp[level].p, nrhs, iters, prec));
+  SOLVER_HIP(hipStreamSynchronize(st->stream));
+  return MRHS_OK;
+}
+
 mrhs_status mrhs_mg_setup(mrhs_mg mg, const mrhs_setup_params* prm) {
   if (!mg) return MRHS_ERR_INVALID_ARG;
   mrhs_ctx ctx = mg->ctx;
@@ -670,7 +832,6 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
     s = ensure(ctx, st->V64, (size_t)(m + 1) * f64);
     if (s == MRHS_OK) s = ensure(ctx, st->Z32, (size_t)m * f32);
     if (s == MRHS_OK) s = ensure(ctx, st->w64, f64);
-    if (s == MRHS_OK) s = ensure(ctx, st->r64, f64);
     if (s != MRHS_OK) return s;
     st->m = m;
     st->on = n;
@@ -696,20 +857,20 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
     SOLVER_HIP(hipStreamSynchronize(ss));
     return MRHS_OK;
   };
-  // y = diag(sc) x in FP64; with preconditioning also FP32(y) into the
-  // V-cycle's input buffer (the next direction to precondition is y)
-  auto scale_by = [&](void* y, const void* xx, const std::vector<double>& sc) -> mrhs_status {
-    SOLVER_HIP(hipMemcpyAsync(st->scl.p, sc.data(), n * 8, hipMemcpyHostToDevice, ss));
-    SOLVER_HIP(launch_scale_cols_dual(y, prm->precondition ? st->lb[0].p : nullptr, xx,
-                                      static_cast<const double*>(st->scl.p), rows, n, ss));
-    SOLVER_HIP(hipStreamSynchronize(ss));  // sc is host memory the caller may change
-    return MRHS_OK;
-  };
-  // w -= sum_i c_i V_i (c from the last multi-dot) and q = ||w||^2 per RHS, one pass
-  // (the first nprod products of the multi-dot are copied to hout)
-  auto project_out = [&](const std::vector<const void*>& vs, int cnt, int nprod, std::vector<std::complex<double>>& hout,
-                         std::vector<double>& qout) -> mrhs_status {
-    SOLVER_HIP(launch_multi_axpy_norm(st->w64.p, st->coef.p, vs.data(), cnt, -1.0, rows, n, st->qn.p, st->part.p, ss));
+  // The Krylov vectors are stored unnormalised: V64[i] holds u_i = hv_i v_i
+  // with v_i the orthonormal vector and hv_i = ||u_i|| (per RHS, on the host),
+  // and Z32[i] holds M u_i, so that z_i = (M u_i) / hv_i.  No pass over a
+  // field is spent on scaling: every 1 / hv factor lives in the host scalars
+  // (Hessenberg entries, solution coefficients) or in the per-(i, RHS) factors
+  // 1 / hv_i^2 the Gram-Schmidt update reads from the device.
+  //
+  // u_{j+1} = yin - sum_i <u_i, yin> / hv_i^2 u_i into V64[j + 1] (and its FP32
+  // rounding into the V-cycle's input), q = ||u_{j+1}||^2 per RHS, one pass;
+  // the first nprod products of the multi-dot are copied to hout
+  auto project_out = [&](const void* yin, const std::vector<const void*>& vs, int cnt, int nprod, void* yout,
+                         std::vector<std::complex<double>>& hout, std::vector<double>& qout) -> mrhs_status {
+    SOLVER_HIP(launch_multi_axpy_norm(yout, prm->precondition ? st->lb[0].p : nullptr, yin, st->coef.p,
+                                      st->scl.p, vs.data(), cnt, -1.0, rows, n, st->qn.p, st->part.p, ss));
     SOLVER_HIP(hipMemcpyAsync(hout.data(), st->coef.p, (size_t)nprod * n * 16, hipMemcpyDeviceToHost, ss));
     SOLVER_HIP(hipMemcpyAsync(qout.data(), st->qn.p, n * 8, hipMemcpyDeviceToHost, ss));
     SOLVER_HIP(hipStreamSynchronize(ss));
@@ -717,22 +878,26 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   };
 
   using cd = std::complex<double>;
-  std::vector<double> bn(n), q(n), rel(n, 1.0), sc(n);
+  std::vector<double> bn(n), q(n), rel(n, 1.0);
   s = norms(b, bn);
   if (s != MRHS_OK) return s;
   for (int k = 0; k < n; ++k) bn[k] = std::sqrt(bn[k]);
   std::vector<int> done(n, 0);
   std::vector<cd> H((size_t)n * (m + 1) * m), g((size_t)n * (m + 1)), cs((size_t)n * m), sn((size_t)n * m);
   std::vector<cd> hc((size_t)(m + 2) * n), hc2((size_t)(m + 2) * n), y((size_t)m * n);
+  // ih[i][k] = 1 / hv_i of column k (0 for a converged column or a zero vector);
+  // ih2 = ih^2, the factors of the Gram-Schmidt update
+  std::vector<double> ih((size_t)(m + 1) * n), ih2((size_t)(m + 1) * n);
   int iters = 0, cycles = 0, reorth = 0;
   bool all_done = false;
   auto Hel = [&](int k, int i, int j) -> cd& { return H[((size_t)k * (m + 1) + i) * m + j]; };
 
   while (true) {
-    // true residual r = b - D x in FP64
+    // true residual r = b - D x in FP64, straight into V64[0] = u_0 (and its
+    // FP32 rounding into the V-cycle's input)
     SOLVER_HIP(D64(st->w64.p, x));
-    SOLVER_HIP(launch_sub(1, st->r64.p, b, st->w64.p, rows * n, ss));
-    s = norms(st->r64.p, q);
+    SOLVER_HIP(launch_sub_dual(Vj(0), prm->precondition ? st->lb[0].p : nullptr, b, st->w64.p, rows * n, ss));
+    s = norms(Vj(0), q);
     if (s != MRHS_OK) return s;
     all_done = true;
     for (int k = 0; k < n; ++k) {
@@ -740,21 +905,20 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       rel[k] = bn[k] > 0 ? beta / bn[k] : 0.0;
       done[k] = rel[k] <= prm->tol;
       all_done = all_done && done[k];
-      sc[k] = (beta > 0 && !done[k]) ? 1.0 / beta : 0.0;
+      ih[k] = (beta > 0 && !done[k]) ? 1.0 / beta : 0.0;
+      ih2[k] = ih[k] * ih[k];
       g[(size_t)k * (m + 1)] = done[k] ? 0.0 : beta;
       for (int i = 1; i <= m; ++i) g[(size_t)k * (m + 1) + i] = 0.0;
     }
     if (all_done || iters >= prm->max_iters) break;
     ++cycles;
-    s = scale_by(Vj(0), st->r64.p, sc);
-    if (s != MRHS_OK) return s;
     int jdone = 0;
     for (int j = 0; j < m && iters < prm->max_iters; ++j) {
       ++iters;
-      // z_j = M v_j
+      // Z32[j] = M u_j
       {
         auto tp = std::chrono::steady_clock::now();
-        if (prm->precondition) {  // lb[0] already holds FP32(v_j), written with v_j
+        if (prm->precondition) {  // lb[0] already holds FP32(u_j), written with u_j
           s = run_vcycle(mg, st, n, prm->vc, prm->use_graph != 0, Zj(j), j);
           if (s != MRHS_OK) return s;
         } else {
@@ -766,34 +930,39 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
           t_pre += std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
         }
       }
-      // w = D z_j in FP64, reading the FP32 direction directly (exact widening)
-      SOLVER_HIP(launch_fine_f64_in32(ctx->g, ctx->kappa, ctx->U64.p, ctx->A64.p, Zj(j), st->w64.p, n, ss));
-      // classical Gram-Schmidt; the first pass also yields ||w||^2 (w is the
-      // last vector of the multi-dot), and a second pass is made only when
-      // the projection removed more than half of ||w||^2 for some
-      // right-hand side ("twice is enough")
+      // w_hat = D Z32[j] in FP64, reading the FP32 direction directly (exact
+      // widening); D z_j = w_hat ih_j
+      SOLVER_HIP(launch_fine_f64_in32(ctx->g, ctx->kappa, ctx->U64.p, ctx->A64.p, Zj(j), st->w64.p, n, ss,
+                                      &ctx->fine_cfg[n]));
+      // classical Gram-Schmidt; the first pass also yields ||w_hat||^2 (w_hat is
+      // the last vector of the multi-dot), and a second pass is made only when
+      // the projection removed more than 1 - reorth_eta of it for some RHS
+      SOLVER_HIP(hipMemcpyAsync(st->scl.p, ih2.data(), (size_t)(j + 1) * n * 8, hipMemcpyHostToDevice, ss));
       std::vector<const void*> vs(j + 2);
       for (int i = 0; i <= j; ++i) vs[i] = Vj(i);
       vs[j + 1] = st->w64.p;
       SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 2, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
-      s = project_out(vs, j + 1, j + 2, hc, q);  // the last of the j + 2 products is ||w||^2
+      s = project_out(st->w64.p, vs, j + 1, j + 2, Vj(j + 1), hc, q);  // the last of the j + 2 products is ||w_hat||^2
       if (s != MRHS_OK) return s;
       bool again = false;
       for (int k = 0; k < n; ++k)
         if (!done[k] && q[k] < prm->reorth_eta * hc[(size_t)(j + 1) * n + k].real()) again = true;
       std::fill(hc2.begin(), hc2.end(), cd(0.0));
       if (again) {
-        SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
-        s = project_out(vs, j + 1, j + 1, hc2, q);
+        SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, Vj(j + 1), rows, n, st->coef.p, st->part.p, ss));
+        s = project_out(Vj(j + 1), vs, j + 1, j + 1, Vj(j + 1), hc2, q);
         if (s != MRHS_OK) return s;
         ++reorth;
       }
       bool all_conv = true;
       for (int k = 0; k < n; ++k) {
-        for (int i = 0; i <= j; ++i) Hel(k, i, j) = hc[(size_t)i * n + k] + hc2[(size_t)i * n + k];
-        const double hn = std::sqrt(q[k]);
-        Hel(k, j + 1, j) = hn;
-        sc[k] = hn > 0 ? 1.0 / hn : 0.0;
+        const double ihj = ih[(size_t)j * n + k];
+        for (int i = 0; i <= j; ++i)
+          Hel(k, i, j) = (hc[(size_t)i * n + k] + hc2[(size_t)i * n + k]) * (ih[(size_t)i * n + k] * ihj);
+        const double un = std::sqrt(q[k]);
+        Hel(k, j + 1, j) = un * ihj;
+        ih[(size_t)(j + 1) * n + k] = (un > 0 && !done[k]) ? 1.0 / un : 0.0;
+        ih2[(size_t)(j + 1) * n + k] = ih[(size_t)(j + 1) * n + k] * ih[(size_t)(j + 1) * n + k];
         // apply the previous rotations to column j, then a new one
         for (int i = 0; i < j; ++i) {
           const cd a = Hel(k, i, j), c = Hel(k, i + 1, j);
@@ -818,12 +987,10 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
         const double est = bn[k] > 0 ? std::abs(g[(size_t)k * (m + 1) + j + 1]) / bn[k] : 0.0;
         if (!done[k] && est > prm->tol) all_conv = false;
       }
-      s = scale_by(Vj(j + 1), st->w64.p, sc);
-      if (s != MRHS_OK) return s;
       jdone = j + 1;
       if (all_conv) break;
     }
-    // y = R^{-1} g per RHS, x += Z y
+    // y = R^{-1} g per RHS, x += sum_i y_i z_i = sum_i (y_i ih_i) Z32[i]
     for (int k = 0; k < n; ++k) {
       for (int i = jdone - 1; i >= 0; --i) {
         cd acc = g[(size_t)k * (m + 1) + i];
@@ -833,11 +1000,14 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       }
     }
     if (jdone > 0) {
-      SOLVER_HIP(hipMemcpyAsync(st->coef.p, y.data(), (size_t)jdone * n * 16, hipMemcpyHostToDevice, ss));
+      std::vector<cd> yz((size_t)jdone * n);
+      for (int i = 0; i < jdone; ++i)
+        for (int k = 0; k < n; ++k) yz[(size_t)i * n + k] = y[(size_t)i * n + k] * ih[(size_t)i * n + k];
+      SOLVER_HIP(hipMemcpyAsync(st->coef.p, yz.data(), (size_t)jdone * n * 16, hipMemcpyHostToDevice, ss));
       std::vector<const void*> zs(jdone);
       for (int i = 0; i < jdone; ++i) zs[i] = Zj(i);
       SOLVER_HIP(launch_multi_axpy(0, x, st->coef.p, zs.data(), jdone, 1.0, rows, n, ss));
-      SOLVER_HIP(hipStreamSynchronize(ss));  // y is host memory reused next cycle
+      SOLVER_HIP(hipStreamSynchronize(ss));  // yz is host memory
     }
   }
   SOLVER_HIP(hipStreamSynchronize(ss));

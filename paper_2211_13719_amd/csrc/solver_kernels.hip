@@ -146,9 +146,12 @@ __global__ __launch_bounds__(kB) void multi_axpy(double2* __restrict__ y, const 
   y[e] = acc;
 }
 
-// y_k += s sum_i c[i][k] x_i (y, x_i FP64) and, in the same pass, the
-// partial sums of ||y_k||^2 of the updated y: partial[b][k], fixed order.
-__global__ __launch_bounds__(kB) void multi_axpy_norm(double2* __restrict__ y, const double2* __restrict__ c,
+// y_k = yin_k + s sum_i c[i][k] x_i (y, yin, x_i FP64; y may be yin) and, in
+// the same pass, its FP32 rounding into y32 (if given) and the partial sums
+// of ||y_k||^2: partial[b][k], fixed order.
+// cs (if given): a real factor per (i, column), cs[i * nrhs + k], multiplying c.
+__global__ __launch_bounds__(kB) void multi_axpy_norm(double2* y, float2* __restrict__ y32, const double2* yin,
+                                                      const double2* __restrict__ c, const double* __restrict__ cs,
                                                       Ptrs xs, int m, double s, long rows, int nrhs, int tpb,
                                                       double* __restrict__ part) {
   __shared__ double red[kB];
@@ -160,16 +163,18 @@ __global__ __launch_bounds__(kB) void multi_axpy_norm(double2* __restrict__ y, c
     const long step = (long)gridDim.x * rpb;
     for (long row = (long)blockIdx.x * rpb + t / nrhs; row < rows; row += step) {
       const long e = row * nrhs + k;
-      double2 acc = y[e];
+      double2 acc = yin[e];
 #pragma unroll 4
       for (int i = 0; i < m; ++i) {
         const double2 xv = static_cast<const double2*>(xs.p[i])[e];
         const double2 ci = c[i * nrhs + k];
-        const double cr = s * ci.x, cim = s * ci.y;
+        const double f = cs ? s * cs[i * nrhs + k] : s;
+        const double cr = f * ci.x, cim = f * ci.y;
         acc.x = fma(cr, xv.x, fma(-cim, xv.y, acc.x));
         acc.y = fma(cr, xv.y, fma(cim, xv.x, acc.y));
       }
       y[e] = acc;
+      if (y32) y32[e] = make_float2((float)acc.x, (float)acc.y);
       acc2 = fma(acc.x, acc.x, fma(acc.y, acc.y, acc2));
     }
   }
@@ -195,20 +200,6 @@ __global__ __launch_bounds__(kB) void col_sum_final(const double* __restrict__ p
     __syncthreads();
   }
   if (t == 0) out[k] = red[0];
-}
-
-// y_k = s_k x_k in FP64 and, if y32 is given, its FP32 rounding too
-__global__ __launch_bounds__(kB) void scale_cols_dual(double2* __restrict__ y, float2* __restrict__ y32,
-                                                      const double2* __restrict__ x, const double* __restrict__ s,
-                                                      long n, int nrhs) {
-  const long e = (long)blockIdx.x * kB + threadIdx.x;
-  if (e >= n) return;
-  const double f = s[e % nrhs];
-  double2 v = x[e];
-  v.x *= f;
-  v.y *= f;
-  y[e] = v;
-  if (y32) y32[e] = make_float2((float)v.x, (float)v.y);
 }
 
 // y_k = s_k x_k, s real per column (device array)
@@ -241,6 +232,19 @@ __global__ __launch_bounds__(kB) void sub_fields(typename c2<T>::type* __restric
   u.x -= v.x;
   u.y -= v.y;
   out[e] = u;
+}
+
+// out = a - b in FP64 and, if out32 is given, its FP32 rounding too
+__global__ __launch_bounds__(kB) void sub_dual(double2* __restrict__ out, float2* __restrict__ out32,
+                                               const double2* __restrict__ a, const double2* __restrict__ b, long n) {
+  const long e = (long)blockIdx.x * kB + threadIdx.x;
+  if (e >= n) return;
+  double2 u = a[e];
+  const double2 v = b[e];
+  u.x -= v.x;
+  u.y -= v.y;
+  out[e] = u;
+  if (out32) out32[e] = make_float2((float)u.x, (float)u.y);
 }
 
 __global__ __launch_bounds__(kB) void add_f32(float2* __restrict__ y, const float2* __restrict__ x, long n) {
@@ -402,6 +406,12 @@ hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long 
   return hipGetLastError();
 }
 
+hipError_t launch_sub_dual(void* out, void* out32, const void* a, const void* b, long n, hipStream_t s) {
+  hipLaunchKernelGGL(sub_dual, dim3(grid_of(n)), dim3(kB), 0, s, static_cast<double2*>(out), static_cast<float2*>(out32),
+                     static_cast<const double2*>(a), static_cast<const double2*>(b), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_add_f32(void* y, const void* x, long n, hipStream_t s) {
   hipLaunchKernelGGL(add_f32, dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(y), static_cast<const float2*>(x),
                      n);
@@ -449,25 +459,22 @@ hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_multi_axpy_norm(void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
-                                 int nrhs, void* norms, void* scratch, hipStream_t s) {
+hipError_t launch_multi_axpy_norm(void* y, void* y32, const void* yin, const void* coef, const void* cscale,
+                                 const void* const* xs, int m, double sgn, long rows, int nrhs, void* norms,
+                                 void* scratch, hipStream_t s) {
   if (m < 1 || m > kMaxMultiDot || nrhs < 1 || nrhs > kB) return hipErrorInvalidValue;
   Ptrs p{};
   for (int i = 0; i < m; ++i) p.p[i] = xs[i];
   const int tpb = tpb_of(nrhs), nb = nblk_of(rows, nrhs);
-  hipLaunchKernelGGL(multi_axpy_norm, dim3(nb), dim3(kB), 0, s, static_cast<double2*>(y),
-                     static_cast<const double2*>(coef), p, m, sgn, rows, nrhs, tpb, static_cast<double*>(scratch));
+  hipLaunchKernelGGL(multi_axpy_norm, dim3(nb), dim3(kB), 0, s, static_cast<double2*>(y), static_cast<float2*>(y32),
+                     static_cast<const double2*>(yin), static_cast<const double2*>(coef),
+                     static_cast<const double*>(cscale), p, m, sgn, rows, nrhs, tpb,
+                     static_cast<double*>(scratch));
   hipLaunchKernelGGL(col_sum_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double*>(scratch), nb, nrhs,
                      static_cast<double*>(norms));
   return hipGetLastError();
 }
 
-hipError_t launch_scale_cols_dual(void* y, void* y32, const void* x, const double* sdev, long rows, int nrhs,
-                                  hipStream_t s) {
-  const long n = rows * nrhs;
-  hipLaunchKernelGGL(scale_cols_dual, dim3((unsigned)((n + kB - 1) / kB)), dim3(kB), 0, s, static_cast<double2*>(y),
-                     static_cast<float2*>(y32), static_cast<const double2*>(x), sdev, n, nrhs);
-  return hipGetLastError();
-}
+
 
 }  // namespace mrhs

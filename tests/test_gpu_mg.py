@@ -326,6 +326,127 @@ def test_coarse_tune_keeps_parity(gpu_lib, cdims):
         assert rel(host(o), O.coarse_apply(B32, e32, cdims)) < 1e-6, (n, mg.get_tuning(1, n))
 
 
+@pytest.mark.parametrize("cdims", [(6, 6, 6, 6), (3, 3, 3, 3), (2, 3, 1, 2)])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_coarse_lowp_launch_shapes(gpu_lib, cdims, cfg):
+    """Every launch shape of the BF16/FP16 stencil (four or eight wavefronts per
+    site, one or two 32-column tiles per workgroup) against the oracle on the
+    rounded operands (1e-6) and on the exact ones (2e-2), with ragged column
+    counts (1, 33, 40) as well as full tiles; per column the result equals the
+    column applied alone (same shape)."""
+    import torch
+
+    nb = 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 23)
+    mg.set_blocks(1, B)
+    for n in (1, 12, 33, 40, 64):
+        mg.set_lowp_cfg(1, n, cfg)
+        assert mg.get_lowp_tuning(1, n)["cfg"] == cfg
+        e32 = synth.coarse_source(Vc, nb, n, 29, np.complex64)
+        for fmt in ("bf16", "f16"):
+            o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+            mg.coarse_apply(1, o, dev(e32), fmt)
+            got = host(o)
+            assert rel(got, O.coarse_apply_lowprec(B, e32, cdims, fmt)) < 1e-6, (n, fmt)
+            assert rel(got, O.coarse_apply(B, e32, cdims)) < 2e-2, (n, fmt)
+        if n == 40:
+            mg.set_lowp_cfg(1, 1, cfg)
+            for k in (0, 39):
+                ok = torch.empty((Vc, nb, 1), dtype=torch.complex64, device="cuda")
+                mg.coarse_apply(1, ok, dev(np.ascontiguousarray(e32[:, :, k:k + 1])), "bf16")
+                o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+                mg.coarse_apply(1, o, dev(e32), "bf16")
+                np.testing.assert_array_equal(host(ok)[:, :, 0], host(o)[:, :, k])
+
+
+def test_coarse_tune_lowp_keeps_parity(gpu_lib):
+    """mrhs_mg_tune also picks the BF16/FP16 launch shape per Nrhs; whichever
+    it picks matches the rounded-operand oracle."""
+    import torch
+
+    cdims, nb = (3, 3, 3, 3), 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 31)
+    mg.set_blocks(1, B)
+    ns = [12, 48, 64]
+    mg.tune(ns)
+    for n in ns:
+        assert mg.get_lowp_tuning(1, n)["cfg"] in (0, 1, 2, 3)
+        e32 = synth.coarse_source(Vc, nb, n, 37, np.complex64)
+        for fmt in ("bf16", "f16"):
+            o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+            mg.coarse_apply(1, o, dev(e32), fmt)
+            assert rel(host(o), O.coarse_apply_lowprec(B, e32, cdims, fmt)) < 1e-6, (n, fmt)
+
+
+def _mr_ref(B, b, cdims, iters, fmt):
+    """iters minimal-residual steps from zero on the coarse stencil B, with the
+    device's number formats: the stencil on BF16-rounded operands with exact
+    products (fmt "bf16") or on FP32-rounded blocks (fmt "f32"); p, r and x kept
+    in FP32; alpha = <p, r> / ||p||^2 per column in FP64, rounded to FP32 for
+    the updates."""
+    r = np.asarray(b, dtype=np.complex64)
+    x = np.zeros_like(r)
+    B32 = np.asarray(B).astype(np.complex64)
+    for _ in range(iters):
+        if fmt == "bf16":
+            p = O.coarse_apply_lowprec(B, r, cdims, "bf16").astype(np.complex64)
+        else:
+            p = O.coarse_apply(B32, r, cdims).astype(np.complex64)
+        p64, r64 = p.astype(np.complex128), r.astype(np.complex128)
+        num = np.einsum("sck,sck->k", p64.conj(), r64)
+        den = np.einsum("sck,sck->k", p64.conj(), p64).real
+        a = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0).astype(np.complex64).astype(np.complex128)
+        x = (x.astype(np.complex128) + a * r64).astype(np.complex64)
+        r = (r64 - a * p64).astype(np.complex64)
+    return x
+
+
+@pytest.mark.parametrize("cdims,cfg,prec", [
+    ((3, 3, 3, 3), 0, "bf16"), ((3, 3, 3, 3), 1, "bf16"), ((3, 3, 3, 3), 2, "bf16"), ((3, 3, 3, 3), 3, "bf16"),
+    ((3, 3, 3, 2), 0, "bf16"),
+    ((6, 6, 6, 6), 0, "bf16"),
+    ((3, 3, 3, 3), 0, "f32"),
+])
+def test_coarse_mr_solve_vs_emulation(gpu_lib, cdims, cfg, prec):
+    """The coarsest-level MR solve: on levels of at most 1024 sites with BF16
+    operands every step is one fused launch (stencil, per-site partial sums,
+    last-workgroup step length, update on the fly); 6^4 (1296 sites) and FP32
+    take the separate kernels.  Against an FP64 emulation of the same
+    iteration in the device's number formats, for 1, 12, 40 and 64 RHS: one
+    step agrees to the FP32 accumulation order (1e-5); over 16 steps an FP32
+    rounding difference can move an operand across a BF16 rounding boundary
+    (one BF16 ulp, 2^-8), so the bar there is 2e-3 (FP32 path: 1e-5), and the
+    residual reduction must match the emulation's."""
+    import torch
+
+    nb = 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 41, shift=24.0)  # a shift that lets MR converge
+    mg.set_blocks(1, B)
+    for n in (1, 12, 40, 64):
+        mg.set_lowp_cfg(1, n, cfg)
+        b = synth.coarse_source(Vc, nb, n, 43, np.complex64)
+        for iters, tol in ((1, 1e-5), (16, 2e-3 if prec == "bf16" else 1e-5)):
+            x = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+            mg.coarse_mr_solve(1, x, dev(b), iters, prec)
+            want = _mr_ref(B, b, cdims, iters, prec)
+            got = host(x)
+            assert rel(got, want) < tol, (n, iters, rel(got, want))
+            if iters == 16:
+                res = np.linalg.norm(b - O.coarse_apply(B, got, cdims)) / np.linalg.norm(b)
+                res_ref = np.linalg.norm(b - O.coarse_apply(B, want, cdims)) / np.linalg.norm(b)
+                assert res < 0.5 and abs(res - res_ref) < 0.01 * res_ref, (n, res, res_ref)
+                if n == 12:  # deterministic: a second call gives the same bits
+                    x2 = torch.empty_like(x)
+                    mg.coarse_mr_solve(1, x2, dev(b), iters, prec)
+                    assert torch.equal(x, x2)
+
+
 def test_coarse_apply_nb8_valu(gpu_lib):
     import torch
 
