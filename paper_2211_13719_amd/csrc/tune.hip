@@ -7,9 +7,14 @@
 // keeps the fastest for all later FP32 applies of that Nrhs
 // (the configurations compute bit-identical results: each output element
 // sees the same operations in the same order).  Choices can be persisted in
-// a plain text cache, one line per (device architecture, lattice, Nrhs):
+// a plain text cache, one line per (device architecture, HIP runtime
+// version, lattice, Nrhs):
 //
-//   <arch> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <nt> <chunks> <cap> <microseconds>
+//   <arch> <hip runtime version> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <nt>
+//   <chunks> <cap> <microseconds>
+//
+// (one line each; a line tuned under another runtime or of another format is
+// ignored, so a new ROCm retunes).
 #include <algorithm>
 #include <array>
 #include <cstdio>
@@ -69,6 +74,11 @@ std::vector<std::array<int, 4>> tile_candidates(const Geom& g) {
   return out;
 }
 
+int runtime_version() {
+  int v = 0;
+  return hipRuntimeGetVersion(&v) == hipSuccess ? v : 0;
+}
+
 std::string arch_name(int dev) {
   hipDeviceProp_t p;
   if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
@@ -98,12 +108,13 @@ bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int 
   bool found = false;
   while (std::fgets(line, sizeof(line), f)) {
     char a[64];
-    int L[4], n, R, T[4], curve, occ, nt, ch, cap;
+    int hv, L[4], n, R, T[4], curve, occ, nt, ch, cap;
     float us;
-    if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &L[0], &L[1], &L[2], &L[3], &n,
-                    &R, &T[0], &T[1], &T[2], &T[3], &curve, &occ, &nt, &ch, &cap, &us) != 17)
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %f", a, &hv, &L[0], &L[1], &L[2], &L[3],
+                    &n, &R, &T[0], &T[1], &T[2], &T[3], &curve, &occ, &nt, &ch, &cap, &us) != 18)
       continue;  // lines of other formats are ignored
-    if (arch == a && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] && L[3] == g.L[3] &&
+    if (arch == a && hv == runtime_version() && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] &&
+        L[3] == g.L[3] &&
         (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1) &&
         (occ == 0 || occ == 4) && (nt == 0 || nt == 1) && (ch == 1 || ch == 2 || ch == 4) && nrhs % ch == 0 &&
         (nrhs / ch) % R == 0 && cap >= 0 && cap <= 3) {
@@ -126,8 +137,9 @@ void cache_append(const char* path, const std::string& arch, const Geom& g, int 
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), g.L[0], g.L[1], g.L[2],
-               g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.nt, c.chunks, c.cap, c.us);
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), runtime_version(), g.L[0],
+               g.L[1], g.L[2], g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.nt, c.chunks, c.cap,
+               c.us);
   std::fclose(f);
 }
 

@@ -150,14 +150,27 @@ TUNE_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file
                           "tuning", "fine.txt")
 
 
+def _hip_runtime_version():
+    """hipRuntimeGetVersion of the HIP runtime this process has loaded (the
+    one the library runs on, which keys the autotuner cache)."""
+    import ctypes
+
+    libs = sorted({l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l})
+    v = ctypes.c_int()
+    assert libs and ctypes.CDLL(libs[0]).hipRuntimeGetVersion(ctypes.byref(v)) == 0
+    return v.value
+
+
 def _cached_lines(path, arch, dims):
-    """The autotuner cache's configuration per Nrhs for this lattice (the last
-    matching line wins, as in the library)."""
+    """The autotuner cache's configuration per Nrhs for this lattice and HIP
+    runtime (the last matching line wins, as in the library)."""
     out = {}
+    hv = _hip_runtime_version()
     for line in open(path):
         f = line.split()
-        if len(f) != 17 or f[0] != arch or tuple(map(int, f[1:5])) != tuple(dims):
+        if len(f) != 18 or f[0] != arch or int(f[1]) != hv or tuple(map(int, f[2:6])) != tuple(dims):
             continue
+        f = f[:1] + f[2:]  # drop the runtime version: the fields below as before
         n, R = int(f[5]), int(f[6])
         tile = tuple(map(int, f[7:11]))
         curve, occ, nt, chunks, cap = map(int, f[11:16])
@@ -272,8 +285,8 @@ def test_launch_configurations_bitwise(small, tmp_path, R, tile, curve, occ, nt,
     ctx.dwc(y0, x)  # untuned default (or whatever an earlier test left): compare with FP32 oracle below
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     cache = tmp_path / "cfg.txt"
-    cache.write_text(f"{arch} {' '.join(map(str, dims))} {n} {R} {' '.join(map(str, tile))} {curve} {occ} {nt} "
-                     f"{chunks} {cap} 1.0\n")
+    cache.write_text(f"{arch} {_hip_runtime_version()} {' '.join(map(str, dims))} {n} {R} {' '.join(map(str, tile))} "
+                     f"{curve} {occ} {nt} {chunks} {cap} 1.0\n")
     ctx.tune([n], str(cache))
     got = ctx.get_tuning(n)
     assert got[0] == R and tuple(got[1]) == tile
