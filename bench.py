@@ -72,6 +72,9 @@ SOLVE_MRHS_FINE_EO = True  # 24^3x128, 12 / 24 RHS, nu_post 6: 24 instead of 28 
 # level-1 (6^3 x 32) smoothing on the coarse even-odd Schur complement: 24^3x128, 12 RHS, 18 instead of 21 outer
 # steps, 0.90 vs 1.03 s
 SOLVE_MRHS_COARSE_EO = True
+# Schwarz (SAP) smoothing of the fine level, measured beside the even-odd smoother: cycles per smoothing pass and
+# MR steps per 4^4 block solve
+SOLVE_SAP_CYCLES, SOLVE_SAP_ITERS = 1, 4
 TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
 FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 
@@ -391,6 +394,24 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         torch.cuda.empty_cache()
     except Exception as exc:
         coarse_eo = {"error": f"{type(exc).__name__}: {exc}"}
+    # the same MRHS solve (first batch size) with Schwarz (SAP) smoothing on the
+    # fine level: one cycle of four MR steps per 4^4 block (Sec. 9 outlook)
+    sap = None
+    try:
+        b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, n0, 4000)).cuda()
+        x = torch.zeros_like(b)
+        m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n0, free0)
+        vs = dict(vc, fine_eo=False, fine_sap=True, sap_iters=SOLVE_SAP_ITERS, nu_post=SOLVE_SAP_CYCLES)
+        st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", restart=m, **kw, **vs)
+        sap = {"nrhs": n0, "cycles": SOLVE_SAP_CYCLES, "mr_steps_per_block": SOLVE_SAP_ITERS,
+               "s_per_rhs": round(st["seconds_total"] / n0, 4), "seconds": round(st["seconds_total"], 3),
+               "iters": st["iters"], "converged": int(sum(st["converged"])), "max_true_resid": max(st["rel_resid"])}
+        print(f"[bench] MRHS solve N={n0} with SAP smoothing: {st['seconds_total']:.2f} s, {st['iters']} iterations",
+              file=sys.stderr, flush=True)
+        del b, x
+        torch.cuda.empty_cache()
+    except Exception as exc:
+        sap = {"error": f"{type(exc).__name__}: {exc}"}
     # the comparator is the faster of the two fine smoothers on one RHS, with
     # the FP32 coarse stencil kernel tuned for one RHS
     mg.tune([1])
@@ -426,6 +447,7 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "speedup": round(s1["seconds_total"] / mrhs_res[best]["s_per_rhs"], 3) if best else None,
         "mrhs_phase_s": phases,
         "mrhs_other_level1_smoother": coarse_eo,
+        "mrhs_sap_smoother": sap,
         "config": f"FP64 FGMRES({SOLVE_RESTART}, shorter where the batch's fields would not fit in HBM), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
                   f"levels and BF16 matrix-core restrict/prolong, fine_eo {int(SOLVE_MRHS_FINE_EO)} (fine smoothing "
                   f"on the even-odd Schur complement), coarse_eo {int(SOLVE_MRHS_COARSE_EO)} (level-1 smoothing on "

@@ -359,7 +359,14 @@ mrhs_status mrhs_coarse_self_eo_apply(mrhs_mg mg, int32_t level, void* out, cons
  * With coarse_eo the same elimination on a coarse level, D_c = [[S_e, H_eo],
  * [H_oe, S_o]] with S the self blocks and H the eight hop directions: nu MR
  * steps on (S_e - H_eo S_o^-1 H_oe) e_e = r_e - H_eo S_o^-1 r_o from e_e = 0,
- * then e_o = S_o^-1 (r_o - H_oe e_e), x += e. */
+ * then e_o = S_o^-1 (r_o - H_oe e_e), x += e.
+ * With fine_sap (Sec. 9 outlook, Schwarz smoothing) the fine lattice is cut
+ * into the level-0 aggregates as blocks, coloured (X + Y + Z + T) mod 2 (the
+ * block counts L / b must all be even); one SAP cycle is, for colour c = 0
+ * then 1: r = b - D x, on every block B of colour c sap_iters MR steps on
+ * D_B e_B = r|_B from zero (D_B: D on B with the hops across the block
+ * boundary dropped; step length from the block's own inner products), and
+ * x += e_B. */
 typedef struct {
   int32_t nu_pre;
   int32_t nu_post;
@@ -372,6 +379,10 @@ typedef struct {
                         smoothing steps run on the coarse Schur complement
                         S_e - H_eo S_o^-1 H_oe (Sec. 6, the coarse M_eooe;
                         see below); 0: on D_c */
+  int32_t fine_sap;  /* 1: the fine level smooths with the Schwarz alternating
+                        procedure instead (not together with fine_eo; see
+                        below): nu_pre / nu_post count SAP cycles */
+  int32_t sap_iters; /* MR steps per block solve of a SAP cycle, 1..64 */
 } mrhs_vcycle_params;
 
 typedef struct {

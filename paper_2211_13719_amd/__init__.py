@@ -469,12 +469,15 @@ class Multigrid:
 
     # -- solver ---------------------------------------------------------------------------
     @staticmethod
-    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16", fine_eo=False, coarse_eo=False):
+    def _vc(nu_pre=0, nu_post=4, coarsest_iters=16, coarse_prec="bf16", fine_eo=False, coarse_eo=False,
+            fine_sap=False, sap_iters=4):
         v = _lib.VcycleParams()
         v.nu_pre, v.nu_post, v.coarsest_iters = int(nu_pre), int(nu_post), int(coarsest_iters)
         v.coarse_prec = _PREC_NAMES[coarse_prec]
         v.fine_eo = int(bool(fine_eo))
         v.coarse_eo = int(bool(coarse_eo))
+        v.fine_sap = int(bool(fine_sap))
+        v.sap_iters = int(sap_iters)
         return v
 
     def setup(self, setup_iters: int = 3, smooth_steps: int = 8, adapt_iters: int = 0, **vc):

@@ -81,7 +81,7 @@ SIGNATURES = {
 
 class VcycleParams(C.Structure):
     _fields_ = [("nu_pre", _i32), ("nu_post", _i32), ("coarsest_iters", _i32), ("coarse_prec", _i32),
-                ("fine_eo", _i32), ("coarse_eo", _i32)]
+                ("fine_eo", _i32), ("coarse_eo", _i32), ("fine_sap", _i32), ("sap_iters", _i32)]
 
 
 class SetupParams(C.Structure):

@@ -519,6 +519,7 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_kernel(Geom g, 
       r /= g.L[1];
       const int z = r % g.L[2];
       const int t = r / g.L[2];
+      if (filt.color >= 0 && ((x / filt.b[0] + y / filt.b[1] + z / filt.b[2] + t / filt.b[3]) & 1) != filt.color) return;
       bool f0, b0, f1, b1, f2, b2, f3, b3;
       galerkin_keep(filt, 0, x, f0, b0);
       galerkin_keep(filt, 1, y, f1, b1);
@@ -1040,6 +1041,12 @@ hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void
                                void* out, int nrhs, const DirFilter& f, hipStream_t s) {
   (void)t_bc;  // folded into the links
   return launch_r<double, 1, 3>(g, g.order, kappa, U, A, in, out, nrhs, s, f);
+}
+
+hipError_t launch_fine_dir_f32(const Geom& g, float kappa, const void* U, const void* A, const void* in, void* out,
+                               int nrhs, const DirFilter& f, hipStream_t s) {
+  if (nrhs % 2 == 0) return launch_r<float, 2, 3>(g, g.order, kappa, U, A, in, out, nrhs, s, f);
+  return launch_r<float, 1, 3>(g, g.order, kappa, U, A, in, out, nrhs, s, f);
 }
 
 // FP32: two right-hand sides per thread for even nrhs; FP64: one.

@@ -76,6 +76,10 @@ struct DirFilter {
   int sign = 2;
   int mu = 0;
   int b[4] = {1, 1, 1, 1};
+  // sign 0 only: >= 0 restricts the output to the sites of the blocks of this
+  // colour (X + Y + Z + T) mod 2 (Schwarz smoothing); the other sites are
+  // neither read nor written
+  int color = -1;
 };
 
 struct Buffer {
@@ -160,6 +164,9 @@ hipError_t launch_fine_f64_in32(const Geom& g, double kappa, const void* U, cons
 
 hipError_t launch_fine_dir_f64(const Geom& g, int t_bc, double kappa, const void* U, const void* A, const void* in,
                                void* out, int nrhs, const DirFilter& f, hipStream_t s);
+// FP32 direction-resolved apply (the Schwarz smoother's block operator)
+hipError_t launch_fine_dir_f32(const Geom& g, float kappa, const void* U, const void* A, const void* in, void* out,
+                               int nrhs, const DirFilter& f, hipStream_t s);
 // checkerboarded fine pieces (fine.hip): nhalf = V / 2 sites per parity,
 // tab = that parity's table (four int4 per site)
 // epi 0: out = H in; 1: out = Ablk (H in); 2: out = Ablk in2 + coef (H in)

@@ -73,6 +73,7 @@ hipError_t launch_multi_axpy_norm(void* y, void* y32, const void* yin, const voi
                                  const void* const* xs, int m, double sgn, long rows, int nrhs, void* norms,
                                  void* scratch, hipStream_t s);
 hipError_t launch_sub_dual(void* out, void* out32, const void* a, const void* b, long n, hipStream_t s);
+hipError_t launch_sap_block_mr(const AggGeom& a, int nrhs, int color, void* x, void* rho, const void* q, hipStream_t s);
 
 
 enum Phase { kFine = 0, kRestrict, kProlong, kCoarse, kPhases };
@@ -386,9 +387,43 @@ hipError_t coarse_eo_smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r
   return e;
 }
 
+// Schwarz alternating procedure on the fine level (nu cycles; see the header):
+// blocks are the level-0 aggregates.  On entry r = b - D x; the residual of
+// each colour's half-cycle is r itself (its rows of that colour serve as the
+// block solves' rho), recomputed before the second colour and, if the caller
+// needs it, at the end.
+hipError_t sap_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* b, void* p, int n, int nu,
+                      int iters, bool need_r) {
+  mrhs_ctx ctx = mg->ctx;
+  const AggGeom& a = mg->lv[0].agg;
+  hipStream_t s = st->stream;
+  const long rows = level_rows(mg, 0);
+  hipError_t e = hipSuccess;
+  for (int cyc = 0; cyc < nu && e == hipSuccess; ++cyc) {
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+      if (cyc > 0 || c > 0) {
+        e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
+        if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, s);
+      }
+      DirFilter f;
+      f.sign = 0;
+      f.color = c;
+      for (int m = 0; m < 4; ++m) f.b[m] = a.b[m];
+      for (int i = 0; i < iters && e == hipSuccess; ++i) {
+        e = launch_fine_dir_f32(ctx->g, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, r, p, n, f, s);
+        if (e == hipSuccess) e = launch_sap_block_mr(a, n, c, x, r, p, s);
+      }
+    }
+  }
+  if (need_r && e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
+  if (need_r && e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, s);
+  return e;
+}
+
 // The smoothing pass of the V-cycle on level l.
 hipError_t smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r, const void* b, void* p, int n, int nu,
                   const mrhs_vcycle_params& vc, bool need_r) {
+  if (l == 0 && vc.fine_sap) return sap_smooth(mg, st, x, r, b, p, n, nu, vc.sap_iters, need_r);
   if (l == 0 && vc.fine_eo) return eo_smooth(mg, st, x, r, b, p, n, nu, need_r);
   if (vc.coarse_eo && vc.coarse_prec == MRHS_BF16 && coarse_eo_level(mg, l) && st->ceo[l].p)
     return coarse_eo_smooth(mg, st, l, x, r, b, p, n, nu, need_r);
@@ -461,7 +496,8 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
   const bool same = gs.exec && gs.n == n && gs.out == xout && gs.vc.nu_pre == vc.nu_pre &&
                     gs.vc.nu_post == vc.nu_post && gs.vc.coarsest_iters == vc.coarsest_iters &&
                     gs.vc.coarse_prec == vc.coarse_prec && gs.vc.fine_eo == vc.fine_eo &&
-                    gs.vc.coarse_eo == vc.coarse_eo &&
+                    gs.vc.coarse_eo == vc.coarse_eo && gs.vc.fine_sap == vc.fine_sap &&
+                    gs.vc.sap_iters == vc.sap_iters &&
                     gs.gen == ctx->op_gen;
   if (!same) {
     if (gs.exec) {
@@ -505,6 +541,17 @@ mrhs_status check_vc(mrhs_mg mg, const mrhs_vcycle_params* vc) {
     return fail(mg->ctx, MRHS_ERR_UNSUPPORTED, "coarse precision must be f32, bf16 or f16");
   if (vc->fine_eo != 0 && vc->fine_eo != 1) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "fine_eo must be 0 or 1");
   if (vc->coarse_eo != 0 && vc->coarse_eo != 1) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "coarse_eo must be 0 or 1");
+  if (vc->fine_sap != 0 && vc->fine_sap != 1) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "fine_sap must be 0 or 1");
+  if (vc->fine_sap) {
+    if (vc->fine_eo) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "fine_sap and fine_eo exclude each other");
+    if (vc->sap_iters < 1 || vc->sap_iters > 64)
+      return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "sap_iters = %d outside [1, 64]", vc->sap_iters);
+    if (mg->nlevels < 2) return fail(mg->ctx, MRHS_ERR_STATE, "SAP blocks are the level-0 aggregates: need two levels");
+    for (int m = 0; m < 4; ++m)
+      if (mg->lv[0].agg.C[m] % 2)
+        return fail(mg->ctx, MRHS_ERR_SHAPE, "SAP needs an even number of blocks per direction (direction %d: %d)", m,
+                    mg->lv[0].agg.C[m]);
+  }
   return MRHS_OK;
 }
 

@@ -272,6 +272,78 @@ __global__ __launch_bounds__(kB) void zero_words(uint4* __restrict__ p, long n16
 
 int grid_of(long n) { return (int)((n + kB - 1) / kB); }
 
+// One minimal-residual step of the Schwarz block solves on the blocks of one
+// colour, one workgroup per block (its whole block in one workgroup, so the
+// step length needs no global reduction): with q = D_B rho,
+//   alpha = <q, rho>_B / ||q||^2_B per column (FP64 sums over the block's sites
+//   and components, fixed order),  x += alpha rho,  rho -= alpha q  (FP32).
+// Blocks are the aggregates of a (extent a.b, a.C blocks per direction).
+__global__ __launch_bounds__(kB) void sap_block_mr(AggGeom a, int nrhs, int color, float2* __restrict__ x,
+                                                   float2* __restrict__ rho, const float2* __restrict__ q) {
+  __shared__ double4 red[kB];
+  __shared__ double2 al[kB];
+  const int B = blockIdx.x;
+  const int X = B % a.C[0], Y = (B / a.C[0]) % a.C[1], Z = (B / (a.C[0] * a.C[1])) % a.C[2],
+            T = B / (a.C[0] * a.C[1] * a.C[2]);
+  if (((X + Y + Z + T) & 1) != color) return;  // whole workgroup
+  const int nsb = a.b[0] * a.b[1] * a.b[2] * a.b[3];
+  const long rows = (long)nsb * 12;
+  const int tpb = (kB / nrhs) * nrhs, rpb = tpb / nrhs;
+  const int t = threadIdx.x, k = t % nrhs;
+  // element offset of block row j (local site j / 12, component j % 12), column k
+  auto elem = [&](long j) {
+    int ls = (int)(j / 12);
+    const int c = (int)(j % 12);
+    const int lx = ls % a.b[0];
+    ls /= a.b[0];
+    const int ly = ls % a.b[1];
+    ls /= a.b[1];
+    const int lz = ls % a.b[2];
+    const int lt = ls / a.b[2];
+    const long s = (long)(X * a.b[0] + lx) +
+                   (long)a.L[0] * ((Y * a.b[1] + ly) + (long)a.L[1] * ((Z * a.b[2] + lz) + (long)a.L[2] * (T * a.b[3] + lt)));
+    return (s * 12 + c) * nrhs + k;
+  };
+  double4 acc = make_double4(0, 0, 0, 0);
+  if (t < tpb) {
+    for (long j = t / nrhs; j < rows; j += rpb) {
+      const long e = elem(j);
+      const float2 qv = q[e], rv = rho[e];
+      const double qx = qv.x, qy = qv.y, rx = rv.x, ry = rv.y;
+      acc.x = fma(qx, rx, fma(qy, ry, acc.x));
+      acc.y = fma(qx, ry, fma(-qy, rx, acc.y));
+      acc.z = fma(qx, qx, fma(qy, qy, acc.z));
+    }
+  }
+  red[t] = acc;
+  __syncthreads();
+  if (t < nrhs) {
+    double4 sm = red[t];
+    for (int j = t + nrhs; j < tpb; j += nrhs) {
+      sm.x += red[j].x;
+      sm.y += red[j].y;
+      sm.z += red[j].z;
+    }
+    al[t] = sm.z > 0.0 ? make_double2(sm.x / sm.z, sm.y / sm.z) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (t >= tpb) return;
+  const double2 av = al[k];
+  const float ar = (float)av.x, ai = (float)av.y;
+  for (long j = t / nrhs; j < rows; j += rpb) {
+    const long e = elem(j);
+    const float2 rv = rho[e], qv = q[e];
+    float2 xv = x[e];
+    xv.x = fmaf(ar, rv.x, fmaf(-ai, rv.y, xv.x));
+    xv.y = fmaf(ar, rv.y, fmaf(ai, rv.x, xv.y));
+    x[e] = xv;
+    float2 rn;
+    rn.x = fmaf(-ar, qv.x, fmaf(ai, qv.y, rv.x));
+    rn.y = fmaf(-ar, qv.y, fmaf(-ai, qv.x, rv.y));
+    rho[e] = rn;
+  }
+}
+
 // Gram matrix of the nv <= 16 columns of one field, G[a][b] = sum_rows
 // conj(v_a) v_b: workgroup partials over row ranges (rows staged in LDS,
 // thread (a, b) accumulates one entry in FP64), then a fixed-order sum.
@@ -403,6 +475,13 @@ hipError_t launch_sub(int prec64, void* out, const void* a, const void* b, long 
   else
     hipLaunchKernelGGL((sub_fields<float>), dim3(grid_of(n)), dim3(kB), 0, s, static_cast<float2*>(out),
                        static_cast<const float2*>(a), static_cast<const float2*>(b), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sap_block_mr(const AggGeom& a, int nrhs, int color, void* x, void* rho, const void* q, hipStream_t s) {
+  if (nrhs < 1 || nrhs > kB || (color != 0 && color != 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sap_block_mr, dim3((unsigned)a.Vc), dim3(kB), 0, s, a, nrhs, color, static_cast<float2*>(x),
+                     static_cast<float2*>(rho), static_cast<const float2*>(q));
   return hipGetLastError();
 }
 

@@ -466,3 +466,66 @@ def test_solve_coarse_even_odd_smoother(gpu_lib, nrhs):
     assert st2["iters"] == st["iters"] and torch.equal(x, x2)
     mg.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("dims,block,nrhs,cycles,iters", [
+    ((8, 8, 8, 8), (2, 2, 2, 2), 1, 1, 4),
+    ((8, 8, 8, 8), (2, 2, 2, 2), 12, 2, 3),
+    ((8, 8, 8, 8), (4, 4, 4, 4), 5, 1, 4),
+    ((4, 8, 4, 8), (2, 2, 2, 2), 24, 1, 2),
+])
+def test_sap_smoother_alone(gpu_lib, dims, block, nrhs, cycles, iters):
+    """The Schwarz smoother by itself: two levels, no coarse-grid correction
+    (coarsest_iters = 0), so the V-cycle returns `cycles` SAP cycles from zero
+    on D z = v.  Against the FP64 oracle (oracle.sap), per column, at the FP32
+    bar; several block sizes, cycles and MR steps per block, Nrhs not dividing
+    256."""
+    import torch
+
+    from oracle import sap as S
+
+    U = synth.gauge_haar(dims, 6161)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx, mg = build(gpu_lib, dims, U, [block], [4], setup_iters=1, smooth_steps=2)
+    v = synth.spinor_source(dims, nrhs, 9600, np.complex64)
+    z = torch.empty(v.shape, dtype=torch.complex64, device="cuda")
+    mg.precondition(z, dev(v), nu_pre=0, nu_post=cycles, coarsest_iters=0, coarse_prec="f32", fine_sap=True,
+                    sap_iters=iters)
+    want = S.sap_cycles(U, A, KAPPA, v, np.zeros_like(v, dtype=np.complex128), dims, block, cycles, iters)
+    got = z.cpu().numpy()
+    for k in range(nrhs):
+        err = np.linalg.norm(got[:, :, k] - want[:, :, k]) / np.linalg.norm(want[:, :, k])
+        assert err < 1e-5, (k, err)
+    mg.close()
+    ctx.close()
+
+
+def test_sap_rejects_odd_block_counts_and_eo_together(gpu_lib):
+    import torch
+
+    dims = (6, 4, 4, 4)
+    U = synth.gauge_haar(dims, 1)
+    ctx, mg = build(gpu_lib, dims, U, [(2, 2, 2, 2)], [4], setup_iters=0)
+    v = dev(synth.spinor_source(dims, 1, 1, np.complex64))
+    z = torch.empty_like(v)
+    with pytest.raises(gpu_lib.MrhsError, match="SHAPE"):  # three blocks along x
+        mg.precondition(z, v, fine_sap=True)
+    with pytest.raises(gpu_lib.MrhsError, match="INVALID_ARG"):
+        mg.precondition(z, v, fine_sap=True, fine_eo=True)
+    mg.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 12])
+def test_solve_sap_smoother(small, nrhs):
+    """Solves with SAP smoothing on the fine level (8^4, three levels, BF16
+    coarse levels): the 1e-10 true residual recomputed by the oracle."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = synth.spinor_source(dims, nrhs, 9700)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    st = mg.solve(x, dev(b), tol=1e-10, restart=8, max_iters=400, nu_pre=0, nu_post=1, coarsest_iters=16,
+                  coarse_prec="bf16", fine_sap=True, sap_iters=4)
+    assert all(st["converged"])
+    assert np.all(O.true_residual(U, A, KAPPA, x.cpu().numpy(), b, dims) <= 1e-10)
