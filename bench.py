@@ -85,10 +85,10 @@ FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 # it only while the kernel name, sources and configurations still match.
 FINE_TRAFFIC = {
     "kernel": "fine_kernel<float, 2, 0, true, true, 0, HIP_vector_type<float, 2u> >",
-    "sources": "cd77e70bc5b529f7",
+    "sources": "b3131781c87ab680",
     "configs": {"12": [2, [8, 8, 2, 3], 64], "24": [2, [8, 8, 2, 3], 64], "48": [2, [8, 4, 4, 3], 68],
                 "64": [2, [8, 4, 4, 3], 5]},
-    "bytes_per_launch": 6.719e9,
+    "bytes_per_launch": 6.715e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
@@ -150,6 +150,30 @@ def _cpu_task(task):
         else:  # "solve": the oracle's own FP64 GMRES solve on 8^4
             r = O.solve_ref(c["U8"], c["A8"], KAPPA, c["b8"][:, :, k0:k1], (8, 8, 8, 8))
     return float(np.abs(r).sum())
+
+
+def fabric_probe():
+    """Read bandwidth of a device buffer by its size: torch's sum over an FP32
+    buffer read back to back (the previous pass leaves it in whatever cache
+    holds it), GB/s of bytes read.  16 MiB fits the L2s (4 MiB per XCD), 64
+    and 128 MiB the 256 MiB Infinity Cache but not the L2s, 2 GiB neither."""
+    import torch
+
+    out = {}
+    for mib in (16, 64, 128, 512, 2048):
+        x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+        reps = max(4, (8 << 30) // (mib << 20))
+        for _ in range(3):
+            x.sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            x.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{mib}MiB"] = round((mib << 20) * reps / e0.elapsed_time(e1) / 1e6, 1)
+        del x
+    return {"read_GBps_by_buffer_size": out, "method": "torch.sum over an FP32 buffer, back to back"}
 
 
 def cpu_model():
@@ -308,11 +332,11 @@ def solve_restart(elems, free_bytes, reserve=4 << 30):
     """FGMRES restart length for a batch whose fine fields hold `elems` complex numbers
     (V x 12 x Nrhs): the largest m <= SOLVE_RESTART whose solver fields fit in the device
     memory left after the set-up, less a reserve.  Per complex element: m + 1 FP64 basis
-    vectors, m FP32 preconditioned directions, two FP64 work fields, the caller's FP64 x and
+    vectors, m FP32 preconditioned directions, one FP64 work field, the caller's FP64 x and
     b, four FP32 V-cycle fields of the fine level and five half-lattice FP32 fields of the
     even-odd smoother (2.5 full ones)."""
     for m in range(SOLVE_RESTART, 1, -1):
-        per = 16 * (m + 1) + 8 * m + 2 * 16 + 2 * 16 + 4 * 8 + 20
+        per = 16 * (m + 1) + 8 * m + 16 + 2 * 16 + 4 * 8 + 20
         if elems * per <= free_bytes - reserve:
             return m
     return 2
@@ -474,12 +498,19 @@ def main():
     ap.add_argument("--retune", action="store_true", help="tune the fine kernel afresh, ignoring the cache")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--fabric-probe", action="store_true",
+                    help="only measure the read bandwidth of device buffers of 16 MiB .. 2 GiB (L2-, Infinity-Cache- "
+                         "and HBM-resident) and print it as one JSON line")
     a = ap.parse_args()
 
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the lattice domain decomposition "
               "across GPUs is not part of this build)", file=sys.stderr)
         sys.exit(2)
+
+    if a.fabric_probe:
+        print(json.dumps(fabric_probe()), flush=True)
+        return
 
     # the oracle's timing runs first: its worker processes fork from a process
     # that has not touched the GPU
