@@ -205,42 +205,57 @@ __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int 
   }
   const int u0 = EOmode == 1 ? 2 : 0, u1 = EOmode == 2 ? 2 : 18;
   constexpr int KMAX = (18 + WV - 1) / WV;
+  // units are handled in batches: every load of a batch is issued before its
+  // first matrix instruction, so a wavefront waits for memory once per batch
+  // instead of once per unit (with one tile all of a wavefront's units form
+  // one batch; with two tiles batches of three bound the registers)
+  constexpr int PB = NT == 1 ? KMAX : 3;
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    const int u = u0 + wv + k * WV;
-    const bool live = u < u1;
-    const int uc = live ? u : u0;
-    const int d = uc >> 1, kc = uc & 1;
-    const int nbr = stencil_nbr(g, s, x, d);
-    // input row: EO 1 the neighbour's checkerboard index, EO 2 the output row,
-    // EO 3 both (self term on the output row, hops on the neighbours')
-    const int ii = EOmode == 1 ? nbr / 2 : (EOmode == 2 ? io : (EOmode == 3 ? (d == 0 ? io : nbr / 2) : nbr));
-    const uint4* bp = Bp + ((size_t)s * bstride + d) * 256;
-    const uint4 br = bp[(kc * 2 + 0) * 64 + l];
-    const uint4 bi = bp[(kc * 2 + 1) * 64 + l];
-    float2 ev[NT][8];
+  for (int k0 = 0; k0 < KMAX; k0 += PB) {
+    uint4 br[PB], bi[PB];
+    float2 ev[PB][NT][8];
+    bool live[PB];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int kk = 0; kk < PB; ++kk) {
+      const int u = u0 + wv + (k0 + kk) * WV;
+      live[kk] = (k0 + kk < KMAX) && u < u1;
+      const int uc = live[kk] ? u : u0;
+      const int d = uc >> 1, kc = uc & 1;
+      const int nbr = stencil_nbr(g, s, x, d);
+      // input row: EO 1 the neighbour's checkerboard index, EO 2 the output
+      // row, EO 3 both (self term on the output row, hops on the neighbours')
+      const int ii = EOmode == 1 ? nbr / 2 : (EOmode == 2 ? io : (EOmode == 3 ? (d == 0 ? io : nbr / 2) : nbr));
+      const uint4* bp = Bp + ((size_t)s * bstride + d) * 256;
+      br[kk] = bp[(kc * 2 + 0) * 64 + l];
+      bi[kk] = bp[(kc * 2 + 1) * 64 + l];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) ev[t][q] = fetch(ii, (size_t)(kc * 16 + jh + q) * nrhs + colc[t], t, d);
-    const uint4 nbi = make_uint4(bi.x ^ 0x80008000u, bi.y ^ 0x80008000u, bi.z ^ 0x80008000u, bi.w ^ 0x80008000u);
-    const vec ar = __builtin_bit_cast(vec, br);
-    const vec ai = __builtin_bit_cast(vec, bi);
-    const vec an = __builtin_bit_cast(vec, nbi);
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      float er[8], ei[8];
-      const bool on = live && colok[t];
+        for (int q = 0; q < 8; ++q) ev[kk][t][q] = fetch(ii, (size_t)(kc * 16 + jh + q) * nrhs + colc[t], t, d);
+    }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        er[q] = on ? ev[t][q].x * sc[t] : 0.f;
-        ei[q] = on ? ev[t][q].y * sc[t] : 0.f;
+    for (int kk = 0; kk < PB; ++kk) {
+      const uint4 b_i = bi[kk];
+      const uint4 nbi =
+          make_uint4(b_i.x ^ 0x80008000u, b_i.y ^ 0x80008000u, b_i.z ^ 0x80008000u, b_i.w ^ 0x80008000u);
+      const vec ar = __builtin_bit_cast(vec, br[kk]);
+      const vec ai = __builtin_bit_cast(vec, b_i);
+      const vec an = __builtin_bit_cast(vec, nbi);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        float er[8], ei[8];
+        const bool on = live[kk] && colok[t];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          er[q] = on ? ev[kk][t][q].x * sc[t] : 0.f;
+          ei[q] = on ? ev[kk][t][q].y * sc[t] : 0.f;
+        }
+        const vec vr = O::cvt(er), vi = O::cvt(ei);
+        accR[t] = O::mma(ar, vr, accR[t]);
+        accR[t] = O::mma(an, vi, accR[t]);
+        accI[t] = O::mma(ar, vi, accI[t]);
+        accI[t] = O::mma(ai, vr, accI[t]);
       }
-      const vec vr = O::cvt(er), vi = O::cvt(ei);
-      accR[t] = O::mma(ar, vr, accR[t]);
-      accR[t] = O::mma(an, vi, accR[t]);
-      accI[t] = O::mma(ar, vi, accI[t]);
-      accI[t] = O::mma(ai, vr, accI[t]);
     }
   }
 }
