@@ -153,27 +153,29 @@ def _cpu_task(task):
 
 
 def fabric_probe():
-    """Read bandwidth of a device buffer by its size: torch's sum over an FP32
-    buffer read back to back (the previous pass leaves it in whatever cache
-    holds it), GB/s of bytes read.  16 MiB fits the L2s (4 MiB per XCD), 64
-    and 128 MiB the 256 MiB Infinity Cache but not the L2s, 2 GiB neither."""
+    """Read bandwidth of device buffers by size (mrhs_read_probe: 2048
+    workgroups of 256 threads, grid-stride 16-byte reads, so that each XCD's
+    workgroups cover an eighth of the buffer): 16 MiB fits the L2s (4 MiB per
+    XCD), 64 and 128 MiB the 256 MiB Infinity Cache but not the L2s, 2 GiB
+    neither.  Depth 1 (one load in flight per thread) against depth 8 tells a
+    latency-bound rate from a bandwidth-bound one."""
     import torch
 
+    import paper_2211_13719_amd as mrhs
+
+    ctx = mrhs.Context((2, 2, 2, 2), t_bc=-1)
     out = {}
-    for mib in (16, 64, 128, 512, 2048):
-        x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
-        reps = max(4, (8 << 30) // (mib << 20))
-        for _ in range(3):
-            x.sum()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            x.sum()
-        e1.record()
-        torch.cuda.synchronize()
-        out[f"{mib}MiB"] = round((mib << 20) * reps / e0.elapsed_time(e1) / 1e6, 1)
-        del x
-    return {"read_GBps_by_buffer_size": out, "method": "torch.sum over an FP32 buffer, back to back"}
+    for depth in (1, 4, 8):
+        row = {}
+        for mib in (16, 64, 128, 192, 512, 2048):
+            x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+            sweeps = max(2, (8 << 30) // (mib << 20))
+            ms = ctx.read_probe(x, sweeps, 2048, depth)
+            row[f"{mib}MiB"] = round((mib << 20) * sweeps / ms / 1e6, 1)
+            del x
+        out[f"depth{depth}"] = row
+    ctx.close()
+    return {"read_GBps_by_depth_and_buffer_size": out, "method": "mrhs_read_probe, 2048 workgroups of 256 threads"}
 
 
 def cpu_model():

@@ -200,6 +200,20 @@ mrhs_status mrhs_multi_dot(mrhs_ctx ctx, double* out, const void* const* v, int3
 mrhs_status mrhs_multi_dot_noalloc(mrhs_ctx ctx, double* out, const void* const* v, int32_t m, const void* w,
                                    int64_t nsites, int32_t ncomp, int32_t nrhs, mrhs_prec prec,
                                    int32_t out_on_device);
+
+/* mrhs_read_probe: measurement helper for the rooflines of kernels bound by
+ * their L2 misses.  Reads the device buffer buf (bytes, a multiple of 16)
+ * `sweeps` times with `grid` workgroups of 256 threads, each thread reading
+ * 16-byte words in a grid-stride loop, `depth` (1, 2, 4 or 8) independent
+ * words in flight per thread (after one untimed sweep), and returns the
+ * elapsed time in *ms (HIP events on the context stream).  The bytes read per
+ * second tell which level serves a working set of that size (the L2s, 4 MiB
+ * per XCD; the Infinity Cache; HBM) and, across depths, whether the rate is
+ * bound by bandwidth or by the latency of too few loads in flight.  Bad
+ * sizes, sweeps, grid or depth get MRHS_ERR_INVALID_ARG.  Synchronises. */
+mrhs_status mrhs_read_probe(mrhs_ctx ctx, const void* buf, int64_t bytes, int32_t sweeps, int32_t grid, int32_t depth,
+                            float* ms);
+
 /* mrhs_axpy: y_k <- y_k + alpha_k x_k per column, alpha_k = alpha[2k] + i alpha[2k+1]
  * (FP64, host memory if alpha_on_device = 0, else device memory); the update
  * is computed in FP64 and rounded to prec.  x and y must not overlap. */

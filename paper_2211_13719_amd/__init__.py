@@ -233,6 +233,14 @@ class Context:
         self._check(lib.mrhs_norm2(self._h, C.c_void_p(res.ctypes.data), C.c_void_p(pa), ns, nc, n, prec, 0))
         return res
 
+    def read_probe(self, buf, sweeps: int, grid: int, depth: int = 8) -> float:
+        """Milliseconds for `sweeps` grid-stride reads of the device tensor buf,
+        `depth` independent 16-byte loads in flight per thread."""
+        ms = C.c_float()
+        self._check(lib.mrhs_read_probe(self._h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                        int(sweeps), int(grid), int(depth), C.byref(ms)))
+        return float(ms.value)
+
     def multi_dot(self, vs, w, out=None, noalloc=False):
         """(m, nrhs) complex128 array of <v_j,k, w_k>; into the device tensor
         `out` (complex128, (m, nrhs)) when given.  noalloc selects the entry
