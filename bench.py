@@ -121,6 +121,8 @@ def fine_kernel_name(ctx, n):
     R, _, variant, _ = ctx.get_tuning(n)
     R = R or (2 if n % 2 == 0 else 1)
     occ = 4 if variant & 2 else 0
+    if variant & 128:  # the t-walk kernel
+        return f"fine_walk_kernel<{R}, {occ}>"
     return f"fine_kernel<float, {R}, 0, true, true, {occ}, HIP_vector_type<float, 2u> >"
 
 

@@ -116,6 +116,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
             f"{path} is missing; build it with `python -m paper_2211_13719_amd.build` "
             "(the HIP library is required, there is no CPU fallback)"
         )
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so that the streams and device memory the binding passes in belong to
+    # the runtime the library calls (loaded the other way round, the process
+    # can hold two runtimes and the library's may see no device)
+    import torch  # noqa: F401
+
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

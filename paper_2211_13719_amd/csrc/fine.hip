@@ -594,6 +594,215 @@ hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, con
   return hipGetLastError();
 }
 
+// ---- t-walk variant of D = A - kappa H in FP32 ---------------------------------
+// Every thread owns one site of a spatial block (Bx x By x Bz), R right-hand
+// sides, and a run of Ts consecutive time slices that it visits in turn.  The
+// spinor psi(x, t+1) that slice t loads for its forward t-hop stays in
+// registers: it is the clover input of slice t+1, and transported by
+// U_t(x, t)^dag it is the backward t-hop of slice t+1.  So no t-neighbour is
+// read twice, whatever the cache holds.  (Keeping only the transported half
+// spinor and reading the slice's own spinor again takes fewer registers, 166
+// instead of 224 at R = 2, but measured slower at every Nrhs.)  The threads of one block run
+// together, one slice at a time, and read each other's spinors as spatial
+// neighbours at about the same moment, which keeps those re-reads in the L2
+// even when the bytes in flight exceed it (they do at large Nrhs, where the
+// tiled kernel above re-reads every neighbour from memory).
+//
+// Work units are (RHS chunk, t-run, spatial block), numbered with the block
+// fastest; each XCD takes one contiguous range of their workgroups.  The
+// hops are accumulated in the order of fine_kernel (x, y, z, t; forward
+// before backward) with the same arithmetic, so both kernels give
+// bit-identical results.
+struct WalkShape {
+  int B[3];       // spatial block extents
+  int Ts;         // time slices per thread
+  int nc;         // right-hand sides per chunk
+  int groups;     // threads per site and chunk (nc / R)
+  int bs;         // sites per block
+  int nb[2];      // blocks along x, y
+  int nblk;       // blocks per slice run
+  int nseg;       // t-runs (Lt / Ts)
+  int wg_unit;    // workgroups per unit
+  long total_wg;  // workgroups of the whole launch
+  long per;       // workgroups per XCD
+};
+
+template <int R>
+__device__ __forceinline__ void transport_dag(const cplx<float> (&uu)[3][3], const cplx<float> (&h)[2][3][R],
+                                              cplx<float> (&w)[2][3][R]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cplx<float> z = mk<float>(0, 0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) cmac_conj<float>(z, uu[b][a], h[s][b][j]);
+        w[s][a][j] = z;
+      }
+}
+
+template <int R>
+__device__ __forceinline__ void transport(const cplx<float> (&uu)[3][3], const cplx<float> (&h)[2][3][R],
+                                          cplx<float> (&w)[2][3][R]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cplx<float> z = mk<float>(0, 0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) cmac<float>(z, uu[a][b], h[s][b][j]);
+        w[s][a][j] = z;
+      }
+}
+
+template <int R, int OCC>
+__global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geom g, int nrhs, float kappa,
+                                                                           const cplx<float>* __restrict__ U,
+                                                                           const float* __restrict__ A,
+                                                                           const cplx<float>* __restrict__ in,
+                                                                           cplx<float>* __restrict__ out, WalkShape w,
+                                                                           int nt_out) {
+  const int hw = blockIdx.x;
+  const long wgi = (long)(hw & 7) * w.per + (hw >> 3);
+  if (wgi >= w.total_wg) return;
+  const int unit = (int)(wgi / w.wg_unit);
+  const int tid = (int)(wgi - (long)unit * w.wg_unit) * 256 + (int)threadIdx.x;
+  if (tid >= w.bs * w.groups) return;
+  const int sb = tid / w.groups;
+  const int blk = unit % w.nblk, rest = unit / w.nblk;
+  const int seg = rest % w.nseg, chunk = rest / w.nseg;
+  const int k0 = chunk * w.nc + (tid - sb * w.groups) * R;
+  const int x = (blk % w.nb[0]) * w.B[0] + sb % w.B[0];
+  const int y = ((blk / w.nb[0]) % w.nb[1]) * w.B[1] + (sb / w.B[0]) % w.B[1];
+  const int z = (blk / (w.nb[0] * w.nb[1])) * w.B[2] + sb / (w.B[0] * w.B[1]);
+  const int xs = x + g.L[0] * (y + g.L[1] * z);
+  const int Vs = g.stride[3];
+  const int dxf = x + 1 < g.L[0] ? 1 : 1 - g.L[0], dxb = x > 0 ? -1 : g.L[0] - 1;
+  const int dyf = y + 1 < g.L[1] ? g.stride[1] : g.stride[1] * (1 - g.L[1]);
+  const int dyb = y > 0 ? -g.stride[1] : g.stride[1] * (g.L[1] - 1);
+  const int dzf = z + 1 < g.L[2] ? g.stride[2] : g.stride[2] * (1 - g.L[2]);
+  const int dzb = z > 0 ? -g.stride[2] : g.stride[2] * (g.L[2] - 1);
+
+  const int t0 = seg * w.Ts;
+  cplx<float> self[4][3][R], bwd[2][3][R];
+  {
+    const int sm = xs + Vs * ((t0 == 0 ? g.L[3] : t0) - 1);
+    cplx<float> p[4][3][R], h[2][3][R], uu[3][3];
+    load_spinor<float, R>(in, sm, nrhs, k0, p);
+    project<float, R, 3, -1>(p, h);
+    load_link<float, 3>(U + ((size_t)sm * 4 + 3) * 9, uu);
+    transport_dag<R>(uu, h, bwd);
+    load_spinor<float, R>(in, xs + Vs * t0, nrhs, k0, self);
+  }
+  for (int i = 0; i < w.Ts; ++i) {
+    const int t = t0 + i;
+    const int site = xs + Vs * t;
+    cplx<float> acc[4][3][R];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<float>(0, 0);
+    hop_dir<float, R, 0, true>(site, site + dxf, site + dxb, nrhs, k0, U, in, acc);
+    hop_dir<float, R, 1, true>(site, site + dyf, site + dyb, nrhs, k0, U, in, acc);
+    hop_dir<float, R, 2, true>(site, site + dzf, site + dzb, nrhs, k0, U, in, acc);
+    cplx<float> nxt[4][3][R];
+    load_spinor<float, R>(in, xs + Vs * (t + 1 == g.L[3] ? 0 : t + 1), nrhs, k0, nxt);
+    cplx<float> uu[3][3];
+    load_link<float, 3>(U + ((size_t)site * 4 + 3) * 9, uu);
+    {
+      cplx<float> h[2][3][R], wv[2][3][R];
+      project<float, R, 3, +1>(nxt, h);
+      transport<R>(uu, h, wv);
+      reconstruct<float, R, 3, +1>(acc, wv);
+      pin<float, R>(acc);
+    }
+    reconstruct<float, R, 3, -1>(acc, bwd);
+    pin<float, R>(acc);
+    {
+      cplx<float> h[2][3][R];
+      project<float, R, 3, -1>(self, h);
+      transport_dag<R>(uu, h, bwd);
+    }
+    cplx<float>* o = out + (size_t)site * 12 * nrhs + k0;
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      cplx<float> xin[6][R], yout[6][R];
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int j = 0; j < R; ++j) xin[q][j] = self[(6 * chi + q) / 3][(6 * chi + q) % 3][j];
+      clover_block<float, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int sp = 2 * chi + q / 3, c = q % 3;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          yout[q][j].x = fma(-kappa, acc[sp][c][j].x, yout[q][j].x);
+          yout[q][j].y = fma(-kappa, acc[sp][c][j].y, yout[q][j].y);
+        }
+        store_r<float, R>(o + (6 * chi + q) * nrhs, yout[q], nt_out);
+      }
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < R; ++j) self[sp][c][j] = nxt[sp][c][j];
+  }
+}
+
+// Shape of a t-walk launch for tile T = (Bx, By, Bz, Ts) and nc = nrhs / chunks
+// right-hand sides per chunk; false if the tile does not divide the lattice.
+bool walk_shape(const Geom& g, const int T[4], int nrhs, int R, int chunks, WalkShape& w) {
+  for (int m = 0; m < 4; ++m)
+    if (T[m] < 1 || g.L[m] % T[m]) return false;
+  if (chunks < 1 || nrhs % chunks || (nrhs / chunks) % R) return false;
+  for (int m = 0; m < 3; ++m) w.B[m] = T[m];
+  w.Ts = T[3];
+  w.nc = nrhs / chunks;
+  w.groups = w.nc / R;
+  w.bs = T[0] * T[1] * T[2];
+  w.nb[0] = g.L[0] / T[0];
+  w.nb[1] = g.L[1] / T[1];
+  w.nblk = w.nb[0] * w.nb[1] * (g.L[2] / T[2]);
+  w.nseg = g.L[3] / T[3];
+  w.wg_unit = (w.bs * w.groups + 255) / 256;
+  const long units = (long)chunks * w.nseg * w.nblk;
+  w.total_wg = units * w.wg_unit;
+  w.per = (w.total_wg + 7) / 8;
+  return w.per * 8 <= 0x7fffffffL;
+}
+
+template <int R, int OCC>
+hipError_t launch_walk_r(const Geom& g, const FineCfg& c, float kappa, const void* U, const void* A, const void* in,
+                         void* out, int nrhs, hipStream_t s) {
+  WalkShape w;
+  if (!walk_shape(g, c.T, nrhs, R, c.chunks, w)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fine_walk_kernel<R, OCC>), dim3((unsigned)(w.per * 8)), dim3(256), c.lds, s, g, nrhs, kappa,
+                     reinterpret_cast<const cplx<float>*>(U), reinterpret_cast<const float*>(A),
+                     reinterpret_cast<const cplx<float>*>(in), reinterpret_cast<cplx<float>*>(out), w, c.nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk(const Geom& g, const FineCfg& c, float kappa, const void* U, const void* A, const void* in,
+                       void* out, int nrhs, hipStream_t s) {
+  if (c.occ == 4) {
+    if (c.R == 2) return launch_walk_r<2, 4>(g, c, kappa, U, A, in, out, nrhs, s);
+    if (c.R == 1) return launch_walk_r<1, 4>(g, c, kappa, U, A, in, out, nrhs, s);
+  } else {
+    if (c.R == 2) return launch_walk_r<2, 0>(g, c, kappa, U, A, in, out, nrhs, s);
+    if (c.R == 1) return launch_walk_r<1, 0>(g, c, kappa, U, A, in, out, nrhs, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int MODE>
 hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const void* A, const void* in,
                        void* out, int nrhs, hipStream_t s, const FineCfg* cfg) {
@@ -614,6 +823,7 @@ hipError_t launch_mode(const Geom& g, int t_bc, T kappa, const void* U, const vo
     if (ch < 1 || nrhs % ch || (nrhs / ch) % R) ch = 1;
     const DirFilter f;
     if constexpr (MODE == 0) {
+      if (tuned && cfg->walk) return launch_walk(g, *cfg, kappa, U, A, in, out, nrhs, s);
       if (occ4) {
         if (R == 4) return launch_r<T, 4, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);
         if (R == 2) return launch_r<T, 2, MODE, 4>(g, order, kappa, U, A, in, out, nrhs, s, f, nt, ch, lds);

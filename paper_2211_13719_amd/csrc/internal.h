@@ -63,6 +63,7 @@ struct FineCfg {
   int R = 0;
   int T[4] = {0, 0, 0, 0};
   int curve = 0;               // tile order: 0 lexicographic, 1 Morton in (x, y, z) per t-row of tiles
+  int walk = 0;                // 1: t-walk kernel (MODE 0), T = spatial block and time slices per thread
   int occ = 0;                 // 0: compiler's register choice; 4: at least 4 wavefronts per SIMD
   int nt = 0;                  // 1: non-temporal output stores
   int chunks = 1;              // RHS chunks swept one after the other (1, 2, 4)

@@ -1,5 +1,6 @@
 // Autotuner of the FP32 fine Wilson-clover kernel: for each requested Nrhs it
-// times launch configurations -- traversal tile and tile order, right-hand
+// times launch configurations -- traversal tile and tile order, or the t-walk
+// kernel with its spatial block and time slices per thread, right-hand
 // sides per thread (1, 2, 4), RHS chunks swept in turn (1, 2, 4; the tiles
 // are scanned again if chunking wins), a cap on resident workgroups per CU,
 // register budget, ordinary or non-temporal output stores -- on scratch
@@ -13,6 +14,8 @@
 //   <arch> <hip runtime version> <Lx> <Ly> <Lz> <Lt> <nrhs> <R> <Tx> <Ty> <Tz> <Tt> <curve> <occupancy> <nt>
 //   <chunks> <cap> <microseconds>
 //
+// (curve 2 selects the t-walk kernel, Tx Ty Tz Tt then being its spatial
+// block and time slices per thread)
 // (one line each; a line tuned under another runtime or of another format is
 // ignored, so a new ROCm retunes).
 #include <algorithm>
@@ -74,6 +77,23 @@ std::vector<std::array<int, 4>> tile_candidates(const Geom& g) {
   return out;
 }
 
+// t-walk tiles (spatial block Bx x By x Bz, time slices per thread Ts): the
+// block's sites x Nrhs / R threads should about fill what one XCD keeps
+// resident, and Ts trades the two extra slices each run reads against the
+// number of runs that balance the XCDs.
+std::vector<std::array<int, 4>> walk_candidates(const Geom& g) {
+  const std::array<int, 3> blocks[] = {{8, 8, 8}, {8, 8, 6}, {8, 8, 4}, {8, 8, 3},  {12, 8, 4}, {12, 12, 4},
+                                       {6, 6, 6}, {8, 4, 4}, {4, 4, 4}, {12, 12, 2}, {24, 8, 2}, {24, 4, 4}};
+  std::vector<std::array<int, 4>> out;
+  for (const auto& b : blocks)
+    for (int div : {1, 2, 4, 8}) {
+      if (g.L[3] % div) continue;
+      const int T[4] = {b[0], b[1], b[2], g.L[3] / div};
+      if (divides(g, T)) out.push_back({T[0], T[1], T[2], T[3]});
+    }
+  return out;
+}
+
 int runtime_version() {
   int v = 0;
   return hipRuntimeGetVersion(&v) == hipSuccess ? v : 0;
@@ -115,12 +135,14 @@ bool cache_lookup(const char* path, const std::string& arch, const Geom& g, int 
       continue;  // lines of other formats are ignored
     if (arch == a && hv == runtime_version() && n == nrhs && L[0] == g.L[0] && L[1] == g.L[1] && L[2] == g.L[2] &&
         L[3] == g.L[3] &&
-        (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve == 0 || curve == 1) &&
+        (R == 1 || R == 2 || R == 4) && nrhs % R == 0 && divides(g, T) && (curve >= 0 && curve <= 2) &&
+        (curve != 2 || R <= 2) &&
         (occ == 0 || occ == 4) && (nt == 0 || nt == 1) && (ch == 1 || ch == 2 || ch == 4) && nrhs % ch == 0 &&
         (nrhs / ch) % R == 0 && cap >= 0 && cap <= 3) {
       out.R = R;
       for (int m = 0; m < 4; ++m) out.T[m] = T[m];
-      out.curve = curve;
+      out.walk = curve == 2;  // 2 marks the t-walk kernel
+      out.curve = curve == 2 ? 0 : curve;
       out.occ = occ;
       out.nt = nt;
       out.chunks = ch;
@@ -138,7 +160,8 @@ void cache_append(const char* path, const std::string& arch, const Geom& g, int 
   FILE* f = std::fopen(path, "a");
   if (!f) return;
   std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.2f\n", arch.c_str(), runtime_version(), g.L[0],
-               g.L[1], g.L[2], g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.curve, c.occ, c.nt, c.chunks, c.cap,
+               g.L[1], g.L[2], g.L[3], nrhs, c.R, c.T[0], c.T[1], c.T[2], c.T[3], c.walk ? 2 : c.curve, c.occ, c.nt, c.chunks,
+               c.cap,
                c.us);
   std::fclose(f);
 }
@@ -185,7 +208,7 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
     const int n = nrhs_list[i];
     FineCfg best;
     if (cache_lookup(cache_path, arch, ctx->g, n, best)) {
-      best.order = fine_order_table(ctx, best.T, best.curve);
+      best.order = best.walk ? ctx->g.order : fine_order_table(ctx, best.T, best.curve);
       best.lds = cap_lds(ctx->device, best.cap);
       if (best.cap && !best.lds) best.cap = 0;
       if (best.order) {
@@ -196,7 +219,8 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
     // coordinate descent: tile and tile order first (two RHS per thread for
     // even Nrhs), then RHS per thread, register budget and store kind
     auto time_cfg = [&](FineCfg& cfg) -> hipError_t {
-      cfg.order = fine_order_table(ctx, cfg.T, cfg.curve);
+      // a t-walk ignores the traversal table; the other modes keep the default
+      cfg.order = cfg.walk ? ctx->g.order : fine_order_table(ctx, cfg.T, cfg.curve);
       if (!cfg.order) return hipErrorOutOfMemory;
       std::vector<float> t;
       hipError_t err = hipSuccess;
@@ -230,7 +254,24 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
         }
       }
     };
+    // t-walk: one or two RHS per thread over every walk tile, at the current chunking
+    auto scan_walks = [&](const FineCfg& base) {
+      for (int R : {1, 2}) {
+        if ((n / base.chunks) % R) continue;
+        for (const auto& t : walk_candidates(ctx->g)) {
+          FineCfg cfg = base;
+          cfg.R = R;
+          cfg.walk = 1;
+          cfg.curve = 0;
+          for (int m = 0; m < 4; ++m) cfg.T[m] = t[m];
+          e = time_cfg(cfg);
+          if (e != hipSuccess) return;
+          if (cfg.us < best.us) best = cfg;
+        }
+      }
+    };
     scan_tiles(best);
+    if (e == hipSuccess) scan_walks(best);
     // stages: 0 RHS per thread, 1 RHS chunks, 2 workgroups per CU, 3 register budget, 4 store kind
     for (int stage = 0; stage < 5 && e == hipSuccess; ++stage) {
       const FineCfg cur = best;
@@ -243,7 +284,7 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
       for (int v : opts) {
         FineCfg cfg = cur;
         if (stage == 0) {
-          if (n % v || v == cur.R || (n / cur.chunks) % v) continue;
+          if (n % v || v == cur.R || (n / cur.chunks) % v || (cur.walk && v > 2)) continue;
           cfg.R = v;
         } else if (stage == 1) {
           if (v == cur.chunks || n % v || (n / v) % cur.R) continue;
@@ -265,7 +306,12 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
         if (cfg.us < best.us) best = cfg;
       }
       // chunking changes the bytes per site a sweep keeps in L2: re-scan the tiles
-      if (stage == 1 && e == hipSuccess && best.chunks != cur.chunks) scan_tiles(best);
+      if (stage == 1 && e == hipSuccess && best.chunks != cur.chunks) {
+        if (best.walk)
+          scan_walks(best);
+        else
+          scan_tiles(best);
+      }
     }
     if (e == hipSuccess) {
       ctx->fine_cfg[n] = best;
@@ -290,7 +336,9 @@ mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread,
   if (rhs_per_thread) *rhs_per_thread = c.R;
   if (tile)
     for (int m = 0; m < 4; ++m) tile[m] = c.T[m];
-  if (curve) *curve = c.curve + 2 * (c.occ == 4) + 4 * c.nt + 8 * (c.chunks == 4 ? 2 : c.chunks == 2 ? 1 : 0) + 32 * c.cap;
+  if (curve)
+    *curve = c.curve + 2 * (c.occ == 4) + 4 * c.nt + 8 * (c.chunks == 4 ? 2 : c.chunks == 2 ? 1 : 0) + 32 * c.cap +
+             128 * c.walk;
   if (us) *us = c.us;
   return MRHS_OK;
 }

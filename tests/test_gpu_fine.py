@@ -174,8 +174,9 @@ def _cached_lines(path, arch, dims):
         n, R = int(f[5]), int(f[6])
         tile = tuple(map(int, f[7:11]))
         curve, occ, nt, chunks, cap = map(int, f[11:16])
-        variant = curve + 2 * (occ == 4) + 4 * nt + 8 * {1: 0, 2: 1, 4: 2}[chunks] + 32 * cap
-        out[n] = (R, tile, variant)
+        walk = curve == 2  # the t-walk kernel
+        variant = (0 if walk else curve) + 2 * (occ == 4) + 4 * nt + 8 * {1: 0, 2: 1, 4: 2}[chunks] + 32 * cap
+        out[n] = (R, tile, variant + 128 * walk)
     return out
 
 
@@ -250,7 +251,7 @@ def test_autotune_bitwise_and_cache(small, tmp_path):
     ctx.tune([1, 6, 12], cache)
     for n, (x, y0) in outs.items():
         R, tile, curve, us = ctx.get_tuning(n)
-        assert R in (1, 2, 4) and n % R == 0 and us > 0 and 0 <= curve < 128
+        assert R in (1, 2, 4) and n % R == 0 and us > 0 and 0 <= curve < 256
         assert all(t >= 1 and L % t == 0 for t, L in zip(tile, dims))
         y = torch.empty_like(x)
         ctx.dwc(y, x)
@@ -269,6 +270,11 @@ def test_autotune_bitwise_and_cache(small, tmp_path):
         (4, (8, 4, 4, 1), 0, 0, 0, 2, 2),
         (2, (2, 2, 2, 8), 1, 0, 1, 1, 1),
         (4, (1, 1, 1, 1), 0, 4, 0, 1, 2),
+        # t-walk kernel (curve 2): spatial block, time slices per thread
+        (1, (4, 4, 4, 8), 2, 0, 0, 1, 0),
+        (2, (8, 8, 8, 2), 2, 4, 1, 2, 0),
+        (1, (2, 4, 8, 1), 2, 0, 1, 4, 1),
+        (2, (8, 2, 4, 4), 2, 4, 0, 1, 2),
     ],
 )
 def test_launch_configurations_bitwise(small, tmp_path, R, tile, curve, occ, nt, chunks, cap):
@@ -290,8 +296,40 @@ def test_launch_configurations_bitwise(small, tmp_path, R, tile, curve, occ, nt,
     ctx.tune([n], str(cache))
     got = ctx.get_tuning(n)
     assert got[0] == R and tuple(got[1]) == tile
-    assert got[2] & 1 == curve and bool(got[2] & 2) == (occ == 4) and bool(got[2] & 4) == bool(nt)
+    assert bool(got[2] & 128) == (curve == 2) and got[2] & 1 == curve % 2
+    assert bool(got[2] & 2) == (occ == 4) and bool(got[2] & 4) == bool(nt)
     assert 1 << ((got[2] >> 3) & 3) == chunks
     y = torch.empty_like(x)
     ctx.dwc(y, x)
     assert torch.equal(y, y0)
+
+
+@pytest.mark.parametrize("tile,R,chunks", [((2, 4, 2, 3), 1, 1), ((3, 2, 4, 2), 2, 2), ((6, 4, 8, 6), 1, 4)])
+def test_walk_kernel_on_an_anisotropic_lattice(gpu_lib, tmp_path, tile, R, chunks):
+    """The t-walk kernel on a lattice with four different extents (a mixed-up
+    coordinate or stride shows), against the oracle and bit for bit against
+    the tiled kernel; the runs of Ts slices wrap through the antiperiodic t
+    boundary, and the last tile is one run over the whole t extent."""
+    import torch
+
+    dims = (6, 4, 8, 6)
+    U = synth.gauge_haar(dims, 1301)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx = _ctx(gpu_lib, dims, U)
+    n = 12
+    psi = synth.spinor_source(dims, n, 1302, np.complex64)
+    x = _dev(torch, psi)
+    y0 = torch.empty_like(x)
+    ctx.dwc(y0, x)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "walk.txt"
+    cache.write_text(f"{arch} {_hip_runtime_version()} {' '.join(map(str, dims))} {n} {R} {' '.join(map(str, tile))} "
+                     f"2 0 0 {chunks} 0 1.0\n")
+    ctx.tune([n], str(cache))
+    got = ctx.get_tuning(n)
+    assert got[0] == R and tuple(got[1]) == tile and got[2] & 128
+    y = torch.empty_like(x)
+    ctx.dwc(y, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0)
+    assert rel_l2(y.cpu().numpy(), O.dwc(U, A, KAPPA, psi, dims)) < 1e-6
