@@ -75,6 +75,9 @@ SOLVE_MRHS_COARSE_EO = True
 # Schwarz (SAP) smoothing of the fine level, measured beside the even-odd smoother: cycles per smoothing pass and
 # MR steps per 4^4 block solve
 SOLVE_SAP_CYCLES, SOLVE_SAP_ITERS = 1, 4
+# outer Krylov basis in FP32 between FP64 restarts (FP64 true residual and solution): half the outer solver's
+# memory traffic; the FP64 basis is timed beside it on the first batch size
+SOLVE_KRYLOV_F32 = True
 TUNE_CACHE = os.path.join(HERE, "paper_2211_13719_amd", "tuning", "fine.txt")
 FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 
@@ -332,15 +335,16 @@ def bench_evenodd(ctx, mg, torch, stream, fine, coarse, V, warmup, steps):
     return out
 
 
-def solve_restart(elems, free_bytes, reserve=4 << 30):
+def solve_restart(elems, free_bytes, krylov_f32=SOLVE_KRYLOV_F32, reserve=4 << 30):
     """FGMRES restart length for a batch whose fine fields hold `elems` complex numbers
     (V x 12 x Nrhs): the largest m <= SOLVE_RESTART whose solver fields fit in the device
-    memory left after the set-up, less a reserve.  Per complex element: m + 1 FP64 basis
-    vectors, m FP32 preconditioned directions, one FP64 work field, the caller's FP64 x and
-    b, four FP32 V-cycle fields of the fine level and five half-lattice FP32 fields of the
-    even-odd smoother (2.5 full ones)."""
+    memory left after the set-up, less a reserve.  Per complex element: m + 1 basis vectors
+    (FP64, or FP32 with an FP32 work field beside them), m FP32 preconditioned directions,
+    one FP64 work field, the caller's FP64 x and b, four FP32 V-cycle fields of the fine
+    level and five half-lattice FP32 fields of the even-odd smoother (2.5 full ones)."""
     for m in range(SOLVE_RESTART, 1, -1):
-        per = 16 * (m + 1) + 8 * m + 16 + 2 * 16 + 4 * 8 + 20
+        basis = 8 * (m + 1) + 8 if krylov_f32 else 16 * (m + 1)
+        per = basis + 8 * m + 16 + 2 * 16 + 4 * 8 + 20
         if elems * per <= free_bytes - reserve:
             return m
     return 2
@@ -369,7 +373,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     print(f"[bench] device memory after set-up: {free0 / 2**30:.1f} GiB free of {total / 2**30:.1f} GiB",
           file=sys.stderr, flush=True)
     vc = dict(SOLVE_VC, fine_eo=SOLVE_MRHS_FINE_EO, coarse_eo=SOLVE_MRHS_COARSE_EO)
-    kw = dict(tol=1e-10, max_iters=SOLVE_MAXIT, check=False)
+    kp = mrhs.F32 if SOLVE_KRYLOV_F32 else mrhs.F64
+    kw = dict(tol=1e-10, max_iters=SOLVE_MAXIT, check=False, krylov_prec=kp)
     mrhs_res, phases = {}, None
     for n in nrhs_list:
         m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n, free0)
@@ -440,6 +445,25 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         torch.cuda.empty_cache()
     except Exception as exc:
         sap = {"error": f"{type(exc).__name__}: {exc}"}
+    # the same MRHS solve (first batch size) with the other outer Krylov basis precision
+    other_basis = None
+    try:
+        b = torch.from_numpy(synth.spinor_source(SOLVE_DIMS, n0, 4000)).cuda()
+        x = torch.zeros_like(b)
+        alt = not SOLVE_KRYLOV_F32
+        m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n0, free0, alt)
+        st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", restart=m,
+                      **dict(kw, krylov_prec=mrhs.F32 if alt else mrhs.F64), **vc)
+        other_basis = {"krylov_basis": "fp32" if alt else "fp64", "nrhs": n0, "restart": m,
+                       "s_per_rhs": round(st["seconds_total"] / n0, 4), "seconds": round(st["seconds_total"], 3),
+                       "iters": st["iters"], "converged": int(sum(st["converged"])),
+                       "max_true_resid": max(st["rel_resid"])}
+        print(f"[bench] MRHS solve N={n0} with the {'FP32' if alt else 'FP64'} Krylov basis: "
+              f"{st['seconds_total']:.2f} s, {st['iters']} iterations", file=sys.stderr, flush=True)
+        del b, x
+        torch.cuda.empty_cache()
+    except Exception as exc:
+        other_basis = {"error": f"{type(exc).__name__}: {exc}"}
     # the comparator is the faster of the two fine smoothers on one RHS, with
     # the FP32 coarse stencil kernel tuned for one RHS
     mg.tune([1])
@@ -476,7 +500,10 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "mrhs_phase_s": phases,
         "mrhs_other_level1_smoother": coarse_eo,
         "mrhs_sap_smoother": sap,
-        "config": f"FP64 FGMRES({SOLVE_RESTART}, shorter where the batch's fields would not fit in HBM), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
+        "mrhs_other_krylov_basis": other_basis,
+        "config": f"FP64 FGMRES({SOLVE_RESTART}, shorter where the batch's fields would not fit in HBM) with the "
+                  f"Krylov basis in {'FP32 between FP64 restarts' if SOLVE_KRYLOV_F32 else 'FP64'} (both MRHS and "
+                  f"SRHS), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
                   f"levels and BF16 matrix-core restrict/prolong, fine_eo {int(SOLVE_MRHS_FINE_EO)} (fine smoothing "
                   f"on the even-odd Schur complement), coarse_eo {int(SOLVE_MRHS_COARSE_EO)} (level-1 smoothing on "
                   "the coarse Schur complement), graph replay; SRHS comparator: same solver, one RHS, FP32 "

@@ -411,6 +411,11 @@ typedef struct {
                            ||w||^2 for some RHS: 0.5 is the classical "twice is enough" test, 0 never;
                            one FP64 pass loses about eps / sqrt(reorth_eta) of orthogonality, so 1e-2
                            (the Python default) costs nothing in convergence at FP64 */
+  int32_t krylov_prec;  /* storage of the Krylov basis: MRHS_F64 (0), or MRHS_F32: basis vectors in
+                           FP32 (inner products and updates computed in FP64) and the FP32 operator
+                           in the Arnoldi step, each cycle an FP32 Krylov solve of the FP64 residual;
+                           the restarts (FP64 true residual, FP64 x) reach the same FP64 tolerance,
+                           with half the outer solver's memory traffic and basis footprint */
 } mrhs_solve_params;
 
 typedef struct {
@@ -460,10 +465,12 @@ typedef struct {
 mrhs_status mrhs_mg_setup(mrhs_mg mg, const mrhs_setup_params* params);
 /* mrhs_mg_solve: solves D x_k = b_k for the context's fine operator
  * D = A - kappa H (for the mass form D_m = D / (2 kappa) pass 2 kappa b), by
- * FGMRES(m) in FP64 with the V-cycle as preconditioner.  x: device FP64
- * [V][12][nrhs], in: initial guess, out: solution; b: device FP64, not
- * overlapping x.  Returns MRHS_ERR_NOT_CONVERGED (stats filled, x holds the
- * last iterate) if max_iters is reached first.  Synchronises. */
+ * FGMRES(m) in FP64 with the V-cycle as preconditioner (the Krylov basis in
+ * FP64 or, with params->krylov_prec = MRHS_F32, in FP32 between FP64
+ * restarts).  x: device FP64 [V][12][nrhs], in: initial guess, out: solution;
+ * b: device FP64, not overlapping x.  Returns MRHS_ERR_NOT_CONVERGED (stats
+ * filled, x holds the last iterate) if max_iters is reached first; an
+ * unsupported krylov_prec gets MRHS_ERR_UNSUPPORTED.  Synchronises. */
 mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, const mrhs_solve_params* params,
                           mrhs_solve_stats* stats);
 
@@ -473,7 +480,9 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * configuration -- right-hand sides per thread 1, 2 or 4, a set of site
  * traversal tiles that divide the lattice (including slabs of Lt / 8 time
  * slices, one per XCD, and columns of the full time extent), two tile orders
- * (lexicographic, Morton), the right-hand sides split into 1, 2 or 4 chunks
+ * (lexicographic, Morton), or the t-walk kernel (each thread walks a run of
+ * time slices of one site of a spatial block, carrying its t-neighbours in
+ * registers) with its block and run length, the right-hand sides split into 1, 2 or 4 chunks
  * swept one after the other, at most 1, 2 or 3 workgroups per CU or no limit,
  * two register budgets (the compiler's, and one that admits 4 wavefronts per
  * SIMD) and ordinary or non-temporal output stores -- on
@@ -485,11 +494,13 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * clover.  Synchronises. */
 mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, const char* cache_path);
 /* mrhs_get_tuning: the configuration in use for nrhs: right-hand sides per
- * thread (0 = untuned default), tile[4] (0 = default tile), variant = tile
+ * thread (0 = untuned default), tile[4] (0 = default tile; for the t-walk
+ * kernel its spatial block and time slices per thread), variant = tile
  * order (0 lexicographic, 1 Morton) + 2 if compiled for at least 4
  * wavefronts per SIMD + 4 if the output is written with non-temporal
- * stores + 8 log2(RHS chunks) + 32 (workgroups-per-CU limit, 0 = none),
- * measured microseconds (0 if untuned).  Any output pointer may be NULL. */
+ * stores + 8 log2(RHS chunks) + 32 (workgroups-per-CU limit, 0 = none)
+ * + 128 for the t-walk kernel, measured microseconds (0 if untuned).  Any
+ * output pointer may be NULL. */
 mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
                             float* us);
 

@@ -508,8 +508,9 @@ class Multigrid:
         return z
 
     def solve(self, x, b, tol=1e-10, restart=8, max_iters=500, precondition=True, use_graph=True, timers=False,
-              check=True, reorth_eta=0.01, **vc):
+              check=True, reorth_eta=0.01, krylov_prec=F64, **vc):
         """Solve D x_k = b_k (complex128 fields (V, 12, N); x holds the initial guess).
+        krylov_prec F32 stores the outer Krylov basis in FP32 (FP64 restarts).
         Returns a dict of statistics; raises MrhsError unless converged when check is set."""
         n, prec = self._pair(x, b, 0, 0)
         if prec != F64:
@@ -519,6 +520,7 @@ class Multigrid:
         p.precondition, p.use_graph, p.timers = int(bool(precondition)), int(bool(use_graph)), int(bool(timers))
         p.vc = self._vc(**vc)
         p.reorth_eta = float(reorth_eta)
+        p.krylov_prec = int(krylov_prec)
         st = _lib.SolveStats()
         status = lib.mrhs_mg_solve(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(b.data_ptr()), n, C.byref(p),
                                    C.byref(st))

@@ -91,7 +91,7 @@ class SetupParams(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", _f64), ("restart", _i32), ("max_iters", _i32), ("precondition", _i32), ("use_graph", _i32),
-                ("timers", _i32), ("vc", VcycleParams), ("reorth_eta", _f64)]
+                ("timers", _i32), ("vc", VcycleParams), ("reorth_eta", _f64), ("krylov_prec", _i32)]
 
 
 class SolveStats(C.Structure):

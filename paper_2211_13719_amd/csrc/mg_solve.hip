@@ -69,7 +69,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 size_t col_gram_scratch_bytes();
 hipError_t launch_col_gram(const void* v, long rows, int nv, void* scratch, void* g, hipStream_t s);
 hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipStream_t s);
-hipError_t launch_multi_axpy_norm(void* y, void* y32, const void* yin, const void* coef, const void* cscale,
+hipError_t launch_multi_axpy_norm(int prec64, void* y, void* y32, const void* yin, const void* coef, const void* cscale,
                                  const void* const* xs, int m, double sgn, long rows, int nrhs, void* norms,
                                  void* scratch, hipStream_t s);
 hipError_t launch_sub_dual(void* out, void* out32, const void* a, const void* b, long n, hipStream_t s);
@@ -84,6 +84,7 @@ struct GraphSlot {
   hipGraphExec_t exec = nullptr;
   int n = 0;
   void* out = nullptr;
+  const void* in = nullptr;  // the fine-level right-hand side the cycle reads (null: lb[0])
   mrhs_vcycle_params vc{};
   uint64_t gen = 0;  // the context's operator generation at capture
 };
@@ -104,9 +105,13 @@ struct SolverState {
   // even-odd coarse smoother: seven checkerboard fields per level of ceo_n columns
   Buffer ceo[MRHS_MAX_LEVELS];
   int ceo_n = 0;
-  // outer Krylov
-  int m = 0, on = 0;
-  Buffer V64, Z32, w64;
+  // outer Krylov: the basis (FP64 or FP32, kprec), the preconditioned
+  // directions (FP32), the FP64 work field and, with an FP32 basis, an FP32 one
+  int m = 0, on = 0, kprec = -1;
+  Buffer V64, Z32, w64, w32;
+  // fine-level right-hand side of the V-cycle when it is not lb[0] (an FP32
+  // basis vector of the outer solver, read in place)
+  const void* b0 = nullptr;
   // captured V-cycles, one per destination slot
   GraphSlot graphs[kGraphSlots];
   // phase timers
@@ -130,7 +135,7 @@ void mg_solver_release(mrhs_mg mg) {
     release(st->ceo[l]);
   }
   Buffer* b[] = {&st->alpha, &st->part, &st->scl, &st->coef, &st->qn, &st->gpart, &st->gmat, &st->gT,
-                 &st->V64, &st->Z32, &st->w64, &st->eo, &st->eo_part, &st->mralpha, &st->mrpart};
+                 &st->V64, &st->Z32, &st->w64, &st->w32, &st->eo, &st->eo_part, &st->mralpha, &st->mrpart};
   for (Buffer* x : b) release(*x);
   for (auto& gs : st->graphs)
     if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
@@ -434,7 +439,7 @@ hipError_t smooth(mrhs_mg mg, SolverState* st, int l, void* x, void* r, const vo
 hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_params& vc, void* xout = nullptr) {
   const long rows = level_rows(mg, l);
   const size_t bytes = (size_t)rows * n * 8;
-  void* b = st->lb[l].p;
+  const void* b = (l == 0 && st->b0) ? st->b0 : st->lb[l].p;
   void* x = xout ? xout : st->lx[l].p;
   void* r = st->lr[l].p;
   void* p = st->lp[l].p;
@@ -481,7 +486,7 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   return e;
 }
 
-// Runs one V-cycle on lb[0] -> xout (lx[0] if null), from a captured graph
+// Runs one V-cycle on st->b0 (lb[0] if null) -> xout (lx[0] if null), from a captured graph
 // when asked.  One graph is kept per slot (the outer solver uses slot j for
 // its direction Z_j), so the V-cycle writes straight into its destination.
 mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_params& vc, bool graph,
@@ -497,7 +502,7 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
                     gs.vc.nu_post == vc.nu_post && gs.vc.coarsest_iters == vc.coarsest_iters &&
                     gs.vc.coarse_prec == vc.coarse_prec && gs.vc.fine_eo == vc.fine_eo &&
                     gs.vc.coarse_eo == vc.coarse_eo && gs.vc.fine_sap == vc.fine_sap &&
-                    gs.vc.sap_iters == vc.sap_iters &&
+                    gs.vc.sap_iters == vc.sap_iters && gs.in == st->b0 &&
                     gs.gen == ctx->op_gen;
   if (!same) {
     if (gs.exec) {
@@ -519,6 +524,7 @@ mrhs_status run_vcycle(mrhs_mg mg, SolverState* st, int n, const mrhs_vcycle_par
     gs.n = n;
     gs.vc = vc;
     gs.out = xout;
+    gs.in = st->b0;
     gs.gen = ctx->op_gen;
   }
   SOLVER_HIP(hipGraphLaunch(gs.exec, st->stream));
@@ -850,6 +856,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   if (!(prm->tol > 0.0) || prm->max_iters < 1) return fail(ctx, MRHS_ERR_INVALID_ARG, "bad tol or max_iters");
   if (!(prm->reorth_eta >= 0.0 && prm->reorth_eta <= 1.0))
     return fail(ctx, MRHS_ERR_INVALID_ARG, "reorth_eta must lie in [0, 1]");
+  if (prm->krylov_prec != MRHS_F64 && prm->krylov_prec != MRHS_F32)
+    return fail(ctx, MRHS_ERR_UNSUPPORTED, "Krylov basis precision %d not supported", (int)prm->krylov_prec);
   mrhs_status s = MRHS_OK;
   if (prm->precondition) {
     s = check_vc(mg, &prm->vc);
@@ -871,17 +879,22 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   if (s == MRHS_OK && prm->precondition) s = prepare_eo(mg, st, nrhs, prm->vc);
   if (s != MRHS_OK) return s;
   const int n = nrhs;
+  const bool k32 = prm->krylov_prec == MRHS_F32;
   const size_t f64 = (size_t)rows * n * 16, f32 = (size_t)rows * n * 8;
-  if (st->m < m || st->on < n) {
-    drop_graphs(st);  // they write into Z, which is reallocated
+  const size_t fv = k32 ? f32 : f64;  // one basis vector
+  if (st->m < m || st->on < n || st->kprec != (int)k32) {
+    drop_graphs(st);  // they read V and write into Z, which are reallocated
     release(st->V64);
     release(st->Z32);
-    s = ensure(ctx, st->V64, (size_t)(m + 1) * f64);
+    release(st->w32);
+    s = ensure(ctx, st->V64, (size_t)(m + 1) * fv);
     if (s == MRHS_OK) s = ensure(ctx, st->Z32, (size_t)m * f32);
     if (s == MRHS_OK) s = ensure(ctx, st->w64, f64);
+    if (s == MRHS_OK && k32) s = ensure(ctx, st->w32, f32);
     if (s != MRHS_OK) return s;
     st->m = m;
     st->on = n;
+    st->kprec = k32;
   }
   st->timing = prm->timers != 0;
   st->evused = 0;
@@ -893,13 +906,13 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   const auto t0 = std::chrono::steady_clock::now();
   double t_pre = 0.0;
 
-  auto Vj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->V64.p) + (size_t)j * f64); };
+  auto Vj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->V64.p) + (size_t)j * fv); };
   auto Zj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->Z32.p) + (size_t)j * f32); };
   auto D64 = [&](void* out, const void* in) {
     return launch_fine_f64(ctx->g, ctx->t_bc, 0, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, n, ss);
   };
-  auto norms = [&](const void* a, std::vector<double>& q) -> mrhs_status {
-    SOLVER_HIP(launch_dot(1, 1, a, a, rows, n, st->qn.p, st->part.p, ss));
+  auto norms = [&](const void* a, std::vector<double>& q, int prec64 = 1) -> mrhs_status {
+    SOLVER_HIP(launch_dot(prec64, 1, a, a, rows, n, st->qn.p, st->part.p, ss));
     SOLVER_HIP(hipMemcpyAsync(q.data(), st->qn.p, n * 8, hipMemcpyDeviceToHost, ss));
     SOLVER_HIP(hipStreamSynchronize(ss));
     return MRHS_OK;
@@ -911,13 +924,23 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   // (Hessenberg entries, solution coefficients) or in the per-(i, RHS) factors
   // 1 / hv_i^2 the Gram-Schmidt update reads from the device.
   //
-  // u_{j+1} = yin - sum_i <u_i, yin> / hv_i^2 u_i into V64[j + 1] (and its FP32
-  // rounding into the V-cycle's input), q = ||u_{j+1}||^2 per RHS, one pass;
-  // the first nprod products of the multi-dot are copied to hout
+  // With krylov_prec = MRHS_F32 the basis is stored in FP32 (the Gram-Schmidt
+  // arithmetic and the inner products stay FP64) and D z_j is the FP32
+  // operator: every cycle is then an FP32 Krylov solve of the FP64 residual,
+  // whose relative accuracy (about 1e-6) far exceeds the reduction a cycle of
+  // a few preconditioned steps achieves, and the restarts (FP64 true residual,
+  // FP64 x) carry the solution to the FP64 tolerance, as in iterative
+  // refinement.  It halves the outer solver's memory traffic; the V-cycle
+  // reads each FP32 basis vector in place.
+  //
+  // u_{j+1} = yin - sum_i <u_i, yin> / hv_i^2 u_i into V[j + 1] (and, for an
+  // FP64 basis, its FP32 rounding into the V-cycle's input), q = ||u_{j+1}||^2
+  // per RHS, one pass; the first nprod products of the multi-dot are copied to hout
   auto project_out = [&](const void* yin, const std::vector<const void*>& vs, int cnt, int nprod, void* yout,
                          std::vector<std::complex<double>>& hout, std::vector<double>& qout) -> mrhs_status {
-    SOLVER_HIP(launch_multi_axpy_norm(yout, prm->precondition ? st->lb[0].p : nullptr, yin, st->coef.p,
-                                      st->scl.p, vs.data(), cnt, -1.0, rows, n, st->qn.p, st->part.p, ss));
+    SOLVER_HIP(launch_multi_axpy_norm(k32 ? 0 : 1, yout, (!k32 && prm->precondition) ? st->lb[0].p : nullptr, yin,
+                                      st->coef.p, st->scl.p, vs.data(), cnt, -1.0, rows, n, st->qn.p, st->part.p,
+                                      ss));
     SOLVER_HIP(hipMemcpyAsync(hout.data(), st->coef.p, (size_t)nprod * n * 16, hipMemcpyDeviceToHost, ss));
     SOLVER_HIP(hipMemcpyAsync(qout.data(), st->qn.p, n * 8, hipMemcpyDeviceToHost, ss));
     SOLVER_HIP(hipStreamSynchronize(ss));
@@ -940,16 +963,25 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   auto Hel = [&](int k, int i, int j) -> cd& { return H[((size_t)k * (m + 1) + i) * m + j]; };
 
   while (true) {
-    // true residual r = b - D x in FP64, straight into V64[0] = u_0 (and its
-    // FP32 rounding into the V-cycle's input)
+    // true residual r = b - D x in FP64, straight into V[0] = u_0 (and its
+    // FP32 rounding into the V-cycle's input); with an FP32 basis r stays in
+    // w64 for the convergence test and u_0 is its FP32 rounding
     SOLVER_HIP(D64(st->w64.p, x));
-    SOLVER_HIP(launch_sub_dual(Vj(0), prm->precondition ? st->lb[0].p : nullptr, b, st->w64.p, rows * n, ss));
-    s = norms(Vj(0), q);
+    std::vector<double> qtrue(n);
+    if (k32) {
+      SOLVER_HIP(launch_sub_dual(st->w64.p, Vj(0), b, st->w64.p, rows * n, ss));
+      s = norms(st->w64.p, qtrue);
+      if (s == MRHS_OK) s = norms(Vj(0), q, 0);
+    } else {
+      SOLVER_HIP(launch_sub_dual(Vj(0), prm->precondition ? st->lb[0].p : nullptr, b, st->w64.p, rows * n, ss));
+      s = norms(Vj(0), q);
+      qtrue = q;
+    }
     if (s != MRHS_OK) return s;
     all_done = true;
     for (int k = 0; k < n; ++k) {
       const double beta = std::sqrt(q[k]);
-      rel[k] = bn[k] > 0 ? beta / bn[k] : 0.0;
+      rel[k] = bn[k] > 0 ? std::sqrt(qtrue[k]) / bn[k] : 0.0;
       done[k] = rel[k] <= prm->tol;
       all_done = all_done && done[k];
       ih[k] = (beta > 0 && !done[k]) ? 1.0 / beta : 0.0;
@@ -965,9 +997,13 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
       // Z32[j] = M u_j
       {
         auto tp = std::chrono::steady_clock::now();
-        if (prm->precondition) {  // lb[0] already holds FP32(u_j), written with u_j
+        if (prm->precondition) {  // lb[0] already holds FP32(u_j), written with u_j; an FP32 u_j is read in place
+          st->b0 = k32 ? Vj(j) : nullptr;
           s = run_vcycle(mg, st, n, prm->vc, prm->use_graph != 0, Zj(j), j);
+          st->b0 = nullptr;
           if (s != MRHS_OK) return s;
+        } else if (k32) {
+          SOLVER_HIP(hipMemcpyAsync(Zj(j), Vj(j), f32, hipMemcpyDeviceToDevice, ss));
         } else {
           SOLVER_HIP(launch_convert_f64_to_f32(static_cast<const double*>(Vj(j)), static_cast<float*>(Zj(j)),
                                                2 * rows * n, ss));
@@ -978,25 +1014,30 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
         }
       }
       // w_hat = D Z32[j] in FP64, reading the FP32 direction directly (exact
-      // widening); D z_j = w_hat ih_j
-      SOLVER_HIP(launch_fine_f64_in32(ctx->g, ctx->kappa, ctx->U64.p, ctx->A64.p, Zj(j), st->w64.p, n, ss,
-                                      &ctx->fine_cfg[n]));
+      // widening), or the FP32 operator for an FP32 basis; D z_j = w_hat ih_j
+      void* w = k32 ? st->w32.p : st->w64.p;
+      if (k32)
+        SOLVER_HIP(launch_fine_f32(ctx->g, ctx->t_bc, 0, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, Zj(j), w, n, ss,
+                                   &ctx->fine_cfg[n]));
+      else
+        SOLVER_HIP(launch_fine_f64_in32(ctx->g, ctx->kappa, ctx->U64.p, ctx->A64.p, Zj(j), w, n, ss,
+                                        &ctx->fine_cfg[n]));
       // classical Gram-Schmidt; the first pass also yields ||w_hat||^2 (w_hat is
       // the last vector of the multi-dot), and a second pass is made only when
       // the projection removed more than 1 - reorth_eta of it for some RHS
       SOLVER_HIP(hipMemcpyAsync(st->scl.p, ih2.data(), (size_t)(j + 1) * n * 8, hipMemcpyHostToDevice, ss));
       std::vector<const void*> vs(j + 2);
       for (int i = 0; i <= j; ++i) vs[i] = Vj(i);
-      vs[j + 1] = st->w64.p;
-      SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 2, st->w64.p, rows, n, st->coef.p, st->part.p, ss));
-      s = project_out(st->w64.p, vs, j + 1, j + 2, Vj(j + 1), hc, q);  // the last of the j + 2 products is ||w_hat||^2
+      vs[j + 1] = w;
+      SOLVER_HIP(launch_multi_dot(k32 ? 0 : 1, vs.data(), j + 2, w, rows, n, st->coef.p, st->part.p, ss));
+      s = project_out(w, vs, j + 1, j + 2, Vj(j + 1), hc, q);  // the last of the j + 2 products is ||w_hat||^2
       if (s != MRHS_OK) return s;
       bool again = false;
       for (int k = 0; k < n; ++k)
         if (!done[k] && q[k] < prm->reorth_eta * hc[(size_t)(j + 1) * n + k].real()) again = true;
       std::fill(hc2.begin(), hc2.end(), cd(0.0));
       if (again) {
-        SOLVER_HIP(launch_multi_dot(1, vs.data(), j + 1, Vj(j + 1), rows, n, st->coef.p, st->part.p, ss));
+        SOLVER_HIP(launch_multi_dot(k32 ? 0 : 1, vs.data(), j + 1, Vj(j + 1), rows, n, st->coef.p, st->part.p, ss));
         s = project_out(Vj(j + 1), vs, j + 1, j + 1, Vj(j + 1), hc2, q);
         if (s != MRHS_OK) return s;
         ++reorth;

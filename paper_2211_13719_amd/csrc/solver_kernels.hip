@@ -146,14 +146,18 @@ __global__ __launch_bounds__(kB) void multi_axpy(double2* __restrict__ y, const 
   y[e] = acc;
 }
 
-// y_k = yin_k + s sum_i c[i][k] x_i (y, yin, x_i FP64; y may be yin) and, in
-// the same pass, its FP32 rounding into y32 (if given) and the partial sums
-// of ||y_k||^2: partial[b][k], fixed order.
+// y_k = yin_k + s sum_i c[i][k] x_i (y, yin, x_i all FP64 or all FP32, the
+// arithmetic in FP64; y may be yin) and, in the same pass, the FP32 rounding
+// of an FP64 y into y32 (if given) and the partial sums of ||y_k||^2 of the
+// stored y: partial[b][k], fixed order.
 // cs (if given): a real factor per (i, column), cs[i * nrhs + k], multiplying c.
-__global__ __launch_bounds__(kB) void multi_axpy_norm(double2* y, float2* __restrict__ y32, const double2* yin,
+template <typename T>
+__global__ __launch_bounds__(kB) void multi_axpy_norm(typename c2<T>::type* y, float2* __restrict__ y32,
+                                                      const typename c2<T>::type* yin,
                                                       const double2* __restrict__ c, const double* __restrict__ cs,
                                                       Ptrs xs, int m, double s, long rows, int nrhs, int tpb,
                                                       double* __restrict__ part) {
+  using CT = typename c2<T>::type;
   __shared__ double red[kB];
   const int t = threadIdx.x;
   double acc2 = 0.0;
@@ -163,19 +167,25 @@ __global__ __launch_bounds__(kB) void multi_axpy_norm(double2* y, float2* __rest
     const long step = (long)gridDim.x * rpb;
     for (long row = (long)blockIdx.x * rpb + t / nrhs; row < rows; row += step) {
       const long e = row * nrhs + k;
-      double2 acc = yin[e];
+      const CT y0 = yin[e];
+      double2 acc = make_double2((double)y0.x, (double)y0.y);
 #pragma unroll 4
       for (int i = 0; i < m; ++i) {
-        const double2 xv = static_cast<const double2*>(xs.p[i])[e];
+        const CT xv = static_cast<const CT*>(xs.p[i])[e];
         const double2 ci = c[i * nrhs + k];
         const double f = cs ? s * cs[i * nrhs + k] : s;
         const double cr = f * ci.x, cim = f * ci.y;
-        acc.x = fma(cr, xv.x, fma(-cim, xv.y, acc.x));
-        acc.y = fma(cr, xv.y, fma(cim, xv.x, acc.y));
+        acc.x = fma(cr, (double)xv.x, fma(-cim, (double)xv.y, acc.x));
+        acc.y = fma(cr, (double)xv.y, fma(cim, (double)xv.x, acc.y));
       }
-      y[e] = acc;
-      if (y32) y32[e] = make_float2((float)acc.x, (float)acc.y);
-      acc2 = fma(acc.x, acc.x, fma(acc.y, acc.y, acc2));
+      CT out;
+      out.x = (T)acc.x;
+      out.y = (T)acc.y;
+      y[e] = out;
+      if constexpr (sizeof(T) == 8) {
+        if (y32) y32[e] = make_float2((float)acc.x, (float)acc.y);
+      }
+      acc2 = fma((double)out.x, (double)out.x, fma((double)out.y, (double)out.y, acc2));
     }
   }
   red[t] = acc2;
@@ -235,8 +245,9 @@ __global__ __launch_bounds__(kB) void sub_fields(typename c2<T>::type* __restric
 }
 
 // out = a - b in FP64 and, if out32 is given, its FP32 rounding too
-__global__ __launch_bounds__(kB) void sub_dual(double2* __restrict__ out, float2* __restrict__ out32,
-                                               const double2* __restrict__ a, const double2* __restrict__ b, long n) {
+// out = a - b in FP64 (out may be b) and its FP32 rounding into out32 (if given)
+__global__ __launch_bounds__(kB) void sub_dual(double2* out, float2* __restrict__ out32,
+                                               const double2* __restrict__ a, const double2* b, long n) {
   const long e = (long)blockIdx.x * kB + threadIdx.x;
   if (e >= n) return;
   double2 u = a[e];
@@ -538,17 +549,22 @@ hipError_t launch_col_transform(void* v, long rows, int nv, const void* T, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_multi_axpy_norm(void* y, void* y32, const void* yin, const void* coef, const void* cscale,
-                                 const void* const* xs, int m, double sgn, long rows, int nrhs, void* norms,
-                                 void* scratch, hipStream_t s) {
-  if (m < 1 || m > kMaxMultiDot || nrhs < 1 || nrhs > kB) return hipErrorInvalidValue;
+// prec64: y, yin and the x_i FP64 (y32 optional), else all FP32 (y32 unused)
+hipError_t launch_multi_axpy_norm(int prec64, void* y, void* y32, const void* yin, const void* coef,
+                                 const void* cscale, const void* const* xs, int m, double sgn, long rows, int nrhs,
+                                 void* norms, void* scratch, hipStream_t s) {
+  if (m < 1 || m > kMaxMultiDot || nrhs < 1 || nrhs > kB || (!prec64 && y32)) return hipErrorInvalidValue;
   Ptrs p{};
   for (int i = 0; i < m; ++i) p.p[i] = xs[i];
   const int tpb = tpb_of(nrhs), nb = nblk_of(rows, nrhs);
-  hipLaunchKernelGGL(multi_axpy_norm, dim3(nb), dim3(kB), 0, s, static_cast<double2*>(y), static_cast<float2*>(y32),
-                     static_cast<const double2*>(yin), static_cast<const double2*>(coef),
-                     static_cast<const double*>(cscale), p, m, sgn, rows, nrhs, tpb,
-                     static_cast<double*>(scratch));
+  if (prec64)
+    hipLaunchKernelGGL(multi_axpy_norm<double>, dim3(nb), dim3(kB), 0, s, static_cast<double2*>(y),
+                       static_cast<float2*>(y32), static_cast<const double2*>(yin), static_cast<const double2*>(coef),
+                       static_cast<const double*>(cscale), p, m, sgn, rows, nrhs, tpb, static_cast<double*>(scratch));
+  else
+    hipLaunchKernelGGL(multi_axpy_norm<float>, dim3(nb), dim3(kB), 0, s, static_cast<float2*>(y), nullptr,
+                       static_cast<const float2*>(yin), static_cast<const double2*>(coef),
+                       static_cast<const double*>(cscale), p, m, sgn, rows, nrhs, tpb, static_cast<double*>(scratch));
   hipLaunchKernelGGL(col_sum_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double*>(scratch), nb, nrhs,
                      static_cast<double*>(norms));
   return hipGetLastError();

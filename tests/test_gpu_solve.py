@@ -299,8 +299,8 @@ def test_solve_24x24x24x128_bench_settings(gpu_lib, capsys, tmp_path):
     """The solve workload the benchmark times (24^3 x 128 smooth links at the
     tuned bare mass, three levels, BF16 coarse levels and intergrid, even-odd
     fine smoother, graph-replayed V-cycle, the benchmark's set-up and V-cycle
-    parameters, coarse even-odd smoother on the 6^3 x 32 level, and its first
-    two right-hand sides): every column's true
+    parameters, coarse even-odd smoother on the 6^3 x 32 level, its outer
+    Krylov basis precision, and its first two right-hand sides): every column's true
     residual, recomputed by the FP64 oracle on the host, is at most 1e-10."""
     import json
     import shutil
@@ -337,7 +337,8 @@ def test_solve_24x24x24x128_bench_settings(gpu_lib, capsys, tmp_path):
     say("solve")
     st = mg.solve(x, dev(b), tol=1e-10, restart=bench.SOLVE_RESTART, max_iters=bench.SOLVE_MAXIT,
                   coarse_prec="bf16", use_graph=True, fine_eo=bench.SOLVE_MRHS_FINE_EO,
-                  coarse_eo=bench.SOLVE_MRHS_COARSE_EO, **bench.SOLVE_VC)
+                  coarse_eo=bench.SOLVE_MRHS_COARSE_EO,
+                  krylov_prec=gpu_lib.F32 if bench.SOLVE_KRYLOV_F32 else gpu_lib.F64, **bench.SOLVE_VC)
     assert all(st["converged"])
     xs = x.cpu().numpy()
     mg.close()
@@ -529,3 +530,46 @@ def test_solve_sap_smoother(small, nrhs):
                   coarse_prec="bf16", fine_sap=True, sap_iters=4)
     assert all(st["converged"])
     assert np.all(O.true_residual(U, A, KAPPA, x.cpu().numpy(), b, dims) <= 1e-10)
+
+
+@pytest.mark.parametrize("nrhs", [1, 12])
+def test_solve_fp32_krylov_basis(small, gpu_lib, nrhs):
+    """Krylov basis stored in FP32 between FP64 restarts: the same FP64
+    true-residual target, checked by the oracle, in about as many steps as
+    the FP64 basis, and the graph-replayed V-cycle (which then reads each
+    FP32 basis vector in place) gives the graph-free run's solution bit for
+    bit."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = synth.spinor_source(dims, nrhs, 9100)
+    x64 = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    s64 = mg.solve(x64, dev(b), coarse_prec="bf16", fine_eo=1)
+    x32 = torch.zeros_like(x64)
+    s32 = mg.solve(x32, dev(b), coarse_prec="bf16", fine_eo=1, krylov_prec=gpu_lib.F32)
+    assert all(s32["converged"]) and max(s32["rel_resid"]) <= 1e-10
+    assert np.all(O.true_residual(U, A, KAPPA, x32.cpu().numpy(), b, dims) <= 1e-10)
+    assert s32["iters"] <= s64["iters"] + 3, (s32["iters"], s64["iters"])
+    x_ng = torch.zeros_like(x64)
+    s_ng = mg.solve(x_ng, dev(b), coarse_prec="bf16", fine_eo=1, krylov_prec=gpu_lib.F32, use_graph=False)
+    assert s_ng["iters"] == s32["iters"] and torch.equal(x_ng, x32)
+    # and the FP64 basis still solves after the FP32 one (buffers re-sized back)
+    x64b = torch.zeros_like(x64)
+    s64b = mg.solve(x64b, dev(b), coarse_prec="bf16", fine_eo=1)
+    assert s64b["iters"] == s64["iters"] and torch.equal(x64b, x64)
+
+
+def test_unpreconditioned_fp32_krylov_and_bad_precision(small, gpu_lib):
+    """Plain restarted GMRES with an FP32 basis still reaches the FP64 target
+    through its FP64 restarts; a basis precision other than FP64 or FP32 is
+    refused."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    b = synth.spinor_source(dims, 3, 56)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    st = mg.solve(x, dev(b), precondition=False, restart=15, max_iters=2000, krylov_prec=gpu_lib.F32)
+    assert all(st["converged"]) and st["cycles"] >= 2
+    assert np.all(O.true_residual(U, A, KAPPA, x.cpu().numpy(), b, dims) <= 1e-10)
+    with pytest.raises(gpu_lib.MrhsError, match="UNSUPPORTED"):
+        mg.solve(torch.zeros_like(x), dev(b), krylov_prec=gpu_lib.BF16)
