@@ -87,12 +87,12 @@ FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 # the launch configurations it was counted under.  `roofline.traffic` carries
 # it only while the kernel name, sources and configurations still match.
 FINE_TRAFFIC = {
-    "kernel": "fine_kernel<float, 2, 0, true, true, 0, HIP_vector_type<float, 2u> >",
-    "sources": "b3131781c87ab680",
-    "configs": {"12": [2, [8, 8, 2, 3], 64], "24": [2, [8, 8, 2, 3], 64], "48": [2, [8, 4, 4, 3], 68],
-                "64": [2, [8, 4, 4, 3], 5]},
-    "bytes_per_launch": 6.715e9,
-    "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 12, 24, 48, 64; "
+    "kernel": "fine_walk_kernel<2, 0>",
+    "sources": "d85e6171a54e7d59",
+    "configs": {"6": [2, [4, 4, 4, 3], 224], "12": [2, [24, 8, 2, 3], 224], "24": [2, [24, 8, 2, 3], 132],
+                "48": [2, [24, 4, 4, 3], 132], "64": [2, [6, 6, 6, 12], 132]},
+    "bytes_per_launch": 5.252e9,
+    "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
 
