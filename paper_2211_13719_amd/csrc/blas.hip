@@ -197,6 +197,67 @@ __global__ __launch_bounds__(kBlock) void multidot_partial(PtrList v, int m,
   }
 }
 
+// Multi-dot pass 1 for FP32 fields of even nrhs: each thread owns a pair of
+// adjacent columns and reads them as one 16-byte word per row, so a
+// wavefront has twice the bytes of the one-column kernel in flight per load
+// (that kernel is bound by the latency of its 8-byte loads).  Thread t owns
+// columns 2 (t % (nrhs / 2)) and the next; the partial layout is the
+// one-column kernel's.  MMAX >= m bounds the accumulators kept in registers.
+template <int MMAX>
+__global__ __launch_bounds__(kBlock) void multidot_partial_pair(PtrList v, int m, const float4* __restrict__ w,
+                                                                long rows, int npair, int tpb,
+                                                                double2* __restrict__ partial) {
+  __shared__ double2 red[kBlock];
+  const int t = threadIdx.x;
+  const int rpb = tpb / npair;
+  double2 acc[MMAX][2];
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) acc[j][0] = acc[j][1] = make_double2(0.0, 0.0);
+  if (t < tpb) {
+    const int kp = t % npair;
+    const long r0 = (long)blockIdx.x * rpb + t / npair;
+    const long step = (long)gridDim.x * rpb;
+    for (long r = r0; r < rows; r += step) {
+      const long e = r * npair + kp;
+      const float4 y = w[e];
+#pragma unroll
+      for (int j = 0; j < MMAX; ++j) {
+        if (j < m) {
+          const float4 x = static_cast<const float4*>(v.p[j])[e];
+          acc[j][0].x = fma((double)x.x, (double)y.x, acc[j][0].x);
+          acc[j][0].x = fma((double)x.y, (double)y.y, acc[j][0].x);
+          acc[j][0].y = fma((double)x.x, (double)y.y, acc[j][0].y);
+          acc[j][0].y = fma(-(double)x.y, (double)y.x, acc[j][0].y);
+          acc[j][1].x = fma((double)x.z, (double)y.z, acc[j][1].x);
+          acc[j][1].x = fma((double)x.w, (double)y.w, acc[j][1].x);
+          acc[j][1].y = fma((double)x.z, (double)y.w, acc[j][1].y);
+          acc[j][1].y = fma(-(double)x.w, (double)y.z, acc[j][1].y);
+        }
+      }
+    }
+  }
+  const int nrhs = 2 * npair;
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) {
+    if (j < m) {  // m is uniform across the workgroup, so the barriers are too
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        red[t] = acc[j][c];
+        __syncthreads();
+        if (t < npair) {
+          double2 s = red[t];
+          for (int i = t + npair; i < tpb; i += npair) {
+            s.x += red[i].x;
+            s.y += red[i].y;
+          }
+          partial[((long)blockIdx.x * m + j) * nrhs + 2 * t + c] = s;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 int threads_per_block(int nrhs) { return nrhs >= kBlock ? kBlock : (kBlock / nrhs) * nrhs; }
 
 int partial_blocks(long rows, int nrhs) {
@@ -248,12 +309,31 @@ hipError_t launch_multi_dot(int prec64, const void* const* v, int m, const void*
   const int tpb = threads_per_block(nrhs);
   const int nb = partial_blocks(rows, nrhs);
   double2* part = static_cast<double2*>(scratch);
-  if (prec64)
+  if (prec64) {
     hipLaunchKernelGGL((multidot_partial<double>), dim3(nb), dim3(kBlock), 0, s, pl, m,
                        static_cast<const double2*>(w), rows, nrhs, tpb, part);
-  else
+  } else if (nrhs % 2 == 0) {
+    // column pairs as 16-byte words; at most as many workgroups as the one-column kernel
+    const int npair = nrhs / 2;
+    const int tpb2 = threads_per_block(npair);
+    const int nb2 = partial_blocks(rows, npair);
+    if (m <= 4)
+      hipLaunchKernelGGL((multidot_partial_pair<4>), dim3(nb2), dim3(kBlock), 0, s, pl, m,
+                         static_cast<const float4*>(w), rows, npair, tpb2, part);
+    else if (m <= 10)
+      hipLaunchKernelGGL((multidot_partial_pair<10>), dim3(nb2), dim3(kBlock), 0, s, pl, m,
+                         static_cast<const float4*>(w), rows, npair, tpb2, part);
+    else
+      hipLaunchKernelGGL((multidot_partial_pair<kMaxMultiDot>), dim3(nb2), dim3(kBlock), 0, s, pl, m,
+                         static_cast<const float4*>(w), rows, npair, tpb2, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((dot_final<0>), dim3(m * nrhs), dim3(kBlock), 0, s, part, nb2, m * nrhs, out);
+    return hipGetLastError();
+  } else {
     hipLaunchKernelGGL((multidot_partial<float>), dim3(nb), dim3(kBlock), 0, s, pl, m,
                        static_cast<const float2*>(w), rows, nrhs, tpb, part);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the partials of (block, j) for column k sit at ((block * m + j) * nrhs + k): viewed as

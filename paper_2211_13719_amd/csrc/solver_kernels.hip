@@ -197,6 +197,57 @@ __global__ __launch_bounds__(kB) void multi_axpy_norm(typename c2<T>::type* y, f
   }
 }
 
+// multi_axpy_norm for FP32 fields of even nrhs: each thread owns a pair of
+// adjacent columns, read and written as one 16-byte word per row (twice the
+// bytes in flight per load of the one-column kernel); same arithmetic per
+// element, partials part[b][k] in the same layout.
+__global__ __launch_bounds__(kB) void multi_axpy_norm_pair(float4* y, const float4* yin,
+                                                           const double2* __restrict__ c, const double* __restrict__ cs,
+                                                           Ptrs xs, int m, double s, long rows, int npair, int tpb,
+                                                           double* __restrict__ part) {
+  __shared__ double red[kB];
+  const int t = threadIdx.x;
+  const int nrhs = 2 * npair;
+  double acc2[2] = {0.0, 0.0};
+  if (t < tpb) {
+    const int kp = t % npair;
+    const int rpb = tpb / npair;
+    const long step = (long)gridDim.x * rpb;
+    const int k0 = 2 * kp;
+    for (long row = (long)blockIdx.x * rpb + t / npair; row < rows; row += step) {
+      const long e = row * npair + kp;
+      const float4 y0 = yin[e];
+      double2 a0 = make_double2((double)y0.x, (double)y0.y), a1 = make_double2((double)y0.z, (double)y0.w);
+#pragma unroll 4
+      for (int i = 0; i < m; ++i) {
+        const float4 xv = static_cast<const float4*>(xs.p[i])[e];
+        const double2 c0 = c[i * nrhs + k0], c1 = c[i * nrhs + k0 + 1];
+        const double f0 = cs ? s * cs[i * nrhs + k0] : s, f1 = cs ? s * cs[i * nrhs + k0 + 1] : s;
+        const double r0 = f0 * c0.x, i0 = f0 * c0.y, r1 = f1 * c1.x, i1 = f1 * c1.y;
+        a0.x = fma(r0, (double)xv.x, fma(-i0, (double)xv.y, a0.x));
+        a0.y = fma(r0, (double)xv.y, fma(i0, (double)xv.x, a0.y));
+        a1.x = fma(r1, (double)xv.z, fma(-i1, (double)xv.w, a1.x));
+        a1.y = fma(r1, (double)xv.w, fma(i1, (double)xv.z, a1.y));
+      }
+      const float4 out = make_float4((float)a0.x, (float)a0.y, (float)a1.x, (float)a1.y);
+      y[e] = out;
+      acc2[0] = fma((double)out.x, (double)out.x, fma((double)out.y, (double)out.y, acc2[0]));
+      acc2[1] = fma((double)out.z, (double)out.z, fma((double)out.w, (double)out.w, acc2[1]));
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    red[t] = acc2[h];
+    __syncthreads();
+    if (t < npair) {
+      double v = red[t];
+      for (int j = t + npair; j < tpb; j += npair) v += red[j];
+      part[(long)blockIdx.x * nrhs + 2 * t + h] = v;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kB) void col_sum_final(const double* __restrict__ part, int nblk, int nrhs,
                                                     double* __restrict__ out) {
   __shared__ double red[kB];
@@ -561,7 +612,16 @@ hipError_t launch_multi_axpy_norm(int prec64, void* y, void* y32, const void* yi
     hipLaunchKernelGGL(multi_axpy_norm<double>, dim3(nb), dim3(kB), 0, s, static_cast<double2*>(y),
                        static_cast<float2*>(y32), static_cast<const double2*>(yin), static_cast<const double2*>(coef),
                        static_cast<const double*>(cscale), p, m, sgn, rows, nrhs, tpb, static_cast<double*>(scratch));
-  else
+  else if (nrhs % 2 == 0) {
+    const int npair = nrhs / 2, tpb2 = tpb_of(npair), nb2 = nblk_of(rows, npair);
+    hipLaunchKernelGGL(multi_axpy_norm_pair, dim3(nb2), dim3(kB), 0, s, static_cast<float4*>(y),
+                       static_cast<const float4*>(yin), static_cast<const double2*>(coef),
+                       static_cast<const double*>(cscale), p, m, sgn, rows, npair, tpb2,
+                       static_cast<double*>(scratch));
+    hipLaunchKernelGGL(col_sum_final, dim3(nrhs), dim3(kB), 0, s, static_cast<const double*>(scratch), nb2, nrhs,
+                       static_cast<double*>(norms));
+    return hipGetLastError();
+  } else
     hipLaunchKernelGGL(multi_axpy_norm<float>, dim3(nb), dim3(kB), 0, s, static_cast<float2*>(y), nullptr,
                        static_cast<const float2*>(yin), static_cast<const double2*>(coef),
                        static_cast<const double*>(cscale), p, m, sgn, rows, nrhs, tpb, static_cast<double*>(scratch));

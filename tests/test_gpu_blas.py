@@ -76,12 +76,13 @@ def test_dot_deterministic_and_column_independent(ctx):
     np.testing.assert_allclose(ctx.norm2(ta), ctx.dot(ta, ta).real, rtol=1e-14)
 
 
-@pytest.mark.parametrize("m", [1, 3, 16])
+@pytest.mark.parametrize("n", [12, 7])  # FP32 at even n: the column-pair kernel; odd n: one column per thread
+@pytest.mark.parametrize("m", [1, 3, 9, 16])
 @pytest.mark.parametrize("dt", [np.complex64, np.complex128])
-def test_multi_dot(ctx, m, dt):
+def test_multi_dot(ctx, m, dt, n):
     import torch
 
-    ns, nc, n = 2000, 12, 12
+    ns, nc = 2000, 12
     w = synth.coarse_source(ns, nc, n, 9, dt)
     vs = [synth.coarse_source(ns, nc, n, 100 + 50 * j, dt) for j in range(m)]
     got = ctx.multi_dot([_dev(torch, v) for v in vs], _dev(torch, w))
