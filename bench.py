@@ -67,7 +67,9 @@ SOLVE_SETUP = dict(setup_iters=15, smooth_steps=30, adapt_iters=0)
 # 24^3x128, 12 RHS, even-odd fine smoother: nu_post 4 with 128 coarsest steps 1.09 s (23 outer steps),
 # nu_post 6 with 64 steps 1.31 s (24); on one RHS 4 / 128 is the fastest setting measured too (0.367 s)
 SOLVE_VC = dict(nu_pre=0, nu_post=4, coarsest_iters=128)
-SOLVE_RESTART, SOLVE_MAXIT = 8, 1000
+# FGMRES restart length with the FP32 basis, 24^3x128 (seconds, 18 outer steps at every m): 12 RHS m = 4 / 5 / 6 /
+# 8 / 10: 0.700 / 0.689 / 0.694 / 0.710 / 0.711; 48 RHS m = 4 / 5 / 6 / 7: 2.122 / 2.102 / 2.112 / 2.124
+SOLVE_RESTART, SOLVE_MAXIT = 5, 1000
 SOLVE_MRHS_FINE_EO = True  # 24^3x128, 12 / 24 RHS, nu_post 6: 24 instead of 28 outer steps, 10-13 % less time
 # level-1 (6^3 x 32) smoothing on the coarse even-odd Schur complement: 24^3x128, 12 RHS, 18 instead of 21 outer
 # steps, 0.90 vs 1.03 s
