@@ -362,6 +362,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     del U
     ctx.build_clover(CSW, kappa)
     ctx.tune(sorted({1, 16, *nrhs_list}), cache)
+    eo_hop = {str(n): dict(zip(("walk", "rhs_per_thread", "tile", "us", "us_tiled"), ctx.get_eo_walk(n)))
+              for n in sorted({1, *nrhs_list})}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     t0 = time.perf_counter()
     for l in range(2):
@@ -503,6 +505,7 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "mrhs_other_level1_smoother": coarse_eo,
         "mrhs_sap_smoother": sap,
         "mrhs_other_krylov_basis": other_basis,
+        "eo_hop_kernel": eo_hop,
         "config": f"FP64 FGMRES({SOLVE_RESTART}, shorter where the batch's fields would not fit in HBM) with the "
                   f"Krylov basis in {'FP32 between FP64 restarts' if SOLVE_KRYLOV_F32 else 'FP64'} (both MRHS and "
                   f"SRHS), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
@@ -581,6 +584,8 @@ def main():
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
     ctx.tune(list(NRHS_FINE), cache)
     tuning = {str(n): dict(zip(("rhs_per_thread", "tile", "variant", "tuned_us"), ctx.get_tuning(n))) for n in NRHS_FINE}
+    eo_tuning = {str(n): dict(zip(("walk", "rhs_per_thread", "tile", "us", "us_tiled"), ctx.get_eo_walk(n)))
+                 for n in NRHS_FINE}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
     mg.block_orthonormalise(0)
@@ -785,6 +790,7 @@ def main():
         "composite_step": composite,
         "evenodd": evenodd,
         "fine_tuning": tuning,
+        "eo_hop_tuning": eo_tuning,
         "coarse_f32_tuning": coarse_tuning,
         "fine_sources": fine_sources_digest(),
         "solve": None,

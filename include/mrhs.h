@@ -145,6 +145,22 @@ mrhs_status mrhs_clover_apply(mrhs_ctx ctx, void* out, const void* in, int32_t n
  * MRHS_ERR_STATE before the links are set. */
 mrhs_status mrhs_hop_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, int32_t out_parity,
                               mrhs_prec prec);
+/* mrhs_set_eo_walk: launch shape of the FP32 checkerboard hop (mrhs_hop_eo_apply,
+ * mrhs_schur_apply and the even-odd smoother) for nrhs right-hand sides:
+ * tile = (Bx, By, Bz, Ts) selects the t-walk kernel (each thread walks Ts
+ * output sites of one site of a Bx x By x Bz spatial block, every second
+ * time slice, carrying the backward t-hop in registers; Bx By Bz >= 16, the
+ * block must divide the spatial extents and Ts divide Lt / 2) with
+ * rhs_per_thread 1 or 2 (0: two for even nrhs, else one); tile = NULL
+ * selects the tiled kernel.  mrhs_tune chooses it by timing (lattices with
+ * even extents).  The fields computed are bit-identical either way.  An
+ * invalid shape gets MRHS_ERR_INVALID_ARG. */
+mrhs_status mrhs_set_eo_walk(mrhs_ctx ctx, int32_t nrhs, const int32_t* tile, int32_t rhs_per_thread);
+/* mrhs_get_eo_walk: the shape in use for nrhs (*on = 0: tiled kernel), and
+ * the times the last mrhs_tune measured for it and for the tiled kernel
+ * (microseconds, 0 if not measured).  Any output pointer may be NULL. */
+mrhs_status mrhs_get_eo_walk(mrhs_ctx ctx, int32_t nrhs, int32_t* on, int32_t* rhs_per_thread, int32_t tile[4],
+                             float* us, float* us_tiled);
 /* mrhs_clover_eo_apply: out = A_p in (inverse = 0) or out = A_p^-1 in
  * (inverse = 1) on parity p, A_p the chiral 6x6 clover blocks of the parity-p
  * sites.  The inverse blocks are computed once per clover term in FP64
@@ -488,7 +504,9 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * SIMD) and ordinary or non-temporal output stores -- on
  * scratch fields, and keeps the
  * fastest for later FP32 applies of that nrhs on this context.  All
- * configurations give bit-identical results.  cache_path (may be NULL) names
+ * configurations give bit-identical results.  On lattices with even extents
+ * it also chooses the checkerboard hop's kernel (tiled or t-walk, see
+ * mrhs_set_eo_walk) per nrhs, by timing, every call.  cache_path (may be NULL) names
  * a text file: existing entries for this device architecture, lattice and
  * nrhs are used without timing, new choices are appended.  Needs links and
  * clover.  Synchronises. */

@@ -233,6 +233,19 @@ class Context:
         self._check(lib.mrhs_norm2(self._h, C.c_void_p(res.ctypes.data), C.c_void_p(pa), ns, nc, n, prec, 0))
         return res
 
+    def set_eo_walk(self, nrhs: int, tile=None, rhs_per_thread: int = 0):
+        """Checkerboard hop kernel for nrhs: tile (Bx, By, Bz, Ts) = t-walk, None = tiled."""
+        t = None if tile is None else (C.c_int32 * 4)(*[int(v) for v in tile])
+        self._check(lib.mrhs_set_eo_walk(self._h, int(nrhs), t, int(rhs_per_thread)))
+
+    def get_eo_walk(self, nrhs: int):
+        """(on, rhs_per_thread, tile, us, us_tiled) of the checkerboard hop for nrhs."""
+        on, r = C.c_int32(), C.c_int32()
+        t = (C.c_int32 * 4)()
+        us, ut = C.c_float(), C.c_float()
+        self._check(lib.mrhs_get_eo_walk(self._h, int(nrhs), C.byref(on), C.byref(r), t, C.byref(us), C.byref(ut)))
+        return bool(on.value), r.value, tuple(t), float(us.value), float(ut.value)
+
     def read_probe(self, buf, sweeps: int, grid: int, depth: int = 8) -> float:
         """Milliseconds for `sweeps` grid-stride reads of the device tensor buf,
         `depth` independent 16-byte loads in flight per thread."""

@@ -486,7 +486,42 @@ mrhs_status mrhs_hop_eo_apply(mrhs_ctx ctx, void* out, const void* in, int32_t n
   const int p64 = prec == MRHS_F64;
   MRHS_HIP(ctx, launch_hop_eo(p64, ctx->g.V / 2, static_cast<const int4*>(ctx->eo_tab[out_parity].p),
                               static_cast<const int*>(ctx->eo_order[out_parity].p), p64 ? ctx->U64.p : ctx->U32.p,
-                              in, out, nrhs, ctx->stream));
+                              in, out, nrhs, ctx->stream, 0, nullptr, nullptr, 0.0, &ctx->g, out_parity,
+                              &ctx->eo_walk[nrhs]));
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_set_eo_walk(mrhs_ctx ctx, int32_t nrhs, const int32_t* tile, int32_t rhs_per_thread) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  EoWalk w;
+  if (tile) {
+    if (!eo_walk_fits(ctx->g, tile, nrhs, rhs_per_thread))
+      return fail(ctx, MRHS_ERR_INVALID_ARG, "checkerboard walk %dx%dx%d x %d (R = %d) does not fit the lattice",
+                  tile[0], tile[1], tile[2], tile[3], rhs_per_thread);
+    w.on = 1;
+    w.R = rhs_per_thread;
+    for (int m = 0; m < 3; ++m) w.B[m] = tile[m];
+    w.Ts = tile[3];
+  }
+  ctx->eo_walk[nrhs] = w;
+  ctx->op_gen++;  // captured V-cycles hold the launch shape
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_get_eo_walk(mrhs_ctx ctx, int32_t nrhs, int32_t* on, int32_t* rhs_per_thread, int32_t tile[4],
+                             float* us, float* us_tiled) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  const EoWalk& w = ctx->eo_walk[nrhs];
+  if (on) *on = w.on;
+  if (rhs_per_thread) *rhs_per_thread = w.R;
+  if (tile) {
+    for (int m = 0; m < 3; ++m) tile[m] = w.B[m];
+    tile[3] = w.Ts;
+  }
+  if (us) *us = w.us;
+  if (us_tiled) *us_tiled = w.us_tiled;
   return MRHS_OK;
 }
 
@@ -528,9 +563,10 @@ mrhs_status mrhs_schur_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nr
   // t2 = A_o^-1 (H_oe in), out = A_e in - kappa^2 (H_eo t2): two fused launches
   const auto* oe = static_cast<const int*>(ctx->eo_order[0].p);
   const auto* oo = static_cast<const int*>(ctx->eo_order[1].p);
-  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, oo, U, in, t2, nrhs, ctx->stream, 1, p64 ? ctx->Ainv64.p : ctx->Ainv32.p));
+  MRHS_HIP(ctx, launch_hop_eo(p64, nh, to, oo, U, in, t2, nrhs, ctx->stream, 1, p64 ? ctx->Ainv64.p : ctx->Ainv32.p,
+                              nullptr, 0.0, &ctx->g, 1, &ctx->eo_walk[nrhs]));
   MRHS_HIP(ctx, launch_hop_eo(p64, nh, te, oe, U, t2, out, nrhs, ctx->stream, 2, p64 ? ctx->A64.p : ctx->A32.p, in,
-                              -ctx->kappa * ctx->kappa));
+                              -ctx->kappa * ctx->kappa, &ctx->g, 0, &ctx->eo_walk[nrhs]));
   return MRHS_OK;
 }
 

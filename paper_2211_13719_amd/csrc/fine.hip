@@ -873,45 +873,17 @@ hipError_t launch_fine(const Geom& g, int t_bc, int mode, T kappa, const void* U
 // EPI 2, the minimal-residual step p = Dhat r, in2 = r) also writes per
 // workgroup b and column k the partial sums (Re <p, r>, Im <p, r>, ||p||^2)
 // in FP64 to part[b][k], summed over the workgroup's threads in a fixed order.
-template <typename T, int R, int EPI, bool FULL2, bool ADDF, bool DOT = false>
-__global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
-                                                     const int* __restrict__ order, int nblocks,
-                                                     const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
-                                                     cplx<T>* __restrict__ out, const T* __restrict__ Ablk,
-                                                     const cplx<T>* __restrict__ in2, T coef,
-                                                     double4* __restrict__ part = nullptr) {
-  static_assert(!DOT || (EPI == 2 && !ADDF), "the MR partial sums go with the second Schur hop");
-  const int per = (nblocks + 7) >> 3;
-  const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (b >= nblocks) return;  // the whole workgroup
-  const int groups = nrhs / R;
-  const long gid = (long)b * 256 + threadIdx.x;
-  const long total = (long)nhalf * groups;
-  // with DOT every thread reaches the workgroup's barrier: one past the end
-  // recomputes the last entry, stores nothing and adds zeros
-  const bool valid = gid < total;
-  if (!DOT && !valid) return;
-  const long gv = valid ? gid : total - 1;
-  const int pidx = (int)(gv / groups);
-  const int k0 = (int)(gv - (long)pidx * groups) * R;
-  double dre[R], dim[R], dpp[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) dre[j] = dim[j] = dpp[j] = 0.0;
-  const int i = order[pidx];
-  const int4 n0 = tab[4 * i], n1 = tab[4 * i + 1], s0 = tab[4 * i + 2], s1 = tab[4 * i + 3];
-  cplx<T> acc[4][3][R];
-#pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
-  hop_dir<T, R, 0, true>(s0.x, n0.x, n0.y, nrhs, k0, U, in, acc, true, true, s0.y);
-  hop_dir<T, R, 1, true>(s0.x, n0.z, n0.w, nrhs, k0, U, in, acc, true, true, s0.z);
-  hop_dir<T, R, 2, true>(s0.x, n1.x, n1.y, nrhs, k0, U, in, acc, true, true, s0.w);
-  hop_dir<T, R, 3, true>(s0.x, n1.z, n1.w, nrhs, k0, U, in, acc, true, true, s1.x);
-  cplx<T>* o = out + (size_t)(ADDF ? s0.x : i) * 12 * nrhs + k0;
-  const cplx<T>* q = in2 + (size_t)(FULL2 ? s0.x : i) * 12 * nrhs + k0;
+// The stores of one output site of hop_eo_kernel / hop_eo_walk_kernel (EPI,
+// FULL2, ADDF as there): i its checkerboard index, site its lattice site,
+// acc = (H in) at the site; with DOT the site's terms of the partial sums are
+// added to dre, dim, dpp (nothing is stored for an invalid thread).
+template <typename T, int R, int EPI, bool FULL2, bool ADDF, bool DOT>
+__device__ __forceinline__ void hop_eo_epilogue(int i, int site, int nrhs, int k0, bool valid,
+                                                const cplx<T> (&acc)[4][3][R], cplx<T>* __restrict__ out,
+                                                const T* __restrict__ Ablk, const cplx<T>* __restrict__ in2, T coef,
+                                                double (&dre)[R], double (&dim)[R], double (&dpp)[R]) {
+  cplx<T>* o = out + (size_t)(ADDF ? site : i) * 12 * nrhs + k0;
+  const cplx<T>* q = in2 + (size_t)(FULL2 ? site : i) * 12 * nrhs + k0;
   // y = the stored value of component r of chirality chi
   auto put = [&](cplx<T>* dst, const cplx<T> (&y)[R]) {
     if constexpr (DOT) {
@@ -968,7 +940,7 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
             }
         }
       }
-      clover_block<T, R>(Ablk + ((size_t)s0.x * 2 + chi) * 36, xin, yout);
+      clover_block<T, R>(Ablk + ((size_t)site * 2 + chi) * 36, xin, yout);
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
         if constexpr (EPI == 2) {
@@ -991,30 +963,193 @@ __global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const 
       }
     }
   }
-  if constexpr (DOT) {
-    // thread u of the workgroup holds columns ((b 256 + u) mod groups) R + j
-    __shared__ double red[256 * R * 3];
-    const int t = threadIdx.x;
+}
+
+// DOT: per-workgroup partial sums in a fixed order.  Thread u of the
+// workgroup holds column group (first + u) mod groups (first = the group
+// index of its thread 0); columns k < nrhs go to row[k].
+template <int R>
+__device__ __forceinline__ void hop_eo_dot_store(const double (&dre)[R], const double (&dim)[R],
+                                                 const double (&dpp)[R], bool valid, long first, int groups,
+                                                 int nrhs, double4* __restrict__ row) {
+  __shared__ double red[256 * R * 3];
+  const int t = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      red[(t * R + j) * 3 + 0] = valid ? dre[j] : 0.0;
-      red[(t * R + j) * 3 + 1] = valid ? dim[j] : 0.0;
-      red[(t * R + j) * 3 + 2] = valid ? dpp[j] : 0.0;
-    }
-    __syncthreads();
-    if (t < nrhs) {
-      const int gi = t / R, j = t - (t / R) * R;
-      int u = gi - (int)(((long)b * 256) % groups);
-      if (u < 0) u += groups;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (; u < 256; u += groups) {
-        s0 += red[(u * R + j) * 3 + 0];
-        s1 += red[(u * R + j) * 3 + 1];
-        s2 += red[(u * R + j) * 3 + 2];
-      }
-      part[(long)b * nrhs + t] = make_double4(s0, s1, s2, 0.0);
-    }
+  for (int j = 0; j < R; ++j) {
+    red[(t * R + j) * 3 + 0] = valid ? dre[j] : 0.0;
+    red[(t * R + j) * 3 + 1] = valid ? dim[j] : 0.0;
+    red[(t * R + j) * 3 + 2] = valid ? dpp[j] : 0.0;
   }
+  __syncthreads();
+  if (t < nrhs) {
+    const int gi = t / R, j = t - (t / R) * R;
+    int u = gi - (int)(first % groups);
+    if (u < 0) u += groups;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (; u < 256; u += groups) {
+      s0 += red[(u * R + j) * 3 + 0];
+      s1 += red[(u * R + j) * 3 + 1];
+      s2 += red[(u * R + j) * 3 + 2];
+    }
+    row[t] = make_double4(s0, s1, s2, 0.0);
+  }
+}
+
+template <typename T, int R, int EPI, bool FULL2, bool ADDF, bool DOT = false>
+__global__ __launch_bounds__(256) void hop_eo_kernel(int nhalf, int nrhs, const int4* __restrict__ tab,
+                                                     const int* __restrict__ order, int nblocks,
+                                                     const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ in,
+                                                     cplx<T>* __restrict__ out, const T* __restrict__ Ablk,
+                                                     const cplx<T>* __restrict__ in2, T coef,
+                                                     double4* __restrict__ part = nullptr) {
+  static_assert(!DOT || (EPI == 2 && !ADDF), "the MR partial sums go with the second Schur hop");
+  const int per = (nblocks + 7) >> 3;
+  const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (b >= nblocks) return;  // the whole workgroup
+  const int groups = nrhs / R;
+  const long gid = (long)b * 256 + threadIdx.x;
+  const long total = (long)nhalf * groups;
+  // with DOT every thread reaches the workgroup's barrier: one past the end
+  // recomputes the last entry, stores nothing and adds zeros
+  const bool valid = gid < total;
+  if (!DOT && !valid) return;
+  const long gv = valid ? gid : total - 1;
+  const int pidx = (int)(gv / groups);
+  const int k0 = (int)(gv - (long)pidx * groups) * R;
+  double dre[R], dim[R], dpp[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) dre[j] = dim[j] = dpp[j] = 0.0;
+  const int i = order[pidx];
+  const int4 n0 = tab[4 * i], n1 = tab[4 * i + 1], s0 = tab[4 * i + 2], s1 = tab[4 * i + 3];
+  cplx<T> acc[4][3][R];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
+  hop_dir<T, R, 0, true>(s0.x, n0.x, n0.y, nrhs, k0, U, in, acc, true, true, s0.y);
+  hop_dir<T, R, 1, true>(s0.x, n0.z, n0.w, nrhs, k0, U, in, acc, true, true, s0.z);
+  hop_dir<T, R, 2, true>(s0.x, n1.x, n1.y, nrhs, k0, U, in, acc, true, true, s0.w);
+  hop_dir<T, R, 3, true>(s0.x, n1.z, n1.w, nrhs, k0, U, in, acc, true, true, s1.x);
+  hop_eo_epilogue<T, R, EPI, FULL2, ADDF, DOT>(i, s0.x, nrhs, k0, valid, acc, out, Ablk, in2, coef, dre, dim, dpp);
+  if constexpr (DOT) hop_eo_dot_store<R>(dre, dim, dpp, valid, (long)b * 256, groups, nrhs, part + (long)b * nrhs);
+}
+
+// t-walk form of hop_eo_kernel (FP32): a thread owns one site of a spatial
+// block, R right-hand sides and a run of Ts output sites of its parity along
+// t (every second time slice).  The input spinor at t + 1 that the forward
+// t-hop of output t loads is, transported by U_t(x, t + 1)^dag, the backward
+// t-hop of output t + 2: it is carried in registers instead of read again.
+// Hops are accumulated in the order of hop_eo_kernel (x, y, z, t; forward
+// before backward) with the same arithmetic, and the stores are the same
+// epilogue, so both kernels give bit-identical fields (DOT partials are per
+// workgroup, so the sums' grouping differs).  Work units and the XCD split
+// are those of fine_walk_kernel; `parity` is the output parity.
+template <int R, int EPI, bool FULL2, bool ADDF, bool DOT>
+__global__ __launch_bounds__(256) void hop_eo_walk_kernel(Geom g, int parity, int nrhs, WalkShape w,
+                                                          const cplx<float>* __restrict__ U,
+                                                          const cplx<float>* __restrict__ in,
+                                                          cplx<float>* __restrict__ out, const float* __restrict__ Ablk,
+                                                          const cplx<float>* __restrict__ in2, float coef,
+                                                          double4* __restrict__ part) {
+  static_assert(!DOT || (EPI == 2 && !ADDF), "the MR partial sums go with the second Schur hop");
+  const int hw = blockIdx.x;
+  const long wgi = (long)(hw & 7) * w.per + (hw >> 3);
+  if (wgi >= w.total_wg) return;  // the whole workgroup
+  const int unit = (int)(wgi / w.wg_unit);
+  const int wl = (int)(wgi - (long)unit * w.wg_unit);
+  const int tid = wl * 256 + (int)threadIdx.x;
+  // with DOT every thread reaches the workgroup's barrier; a thread past the
+  // unit's end walks the unit's last site, stores nothing and adds zeros
+  const bool valid = tid < w.bs * w.groups;
+  if (!DOT && !valid) return;
+  const int tv = valid ? tid : w.bs * w.groups - 1;
+  const int sb = tv / w.groups;
+  const int blk = unit % w.nblk, seg = unit / w.nblk;
+  const int k0 = (tv - sb * w.groups) * R;
+  const int x = (blk % w.nb[0]) * w.B[0] + sb % w.B[0];
+  const int y = ((blk / w.nb[0]) % w.nb[1]) * w.B[1] + (sb / w.B[0]) % w.B[1];
+  const int z = (blk / (w.nb[0] * w.nb[1])) * w.B[2] + sb / (w.B[0] * w.B[1]);
+  const int xs = x + g.L[0] * (y + g.L[1] * z);
+  const int Vs = g.stride[3];
+  const int dxf = x + 1 < g.L[0] ? 1 : 1 - g.L[0], dxb = x > 0 ? -1 : g.L[0] - 1;
+  const int dyf = y + 1 < g.L[1] ? g.stride[1] : g.stride[1] * (1 - g.L[1]);
+  const int dyb = y > 0 ? -g.stride[1] : g.stride[1] * (g.L[1] - 1);
+  const int dzf = z + 1 < g.L[2] ? g.stride[2] : g.stride[2] * (1 - g.L[2]);
+  const int dzb = z > 0 ? -g.stride[2] : g.stride[2] * (g.L[2] - 1);
+  // output times t = t0 + 2 q, q < Ts, of this site's parity
+  const int t0 = (parity ^ ((x + y + z) & 1)) + 2 * seg * w.Ts;
+  double dre[R], dim[R], dpp[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) dre[j] = dim[j] = dpp[j] = 0.0;
+  cplx<float> bwd[2][3][R];
+  {
+    const int sm = xs + Vs * ((t0 == 0 ? g.L[3] : t0) - 1);
+    cplx<float> p[4][3][R], h[2][3][R], uu[3][3];
+    load_spinor<float, R>(in, sm >> 1, nrhs, k0, p);
+    project<float, R, 3, -1>(p, h);
+    load_link<float, 3>(U + ((size_t)sm * 4 + 3) * 9, uu);
+    transport_dag<R>(uu, h, bwd);
+  }
+  for (int q = 0; q < w.Ts; ++q) {
+    const int t = t0 + 2 * q;
+    const int site = xs + Vs * t;
+    cplx<float> acc[4][3][R];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<float>(0, 0);
+    hop_dir<float, R, 0, true>(site, (site + dxf) >> 1, (site + dxb) >> 1, nrhs, k0, U, in, acc, true, true,
+                               site + dxb);
+    hop_dir<float, R, 1, true>(site, (site + dyf) >> 1, (site + dyb) >> 1, nrhs, k0, U, in, acc, true, true,
+                               site + dyb);
+    hop_dir<float, R, 2, true>(site, (site + dzf) >> 1, (site + dzb) >> 1, nrhs, k0, U, in, acc, true, true,
+                               site + dzb);
+    const int sp1 = xs + Vs * (t + 1 == g.L[3] ? 0 : t + 1);
+    {
+      cplx<float> p[4][3][R], hf[2][3][R], hb[2][3][R], uu[3][3], wv[2][3][R];
+      load_spinor<float, R>(in, sp1 >> 1, nrhs, k0, p);
+      project<float, R, 3, +1>(p, hf);
+      project<float, R, 3, -1>(p, hb);
+      load_link<float, 3>(U + ((size_t)site * 4 + 3) * 9, uu);
+      transport<R>(uu, hf, wv);
+      reconstruct<float, R, 3, +1>(acc, wv);
+      pin<float, R>(acc);
+      reconstruct<float, R, 3, -1>(acc, bwd);
+      pin<float, R>(acc);
+      // the backward t-hop of output t + 2: U_t(x, t + 1)^dag P psi(t + 1)
+      load_link<float, 3>(U + ((size_t)sp1 * 4 + 3) * 9, uu);
+      transport_dag<R>(uu, hb, bwd);
+    }
+    hop_eo_epilogue<float, R, EPI, FULL2, ADDF, DOT>(site >> 1, site, nrhs, k0, valid, acc, out, Ablk, in2, coef,
+                                                     dre, dim, dpp);
+  }
+  if constexpr (DOT) hop_eo_dot_store<R>(dre, dim, dpp, valid, (long)wl * 256, w.groups, nrhs, part + wgi * nrhs);
+}
+
+// Shape of a checkerboard t-walk: spatial block B, Ts output sites per run
+// (2 Ts time slices); false unless B divides the spatial extents and Ts
+// divides Lt / 2.
+bool eo_walk_shape(const Geom& g, const int B[3], int Ts, int nrhs, int R, WalkShape& w) {
+  for (int m = 0; m < 3; ++m)
+    if (B[m] < 1 || g.L[m] % B[m]) return false;
+  if (Ts < 1 || g.L[3] % 2 || (g.L[3] / 2) % Ts || nrhs % R) return false;
+  for (int m = 0; m < 3; ++m) w.B[m] = B[m];
+  w.Ts = Ts;
+  w.nc = nrhs;
+  w.groups = nrhs / R;
+  w.bs = B[0] * B[1] * B[2];
+  w.nb[0] = g.L[0] / B[0];
+  w.nb[1] = g.L[1] / B[1];
+  w.nblk = w.nb[0] * w.nb[1] * (g.L[2] / B[2]);
+  w.nseg = (g.L[3] / 2) / Ts;
+  w.wg_unit = (w.bs * w.groups + 255) / 256;
+  w.total_wg = (long)w.nseg * w.nblk * w.wg_unit;
+  w.per = (w.total_wg + 7) / 8;
+  return w.per * 8 <= 0x7fffffffL;
 }
 
 // M_ooee (or its inverse, given the inverse blocks): out = A in + coef add on
@@ -1186,6 +1321,45 @@ hipError_t launch_hop_eo_dot_r(int nhalf, int nrhs, const int4* tab, const int* 
   return hipGetLastError();
 }
 
+template <int R, int EPI, bool FULL2, bool ADDF, bool DOT>
+hipError_t launch_hop_eo_walk_k(const Geom& g, int parity, int nrhs, const EoWalk& ew, const void* U, const void* in,
+                                void* out, const void* Ablk, const void* in2, double coef, void* part, long* nblk,
+                                hipStream_t s) {
+  WalkShape w;
+  if (!eo_walk_shape(g, ew.B, ew.Ts, nrhs, R, w)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((hop_eo_walk_kernel<R, EPI, FULL2, ADDF, DOT>), dim3((unsigned)(w.per * 8)), dim3(256), 0, s, g,
+                     parity, nrhs, w, static_cast<const float2*>(U), static_cast<const float2*>(in),
+                     static_cast<float2*>(out), static_cast<const float*>(Ablk), static_cast<const float2*>(in2),
+                     (float)coef, static_cast<double4*>(part));
+  if (nblk) *nblk = w.total_wg;
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_hop_eo_walk_r(int epi, const Geom& g, int parity, int nrhs, const EoWalk& ew, const void* U,
+                                const void* in, void* out, const void* Ablk, const void* in2, double coef,
+                                hipStream_t s) {
+  switch (epi) {
+    case 0:
+      return launch_hop_eo_walk_k<R, 0, false, false, false>(g, parity, nrhs, ew, U, in, out, Ablk, in2, coef,
+                                                             nullptr, nullptr, s);
+    case 1:
+      return launch_hop_eo_walk_k<R, 1, false, false, false>(g, parity, nrhs, ew, U, in, out, Ablk, in2, coef,
+                                                             nullptr, nullptr, s);
+    case 2:
+      return launch_hop_eo_walk_k<R, 2, false, false, false>(g, parity, nrhs, ew, U, in, out, Ablk, in2, coef,
+                                                             nullptr, nullptr, s);
+    case 3:
+      return launch_hop_eo_walk_k<R, 3, true, false, false>(g, parity, nrhs, ew, U, in, out, Ablk, in2, coef,
+                                                            nullptr, nullptr, s);
+    case 4:
+      return launch_hop_eo_walk_k<R, 4, true, true, false>(g, parity, nrhs, ew, U, in, out, Ablk, in2, coef,
+                                                           nullptr, nullptr, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 // epi 0..2 on checkerboard fields (FP32 and FP64); the smoother's forms 3
 // (in2 full-lattice) and 4 (in2 full-lattice, added into a full-lattice out)
 // in FP32 only.
@@ -1259,29 +1433,58 @@ hipError_t launch_fine_dir_f32(const Geom& g, float kappa, const void* U, const 
   return launch_r<float, 1, 3>(g, g.order, kappa, U, A, in, out, nrhs, s, f);
 }
 
-// FP32: two right-hand sides per thread for even nrhs; FP64: one.
+// FP32: two right-hand sides per thread for even nrhs; FP64: one.  With a
+// t-walk configuration (g, parity and ew->on given; FP32 only) the walk
+// kernel runs instead of the tiled one, on the same fields.
 hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
                          void* out, int nrhs, hipStream_t s, int epi, const void* Ablk, const void* in2,
-                         double coef) {
+                         double coef, const Geom* g, int parity, const EoWalk* ew) {
   const bool need_a = epi == 1 || epi == 2 || epi == 4, need_in2 = epi >= 2;
   if (!tab || !order || epi < 0 || epi > 4 || (need_a && !Ablk) || (need_in2 && !in2)) return hipErrorInvalidValue;
+  if (!prec64 && g && ew && ew->on) {
+    const int R = ew->R ? ew->R : (nrhs % 2 == 0 ? 2 : 1);
+    if (R == 2) return launch_hop_eo_walk_r<2>(epi, *g, parity, nrhs, *ew, U, in, out, Ablk, in2, coef, s);
+    if (R == 1) return launch_hop_eo_walk_r<1>(epi, *g, parity, nrhs, *ew, U, in, out, Ablk, in2, coef, s);
+    return hipErrorInvalidValue;
+  }
   if (prec64) return launch_hop_eo_r<double, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
   if (nrhs % 2 == 0) return launch_hop_eo_r<float, 2>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
   return launch_hop_eo_r<float, 1>(epi, nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, s);
 }
 
+bool eo_walk_fits(const Geom& g, const int tile[4], int nrhs, int R) {
+  WalkShape w;
+  if (R == 0) R = nrhs % 2 == 0 ? 2 : 1;
+  return (R == 1 || R == 2) && tile[0] * tile[1] * tile[2] >= kEoWalkMinBlock &&
+         eo_walk_shape(g, tile, tile[3], nrhs, R, w);
+}
+
 // FP32 epi 2 with the minimal-residual partial sums (see hop_eo_kernel).
 // The partials of one launch: sized for one RHS per thread, which bounds
-// every nrhs' <= nrhs as well.
+// every nrhs' <= nrhs as well, plus one workgroup per work unit of a t-walk
+// whose spatial block has at least kEoWalkMinBlock sites (the walk's units
+// may end in a partial workgroup).
 size_t hop_eo_dot_scratch_bytes(int nhalf, int nrhs) {
-  const long nblocks = ((long)nhalf * nrhs + 255) / 256;
+  const long nblocks = ((long)nhalf * nrhs + 255) / 256 + nhalf / kEoWalkMinBlock + 1;
   return (size_t)nblocks * nrhs * sizeof(double4);
 }
 
 hipError_t launch_hop_eo_dot(int nhalf, const int4* tab, const int* order, const void* U, const void* in, void* out,
                              const void* Ablk, const void* in2, double coef, int nrhs, void* part, int* nblk,
-                             hipStream_t s) {
+                             hipStream_t s, const Geom* g, int parity, const EoWalk* ew) {
   if (!tab || !order || !Ablk || !in2 || !part || !nblk || nrhs < 1 || nrhs > 256) return hipErrorInvalidValue;
+  if (g && ew && ew->on) {
+    if (ew->B[0] * ew->B[1] * ew->B[2] < kEoWalkMinBlock) return hipErrorInvalidValue;
+    long nb = 0;
+    const int R = ew->R ? ew->R : (nrhs % 2 == 0 ? 2 : 1);
+    if (R != 1 && R != 2) return hipErrorInvalidValue;
+    hipError_t e = R == 2 ? launch_hop_eo_walk_k<2, 2, false, false, true>(*g, parity, nrhs, *ew, U, in, out, Ablk,
+                                                                           in2, coef, part, &nb, s)
+                          : launch_hop_eo_walk_k<1, 2, false, false, true>(*g, parity, nrhs, *ew, U, in, out, Ablk,
+                                                                           in2, coef, part, &nb, s);
+    *nblk = (int)nb;
+    return e;
+  }
   if (nrhs % 2 == 0)
     return launch_hop_eo_dot_r<2>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, part, nblk, s);
   return launch_hop_eo_dot_r<1>(nhalf, nrhs, tab, order, U, in, out, Ablk, in2, coef, part, nblk, s);

@@ -73,6 +73,18 @@ struct FineCfg {
   float us = 0.f;              // measured time of the choice
 };
 
+// t-walk configuration of the checkerboard hop for one nrhs (FP32): spatial
+// block B and Ts output sites per run; on = 0 runs the tiled kernel.
+constexpr int kEoWalkMinBlock = 16;  // smallest spatial block a walk may use
+struct EoWalk {
+  int on = 0;
+  int R = 0;  // right-hand sides per thread (0: two for even nrhs, else one)
+  int B[3] = {0, 0, 0};
+  int Ts = 0;
+  float us = 0.f;        // measured time of the choice (0 if set by hand)
+  float us_tiled = 0.f;  // the tiled kernel's time in the same measurement
+};
+
 struct DirFilter {
   int sign = 2;
   int mu = 0;
@@ -114,6 +126,7 @@ struct mrhs_ctx_s {
 
   // autotuned launch configurations of the FP32 fine kernel, by nrhs
   mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
+  mrhs::EoWalk eo_walk[MRHS_MAX_NRHS + 1];
 
   // checkerboard tables (per parity, four int4 per site, and the traversal
   // order of its sites) and the inverse clover blocks, built on first use; an
@@ -174,9 +187,21 @@ hipError_t launch_fine_dir_f32(const Geom& g, float kappa, const void* U, const 
 // (Ablk: packed clover blocks or their inverses; in2 on the output parity);
 // FP32 only: 3: out = in2 + coef (H in) and 4: out += Ablk (in2 + coef (H in)),
 // both with in2 a full-lattice field and 4 adding into a full-lattice out
+// whether tile = (Bx, By, Bz, Ts) with R right-hand sides per thread (0:
+// the default) is a valid checkerboard walk for nrhs
+bool eo_walk_fits(const Geom& g, const int tile[4], int nrhs, int R);
+// With g, the output parity and an EoWalk that is on (FP32 only), the t-walk
+// kernel runs instead of the tiled one (same results).
 hipError_t launch_hop_eo(int prec64, int nhalf, const int4* tab, const int* order, const void* U, const void* in,
                          void* out, int nrhs, hipStream_t s, int epi = 0, const void* Ablk = nullptr,
-                         const void* in2 = nullptr, double coef = 0.0);
+                         const void* in2 = nullptr, double coef = 0.0, const Geom* g = nullptr, int parity = 0,
+                         const EoWalk* ew = nullptr);
+// epi 2 (FP32) that also writes the minimal-residual partial sums of
+// <out, in2> and ||out||^2 per workgroup to part (*nblk rows of nrhs double4)
+size_t hop_eo_dot_scratch_bytes(int nhalf, int nrhs);
+hipError_t launch_hop_eo_dot(int nhalf, const int4* tab, const int* order, const void* U, const void* in, void* out,
+                             const void* Ablk, const void* in2, double coef, int nrhs, void* part, int* nblk,
+                             hipStream_t s, const Geom* g = nullptr, int parity = 0, const EoWalk* ew = nullptr);
 // full_in: in is a full-lattice field (its parity rows are read)
 hipError_t launch_clover_eo(int prec64, int nhalf, const int4* tab, const void* A, const void* in, const void* add,
                             double coef, void* out, int nrhs, hipStream_t s, bool full_in = false);

@@ -53,10 +53,6 @@ hipError_t launch_mr_alpha(const void* p, const void* r, long rows, int nrhs, vo
                            hipStream_t s);
 hipError_t launch_mr_update(void* x, void* r, const void* p, const void* alpha, long rows, int nrhs, hipStream_t s);
 hipError_t launch_mr_final(const void* part, int nblk, int nrhs, void* alpha, hipStream_t s);
-size_t hop_eo_dot_scratch_bytes(int nhalf, int nrhs);
-hipError_t launch_hop_eo_dot(int nhalf, const int4* tab, const int* order, const void* U, const void* in, void* out,
-                             const void* Ablk, const void* in2, double coef, int nrhs, void* part, int* nblk,
-                             hipStream_t s);
 hipError_t launch_multi_axpy(int x64, void* y, const void* coef, const void* const* xs, int m, double sgn, long rows,
                              int nrhs, hipStream_t s);
 hipError_t launch_scale_cols(int prec64, void* y, const void* x, const double* sdev, long rows, int nrhs,
@@ -318,19 +314,22 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   hipStream_t s = st->stream;
   // rhat = r_e + kappa H_eo (A_o^-1 r_o), reading r's rows in place
   hipError_t e = launch_clover_eo(0, nh, tabo, Ai, r, nullptr, 0.0, to, n, s, true);
-  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to, rho, n, s, 3, nullptr, r, k);
+  const Geom* g = &ctx->g;
+  const EoWalk* ew = &ctx->eo_walk[n];
+  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabe, orde, U, to, rho, n, s, 3, nullptr, r, k, g, 0, ew);
   if (e == hipSuccess) e = launch_zero(ee, hb, s);
   for (int i = 0; i < nu && e == hipSuccess; ++i) {
     // q = Dhat rho: to2 = A_o^-1 (H_oe rho), q = A_e rho - kappa^2 (H_eo to2), fused launches;
     // the second also sums <q, rho> and ||q||^2 per workgroup for the step length
     int nblk = 0;
-    e = launch_hop_eo(0, nh, tabo, ordo, U, rho, to2, n, s, 1, Ai);
-    if (e == hipSuccess) e = launch_hop_eo_dot(nh, tabe, orde, U, to2, q, A, rho, -k * k, n, st->eo_part.p, &nblk, s);
+    e = launch_hop_eo(0, nh, tabo, ordo, U, rho, to2, n, s, 1, Ai, nullptr, 0.0, g, 1, ew);
+    if (e == hipSuccess)
+      e = launch_hop_eo_dot(nh, tabe, orde, U, to2, q, A, rho, -k * k, n, st->eo_part.p, &nblk, s, g, 0, ew);
     if (e == hipSuccess) e = launch_mr_final(st->eo_part.p, nblk, n, st->alpha.p, s);
     if (e == hipSuccess) e = launch_mr_update(ee, rho, q, st->alpha.p, hrows, n, s);
   }
   // x_o += A_o^-1 (r_o + kappa H_oe e_e) in one launch, x_e += e_e
-  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabo, ordo, U, ee, x, n, s, 4, Ai, r, k);
+  if (e == hipSuccess) e = launch_hop_eo(0, nh, tabo, ordo, U, ee, x, n, s, 4, Ai, r, k, g, 1, ew);
   if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabe, x, ee, n, s);
   // r = b - D x
   if (need_r && e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);

@@ -318,6 +318,106 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
       cache_append(cache_path, arch, ctx->g, n, best);
     }
   }
+  // The checkerboard hop of the even-odd smoother (lattices with even
+  // extents): tiled kernel or t-walk, timed as one Schur step's pair of
+  // launches (output parity 1 with a clover factor, output parity 0 with the
+  // factor, the combination and the MR sums) on the same scratch fields; the
+  // clover blocks stand in for their inverses (same layout and cost).  The
+  // results are bit-identical either way (the MR sums up to their grouping),
+  // so the choice is made afresh by every call and not cached.
+  bool even = true;
+  for (int m = 0; m < 4; ++m) even = even && ctx->g.L[m] % 2 == 0;
+  if (even && e == hipSuccess) {
+    mrhs_status est = ensure_eo_tables(ctx);
+    Buffer part;
+    const int nhalf = ctx->g.V / 2;
+    if (est == MRHS_OK) est = ensure(ctx, part, hop_eo_dot_scratch_bytes(nhalf, nmax));
+    if (est != MRHS_OK) {
+      (void)hipStreamSynchronize(ctx->stream);
+      release(in);
+      release(out);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      return est;
+    }
+    const auto* te = static_cast<const int4*>(ctx->eo_tab[0].p);
+    const auto* to = static_cast<const int4*>(ctx->eo_tab[1].p);
+    const auto* oe = static_cast<const int*>(ctx->eo_order[0].p);
+    const auto* oo = static_cast<const int*>(ctx->eo_order[1].p);
+    char* half2 = static_cast<char*>(out.p) + (size_t)nhalf * 12 * nmax * 8;  // second half of out
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+      const int n = nrhs_list[i];
+      auto time_eo = [&](const EoWalk& w, float& us) -> hipError_t {
+        std::vector<float> t;
+        hipError_t err = hipSuccess;
+        for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+          int nb = 0;
+          err = hipEventRecord(e0, ctx->stream);
+          if (err == hipSuccess)
+            err = launch_hop_eo(0, nhalf, to, oo, ctx->U32.p, in.p, out.p, n, ctx->stream, 1, ctx->A32.p, nullptr,
+                                0.0, &ctx->g, 1, &w);
+          if (err == hipSuccess)
+            err = launch_hop_eo_dot(nhalf, te, oe, ctx->U32.p, out.p, half2, ctx->A32.p, in.p, -0.01, n, part.p, &nb,
+                                    ctx->stream, &ctx->g, 0, &w);
+          if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+          if (err == hipSuccess) err = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) t.push_back(ms * 1000.f);
+        }
+        if (err != hipSuccess) return err;
+        std::sort(t.begin(), t.end());
+        us = t[t.size() / 2];
+        return hipSuccess;
+      };
+      EoWalk best;  // tiled
+      e = time_eo(best, best.us);
+      const float tiled = best.us;
+      // coordinate descent: spatial block at a short run, then the run length, then R
+      const int Lh = ctx->g.L[3] / 2;
+      const int ts0 = Lh % 4 == 0 ? 4 : (Lh % 2 == 0 ? 2 : 1);
+      const std::array<int, 3> blocks[] = {{4, 4, 4}, {8, 4, 4}, {8, 8, 4}, {6, 6, 4}, {12, 4, 4},
+                                           {24, 4, 4}, {4, 4, 2}, {8, 8, 8}, {6, 6, 6}};
+      auto consider = [&](EoWalk w) {
+        const int tile[4] = {w.B[0], w.B[1], w.B[2], w.Ts};
+        if (e != hipSuccess || !eo_walk_fits(ctx->g, tile, n, w.R)) return;
+        e = time_eo(w, w.us);
+        if (e == hipSuccess && w.us < best.us) best = w;
+      };
+      for (const auto& b : blocks) {
+        EoWalk w;
+        w.on = 1;
+        for (int m = 0; m < 3; ++m) w.B[m] = b[m];
+        w.Ts = ts0;
+        consider(w);
+      }
+      if (best.on) {
+        const EoWalk base = best;
+        for (int ts : {1, 2, 4, 8, 16, Lh}) {
+          if (ts == base.Ts) continue;
+          EoWalk w = base;
+          w.Ts = ts;
+          consider(w);
+        }
+        const EoWalk base2 = best;
+        for (int R : {1, 2}) {
+          const int r0 = base2.R ? base2.R : (n % 2 == 0 ? 2 : 1);
+          if (R == r0) continue;
+          EoWalk w = base2;
+          w.R = R;
+          consider(w);
+        }
+      }
+      if (e == hipSuccess) {
+        best.us_tiled = tiled;
+        if (!best.on) best.us = tiled;
+        ctx->eo_walk[n] = best;
+      }
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    release(part);
+    ctx->op_gen++;  // captured V-cycles hold the hop's launch shape
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   hipError_t es = hipStreamSynchronize(ctx->stream);

@@ -221,3 +221,70 @@ def test_coarse_eo_odd_extent_rejected(gpu_lib):
     b = torch.zeros_like(a)
     with pytest.raises((gpu_lib.MrhsError, ValueError)):
         mg.coarse_hop_eo(1, b, a, 0)
+
+
+# t-walk shapes of the checkerboard hop on the 4x6x4x8 lattice: spatial block
+# (Bx, By, Bz) of at least 16 sites, Ts output sites per run (Ts | Lt / 2 = 4),
+# RHS per thread (0: the default for the parity of nrhs)
+WALKS = [((4, 2, 2, 1), 0), ((2, 6, 2, 2), 1), ((4, 6, 4, 4), 0), ((2, 2, 4, 4), 2), ((4, 3, 2, 2), 1)]
+
+
+@pytest.mark.parametrize("walk,R", WALKS)
+@pytest.mark.parametrize("nrhs", [1, 6, 13, 24])
+def test_hop_eo_walk_bitwise(lat, walk, R, nrhs):
+    """The t-walk checkerboard hop gives the tiled kernel's fields bit for bit
+    (both output parities, and the two fused Schur launches), whatever the
+    block, run length and RHS per thread; the walks wrap through the
+    antiperiodic t boundary.  The tiled kernel is pinned to the oracle above."""
+    import torch
+
+    dims, U, A, ctx = lat
+    if R == 2 and nrhs % 2:
+        pytest.skip("two RHS per thread need an even nrhs")
+    ctx.set_eo_walk(nrhs, None)
+    outs = {}
+    for p in (0, 1):
+        psi = dev(EO.to_cb(synth.spinor_source(dims, nrhs, 70 + p, np.complex64), dims, 1 - p))
+        o = torch.empty_like(psi)
+        ctx.hop_eo(o, psi, p)
+        outs[p] = (psi, o.clone())
+    chi = dev(EO.to_cb(synth.spinor_source(dims, nrhs, 80, np.complex64), dims, 0))
+    s0 = torch.empty_like(chi)
+    ctx.schur(s0, chi)
+    ctx.set_eo_walk(nrhs, walk, R)
+    on, r, tile, _, _ = ctx.get_eo_walk(nrhs)
+    assert on and tuple(tile) == walk and r == R
+    for p in (0, 1):
+        psi, o0 = outs[p]
+        o = torch.empty_like(psi)
+        ctx.hop_eo(o, psi, p)
+        assert torch.equal(o, o0), p
+    s1 = torch.empty_like(chi)
+    ctx.schur(s1, chi)
+    assert torch.equal(s1, s0)
+    ctx.set_eo_walk(nrhs, None)
+
+
+def test_eo_walk_rejects_bad_shapes(lat, gpu_lib):
+    dims, U, A, ctx = lat
+    for tile, R in [((4, 4, 4, 1), 0), ((2, 2, 2, 1), 0), ((4, 6, 4, 3), 0), ((4, 6, 4, 1), 2), ((4, 6, 4, 1), 3)]:
+        n = 5 if R == 2 else 6
+        with pytest.raises(gpu_lib.MrhsError, match="INVALID_ARG"):
+            ctx.set_eo_walk(n, tile, R)  # block not dividing 6, < 16 sites, Ts not dividing 4, R = 2 at odd nrhs, R = 3
+
+
+def test_tune_chooses_a_checkerboard_kernel(gpu_lib):
+    """mrhs_tune times the checkerboard hop on a lattice with even extents and
+    keeps a valid choice, tiled or walk, with both times recorded."""
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_haar(dims, 4002)
+    ctx = gpu_lib.Context(dims, t_bc=-1)
+    ctx.set_gauge(U)
+    ctx.build_clover(CSW, KAPPA)
+    ctx.tune([4, 7])
+    for n in (4, 7):
+        on, r, tile, us, ut = ctx.get_eo_walk(n)
+        assert ut > 0 and us > 0 and us <= ut * 1.0001
+        if on:
+            assert all(d % b == 0 for d, b in zip(dims[:3], tile[:3])) and (dims[3] // 2) % tile[3] == 0
+    ctx.close()

@@ -269,19 +269,25 @@ def _eo_smoother_ref(U, A, kappa, b, dims, nu):
     ((4, 6, 4, 6), (2, 2, 2, 2), 4, 12),
     ((4, 6, 4, 6), (2, 2, 2, 2), 4, 3),
 ])
-def test_even_odd_smoother_alone(gpu_lib, dims, block, nv, nrhs):
+@pytest.mark.parametrize("walk", [False, True])
+def test_even_odd_smoother_alone(gpu_lib, dims, block, nv, nrhs, walk):
     """The fine even-odd smoother by itself: with two levels, no pre-smoothing
     and no coarsest-level steps the coarse correction is exactly zero, so the
     V-cycle returns nu_post = 3 even-odd MR steps applied to v.  Its step
     lengths come from the per-workgroup sums in the checkerboard hop's
     epilogue; any slip in their column mapping (Nrhs not dividing 256, one
     RHS per thread, a ragged last workgroup on the 4x6x4x6 lattice) changes
-    alpha and fails the comparison with the FP64 reference at the FP32 bar."""
+    alpha and fails the comparison with the FP64 reference at the FP32 bar.
+    With `walk` the checkerboard hops run as the t-walk kernel, whose sums are
+    grouped per walk workgroup (a partial workgroup at the end of each block's
+    threads on 4x6x4x6)."""
     import torch
 
     U = synth.gauge_haar(dims, 4242)
     A = O.clover_packed(U, dims, CSW, KAPPA)
     ctx, mg = build(gpu_lib, dims, U, [block], [nv], setup_iters=1, smooth_steps=4)
+    if walk:
+        ctx.set_eo_walk(nrhs, (4, 4, 2, 2) if dims[0] == 8 else (2, 2, 4, 3))
     v = synth.spinor_source(dims, nrhs, 9300, np.complex64)
     z = torch.empty(v.shape, dtype=torch.complex64, device="cuda")
     mg.precondition(z, dev(v), nu_pre=0, nu_post=3, coarsest_iters=0, coarse_prec="bf16", fine_eo=True)
