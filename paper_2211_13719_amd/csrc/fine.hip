@@ -6,8 +6,11 @@
 //
 // Work decomposition: one thread owns one site and R consecutive right-hand
 // sides (R in 1, 2, 4 and the traversal tile below are chosen per Nrhs by the
-// autotuner; untuned: R = 2 for even Nrhs in FP32, else 1).  Fields are [site][12][nrhs] complex, so the nrhs/R threads of a site
-// are adjacent lanes that read contiguous memory for every component, and all
+// autotuner; untuned: R = 2 for even Nrhs in FP32, else 1), or, in the t-walk
+// kernels further down, one site of a spatial block, R right-hand sides and a
+// run of time slices.  Fields are [site][12][nrhs] complex, so the nrhs/R
+// threads of a site are adjacent lanes that read contiguous memory for every
+// component, and all
 // of them share the site's links and clover blocks (one cache line serves the
 // whole group: the gauge-field reuse of Sec. 2).  Each neighbour spinor is
 // spin-projected to a half spinor (2 spins x 3 colours) before the SU(3)
@@ -602,11 +605,12 @@ hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, con
 // U_t(x, t)^dag it is the backward t-hop of slice t+1.  So no t-neighbour is
 // read twice, whatever the cache holds.  (Keeping only the transported half
 // spinor and reading the slice's own spinor again takes fewer registers, 166
-// instead of 224 at R = 2, but measured slower at every Nrhs.)  The threads of one block run
-// together, one slice at a time, and read each other's spinors as spatial
-// neighbours at about the same moment, which keeps those re-reads in the L2
-// even when the bytes in flight exceed it (they do at large Nrhs, where the
-// tiled kernel above re-reads every neighbour from memory).
+// instead of 224 at R = 2, but measured slower at every Nrhs.)  The threads
+// of one block walk together, a slice at a time, and read each other's
+// spinors as spatial neighbours within about one slice step of their load,
+// so more of those re-reads hit the L2 than in the tiled kernel; rows that
+// cross a block face, or whose owner has drifted a step away, still come
+// from memory.
 //
 // Work units are (RHS chunk, t-run, spatial block), numbered with the block
 // fastest; each XCD takes one contiguous range of their workgroups.  The
