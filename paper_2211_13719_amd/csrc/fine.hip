@@ -663,13 +663,16 @@ __device__ __forceinline__ void transport(const cplx<float> (&uu)[3][3], const c
       }
 }
 
-template <int R, int OCC>
+// RES: out = bres - D in (the residual), the subtraction in FP32 after the
+// operator, exactly as a separate pass would do it.
+template <int R, int OCC, bool RES = false>
 __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geom g, int nrhs, float kappa,
                                                                            const cplx<float>* __restrict__ U,
                                                                            const float* __restrict__ A,
                                                                            const cplx<float>* __restrict__ in,
                                                                            cplx<float>* __restrict__ out, WalkShape w,
-                                                                           int nt_out) {
+                                                                           int nt_out,
+                                                                           const cplx<float>* __restrict__ bres = nullptr) {
   const int hw = blockIdx.x;
   const long wgi = (long)(hw & 7) * w.per + (hw >> 3);
   if (wgi >= w.total_wg) return;
@@ -750,6 +753,12 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geo
           yout[q][j].x = fma(-kappa, acc[sp][c][j].x, yout[q][j].x);
           yout[q][j].y = fma(-kappa, acc[sp][c][j].y, yout[q][j].y);
         }
+        if constexpr (RES) {
+          cplx<float> bv[R];
+          load_r<float, R>(bres + (size_t)site * 12 * nrhs + k0 + (6 * chi + q) * nrhs, bv);
+#pragma unroll
+          for (int j = 0; j < R; ++j) yout[q][j] = sub<float>(bv[j], yout[q][j]);
+        }
         store_r<float, R>(o + (6 * chi + q) * nrhs, yout[q], nt_out);
       }
     }
@@ -784,27 +793,36 @@ bool walk_shape(const Geom& g, const int T[4], int nrhs, int R, int chunks, Walk
   return w.per * 8 <= 0x7fffffffL;
 }
 
-template <int R, int OCC>
+template <int R, int OCC, bool RES>
 hipError_t launch_walk_r(const Geom& g, const FineCfg& c, float kappa, const void* U, const void* A, const void* in,
-                         void* out, int nrhs, hipStream_t s) {
+                         void* out, int nrhs, hipStream_t s, const void* bres) {
   WalkShape w;
   if (!walk_shape(g, c.T, nrhs, R, c.chunks, w)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fine_walk_kernel<R, OCC>), dim3((unsigned)(w.per * 8)), dim3(256), c.lds, s, g, nrhs, kappa,
-                     reinterpret_cast<const cplx<float>*>(U), reinterpret_cast<const float*>(A),
-                     reinterpret_cast<const cplx<float>*>(in), reinterpret_cast<cplx<float>*>(out), w, c.nt);
+  hipLaunchKernelGGL((fine_walk_kernel<R, OCC, RES>), dim3((unsigned)(w.per * 8)), dim3(256), c.lds, s, g, nrhs,
+                     kappa, reinterpret_cast<const cplx<float>*>(U), reinterpret_cast<const float*>(A),
+                     reinterpret_cast<const cplx<float>*>(in), reinterpret_cast<cplx<float>*>(out), w, c.nt,
+                     reinterpret_cast<const cplx<float>*>(bres));
   return hipGetLastError();
 }
 
-hipError_t launch_walk(const Geom& g, const FineCfg& c, float kappa, const void* U, const void* A, const void* in,
-                       void* out, int nrhs, hipStream_t s) {
+// bres given: out = bres - D in
+template <bool RES>
+hipError_t launch_walk_res(const Geom& g, const FineCfg& c, float kappa, const void* U, const void* A, const void* in,
+                           void* out, int nrhs, hipStream_t s, const void* bres) {
   if (c.occ == 4) {
-    if (c.R == 2) return launch_walk_r<2, 4>(g, c, kappa, U, A, in, out, nrhs, s);
-    if (c.R == 1) return launch_walk_r<1, 4>(g, c, kappa, U, A, in, out, nrhs, s);
+    if (c.R == 2) return launch_walk_r<2, 4, RES>(g, c, kappa, U, A, in, out, nrhs, s, bres);
+    if (c.R == 1) return launch_walk_r<1, 4, RES>(g, c, kappa, U, A, in, out, nrhs, s, bres);
   } else {
-    if (c.R == 2) return launch_walk_r<2, 0>(g, c, kappa, U, A, in, out, nrhs, s);
-    if (c.R == 1) return launch_walk_r<1, 0>(g, c, kappa, U, A, in, out, nrhs, s);
+    if (c.R == 2) return launch_walk_r<2, 0, RES>(g, c, kappa, U, A, in, out, nrhs, s, bres);
+    if (c.R == 1) return launch_walk_r<1, 0, RES>(g, c, kappa, U, A, in, out, nrhs, s, bres);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_walk(const Geom& g, const FineCfg& c, float kappa, const void* U, const void* A, const void* in,
+                       void* out, int nrhs, hipStream_t s, const void* bres = nullptr) {
+  if (bres) return launch_walk_res<true>(g, c, kappa, U, A, in, out, nrhs, s, bres);
+  return launch_walk_res<false>(g, c, kappa, U, A, in, out, nrhs, s, nullptr);
 }
 
 template <typename T, int MODE>
@@ -1410,6 +1428,15 @@ hipError_t launch_clover_eo_r(int nhalf, int nrhs, const int4* tab, const void* 
 hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U, const void* A,
                            const void* in, void* out, int nrhs, hipStream_t s, const FineCfg* cfg) {
   return launch_fine<float>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s, cfg);
+}
+
+// r = b - D x in FP32 in one launch when the tuned configuration of nrhs is
+// the t-walk kernel; false (nothing launched) otherwise.
+bool launch_fine_residual_f32(const Geom& g, float kappa, const void* U, const void* A, const void* x, const void* b,
+                              void* r, int nrhs, hipStream_t s, const FineCfg* cfg, hipError_t* err) {
+  if (!cfg || cfg->R <= 0 || !cfg->walk || !b) return false;
+  *err = launch_walk(g, *cfg, kappa, U, A, x, r, nrhs, s, b);
+  return true;
 }
 
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U, const void* A,

@@ -170,6 +170,11 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const void* U,
                            const void* A, const void* in, void* out, int nrhs, hipStream_t s,
                            const FineCfg* cfg = nullptr);
+// r = b - D x (FP32) in one launch if the tuned configuration of nrhs allows
+// it (the t-walk kernel): returns true and the launch status in *err, else
+// false with nothing launched
+bool launch_fine_residual_f32(const Geom& g, float kappa, const void* U, const void* A, const void* x, const void* b,
+                              void* r, int nrhs, hipStream_t s, const FineCfg* cfg, hipError_t* err);
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U,
                            const void* A, const void* in, void* out, int nrhs, hipStream_t s);
 // D = A - kappa H in FP64 on an FP32 input field (widened exactly on load)

@@ -252,6 +252,21 @@ hipError_t apply_level(mrhs_mg mg, int l, void* out, const void* in, int n, mrhs
                             L.lowp_cfg[n]);
 }
 
+// r = b - D_l x (FP32 fields, p a work field): on the fine level one fused
+// launch where the tuned kernel allows it, else the operator into p and the
+// subtraction (same arithmetic either way).
+hipError_t residual_level(mrhs_mg mg, int l, void* r, const void* b, const void* x, void* p, int n, mrhs_prec cp,
+                          hipStream_t s) {
+  mrhs_ctx ctx = mg->ctx;
+  hipError_t e = hipSuccess;
+  if (l == 0 && launch_fine_residual_f32(ctx->g, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, x, b, r, n, s,
+                                         &ctx->fine_cfg[n], &e))
+    return e;
+  e = apply_level(mg, l, p, x, n, cp, s);
+  if (e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, l) * n, s);
+  return e;
+}
+
 // nu MR steps on a small coarse level with BF16 operands, two launches each
 // (fused stencil, update and per-site inner products; step length), then one
 // launch for the last update of x and r.  p and the level's second r / p
@@ -332,8 +347,7 @@ hipError_t eo_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void* 
   if (e == hipSuccess) e = launch_hop_eo(0, nh, tabo, ordo, U, ee, x, n, s, 4, Ai, r, k, g, 1, ew);
   if (e == hipSuccess) e = launch_eo_scatter_add(nh, tabe, x, ee, n, s);
   // r = b - D x
-  if (need_r && e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
-  if (need_r && e == hipSuccess) e = launch_sub(0, r, b, p, level_rows(mg, 0) * n, s);
+  if (need_r && e == hipSuccess) e = residual_level(mg, 0, r, b, x, p, n, MRHS_F32, s);
   return e;
 }
 
@@ -406,8 +420,7 @@ hipError_t sap_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void*
   for (int cyc = 0; cyc < nu && e == hipSuccess; ++cyc) {
     for (int c = 0; c < 2 && e == hipSuccess; ++c) {
       if (cyc > 0 || c > 0) {
-        e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
-        if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, s);
+        e = residual_level(mg, 0, r, b, x, p, n, MRHS_F32, s);
       }
       DirFilter f;
       f.sign = 0;
@@ -419,8 +432,7 @@ hipError_t sap_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void*
       }
     }
   }
-  if (need_r && e == hipSuccess) e = apply_level(mg, 0, p, x, n, MRHS_F32, s);
-  if (need_r && e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, s);
+  if (need_r && e == hipSuccess) e = residual_level(mg, 0, r, b, x, p, n, MRHS_F32, s);
   return e;
 }
 
@@ -479,8 +491,7 @@ hipError_t vcycle(mrhs_mg mg, SolverState* st, int l, int n, const mrhs_vcycle_p
   }
   PhaseMark pm(st, ph);
   e = pre ? launch_add_f32(x, p, rows * n, st->stream) : hipSuccess;
-  if (e == hipSuccess) e = apply_level(mg, l, p, x, n, cp, st->stream);
-  if (e == hipSuccess) e = launch_sub(0, r, b, p, rows * n, st->stream);
+  if (e == hipSuccess) e = residual_level(mg, l, r, b, x, p, n, cp, st->stream);
   if (e == hipSuccess) e = smooth(mg, st, l, x, r, b, p, n, vc.nu_post, vc, false);
   return e;
 }

@@ -579,3 +579,32 @@ def test_unpreconditioned_fp32_krylov_and_bad_precision(small, gpu_lib):
     assert np.all(O.true_residual(U, A, KAPPA, x.cpu().numpy(), b, dims) <= 1e-10)
     with pytest.raises(gpu_lib.MrhsError, match="UNSUPPORTED"):
         mg.solve(torch.zeros_like(x), dev(b), krylov_prec=gpu_lib.BF16)
+
+
+def test_vcycle_same_with_walk_and_fused_residual(small, tmp_path):
+    """With the fine kernel tuned to the t-walk, the V-cycle's fine-level
+    residual r = b - D x runs as one fused launch; with the tiled kernel it
+    is the operator and a subtraction.  Both compute the same FP32 values,
+    so the preconditioned vectors agree bit for bit (full-lattice and
+    even-odd smoothers)."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    n = 6
+    v = dev(synth.spinor_source(dims, n, 9400, np.complex64))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    from test_gpu_fine import _hip_runtime_version
+
+    def run(tile, curve, fine_eo):
+        cache = tmp_path / f"c{curve}.txt"
+        cache.write_text(f"{arch} {_hip_runtime_version()} {' '.join(map(str, dims))} {n} 2 "
+                         f"{' '.join(map(str, tile))} {curve} 0 0 1 0 1.0\n")
+        ctx.tune([n], str(cache))
+        assert bool(ctx.get_tuning(n)[2] & 128) == (curve == 2)
+        z = torch.empty_like(v)
+        mg.precondition(z, v, nu_pre=1, nu_post=2, coarsest_iters=8, coarse_prec="bf16", fine_eo=fine_eo)
+        return z
+    for fine_eo in (False, True):
+        z_walk = run((4, 4, 2, 2), 2, fine_eo)
+        z_tiled = run((2, 2, 2, 2), 0, fine_eo)
+        assert torch.equal(z_tiled, z_walk), fine_eo
