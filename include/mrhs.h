@@ -328,21 +328,25 @@ mrhs_status mrhs_coarse_apply(mrhs_mg mg, int32_t level, void* out, const void* 
  * mrhs_coarse_apply with MRHS_F32 and for V-cycles with FP32 coarse levels
  * (untuned: the matrix cores), and (b) the launch shapes of the BF16/FP16
  * matrix-core stencil (four or eight wavefronts per site, one or two
- * 32-column tiles of right-hand sides per workgroup; untuned: four and one),
- * used for BF16 and FP16 applies and V-cycles, and (c) on levels of at most
- * 1024 sites the same shapes for the fused BF16 minimal-residual step of the
- * coarsest-level solve.  Synchronises; drops the solver's captured V-cycles
+ * 32-column tiles of right-hand sides per workgroup, the two as separate or
+ * interleaved columns; untuned: four and one), used for BF16 and FP16 applies
+ * and V-cycles, and (c) on levels of at most 1024 sites the shapes without
+ * interleaving for the fused BF16 minimal-residual step of the coarsest-level
+ * solve.  Synchronises; drops the solver's captured V-cycles
  * and work buffers, which the next solve rebuilds. */
 mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count);
 /* mrhs_mg_get_tuning: *f32_valu = 1 when level uses the vector-ALU FP32
  * stencil for nrhs (always for Nb != 32), 0 for the FP32 matrix cores;
  * *lowp_cfg (if not NULL) = the BF16/FP16 stencil's launch shape, bit 0 eight
- * wavefronts per site (else four), bit 1 two 32-column tiles per workgroup. */
+ * wavefronts per site (else four), cfg >> 1 the column tiling: 0 one
+ * 32-column tile per workgroup, 1 two, 2 two tiles of interleaved column
+ * pairs read with 16-byte loads (even nrhs; run as 1 otherwise). */
 mrhs_status mrhs_mg_get_tuning(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t* f32_valu, int32_t* lowp_cfg);
 /* mrhs_mg_set_lowp_cfg: sets the BF16/FP16 stencil's launch shape (and that
- * of the fused MR step) for level and nrhs by hand (0..3, bits as in
- * mrhs_mg_get_tuning), e.g. to restore a persisted tuning; every shape
- * computes the same operator.  Captured V-cycles are recaptured. */
+ * of the fused MR step, which has no column-pair form: 4 / 5 give it 2 / 3)
+ * for level and nrhs by hand (0..5, as in mrhs_mg_get_tuning), e.g. to
+ * restore a persisted tuning; every shape computes the same operator.
+ * Captured V-cycles are recaptured. */
 mrhs_status mrhs_mg_set_lowp_cfg(mrhs_mg mg, int32_t level, int32_t nrhs, int32_t cfg);
 
 /* Even-odd pieces of the coarse stencil, Sec. 6 (the coarse-level M_eooe):

@@ -6,11 +6,14 @@
 // Complex arithmetic is split into real products,
 //   Re O += Re B Re E - Im B Im E,   Im O += Re B Im E + Im B Re E,
 // four v_mfma_f32_32x32x16 per 16-wide slice of the contraction index j.
-// One workgroup owns one site and a 32-column tile of right-hand sides; its
-// four wavefronts take the nine directions in turn (d = w, w + 4, w + 8) and
-// their partial sums are added through LDS in a fixed order, which gives the
-// latency-bound small coarse lattices four times the wavefronts in flight.
-// Rows of the 32 x 32 output are the 32 coarse components i, columns the
+// One workgroup owns one site and one or two 32-column tiles of right-hand
+// sides (two tiles either as columns c0.. and c0 + 32.., or interleaved, even
+// columns in one tile and odd in the other, so that a lane reads a column pair
+// with one 16-byte load).  The 18 units of work of a site (nine directions,
+// two 16-wide slices of j) are dealt to its four or eight wavefronts in turn,
+// and their partial sums are added through LDS in a fixed order, which gives
+// the latency-bound small coarse lattices several wavefronts per site.  Rows
+// of the 32 x 32 output are the 32 coarse components i, columns the
 // right-hand sides.
 //
 // Operand layouts of v_mfma_f32_32x32x16_{bf16,f16} (lane l, 8 values each):
@@ -23,9 +26,10 @@
 // ([site][j][rhs]); each lane reads its eight values (256-byte contiguous runs
 // across the wavefront) and rounds them from FP32 to BF16/FP16 on the fly
 // (hardware conversion, round to nearest even; the one-time block pack,
-// which starts from FP64, uses the explicit conversions of rounding.h).  FP16 operands are first scaled per right-hand side by a power
-// of two, 2^-E with max_k |x| = m 2^E, m in [0.5, 1), and the output is
-// scaled back in FP32; the power of two keeps the scaling exact.
+// which starts from FP64, uses the explicit conversions of rounding.h).
+// FP16 operands are first scaled per right-hand side by a power of two,
+// 2^-E with max_k |x| = m 2^E, m in [0.5, 1), and the output is scaled back in
+// FP32; the power of two keeps the scaling exact.
 #include "mg_internal.h"
 #include "rounding.h"
 
@@ -184,11 +188,16 @@ __device__ __forceinline__ int stencil_nbr(const Geom& g, int s, const int (&x)[
 // on a valid unit with zero operands (straight-line loads, no branch).
 // fetch(row, e, t, d) returns the FP32 operand at row `row` (of the input
 // field of direction d), element offset e = j nrhs + column, for tile t.
-template <bool F16, int WV, int NT, class Fetch>
+// PAIR (with NT = 2): tile 0 holds the even and tile 1 the odd columns of a
+// 64-column group, lane l columns c0 + 2 (l % 32) and the next, so each
+// operand row is one 16-byte load fetch4(row, e, d) of the column pair at
+// element offset e (colc[0] the even column) instead of two 8-byte loads.
+template <bool F16, int WV, int NT, bool PAIR = false, class Fetch, class Fetch4>
 __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int EOmode, int nrhs, const uint4* Bp,
                                               int bstride, const int (&colc)[NT], const bool (&colok)[NT],
-                                              const float (&sc)[NT], Fetch&& fetch, f32x16 (&accR)[NT],
-                                              f32x16 (&accI)[NT]) {
+                                              const float (&sc)[NT], Fetch&& fetch, Fetch4&& fetch4,
+                                              f32x16 (&accR)[NT], f32x16 (&accI)[NT]) {
+  static_assert(!PAIR || NT == 2, "column pairs fill two tiles");
   using O = Op<F16>;
   using vec = typename O::vec;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -208,8 +217,11 @@ __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int 
   // units are handled in batches: every load of a batch is issued before its
   // first matrix instruction, so a wavefront waits for memory once per batch
   // instead of once per unit (with one tile all of a wavefront's units form
-  // one batch; with two tiles batches of three bound the registers)
-  constexpr int PB = NT == 1 ? KMAX : 3;
+  // one batch; with two tiles batches of three bound the registers, and for
+  // column pairs smaller batches buy occupancy: measured on 6^3x32 at 64
+  // columns, one-unit batches on four wavefronts run 129 us against 135 us
+  // for two and 153 us for the one-tile shape)
+  constexpr int PB = NT == 1 ? KMAX : (PAIR ? (WV == 4 ? 1 : 2) : 3);
 #pragma unroll
   for (int k0 = 0; k0 < KMAX; k0 += PB) {
     uint4 br[PB], bi[PB];
@@ -228,10 +240,19 @@ __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int 
       const uint4* bp = Bp + ((size_t)s * bstride + d) * 256;
       br[kk] = bp[(kc * 2 + 0) * 64 + l];
       bi[kk] = bp[(kc * 2 + 1) * 64 + l];
+      if constexpr (PAIR) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+        for (int q = 0; q < 8; ++q) {
+          const float4 v = fetch4(ii, (size_t)(kc * 16 + jh + q) * nrhs + colc[0], d);
+          ev[kk][0][q] = make_float2(v.x, v.y);
+          ev[kk][NT - 1][q] = make_float2(v.z, v.w);
+        }
+      } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ev[kk][t][q] = fetch(ii, (size_t)(kc * 16 + jh + q) * nrhs + colc[t], t, d);
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) ev[kk][t][q] = fetch(ii, (size_t)(kc * 16 + jh + q) * nrhs + colc[t], t, d);
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < PB; ++kk) {
@@ -264,7 +285,7 @@ __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int 
 // tiles of right-hand sides).
 // EO = 3 (the coarse Schur complement's outer product, all extents even):
 // out = S_p in - H_{p,1-p} in2 on parity p, in on parity p, in2 on 1 - p.
-template <bool F16, int EO, int WV, int NT>
+template <bool F16, int EO, int WV, int NT, bool PAIR = false>
 __global__ __launch_bounds__(64 * WV) void coarse_mfma_kernel(Geom g, int nrhs, const uint4* __restrict__ Bp,
                                                               const float2* __restrict__ in, float2* __restrict__ out,
                                                               const float* __restrict__ scale, int nblocks,
@@ -284,9 +305,10 @@ __global__ __launch_bounds__(64 * WV) void coarse_mfma_kernel(Geom g, int nrhs, 
   float sc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    col[t] = c0 + 32 * t + (l & 31);
+    // PAIR: lane l owns the column pair c0 + 2 (l % 32), + 1 (nrhs even)
+    col[t] = PAIR ? c0 + 2 * (l & 31) + t : c0 + 32 * t + (l & 31);
     colok[t] = col[t] < nrhs;
-    colc[t] = colok[t] ? col[t] : nrhs - 1;
+    colc[t] = colok[t] ? col[t] : (PAIR ? nrhs - 2 + t : nrhs - 1);
     sc[t] = (F16 && colok[t]) ? scale[col[t]] : 1.0f;
   }
   f32x16 accR[NT], accI[NT];
@@ -295,27 +317,47 @@ __global__ __launch_bounds__(64 * WV) void coarse_mfma_kernel(Geom g, int nrhs, 
     accR[t] = f32x16{};
     accI[t] = f32x16{};
   }
-  stencil_units<F16, WV, NT>(g, s, io, EO, nrhs, Bp, bstride, colc, colok, sc,
-                             [&](int ii, size_t e, int, int d) {
-                               if (EO == 3 && d > 0) {  // minus the hop term, read from the second field
-                                 const float2 v = in2[(size_t)ii * kNb * nrhs + e];
-                                 return make_float2(-v.x, -v.y);
-                               }
-                               return in[(size_t)ii * kNb * nrhs + e];
-                             },
-                             accR, accI);
+  stencil_units<F16, WV, NT, PAIR>(
+      g, s, io, EO, nrhs, Bp, bstride, colc, colok, sc,
+      [&](int ii, size_t e, int, int d) {
+        if (EO == 3 && d > 0) {  // minus the hop term, read from the second field
+          const float2 v = in2[(size_t)ii * kNb * nrhs + e];
+          return make_float2(-v.x, -v.y);
+        }
+        return in[(size_t)ii * kNb * nrhs + e];
+      },
+      [&](int ii, size_t e, int d) {
+        if (EO == 3 && d > 0) {
+          const float4 v = *reinterpret_cast<const float4*>(in2 + (size_t)ii * kNb * nrhs + e);
+          return make_float4(-v.x, -v.y, -v.z, -v.w);
+        }
+        return *reinterpret_cast<const float4*>(in + (size_t)ii * kNb * nrhs + e);
+      },
+      accR, accI);
 #pragma unroll
   for (int t = 0; t < NT; ++t) reduce_waves_t<WV>(accR[t], accI[t], red);
   if ((threadIdx.x >> 6) != 0) return;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    if (!colok[t]) continue;
-    const float inv = F16 ? 1.0f / sc[t] : 1.0f;  // exact: sc is a power of two
-    float2* o = out + (size_t)io * kNb * nrhs + col[t];
+  if constexpr (PAIR) {
+    if (!colok[0]) return;
+    const float inv0 = F16 ? 1.0f / sc[0] : 1.0f, inv1 = F16 ? 1.0f / sc[1] : 1.0f;
+    float4* o = reinterpret_cast<float4*>(out + (size_t)io * kNb * nrhs + col[0]);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-      o[(size_t)row * nrhs] = make_float2(accR[t][r] * inv, accI[t][r] * inv);
+      o[(size_t)row * nrhs / 2] =
+          make_float4(accR[0][r] * inv0, accI[0][r] * inv0, accR[1][r] * inv1, accI[1][r] * inv1);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (!colok[t]) continue;
+      const float inv = F16 ? 1.0f / sc[t] : 1.0f;  // exact: sc is a power of two
+      float2* o = out + (size_t)io * kNb * nrhs + col[t];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+        o[(size_t)row * nrhs] = make_float2(accR[t][r] * inv, accI[t][r] * inv);
+      }
     }
   }
 }
@@ -382,7 +424,7 @@ __global__ __launch_bounds__(64 * WV) void coarse_mr_step_kernel(
                                  if (first) return rv;
                                  return mr_residual(rv, pold[o], ar[t], ai[t]);
                                },
-                               accR, accI);
+                               [](int, size_t, int) { return make_float4(0.f, 0.f, 0.f, 0.f); }, accR, accI);
 #pragma unroll
   for (int t = 0; t < NT; ++t) reduce_waves_t<WV>(accR[t], accI[t], red);
   // epilogue on wavefront 0: own-site r_i, x_i, p_i and the partial sums
@@ -687,12 +729,12 @@ hipError_t launch_column_scale(const void* in, long rows, int nrhs, void* work, 
 
 namespace {
 
-template <bool F16, int WV, int NT>
+template <bool F16, int WV, int NT, bool PAIR = false>
 hipError_t launch_stencil_t(const Geom& g, int nrhs, const void* packed, const void* in, void* out, const float* scale,
                             hipStream_t s) {
   const int blocks = (int)((long)g.V * ((nrhs + 32 * NT - 1) / (32 * NT)));
   const int grid = ((blocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((coarse_mfma_kernel<F16, 0, WV, NT>), dim3(grid), dim3(64 * WV), 0, s, g, nrhs,
+  hipLaunchKernelGGL((coarse_mfma_kernel<F16, 0, WV, NT, PAIR>), dim3(grid), dim3(64 * WV), 0, s, g, nrhs,
                      static_cast<const uint4*>(packed), static_cast<const float2*>(in), static_cast<float2*>(out),
                      scale, blocks, 0, 9, nullptr);
   return hipGetLastError();
@@ -718,23 +760,32 @@ hipError_t launch_mr_t(const Geom& g, int nrhs, const void* packed, const void* 
 }  // namespace
 
 // cfg: launch shape of the BF16/FP16 stencil, bit 0 eight wavefronts per
-// workgroup (else four), bit 1 two 32-column tiles per workgroup (else one).
+// workgroup (else four); cfg >> 1 the column tiling: 0 one 32-column tile per
+// workgroup, 1 two, 2 two tiles as interleaved column pairs read with 16-byte
+// loads (fields are 16-byte aligned, which the entry points check).  The pair
+// form needs an even nrhs; for an odd one cfg 4 / 5 run as cfg 2 / 3 (the same
+// result).
 hipError_t launch_coarse_mfma(int f16, const Geom& g, int nb, int nrhs, const void* packed, const void* in, void* out,
                               const float* scale, hipStream_t s, int cfg) {
-  if (nb != kNb || cfg < 0 || cfg > 3) return hipErrorInvalidValue;
+  if (nb != kNb || cfg < 0 || cfg >= kLowpCfgs) return hipErrorInvalidValue;
+  if (cfg >= 4 && (nrhs & 1)) cfg -= 2;
   if (f16) {
     switch (cfg) {
       case 0: return launch_stencil_t<true, 4, 1>(g, nrhs, packed, in, out, scale, s);
       case 1: return launch_stencil_t<true, 8, 1>(g, nrhs, packed, in, out, scale, s);
       case 2: return launch_stencil_t<true, 4, 2>(g, nrhs, packed, in, out, scale, s);
-      default: return launch_stencil_t<true, 8, 2>(g, nrhs, packed, in, out, scale, s);
+      case 3: return launch_stencil_t<true, 8, 2>(g, nrhs, packed, in, out, scale, s);
+      case 4: return launch_stencil_t<true, 4, 2, true>(g, nrhs, packed, in, out, scale, s);
+      default: return launch_stencil_t<true, 8, 2, true>(g, nrhs, packed, in, out, scale, s);
     }
   }
   switch (cfg) {
     case 0: return launch_stencil_t<false, 4, 1>(g, nrhs, packed, in, out, scale, s);
     case 1: return launch_stencil_t<false, 8, 1>(g, nrhs, packed, in, out, scale, s);
     case 2: return launch_stencil_t<false, 4, 2>(g, nrhs, packed, in, out, scale, s);
-    default: return launch_stencil_t<false, 8, 2>(g, nrhs, packed, in, out, scale, s);
+    case 3: return launch_stencil_t<false, 8, 2>(g, nrhs, packed, in, out, scale, s);
+    case 4: return launch_stencil_t<false, 4, 2, true>(g, nrhs, packed, in, out, scale, s);
+    default: return launch_stencil_t<false, 8, 2, true>(g, nrhs, packed, in, out, scale, s);
   }
 }
 

@@ -75,6 +75,7 @@ struct FineCfg {
 
 // t-walk configuration of the checkerboard hop for one nrhs (FP32): spatial
 // block B and Ts output sites per run; on = 0 runs the tiled kernel.
+constexpr int kLowpCfgs = 6;        // launch shapes of the BF16/FP16 coarse stencil
 constexpr int kEoWalkMinBlock = 16;  // smallest spatial block a walk may use
 struct EoWalk {
   int on = 0;

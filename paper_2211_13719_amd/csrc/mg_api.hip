@@ -628,12 +628,14 @@ mrhs_status mrhs_mg_tune(mrhs_mg mg, const int32_t* nrhs_list, int32_t count) {
       }
       L.f32_valu[n] = (signed char)(e == hipSuccess && best[1] < best[0]);
       // launch shape of the BF16 / FP16 stencil: four or eight wavefronts per
-      // site, one or two 32-column tiles per workgroup (timed in BF16; the
-      // FP16 kernel has the same structure)
+      // site, one or two 32-column tiles per workgroup, the two as separate
+      // or interleaved columns (timed in BF16; the FP16 kernel has the same
+      // structure)
       float lbest = 1e30f;
       int lcfg = 0;
-      for (int c = 0; c < 4 && e == hipSuccess; ++c) {
-        if ((c & 2) && n <= 32) continue;  // a second tile would be empty
+      for (int c = 0; c < kLowpCfgs && e == hipSuccess; ++c) {
+        if (c >= 2 && n <= 32) continue;  // a second tile would be empty
+        if (c >= 4 && (n & 1)) continue;  // column pairs need an even nrhs
         std::vector<float> t;
         for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
           e = hipEventRecord(e0, ctx->stream);
@@ -735,9 +737,10 @@ mrhs_status mrhs_mg_set_lowp_cfg(mrhs_mg mg, int32_t level, int32_t nrhs, int32_
   if (st != MRHS_OK) return st;
   if (nrhs < 1 || nrhs > MRHS_MAX_NRHS)
     return fail(mg->ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
-  if (cfg < 0 || cfg > 3) return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "launch shape %d outside [0, 3]", cfg);
+  if (cfg < 0 || cfg >= kLowpCfgs)
+    return fail(mg->ctx, MRHS_ERR_INVALID_ARG, "launch shape %d outside [0, %d]", cfg, kLowpCfgs - 1);
   mg->lv[level].lowp_cfg[nrhs] = (signed char)cfg;
-  mg->lv[level].mr_cfg[nrhs] = (signed char)cfg;
+  mg->lv[level].mr_cfg[nrhs] = (signed char)(cfg >= 4 ? cfg - 2 : cfg);  // the MR step has no pair form
   ++mg->ctx->op_gen;  // captured V-cycles hold the previous shape
   return MRHS_OK;
 }

@@ -415,7 +415,6 @@ hipError_t sap_smooth(mrhs_mg mg, SolverState* st, void* x, void* r, const void*
   mrhs_ctx ctx = mg->ctx;
   const AggGeom& a = mg->lv[0].agg;
   hipStream_t s = st->stream;
-  const long rows = level_rows(mg, 0);
   hipError_t e = hipSuccess;
   for (int cyc = 0; cyc < nu && e == hipSuccess; ++cyc) {
     for (int c = 0; c < 2 && e == hipSuccess; ++c) {

@@ -327,13 +327,14 @@ def test_coarse_tune_keeps_parity(gpu_lib, cdims):
 
 
 @pytest.mark.parametrize("cdims", [(6, 6, 6, 6), (3, 3, 3, 3), (2, 3, 1, 2)])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 def test_coarse_lowp_launch_shapes(gpu_lib, cdims, cfg):
     """Every launch shape of the BF16/FP16 stencil (four or eight wavefronts per
-    site, one or two 32-column tiles per workgroup) against the oracle on the
-    rounded operands (1e-6) and on the exact ones (2e-2), with ragged column
-    counts (1, 33, 40) as well as full tiles; per column the result equals the
-    column applied alone (same shape)."""
+    site, one or two 32-column tiles per workgroup, the two separate or as
+    interleaved column pairs) against the oracle on the rounded operands (1e-6)
+    and on the exact ones (2e-2), with ragged column counts (1, 33, 40) as well
+    as full tiles (odd counts run the pair shapes as two separate tiles); per
+    column the result equals the column applied alone (same shape)."""
     import torch
 
     nb = 32
@@ -374,7 +375,7 @@ def test_coarse_tune_lowp_keeps_parity(gpu_lib):
     ns = [12, 48, 64]
     mg.tune(ns)
     for n in ns:
-        assert mg.get_lowp_tuning(1, n)["cfg"] in (0, 1, 2, 3)
+        assert mg.get_lowp_tuning(1, n)["cfg"] in range(6)
         e32 = synth.coarse_source(Vc, nb, n, 37, np.complex64)
         for fmt in ("bf16", "f16"):
             o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
@@ -407,6 +408,7 @@ def _mr_ref(B, b, cdims, iters, fmt):
 
 @pytest.mark.parametrize("cdims,cfg,prec", [
     ((3, 3, 3, 3), 0, "bf16"), ((3, 3, 3, 3), 1, "bf16"), ((3, 3, 3, 3), 2, "bf16"), ((3, 3, 3, 3), 3, "bf16"),
+    ((3, 3, 3, 3), 5, "bf16"),
     ((3, 3, 3, 2), 0, "bf16"),
     ((6, 6, 6, 6), 0, "bf16"),
     ((3, 3, 3, 3), 0, "f32"),
