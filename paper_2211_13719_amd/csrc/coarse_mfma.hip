@@ -170,13 +170,20 @@ __device__ __forceinline__ int cb_site(const Geom& g, int i, int p) {
 }
 
 // Neighbour of site s (coordinates x) in direction d of the stencil
-// (self, +x, -x, +y, -y, +z, -z, +t, -t), periodic.
+// (self, +x, -x, +y, -y, +z, -z, +t, -t), periodic.  Only constant indices
+// into the geometry: indexed by a per-lane direction it is read from memory,
+// and every such read waits for all loads issued before it, which would
+// serialise the units of a wavefront.
 __device__ __forceinline__ int stencil_nbr(const Geom& g, int s, const int (&x)[4], int d) {
-  if (d == 0) return s;
-  const int mu = (d - 1) >> 1;
-  const int c = x[mu] + (((d - 1) & 1) ? -1 : 1);
-  const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
-  return s + (cw - x[mu]) * g.stride[mu];
+  int off = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int fw = x[m] + 1 < g.L[m] ? g.stride[m] : g.stride[m] * (1 - g.L[m]);
+    const int bw = x[m] > 0 ? -g.stride[m] : g.stride[m] * (g.L[m] - 1);
+    off = d == 2 * m + 1 ? fw : off;
+    off = d == 2 * m + 2 ? bw : off;
+  }
+  return s + off;
 }
 
 // The stencil's work on one site, split into units (d, kc) = (direction,
@@ -200,7 +207,8 @@ __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int 
   static_assert(!PAIR || NT == 2, "column pairs fill two tiles");
   using O = Op<F16>;
   using vec = typename O::vec;
-  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wavefront index, and with it each unit's direction, is uniform
+  const int l = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int jh = 8 * (l >> 5);
   int x[4];
   {
@@ -319,19 +327,17 @@ __global__ __launch_bounds__(64 * WV) void coarse_mfma_kernel(Geom g, int nrhs, 
   }
   stencil_units<F16, WV, NT, PAIR>(
       g, s, io, EO, nrhs, Bp, bstride, colc, colok, sc,
+      // EO 3: minus the hop term, read from the second field (the field is
+      // selected before the load, so no branch separates the loads)
       [&](int ii, size_t e, int, int d) {
-        if (EO == 3 && d > 0) {  // minus the hop term, read from the second field
-          const float2 v = in2[(size_t)ii * kNb * nrhs + e];
-          return make_float2(-v.x, -v.y);
-        }
-        return in[(size_t)ii * kNb * nrhs + e];
+        const bool hop = EO == 3 && d > 0;
+        const float2 v = (hop ? in2 : in)[(size_t)ii * kNb * nrhs + e];
+        return hop ? make_float2(-v.x, -v.y) : v;
       },
       [&](int ii, size_t e, int d) {
-        if (EO == 3 && d > 0) {
-          const float4 v = *reinterpret_cast<const float4*>(in2 + (size_t)ii * kNb * nrhs + e);
-          return make_float4(-v.x, -v.y, -v.z, -v.w);
-        }
-        return *reinterpret_cast<const float4*>(in + (size_t)ii * kNb * nrhs + e);
+        const bool hop = EO == 3 && d > 0;
+        const float4 v = *reinterpret_cast<const float4*>((hop ? in2 : in) + (size_t)ii * kNb * nrhs + e);
+        return hop ? make_float4(-v.x, -v.y, -v.z, -v.w) : v;
       },
       accR, accI);
 #pragma unroll
@@ -384,11 +390,13 @@ __device__ __forceinline__ float2 mr_residual(float2 rv, float2 pv, float ar, fl
 //   a fixed order into a_i = <p_i, r_i> / ||p_i||^2 per column.
 // first: step 0, r_0 = rold as given, x untouched.  Fields [V][Nb][nrhs] FP32;
 // rold / pold and rnew / pnew are different buffers (ping-pong across steps).
-template <int WV, int NT>
+// The step is a template parameter: a run-time flag around the operand loads
+// becomes a branch per load, each waiting for the loads before it.
+template <int WV, int NT, bool first>
 __global__ __launch_bounds__(64 * WV) void coarse_mr_step_kernel(
     Geom g, int nrhs, const uint4* __restrict__ Bp, const float2* __restrict__ rold, const float2* __restrict__ pold,
     float2* __restrict__ rnew, float2* __restrict__ pnew, float2* __restrict__ x, const double2* __restrict__ aold,
-    double4* __restrict__ part, int nblocks, int first) {
+    double4* __restrict__ part, int nblocks) {
   __shared__ float red[WV / 2][64][32];
   __shared__ double4 dred[64];
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -421,8 +429,8 @@ __global__ __launch_bounds__(64 * WV) void coarse_mr_step_kernel(
                                [&](int ii, size_t e, int t, int) {
                                  const size_t o = (size_t)ii * kNb * nrhs + e;
                                  const float2 rv = rold[o];
-                                 if (first) return rv;
-                                 return mr_residual(rv, pold[o], ar[t], ai[t]);
+                                 if constexpr (first) return rv;
+                                 else return mr_residual(rv, pold[o], ar[t], ai[t]);
                                },
                                [](int, size_t, int) { return make_float4(0.f, 0.f, 0.f, 0.f); }, accR, accI);
 #pragma unroll
@@ -434,28 +442,45 @@ __global__ __launch_bounds__(64 * WV) void coarse_mr_step_kernel(
   if (wv == 0) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      if (!colok[t]) continue;
-      const size_t base = (size_t)s * kNb * nrhs + col[t];
+      // the loads of eight rows first (clamped column), then their arithmetic
+      // and stores: interleaved, each load would wait for the stores before
+      // it; eight rows at a time bound the registers
+      const size_t base = (size_t)s * kNb * nrhs + colc[t];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-        const size_t o = base + (size_t)row * nrhs;
-        const float2 rv = rold[o];
-        float2 ri = rv;
-        if (!first) {
-          ri = mr_residual(rv, pold[o], ar[t], ai[t]);
-          float2 xv = x[o];
-          xv.x = fmaf(ar[t], rv.x, fmaf(-ai[t], rv.y, xv.x));
-          xv.y = fmaf(ar[t], rv.y, fmaf(ai[t], rv.x, xv.y));
-          x[o] = xv;
-          rnew[o] = ri;
+      for (int h = 0; h < 16; h += 8) {
+        float2 rv[8], pv[8], xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int r = h + q;
+          const size_t o = base + (size_t)(8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * nrhs;
+          rv[q] = rold[o];
+          if constexpr (!first) {
+            pv[q] = pold[o];
+            xv[q] = x[o];
+          }
         }
-        const float2 p = make_float2(accR[t][r], accI[t][r]);
-        pnew[o] = p;
-        const double px = p.x, py = p.y, rx = ri.x, ry = ri.y;
-        sum[t].x = fma(px, rx, fma(py, ry, sum[t].x));
-        sum[t].y = fma(px, ry, fma(-py, rx, sum[t].y));
-        sum[t].z = fma(px, px, fma(py, py, sum[t].z));
+        if (colok[t]) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int r = h + q;
+            const size_t o = base + (size_t)(8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * nrhs;
+            float2 ri = rv[q];
+            if constexpr (!first) {
+              ri = mr_residual(rv[q], pv[q], ar[t], ai[t]);
+              float2 xn = xv[q];
+              xn.x = fmaf(ar[t], rv[q].x, fmaf(-ai[t], rv[q].y, xn.x));
+              xn.y = fmaf(ar[t], rv[q].y, fmaf(ai[t], rv[q].x, xn.y));
+              x[o] = xn;
+              rnew[o] = ri;
+            }
+            const float2 p = make_float2(accR[t][r], accI[t][r]);
+            pnew[o] = p;
+            const double px = p.x, py = p.y, rx = ri.x, ry = ri.y;
+            sum[t].x = fma(px, rx, fma(py, ry, sum[t].x));
+            sum[t].y = fma(px, ry, fma(-py, rx, sum[t].y));
+            sum[t].z = fma(px, px, fma(py, py, sum[t].z));
+          }
+        }
       }
     }
   }
@@ -565,14 +590,8 @@ __global__ __launch_bounds__(256) void coarse_mfma_f32_kernel(Geom g, int nrhs, 
   }
   f32x16 accR = {}, accI = {};
   const int d0 = EO == 1 ? 1 : 0, d1 = EO == 2 ? 1 : 9;
-  for (int d = d0 + (threadIdx.x >> 6); d < d1; d += 4) {
-    int nbr = s;
-    if (d > 0) {
-      const int mu = (d - 1) >> 1;
-      const int c = x[mu] + (((d - 1) & 1) ? -1 : 1);
-      const int cw = c < 0 ? g.L[mu] - 1 : (c >= g.L[mu] ? 0 : c);
-      nbr = s + (cw - x[mu]) * g.stride[mu];
-    }
+  for (int d = d0 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); d < d1; d += 4) {
+    const int nbr = stencil_nbr(g, s, x, d);
     const int ii = EO == 1 ? nbr / 2 : (EO == 2 ? io : nbr);  // input row
     const float4* bp = Bp + ((size_t)s * bstride + d) * 2 * 64 * 4;
     float br[16], bi[16];
@@ -745,11 +764,11 @@ hipError_t launch_mr_t(const Geom& g, int nrhs, const void* packed, const void* 
                        void* pnew, void* x, const void* aold, void* anew, void* part, int first, hipStream_t s) {
   const int blocks = (int)((long)g.V * ((nrhs + 32 * NT - 1) / (32 * NT)));
   const int grid = ((blocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((coarse_mr_step_kernel<WV, NT>), dim3(grid), dim3(64 * WV), 0, s, g, nrhs,
-                     static_cast<const uint4*>(packed), static_cast<const float2*>(rold),
-                     static_cast<const float2*>(pold), static_cast<float2*>(rnew), static_cast<float2*>(pnew),
-                     static_cast<float2*>(x), static_cast<const double2*>(aold), static_cast<double4*>(part), blocks,
-                     first);
+  auto k = first ? coarse_mr_step_kernel<WV, NT, true> : coarse_mr_step_kernel<WV, NT, false>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WV), 0, s, g, nrhs, static_cast<const uint4*>(packed),
+                     static_cast<const float2*>(rold), static_cast<const float2*>(pold), static_cast<float2*>(rnew),
+                     static_cast<float2*>(pnew), static_cast<float2*>(x), static_cast<const double2*>(aold),
+                     static_cast<double4*>(part), blocks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mr_site_alpha_kernel, dim3(nrhs), dim3(256), 0, s, static_cast<const double4*>(part), g.V, nrhs,
