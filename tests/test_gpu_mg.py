@@ -416,8 +416,8 @@ def _mr_ref(B, b, cdims, iters, fmt):
 def test_coarse_mr_solve_vs_emulation(gpu_lib, cdims, cfg, prec):
     """The coarsest-level MR solve: on levels of at most 1024 sites with BF16
     operands every step is one fused launch (stencil, per-site partial sums,
-    last-workgroup step length, update on the fly); 6^4 (1296 sites) and FP32
-    take the separate kernels.  Against an FP64 emulation of the same
+    update on the fly) and a small one that sums the partials into the step
+    length; 6^4 (1296 sites) and FP32 take the separate kernels.  Against an FP64 emulation of the same
     iteration in the device's number formats, for 1, 12, 40 and 64 RHS: one
     step agrees to the FP32 accumulation order (1e-5); over 16 steps an FP32
     rounding difference can move an operand across a BF16 rounding boundary
