@@ -89,11 +89,11 @@ FINE_SOURCES = ("fine.hip", "internal.h", "api.hip")
 # the launch configurations it was counted under.  `roofline.traffic` carries
 # it only while the kernel name, sources and configurations still match.
 FINE_TRAFFIC = {
-    "kernel": "fine_walk_kernel<2, 0>",
-    "sources": "d85e6171a54e7d59",
+    "kernel": "fine_walk_kernel<2, 0, false>",
+    "sources": "5dda44bc797bacd9",
     "configs": {"6": [2, [4, 4, 4, 3], 224], "12": [2, [24, 8, 2, 3], 224], "24": [2, [24, 8, 2, 3], 132],
                 "48": [2, [24, 4, 4, 3], 132], "64": [2, [6, 6, 6, 12], 132]},
-    "bytes_per_launch": 5.252e9,
+    "bytes_per_launch": 5.254e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
@@ -127,7 +127,7 @@ def fine_kernel_name(ctx, n):
     R = R or (2 if n % 2 == 0 else 1)
     occ = 4 if variant & 2 else 0
     if variant & 128:  # the t-walk kernel
-        return f"fine_walk_kernel<{R}, {occ}>"
+        return f"fine_walk_kernel<{R}, {occ}, false>"  # false: D itself, not the fused residual
     return f"fine_kernel<float, {R}, 0, true, true, {occ}, HIP_vector_type<float, 2u> >"
 
 
