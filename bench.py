@@ -8,7 +8,8 @@ One step is one pass over every operator of the hot path, each on its
 workload shape (inputs resident in device memory, all synthetic and seeded):
 
   fine D_wc      24^4, FP32, Haar SU(3) links, csw 1.0, kappa 0.13, antiperiodic t,
-                 Gaussian sources; one apply for each Nrhs in 1, 6, 12, 24, 48, 64
+                 Gaussian sources; one apply for each Nrhs in 1, 6, 12, 24, 48, 64;
+                 the FP64 operator (the outer solver's residuals) at Nrhs 1, 12, 48
   coarse D_c     Galerkin blocks of that operator (16 Gaussian vectors per step,
                  FP64 block-orthonormalised, 4^4 then 2^4 aggregates): 6^4 and 3^4
                  coarse lattices, Nb = 32, Nrhs in 12, 24, 48, 64; FP32 vector ALU
@@ -27,7 +28,7 @@ caches); `roofline` is for the dominant kernel.  After the timed region (not par
 mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels
 and intergrid, graph-replayed V-cycle) on 24^3 x 128 smooth links at the bare
 mass stored in tests/golden/smooth_links_mass.json, for batches of 12, 24 and
-48 RHS (FGMRES(8), or the longest restart whose fields fit in the free HBM),
+48 RHS (FGMRES(5), or the longest restart whose fields fit in the free HBM),
 and the same solver on one RHS with FP32 coarse levels, in seconds per RHS to
 a true residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on
 the host's cores (a process pool over right-hand sides) on bounded samples
@@ -53,6 +54,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DIMS = (24, 24, 24, 24)
 KAPPA, CSW = 0.13, 1.0
 NRHS_FINE = (1, 6, 12, 24, 48, 64)
+NRHS_F64 = (1, 12, 48)  # the FP64 operator of the outer solver's residuals, in the step beside the FP32 one
 NRHS_COARSE = (12, 24, 48, 64)
 N_INTER = 24
 NB = 32
@@ -364,6 +366,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
     ctx.tune(sorted({1, 16, *nrhs_list}), cache)
     eo_hop = {str(n): dict(zip(("walk", "rhs_per_thread", "tile", "us", "us_tiled"), ctx.get_eo_walk(n)))
               for n in sorted({1, *nrhs_list})}
+    f64_op = {str(n): dict(zip(("walk", "tile", "variant", "us", "us_tiled"), ctx.get_f64_walk(n)))
+              for n in sorted({1, *nrhs_list})}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     t0 = time.perf_counter()
     for l in range(2):
@@ -506,6 +510,7 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         "mrhs_sap_smoother": sap,
         "mrhs_other_krylov_basis": other_basis,
         "eo_hop_kernel": eo_hop,
+        "fine_f64_kernel": f64_op,
         "config": f"FP64 FGMRES({SOLVE_RESTART}, shorter where the batch's fields would not fit in HBM) with the "
                   f"Krylov basis in {'FP32 between FP64 restarts' if SOLVE_KRYLOV_F32 else 'FP64'} (both MRHS and "
                   f"SRHS), set-up {SOLVE_SETUP}, V-cycle {SOLVE_VC}; MRHS: BF16 coarse "
@@ -586,6 +591,8 @@ def main():
     tuning = {str(n): dict(zip(("rhs_per_thread", "tile", "variant", "tuned_us"), ctx.get_tuning(n))) for n in NRHS_FINE}
     eo_tuning = {str(n): dict(zip(("walk", "rhs_per_thread", "tile", "us", "us_tiled"), ctx.get_eo_walk(n)))
                  for n in NRHS_FINE}
+    f64_tuning = {str(n): dict(zip(("walk", "tile", "variant", "us", "us_tiled"), ctx.get_f64_walk(n)))
+                  for n in NRHS_F64}
     mg = mrhs.Multigrid(ctx, [(4, 4, 4, 4), (2, 2, 2, 2)], [16, 16])
     mg.set_basis(0, synth.gaussian_vectors(V, 16, 12, 300))
     mg.block_orthonormalise(0)
@@ -602,6 +609,10 @@ def main():
         x = torch.from_numpy(np.ascontiguousarray(src[:, :, :n])).to(dev)
         fine[n] = (x, torch.empty_like(x))
     del src
+    fine64 = {}
+    for n in NRHS_F64:
+        x = fine[n][0].to(torch.complex128)
+        fine64[n] = (x, torch.empty_like(x))
     coarse = {}
     for lev in (1, 2):
         for n in NRHS_COARSE:
@@ -622,6 +633,9 @@ def main():
     for n in NRHS_FINE:
         x, yf = fine[n]
         ops.append((("dwc", n), FLOPS_DWC * V * n, fine_bytes(V, n), lambda x=x, yf=yf: ctx.dwc(yf, x)))
+    for n in NRHS_F64:
+        x, yf = fine64[n]
+        ops.append((("dwc_f64", n), FLOPS_DWC * V * n, 2 * fine_bytes(V, n), lambda x=x, yf=yf: ctx.dwc(yf, x)))
     for lev in (1, 2):
         Vc = mg.volume[lev]
         for prec in ("f32", "bf16", "f16"):
@@ -736,6 +750,8 @@ def main():
             prec = "fp16 operands, fp32 accumulation"
         elif name in ("dot", "norm", "block_normalise"):
             prec = "fp32 inputs, fp64 sums"
+        elif name == "dwc_f64":
+            prec = "fp64"
         else:
             prec = "fp32"
         mix[prec] = mix.get(prec, 0.0) + flops / 1e9
@@ -743,8 +759,8 @@ def main():
         "gflops": round(total_flops / (ms_per_step * 1e-3) / 1e9, 1),
         "ms_per_step": round(ms_per_step, 4),
         "gflop_per_step_by_precision": {k: round(v, 2) for k, v in mix.items()},
-        "note": "all ops of one step (fine D_wc, coarse stencils in fp32/bf16/fp16, intergrid, reductions) over the "
-                "step's wall time; a mixed-precision figure, not an fp32 rate",
+        "note": "all ops of one step (fine D_wc in fp32 and fp64, coarse stencils in fp32/bf16/fp16, intergrid, "
+                "reductions) over the step's wall time; a mixed-precision figure, not an fp32 rate",
     }
 
     result = {
@@ -791,6 +807,7 @@ def main():
         "evenodd": evenodd,
         "fine_tuning": tuning,
         "eo_hop_tuning": eo_tuning,
+        "fine_f64_tuning": f64_tuning,
         "coarse_f32_tuning": coarse_tuning,
         "fine_sources": fine_sources_digest(),
         "solve": None,

@@ -510,7 +510,9 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
  * fastest for later FP32 applies of that nrhs on this context.  All
  * configurations give bit-identical results.  On lattices with even extents
  * it also chooses the checkerboard hop's kernel (tiled or t-walk, see
- * mrhs_set_eo_walk) per nrhs, by timing, every call.  cache_path (may be NULL) names
+ * mrhs_set_eo_walk) per nrhs, by timing, every call, and, when the FP64
+ * links and clover are present, the FP64 operator's kernel (tiled or t-walk,
+ * see mrhs_set_f64_walk), also timed every call.  cache_path (may be NULL) names
  * a text file: existing entries for this device architecture, lattice and
  * nrhs are used without timing, new choices are appended.  Needs links and
  * clover.  Synchronises. */
@@ -525,6 +527,23 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
  * output pointer may be NULL. */
 mrhs_status mrhs_get_tuning(mrhs_ctx ctx, int32_t nrhs, int32_t* rhs_per_thread, int32_t tile[4], int32_t* curve,
                             float* us);
+/* mrhs_set_f64_walk: kernel of the FP64 operator A - kappa H (mrhs_dwc_apply
+ * with MRHS_F64 and the outer solver's residuals) for nrhs right-hand sides:
+ * tile = (Bx, By, Bz, Ts) selects the t-walk kernel, one right-hand side per
+ * thread (each thread walks Ts consecutive time slices of one site of a
+ * Bx x By x Bz spatial block, carrying its t-neighbours in registers; the
+ * block must divide the spatial extents and Ts the time extent); variant
+ * bit 0: non-temporal output stores, bit 1: the register budget of two
+ * workgroups per CU (else the compiler's); tile = NULL selects the tiled
+ * kernel.  The fields computed are bit-identical either way.  A shape that
+ * does not divide the lattice gets MRHS_ERR_INVALID_ARG. */
+mrhs_status mrhs_set_f64_walk(mrhs_ctx ctx, int32_t nrhs, const int32_t* tile, int32_t variant);
+/* mrhs_get_f64_walk: the FP64 operator's kernel for nrhs (*on = 0: tiled),
+ * its tile and variant bits, and the times the last mrhs_tune measured for
+ * it and for the tiled kernel (microseconds, 0 if not measured).  Any output
+ * pointer may be NULL. */
+mrhs_status mrhs_get_f64_walk(mrhs_ctx ctx, int32_t nrhs, int32_t* on, int32_t tile[4], int32_t* variant,
+                              float* us, float* us_tiled);
 
 #ifdef __cplusplus
 }

@@ -246,6 +246,20 @@ class Context:
         self._check(lib.mrhs_get_eo_walk(self._h, int(nrhs), C.byref(on), C.byref(r), t, C.byref(us), C.byref(ut)))
         return bool(on.value), r.value, tuple(t), float(us.value), float(ut.value)
 
+    def set_f64_walk(self, nrhs: int, tile=None, variant: int = 0):
+        """FP64 operator kernel for nrhs: tile (Bx, By, Bz, Ts) = t-walk, None = tiled;
+        variant bit 0 non-temporal stores, bit 1 two-workgroup register budget."""
+        t = None if tile is None else (C.c_int32 * 4)(*[int(v) for v in tile])
+        self._check(lib.mrhs_set_f64_walk(self._h, int(nrhs), t, int(variant)))
+
+    def get_f64_walk(self, nrhs: int):
+        """(on, tile, variant, us, us_tiled) of the FP64 operator for nrhs."""
+        on, v = C.c_int32(), C.c_int32()
+        t = (C.c_int32 * 4)()
+        us, ut = C.c_float(), C.c_float()
+        self._check(lib.mrhs_get_f64_walk(self._h, int(nrhs), C.byref(on), t, C.byref(v), C.byref(us), C.byref(ut)))
+        return bool(on.value), tuple(t), v.value, float(us.value), float(ut.value)
+
     def read_probe(self, buf, sweeps: int, grid: int, depth: int = 8) -> float:
         """Milliseconds for `sweeps` grid-stride reads of the device tensor buf,
         `depth` independent 16-byte loads in flight per thread."""

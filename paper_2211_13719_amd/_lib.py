@@ -54,6 +54,8 @@ SIGNATURES = {
     "mrhs_read_probe": (_i32, [_vp, _vp, _i64, _i32, _i32, _i32, _vp]),
     "mrhs_set_eo_walk": (_i32, [_vp, _i32, _vp, _i32]),
     "mrhs_get_eo_walk": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "mrhs_set_f64_walk": (_i32, [_vp, _i32, _vp, _i32]),
+    "mrhs_get_f64_walk": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mrhs_axpy": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32]),
     "mrhs_mg_create": (_i32, [_vp, _vp, C.POINTER(_vp)]),
     "mrhs_mg_destroy": (None, [_vp]),

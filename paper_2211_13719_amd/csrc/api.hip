@@ -112,7 +112,8 @@ mrhs_status fine_apply(mrhs_ctx ctx, int mode, void* out, const void* in, int32_
     e = launch_fine_f32(ctx->g, ctx->t_bc, mode, (float)ctx->kappa, ctx->U32.p, ctx->A32.p, in, out, nrhs,
                         ctx->stream, &ctx->fine_cfg[nrhs]);
   else
-    e = launch_fine_f64(ctx->g, ctx->t_bc, mode, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, nrhs, ctx->stream);
+    e = launch_fine_f64(ctx->g, ctx->t_bc, mode, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, nrhs, ctx->stream,
+                        &ctx->f64_walk[nrhs]);
   if (e != hipSuccess) return hip_fail(ctx, e, "fine operator launch");
   return MRHS_OK;
 }
@@ -520,6 +521,41 @@ mrhs_status mrhs_get_eo_walk(mrhs_ctx ctx, int32_t nrhs, int32_t* on, int32_t* r
     for (int m = 0; m < 3; ++m) tile[m] = w.B[m];
     tile[3] = w.Ts;
   }
+  if (us) *us = w.us;
+  if (us_tiled) *us_tiled = w.us_tiled;
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_set_f64_walk(mrhs_ctx ctx, int32_t nrhs, const int32_t* tile, int32_t variant) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  F64Walk w;
+  if (tile) {
+    if (!f64_walk_fits(ctx->g, tile, nrhs))
+      return fail(ctx, MRHS_ERR_INVALID_ARG, "FP64 walk %dx%dx%d x %d does not fit the lattice", tile[0], tile[1],
+                  tile[2], tile[3]);
+    w.on = 1;
+    for (int m = 0; m < 3; ++m) w.B[m] = tile[m];
+    w.Ts = tile[3];
+    w.nt = variant & 1;
+    w.occ = (variant & 2) ? 2 : 0;
+  }
+  ctx->f64_walk[nrhs] = w;
+  ctx->op_gen++;  // captured solver graphs hold the launch shape
+  return MRHS_OK;
+}
+
+mrhs_status mrhs_get_f64_walk(mrhs_ctx ctx, int32_t nrhs, int32_t* on, int32_t tile[4], int32_t* variant,
+                              float* us, float* us_tiled) {
+  if (!ctx) return MRHS_ERR_INVALID_ARG;
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS) return fail(ctx, MRHS_ERR_SHAPE, "nrhs = %d outside [1, %d]", nrhs, MRHS_MAX_NRHS);
+  const F64Walk& w = ctx->f64_walk[nrhs];
+  if (on) *on = w.on;
+  if (tile) {
+    for (int m = 0; m < 3; ++m) tile[m] = w.B[m];
+    tile[3] = w.Ts;
+  }
+  if (variant) *variant = w.nt + (w.occ == 2 ? 2 : 0);
   if (us) *us = w.us;
   if (us_tiled) *us_tiled = w.us_tiled;
   return MRHS_OK;

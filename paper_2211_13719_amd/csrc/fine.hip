@@ -631,48 +631,46 @@ struct WalkShape {
   long per;       // workgroups per XCD
 };
 
-template <int R>
-__device__ __forceinline__ void transport_dag(const cplx<float> (&uu)[3][3], const cplx<float> (&h)[2][3][R],
-                                              cplx<float> (&w)[2][3][R]) {
+template <int R, typename T>
+__device__ __forceinline__ void transport_dag(const cplx<T> (&uu)[3][3], const cplx<T> (&h)[2][3][R],
+                                              cplx<T> (&w)[2][3][R]) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int j = 0; j < R; ++j)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cplx<float> z = mk<float>(0, 0);
+        cplx<T> z = mk<T>(0, 0);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) cmac_conj<float>(z, uu[b][a], h[s][b][j]);
+        for (int b = 0; b < 3; ++b) cmac_conj<T>(z, uu[b][a], h[s][b][j]);
         w[s][a][j] = z;
       }
 }
 
-template <int R>
-__device__ __forceinline__ void transport(const cplx<float> (&uu)[3][3], const cplx<float> (&h)[2][3][R],
-                                          cplx<float> (&w)[2][3][R]) {
+template <int R, typename T>
+__device__ __forceinline__ void transport(const cplx<T> (&uu)[3][3], const cplx<T> (&h)[2][3][R],
+                                          cplx<T> (&w)[2][3][R]) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int j = 0; j < R; ++j)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cplx<float> z = mk<float>(0, 0);
+        cplx<T> z = mk<T>(0, 0);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) cmac<float>(z, uu[a][b], h[s][b][j]);
+        for (int b = 0; b < 3; ++b) cmac<T>(z, uu[a][b], h[s][b][j]);
         w[s][a][j] = z;
       }
 }
 
-// RES: out = bres - D in (the residual), the subtraction in FP32 after the
-// operator, exactly as a separate pass would do it.
-template <int R, int OCC, bool RES = false>
-__global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geom g, int nrhs, float kappa,
-                                                                           const cplx<float>* __restrict__ U,
-                                                                           const float* __restrict__ A,
-                                                                           const cplx<float>* __restrict__ in,
-                                                                           cplx<float>* __restrict__ out, WalkShape w,
-                                                                           int nt_out,
-                                                                           const cplx<float>* __restrict__ bres = nullptr) {
+// The walk in precision T (fields, links, clover and arithmetic).  RES:
+// out = bres - D in (the residual), the subtraction after the operator in the
+// same precision, exactly as a separate pass would do it.
+template <typename T, int R, bool RES>
+__device__ __forceinline__ void walk_body(const Geom& g, int nrhs, T kappa, const cplx<T>* __restrict__ U,
+                                          const T* __restrict__ A, const cplx<T>* __restrict__ in,
+                                          cplx<T>* __restrict__ out, const WalkShape& w, int nt_out,
+                                          const cplx<T>* __restrict__ bres) {
   const int hw = blockIdx.x;
   const long wgi = (long)(hw & 7) * w.per + (hw >> 3);
   if (wgi >= w.total_wg) return;
@@ -695,56 +693,56 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geo
   const int dzb = z > 0 ? -g.stride[2] : g.stride[2] * (g.L[2] - 1);
 
   const int t0 = seg * w.Ts;
-  cplx<float> self[4][3][R], bwd[2][3][R];
+  cplx<T> self[4][3][R], bwd[2][3][R];
   {
     const int sm = xs + Vs * ((t0 == 0 ? g.L[3] : t0) - 1);
-    cplx<float> p[4][3][R], h[2][3][R], uu[3][3];
-    load_spinor<float, R>(in, sm, nrhs, k0, p);
-    project<float, R, 3, -1>(p, h);
-    load_link<float, 3>(U + ((size_t)sm * 4 + 3) * 9, uu);
-    transport_dag<R>(uu, h, bwd);
-    load_spinor<float, R>(in, xs + Vs * t0, nrhs, k0, self);
+    cplx<T> p[4][3][R], h[2][3][R], uu[3][3];
+    load_spinor<T, R>(in, sm, nrhs, k0, p);
+    project<T, R, 3, -1>(p, h);
+    load_link<T, 3>(U + ((size_t)sm * 4 + 3) * 9, uu);
+    transport_dag<R, T>(uu, h, bwd);
+    load_spinor<T, R>(in, xs + Vs * t0, nrhs, k0, self);
   }
   for (int i = 0; i < w.Ts; ++i) {
     const int t = t0 + i;
     const int site = xs + Vs * t;
-    cplx<float> acc[4][3][R];
+    cplx<T> acc[4][3][R];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<float>(0, 0);
-    hop_dir<float, R, 0, true>(site, site + dxf, site + dxb, nrhs, k0, U, in, acc);
-    hop_dir<float, R, 1, true>(site, site + dyf, site + dyb, nrhs, k0, U, in, acc);
-    hop_dir<float, R, 2, true>(site, site + dzf, site + dzb, nrhs, k0, U, in, acc);
-    cplx<float> nxt[4][3][R];
-    load_spinor<float, R>(in, xs + Vs * (t + 1 == g.L[3] ? 0 : t + 1), nrhs, k0, nxt);
-    cplx<float> uu[3][3];
-    load_link<float, 3>(U + ((size_t)site * 4 + 3) * 9, uu);
+        for (int j = 0; j < R; ++j) acc[sp][c][j] = mk<T>(0, 0);
+    hop_dir<T, R, 0, true>(site, site + dxf, site + dxb, nrhs, k0, U, in, acc);
+    hop_dir<T, R, 1, true>(site, site + dyf, site + dyb, nrhs, k0, U, in, acc);
+    hop_dir<T, R, 2, true>(site, site + dzf, site + dzb, nrhs, k0, U, in, acc);
+    cplx<T> nxt[4][3][R];
+    load_spinor<T, R>(in, xs + Vs * (t + 1 == g.L[3] ? 0 : t + 1), nrhs, k0, nxt);
+    cplx<T> uu[3][3];
+    load_link<T, 3>(U + ((size_t)site * 4 + 3) * 9, uu);
     {
-      cplx<float> h[2][3][R], wv[2][3][R];
-      project<float, R, 3, +1>(nxt, h);
-      transport<R>(uu, h, wv);
-      reconstruct<float, R, 3, +1>(acc, wv);
-      pin<float, R>(acc);
+      cplx<T> h[2][3][R], wv[2][3][R];
+      project<T, R, 3, +1>(nxt, h);
+      transport<R, T>(uu, h, wv);
+      reconstruct<T, R, 3, +1>(acc, wv);
+      pin<T, R>(acc);
     }
-    reconstruct<float, R, 3, -1>(acc, bwd);
-    pin<float, R>(acc);
+    reconstruct<T, R, 3, -1>(acc, bwd);
+    pin<T, R>(acc);
     {
-      cplx<float> h[2][3][R];
-      project<float, R, 3, -1>(self, h);
-      transport_dag<R>(uu, h, bwd);
+      cplx<T> h[2][3][R];
+      project<T, R, 3, -1>(self, h);
+      transport_dag<R, T>(uu, h, bwd);
     }
-    cplx<float>* o = out + (size_t)site * 12 * nrhs + k0;
+    cplx<T>* o = out + (size_t)site * 12 * nrhs + k0;
 #pragma unroll
     for (int chi = 0; chi < 2; ++chi) {
-      cplx<float> xin[6][R], yout[6][R];
+      cplx<T> xin[6][R], yout[6][R];
 #pragma unroll
       for (int q = 0; q < 6; ++q)
 #pragma unroll
         for (int j = 0; j < R; ++j) xin[q][j] = self[(6 * chi + q) / 3][(6 * chi + q) % 3][j];
-      clover_block<float, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
+      clover_block<T, R>(A + ((size_t)site * 2 + chi) * 36, xin, yout);
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         const int sp = 2 * chi + q / 3, c = q % 3;
@@ -754,12 +752,12 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geo
           yout[q][j].y = fma(-kappa, acc[sp][c][j].y, yout[q][j].y);
         }
         if constexpr (RES) {
-          cplx<float> bv[R];
-          load_r<float, R>(bres + (size_t)site * 12 * nrhs + k0 + (6 * chi + q) * nrhs, bv);
+          cplx<T> bv[R];
+          load_r<T, R>(bres + (size_t)site * 12 * nrhs + k0 + (6 * chi + q) * nrhs, bv);
 #pragma unroll
-          for (int j = 0; j < R; ++j) yout[q][j] = sub<float>(bv[j], yout[q][j]);
+          for (int j = 0; j < R; ++j) yout[q][j] = sub<T>(bv[j], yout[q][j]);
         }
-        store_r<float, R>(o + (6 * chi + q) * nrhs, yout[q], nt_out);
+        store_r<T, R>(o + (6 * chi + q) * nrhs, yout[q], nt_out);
       }
     }
 #pragma unroll
@@ -769,6 +767,27 @@ __global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geo
 #pragma unroll
         for (int j = 0; j < R; ++j) self[sp][c][j] = nxt[sp][c][j];
   }
+}
+
+template <int R, int OCC, bool RES = false>
+__global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_kernel(Geom g, int nrhs, float kappa,
+                                                                           const cplx<float>* __restrict__ U,
+                                                                           const float* __restrict__ A,
+                                                                           const cplx<float>* __restrict__ in,
+                                                                           cplx<float>* __restrict__ out, WalkShape w,
+                                                                           int nt_out,
+                                                                           const cplx<float>* __restrict__ bres = nullptr) {
+  walk_body<float, R, RES>(g, nrhs, kappa, U, A, in, out, w, nt_out, bres);
+}
+
+// The FP64 operator of the outer solver's residuals, one RHS per thread.
+template <int OCC>
+__global__ __launch_bounds__(256, (OCC > 0 ? OCC : 1)) void fine_walk_f64_kernel(Geom g, int nrhs, double kappa,
+                                                            const cplx<double>* __restrict__ U,
+                                                            const double* __restrict__ A,
+                                                            const cplx<double>* __restrict__ in,
+                                                            cplx<double>* __restrict__ out, WalkShape w, int nt_out) {
+  walk_body<double, 1, false>(g, nrhs, kappa, U, A, in, out, w, nt_out, nullptr);
 }
 
 // Shape of a t-walk launch for tile T = (Bx, By, Bz, Ts) and nc = nrhs / chunks
@@ -1112,7 +1131,7 @@ __global__ __launch_bounds__(256) void hop_eo_walk_kernel(Geom g, int parity, in
     load_spinor<float, R>(in, sm >> 1, nrhs, k0, p);
     project<float, R, 3, -1>(p, h);
     load_link<float, 3>(U + ((size_t)sm * 4 + 3) * 9, uu);
-    transport_dag<R>(uu, h, bwd);
+    transport_dag<R, float>(uu, h, bwd);
   }
   for (int q = 0; q < w.Ts; ++q) {
     const int t = t0 + 2 * q;
@@ -1137,14 +1156,14 @@ __global__ __launch_bounds__(256) void hop_eo_walk_kernel(Geom g, int parity, in
       project<float, R, 3, +1>(p, hf);
       project<float, R, 3, -1>(p, hb);
       load_link<float, 3>(U + ((size_t)site * 4 + 3) * 9, uu);
-      transport<R>(uu, hf, wv);
+      transport<R, float>(uu, hf, wv);
       reconstruct<float, R, 3, +1>(acc, wv);
       pin<float, R>(acc);
       reconstruct<float, R, 3, -1>(acc, bwd);
       pin<float, R>(acc);
       // the backward t-hop of output t + 2: U_t(x, t + 1)^dag P psi(t + 1)
       load_link<float, 3>(U + ((size_t)sp1 * 4 + 3) * 9, uu);
-      transport_dag<R>(uu, hb, bwd);
+      transport_dag<R, float>(uu, hb, bwd);
     }
     hop_eo_epilogue<float, R, EPI, FULL2, ADDF, DOT>(site >> 1, site, nrhs, k0, valid, acc, out, Ablk, in2, coef,
                                                      dre, dim, dpp);
@@ -1439,8 +1458,23 @@ bool launch_fine_residual_f32(const Geom& g, float kappa, const void* U, const v
   return true;
 }
 
+bool f64_walk_fits(const Geom& g, const int tile[4], int nrhs) {
+  WalkShape w;
+  return walk_shape(g, tile, nrhs, 1, 1, w);
+}
+
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U, const void* A,
-                           const void* in, void* out, int nrhs, hipStream_t s) {
+                           const void* in, void* out, int nrhs, hipStream_t s, const F64Walk* fw) {
+  if (mode == 0 && fw && fw->on) {
+    const int tile[4] = {fw->B[0], fw->B[1], fw->B[2], fw->Ts};
+    WalkShape w;
+    if (!walk_shape(g, tile, nrhs, 1, 1, w)) return hipErrorInvalidValue;
+    auto k = fw->occ == 2 ? fine_walk_f64_kernel<2> : fine_walk_f64_kernel<0>;
+    hipLaunchKernelGGL(k, dim3((unsigned)(w.per * 8)), dim3(256), 0, s, g, nrhs, kappa,
+                       static_cast<const cplx<double>*>(U), static_cast<const double*>(A),
+                       static_cast<const cplx<double>*>(in), static_cast<cplx<double>*>(out), w, fw->nt);
+    return hipGetLastError();
+  }
   return launch_fine<double>(g, t_bc, mode, kappa, U, A, in, out, nrhs, s, nullptr);
 }
 

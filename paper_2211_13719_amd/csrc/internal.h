@@ -86,6 +86,18 @@ struct EoWalk {
   float us_tiled = 0.f;  // the tiled kernel's time in the same measurement
 };
 
+// The FP64 operator as a t-walk (one RHS per thread): spatial block B and
+// time slices per thread Ts; off means the tiled kernel.
+struct F64Walk {
+  int on = 0;
+  int B[3] = {0, 0, 0};
+  int Ts = 0;
+  int nt = 0;            // non-temporal output stores
+  int occ = 0;           // register budget: 0 the compiler's, 2 for two workgroups per CU
+  float us = 0.f;        // measured time of the choice (0 if set by hand)
+  float us_tiled = 0.f;  // the tiled kernel's time in the same measurement
+};
+
 struct DirFilter {
   int sign = 2;
   int mu = 0;
@@ -128,6 +140,7 @@ struct mrhs_ctx_s {
   // autotuned launch configurations of the FP32 fine kernel, by nrhs
   mrhs::FineCfg fine_cfg[MRHS_MAX_NRHS + 1];
   mrhs::EoWalk eo_walk[MRHS_MAX_NRHS + 1];
+  mrhs::F64Walk f64_walk[MRHS_MAX_NRHS + 1];
 
   // checkerboard tables (per parity, four int4 per site, and the traversal
   // order of its sites) and the inverse clover blocks, built on first use; an
@@ -176,8 +189,12 @@ hipError_t launch_fine_f32(const Geom& g, int t_bc, int mode, float kappa, const
 // false with nothing launched
 bool launch_fine_residual_f32(const Geom& g, float kappa, const void* U, const void* A, const void* x, const void* b,
                               void* r, int nrhs, hipStream_t s, const FineCfg* cfg, hipError_t* err);
+// fw (mode 0 only): the t-walk instead of the tiled kernel when fw->on
 hipError_t launch_fine_f64(const Geom& g, int t_bc, int mode, double kappa, const void* U,
-                           const void* A, const void* in, void* out, int nrhs, hipStream_t s);
+                           const void* A, const void* in, void* out, int nrhs, hipStream_t s,
+                           const F64Walk* fw = nullptr);
+// whether the FP64 walk's tile (B, Ts) divides the lattice
+bool f64_walk_fits(const Geom& g, const int tile[4], int nrhs);
 // D = A - kappa H in FP64 on an FP32 input field (widened exactly on load)
 hipError_t launch_fine_f64_in32(const Geom& g, double kappa, const void* U, const void* A, const void* in, void* out,
                                 int nrhs, hipStream_t s, const FineCfg* cfg = nullptr);

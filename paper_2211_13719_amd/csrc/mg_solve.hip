@@ -918,7 +918,8 @@ mrhs_status mrhs_mg_solve(mrhs_mg mg, void* x, const void* b, int32_t nrhs, cons
   auto Vj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->V64.p) + (size_t)j * fv); };
   auto Zj = [&](int j) { return static_cast<void*>(static_cast<char*>(st->Z32.p) + (size_t)j * f32); };
   auto D64 = [&](void* out, const void* in) {
-    return launch_fine_f64(ctx->g, ctx->t_bc, 0, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, n, ss);
+    return launch_fine_f64(ctx->g, ctx->t_bc, 0, ctx->kappa, ctx->U64.p, ctx->A64.p, in, out, n, ss,
+                           &ctx->f64_walk[n]);
   };
   auto norms = [&](const void* a, std::vector<double>& q, int prec64 = 1) -> mrhs_status {
     SOLVER_HIP(launch_dot(prec64, 1, a, a, rows, n, st->qn.p, st->part.p, ss));

@@ -418,6 +418,82 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
     release(part);
     ctx->op_gen++;  // captured V-cycles hold the hop's launch shape
   }
+  // The FP64 operator (the outer solver's residuals): tiled kernel or t-walk
+  // with one RHS per thread, timed per nrhs on FP64 scratch fields (the FP32
+  // scratch input widened); every walk candidate of the FP32 tuning, then the
+  // register budget and the store kind.  Bit-identical either way, so chosen afresh by every call and
+  // not cached.
+  if (e == hipSuccess && ctx->U64.p && ctx->A64.p) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release(out);
+    Buffer in64, out64;
+    mrhs_status fst = ensure(ctx, in64, 2 * bytes);
+    if (fst == MRHS_OK) fst = ensure(ctx, out64, 2 * bytes);
+    if (fst == MRHS_OK) {
+      e = launch_convert_f32_to_f64(static_cast<const float*>(in.p), static_cast<double*>(in64.p), bytes / 4,
+                                    ctx->stream);
+      for (int i = 0; i < count && e == hipSuccess; ++i) {
+        const int n = nrhs_list[i];
+        auto time64 = [&](const F64Walk& w, float& us) -> hipError_t {
+          std::vector<float> t;
+          hipError_t err = hipSuccess;
+          for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+            err = hipEventRecord(e0, ctx->stream);
+            if (err == hipSuccess)
+              err = launch_fine_f64(ctx->g, ctx->t_bc, 0, ctx->kappa, ctx->U64.p, ctx->A64.p, in64.p, out64.p, n,
+                                    ctx->stream, &w);
+            if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t.push_back(ms * 1000.f);
+          }
+          if (err != hipSuccess) return err;
+          std::sort(t.begin(), t.end());
+          us = t[t.size() / 2];
+          return hipSuccess;
+        };
+        F64Walk best;  // tiled
+        e = time64(best, best.us);
+        const float tiled = best.us;
+        for (const auto& t : walk_candidates(ctx->g)) {
+          if (e != hipSuccess) break;
+          const int tile[4] = {t[0], t[1], t[2], t[3]};
+          if (!f64_walk_fits(ctx->g, tile, n)) continue;
+          F64Walk w;
+          w.on = 1;
+          for (int m = 0; m < 3; ++m) w.B[m] = t[m];
+          w.Ts = t[3];
+          e = time64(w, w.us);
+          if (e == hipSuccess && w.us < best.us) best = w;
+        }
+        for (int stage = 0; stage < 2 && e == hipSuccess && best.on; ++stage) {
+          F64Walk w = best;
+          if (stage == 0)
+            w.occ = 2;  // a register budget for two workgroups per CU
+          else
+            w.nt = 1;  // non-temporal output stores
+          e = time64(w, w.us);
+          if (e == hipSuccess && w.us < best.us) best = w;
+        }
+        if (e == hipSuccess) {
+          best.us_tiled = tiled;
+          if (!best.on) best.us = tiled;
+          ctx->f64_walk[n] = best;
+        }
+      }
+      ctx->op_gen++;
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    release(in64);
+    release(out64);
+    if (fst != MRHS_OK) {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      release(in);
+      return fst;
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   hipError_t es = hipStreamSynchronize(ctx->stream);

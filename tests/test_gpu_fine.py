@@ -333,3 +333,55 @@ def test_walk_kernel_on_an_anisotropic_lattice(gpu_lib, tmp_path, tile, R, chunk
     torch.cuda.synchronize()
     assert torch.equal(y, y0)
     assert rel_l2(y.cpu().numpy(), O.dwc(U, A, KAPPA, psi, dims)) < 1e-6
+
+
+@pytest.mark.parametrize("tile,variant", [((2, 4, 2, 3), 0), ((3, 2, 4, 2), 1), ((6, 4, 8, 6), 2), ((3, 4, 2, 1), 3)])
+def test_f64_walk_kernel(gpu_lib, tile, variant):
+    """The FP64 operator as a t-walk (one RHS per thread; non-temporal stores
+    and the two-workgroup register budget by variant) on a lattice with four
+    different extents: bit for bit the tiled FP64 kernel and within rounding
+    of the FP64 oracle, for 1, 3 and 12 RHS; runs of Ts slices wrap through
+    the antiperiodic t boundary (Ts = 1 to a whole t extent)."""
+    import torch
+
+    dims = (6, 4, 8, 6)
+    U = synth.gauge_haar(dims, 1401)
+    A = O.clover_packed(U, dims, CSW, KAPPA)
+    ctx = _ctx(gpu_lib, dims, U)
+    for n in (1, 3, 12):
+        psi = synth.spinor_source(dims, n, 1402 + n)
+        x = _dev(torch, psi)
+        ctx.set_f64_walk(n, None)
+        y0 = torch.empty_like(x)
+        ctx.dwc(y0, x)
+        ctx.set_f64_walk(n, tile, variant)
+        on, t, v, _, _ = ctx.get_f64_walk(n)
+        assert on and t == tile and v == variant
+        y = torch.empty_like(x)
+        ctx.dwc(y, x)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0), n
+        assert rel_l2(y.cpu().numpy(), O.dwc(U, A, KAPPA, psi, dims)) < 1e-12
+
+
+def test_f64_walk_rejects_and_tunes(gpu_lib):
+    """A tile that does not divide the lattice is refused; mrhs_tune times the
+    FP64 kernels and whichever it keeps gives the tiled kernel's bits."""
+    import torch
+
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_haar(dims, 1501)
+    ctx = _ctx(gpu_lib, dims, U)
+    with pytest.raises(Exception):
+        ctx.set_f64_walk(4, (3, 8, 8, 8))
+    psi = synth.spinor_source(dims, 4, 1502)
+    x = _dev(torch, psi)
+    y0 = torch.empty_like(x)
+    ctx.dwc(y0, x)
+    ctx.tune([4])
+    on, tile, variant, us, us_tiled = ctx.get_f64_walk(4)
+    assert us_tiled > 0 and us > 0 and us <= us_tiled
+    y = torch.empty_like(x)
+    ctx.dwc(y, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0)
