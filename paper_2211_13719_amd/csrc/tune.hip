@@ -421,8 +421,9 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
   // The FP64 operator (the outer solver's residuals): tiled kernel or t-walk
   // with one RHS per thread, timed per nrhs on FP64 scratch fields (the FP32
   // scratch input widened); every walk candidate of the FP32 tuning, then the
-  // register budget and the store kind.  Bit-identical either way, so chosen afresh by every call and
-  // not cached.
+  // register budget and the store kind.  Bit-identical either way, so chosen
+  // afresh by every call and not cached; skipped (tiled kernel) if the FP64
+  // scratch fields do not fit.
   if (e == hipSuccess && ctx->U64.p && ctx->A64.p) {
     (void)hipStreamSynchronize(ctx->stream);
     release(out);
@@ -484,15 +485,10 @@ mrhs_status mrhs_tune(mrhs_ctx ctx, const int32_t* nrhs_list, int32_t count, con
       }
       ctx->op_gen++;
     }
+    // without room for the FP64 scratch fields the tiled kernel stays
     (void)hipStreamSynchronize(ctx->stream);
     release(in64);
     release(out64);
-    if (fst != MRHS_OK) {
-      if (e0) (void)hipEventDestroy(e0);
-      if (e1) (void)hipEventDestroy(e1);
-      release(in);
-      return fst;
-    }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
