@@ -597,7 +597,7 @@ hipError_t launch_r(const Geom& g, const int* order, T kappa, const void* U, con
   return hipGetLastError();
 }
 
-// ---- t-walk variant of D = A - kappa H in FP32 ---------------------------------
+// ---- t-walk variant of D = A - kappa H (FP32; FP64 with one RHS per thread) ----
 // Every thread owns one site of a spatial block (Bx x By x Bz), R right-hand
 // sides, and a run of Ts consecutive time slices that it visits in turn.  The
 // spinor psi(x, t+1) that slice t loads for its forward t-hop stays in
