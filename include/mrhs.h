@@ -121,8 +121,10 @@ mrhs_status mrhs_get_clover(mrhs_ctx ctx, void* A, mrhs_prec prec, int32_t on_de
  *              + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu),
  * i.e. the fine hopping term (D_hop of Sec. 4) fused with the clover term
  * (M_ooee of Sec. 4).  in/out: device fields [V][12][nrhs] in prec
- * (MRHS_F32 or MRHS_F64); they must not overlap.  MRHS_ERR_STATE before
- * links and clover are set. */
+ * (MRHS_F32 or MRHS_F64); they must not overlap.  The launch configuration
+ * is the one mrhs_tune chose for nrhs (FP32: mrhs_get_tuning; FP64:
+ * mrhs_get_f64_walk), else a default; every configuration gives the same
+ * bits.  MRHS_ERR_STATE before links and clover are set. */
 mrhs_status mrhs_dwc_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
 /* mrhs_hop_apply: out = H in (hopping term only, Sec. 4 D_hop). */
 mrhs_status mrhs_hop_apply(mrhs_ctx ctx, void* out, const void* in, int32_t nrhs, mrhs_prec prec);
