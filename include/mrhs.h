@@ -287,7 +287,8 @@ mrhs_status mrhs_mg_block_orthonormalise(mrhs_mg mg, int32_t level);
  * both fields and the sums in that precision (vector ALU).  prec MRHS_BF16:
  * FP32 fields, the basis and the input rounded to BF16 (nearest even) and
  * multiplied on the matrix cores with FP32 accumulation; needs n_v = 16 and
- * aggregates of a multiple of 16 sites, else MRHS_ERR_UNSUPPORTED. */
+ * aggregates of a multiple of 16 sites, at most 4096, else
+ * MRHS_ERR_UNSUPPORTED. */
 mrhs_status mrhs_restrict(mrhs_mg mg, int32_t level, void* coarse, const void* fine, int32_t nrhs, mrhs_prec prec);
 /* mrhs_prolong ("promote", Sec. 5): fine = P coarse,
  *   fine(x, c, k) = sum_i v_i(x)_c coarse(A(x), chi(c) n_v + i, k);

@@ -37,7 +37,7 @@ __device__ __forceinline__ int site_agg(const AggGeom& a, int s) {
 }
 
 // Matrix-core intergrid launchers (intergrid_mfma.hip): n_v = 16, aggregates
-// of a multiple of 16 sites; FP32 fields with either the FP32 basis on the
+// of a multiple of 16 sites, at most 4096; FP32 fields with either the FP32 basis on the
 // FP32 matrix cores or the packed BF16 basis on the BF16 ones.
 bool intergrid_mfma_supported(const AggGeom& a, int h, int nv);
 hipError_t launch_restrict_f32mfma(const AggGeom& a, int h, int nrhs, const void* W32, const void* f, void* y,

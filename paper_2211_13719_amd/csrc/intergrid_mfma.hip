@@ -49,10 +49,22 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 
 constexpr int kNV = 16;
 
-// Site of offset l + j inside aggregate A (consecutive offsets are consecutive
-// x when the aggregate's x-extent is a multiple of 4 and l is too).
-__device__ __forceinline__ int agg_site_j(const AggGeom& a, int A, int l, int j, int s0, bool fast) {
-  return fast ? s0 + j : agg_site(a, A, l + j);
+// The fine sites of aggregate A are computed once per workgroup into LDS:
+// the site of an offset takes a chain of integer divisions by run-time
+// extents, which per use would cost more vector instructions than the matrix
+// products.  Aggregates of up to kAggTab sites (8^4) take these kernels.
+constexpr int kAggTab = 4096;
+
+struct AggSites {
+  const int* tab;
+  __device__ __forceinline__ int operator()(int l) const { return tab[l]; }
+};
+
+// Fills tab (every thread of the workgroup takes part; ends with a barrier).
+__device__ __forceinline__ AggSites agg_sites(const AggGeom& a, int A, int nsa, int* tab) {
+  for (int l = threadIdx.x; l < nsa; l += blockDim.x) tab[l] = agg_site(a, A, l);
+  __syncthreads();
+  return AggSites{tab};
 }
 
 __device__ __forceinline__ bf16x8 to_bf16(const float (&x)[8]) {
@@ -84,7 +96,8 @@ __global__ __launch_bounds__(256) void restrict_bf16_kernel(AggGeom a, int h, in
   const bool kin = k < nrhs;
   const int i = m & 15;
   const bool imrow = m >= 16;
-  const bool fast = (a.b[0] & 3) == 0;
+  __shared__ int stab[kAggTab];
+  const AggSites site_of = agg_sites(a, A, nsa, stab);
   f32x16 acc = {};
   // four MFMA steps' loads in flight together, from clamped addresses with
   // the operands zeroed instead of branching (steps past the end and
@@ -100,10 +113,9 @@ __global__ __launch_bounds__(256) void restrict_bf16_kernel(AggGeom a, int h, in
       const int su = in ? s + u : s0;
       const int c = su / per_c;
       const int l0 = (su - c * per_c) * 8 + 4 * g;
-      const int site0 = agg_site(a, A, l0);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int site = agg_site_j(a, A, l0, j, site0, fast);
+        const int site = site_of(l0 + j);
         const size_t row = (size_t)site * ncomp + chi * h + c;
         const unsigned w = W[row * kNV + i];
         const float2 v = f[row * nrhs + kc];
@@ -154,7 +166,8 @@ __global__ __launch_bounds__(256) void prolong_bf16_kernel(AggGeom a, int h, int
   const int k = tile * 32 + m;
   const bool kin = k < nrhs;
   const bool imrow = m >= 16;
-  const bool fast = (a.b[0] & 3) == 0;
+  __shared__ int stab[kAggTab];
+  const AggSites site_of = agg_sites(a, A, nsa, stab);
   bf16x8 B[2];
 #pragma unroll
   for (int st = 0; st < 2; ++st) {
@@ -180,7 +193,7 @@ __global__ __launch_bounds__(256) void prolong_bf16_kernel(AggGeom a, int h, int
     const int c = r0 / nsa;
     const int l0 = r0 - c * nsa;
     // A operand: row r0 + (m & 15)
-    const size_t arow = (size_t)agg_site(a, A, l0 + (m & 15)) * ncomp + chi * h + c;
+    const size_t arow = (size_t)site_of(l0 + (m & 15)) * ncomp + chi * h + c;
 #pragma unroll
     for (int st = 0; st < 2; ++st) wt[st] = *reinterpret_cast<const u32x4*>(W + arow * kNV + st * 8 + 4 * g);
   };
@@ -200,10 +213,9 @@ __global__ __launch_bounds__(256) void prolong_bf16_kernel(AggGeom a, int h, int
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const int lb = l0 + 8 * half + 4 * g;
-        const int sb = agg_site(a, A, lb);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int site = agg_site_j(a, A, lb, j, sb, fast);
+          const int site = site_of(lb + j);
           const int p = 4 * half + j;
           f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
         }
@@ -242,6 +254,8 @@ __global__ __launch_bounds__(256) void restrict_f32_kernel(AggGeom a, int h, int
   const bool kin = k < nrhs;
   const int i = m & 15;
   const bool imrow = m >= 16;
+  __shared__ int stab[kAggTab];
+  const AggSites site_of = agg_sites(a, A, nsa, stab);
   f32x16 acc = {};
   if constexpr (H > 0) {
     // Software pipeline over the sites of the wavefront: the loads of the
@@ -255,7 +269,7 @@ __global__ __launch_bounds__(256) void restrict_f32_kernel(AggGeom a, int h, int
     auto load = [&](int lb, float2 (&w)[US][H], float2 (&v)[US][H]) {
 #pragma unroll
       for (int u = 0; u < US; ++u) {
-        const size_t row0 = (size_t)agg_site(a, A, lb + u < l1 ? lb + u : l0) * ncomp + chi * H;
+        const size_t row0 = (size_t)site_of(lb + u < l1 ? lb + u : l0) * ncomp + chi * H;
 #pragma unroll
         for (int c = 0; c < H; ++c) {
           w[u][c] = W[(row0 + c) * kNV + i];
@@ -287,7 +301,7 @@ __global__ __launch_bounds__(256) void restrict_f32_kernel(AggGeom a, int h, int
     }
   } else {
     for (int l = l0; l < l1; ++l) {
-      const size_t row0 = (size_t)agg_site(a, A, l) * ncomp + chi * h;
+      const size_t row0 = (size_t)site_of(l) * ncomp + chi * h;
       for (int c = 0; c < h; ++c) {
         const float2 wc = W[(row0 + c) * kNV + i];
         const float2 vc = kin ? f[(row0 + c) * nrhs + k] : make_float2(0.f, 0.f);
@@ -332,7 +346,8 @@ __global__ __launch_bounds__(256) void prolong_f32_kernel(AggGeom a, int h, int 
   const int k = tile * 32 + m;
   const bool kin = k < nrhs;
   const bool imrow = m >= 16;
-  const bool fast = (a.b[0] & 3) == 0;
+  __shared__ int stab[kAggTab];
+  const AggSites site_of = agg_sites(a, A, nsa, stab);
   float bv[kNV];
 #pragma unroll
   for (int i = 0; i < kNV; ++i) {
@@ -352,7 +367,7 @@ __global__ __launch_bounds__(256) void prolong_f32_kernel(AggGeom a, int h, int 
     const int r0 = tc * 16;
     const int c = r0 / nsa;
     const int lb0 = r0 - c * nsa;
-    const size_t arow = (size_t)agg_site(a, A, lb0 + (m & 15)) * ncomp + chi * h + c;
+    const size_t arow = (size_t)site_of(lb0 + (m & 15)) * ncomp + chi * h + c;
     const float4* wr = reinterpret_cast<const float4*>(W + arow * kNV);
 #pragma unroll
     for (int q = 0; q < kNV / 2; ++q) wt[q] = wr[q];  // basis values i = 2q and 2q + 1
@@ -376,10 +391,9 @@ __global__ __launch_bounds__(256) void prolong_f32_kernel(AggGeom a, int h, int 
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const int lb = lb0 + 8 * half + 4 * g;
-        const int sb = agg_site(a, A, lb);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int site = agg_site_j(a, A, lb, j, sb, fast);
+          const int site = site_of(lb + j);
           const int p = 4 * half + j;
           f[((size_t)site * ncomp + chi * h + c) * nrhs + k] = make_float2(acc[p], acc[p + 8]);
         }
@@ -409,7 +423,7 @@ __global__ __launch_bounds__(256) void pack_basis_bf16_kernel(const float2* __re
 
 bool intergrid_mfma_supported(const AggGeom& a, int h, int nv) {
   const int nsa = a.b[0] * a.b[1] * a.b[2] * a.b[3];
-  return nv == kNV && h >= 1 && nsa % 16 == 0;
+  return nv == kNV && h >= 1 && nsa % 16 == 0 && nsa <= kAggTab;
 }
 
 hipError_t launch_pack_basis_bf16(const void* basis32, void* out, long ncomplex, hipStream_t s) {
