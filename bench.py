@@ -95,7 +95,7 @@ FINE_TRAFFIC = {
     "sources": "2bd0a9649f6a2c6c",
     "configs": {"6": [2, [4, 4, 4, 3], 224], "12": [2, [24, 8, 2, 3], 224], "24": [2, [24, 8, 2, 3], 132],
                 "48": [2, [24, 4, 4, 3], 132], "64": [2, [6, 6, 6, 12], 132]},
-    "bytes_per_launch": 5.252e9,
+    "bytes_per_launch": 5.250e9,
     "note": "2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE per dispatch (copy-calibrated), mean over Nrhs 6, 12, 24, 48, 64; "
             "profiles/fine_kernel_hbm_counters_24x24x24x24.md",
 }
