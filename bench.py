@@ -2,7 +2,7 @@
 """Benchmark of the MRHS Wilson-clover multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu-baseline]
-                    [--tune-cache PATH | --retune] [--solve-nrhs 12,24,48] [--m0 M]
+                    [--tune-cache PATH | --retune] [--solve-nrhs 12,24,48,64] [--m0 M]
 
 One step is one pass over every operator of the hot path, each on its
 workload shape (inputs resident in device memory, all synthetic and seeded):
@@ -27,8 +27,8 @@ on, warm (back to back) and cold (after a 1 GiB device copy that flushes the
 caches); `roofline` is for the dominant kernel.  After the timed region (not part of `value`), `solve` times the
 mixed-precision MG solve (FP64 FGMRES, FP32 fine level, BF16 coarse levels
 and intergrid, graph-replayed V-cycle) on 24^3 x 128 smooth links at the bare
-mass stored in tests/golden/smooth_links_mass.json, for batches of 12, 24 and
-48 RHS (FGMRES(5), or the longest restart whose fields fit in the free HBM),
+mass stored in tests/golden/smooth_links_mass.json, for batches of 12, 24, 48
+and 64 RHS (FGMRES(5), or the longest restart whose fields fit in the free HBM),
 and the same solver on one RHS with FP32 coarse levels, in seconds per RHS to
 a true residual of 1e-10.  `cpu_baseline` times the FP64 CPU oracle on
 the host's cores (a process pool over right-hand sides) on bounded samples
@@ -426,6 +426,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n0, free0)
         alt = not SOLVE_MRHS_COARSE_EO
         st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", restart=m, **kw, **dict(vc, coarse_eo=alt))
+        if st["status"] not in (0, 7):
+            mg._check(st["status"])
         coarse_eo = {"coarse_eo": int(alt), "nrhs": n0, "s_per_rhs": round(st["seconds_total"] / n0, 4),
                      "seconds": round(st["seconds_total"], 3), "iters": st["iters"],
                      "converged": int(sum(st["converged"])), "max_true_resid": max(st["rel_resid"])}
@@ -435,6 +437,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         torch.cuda.empty_cache()
     except Exception as exc:
         coarse_eo = {"error": f"{type(exc).__name__}: {exc}"}
+        b = x = None
+        torch.cuda.empty_cache()
     # the same MRHS solve (first batch size) with Schwarz (SAP) smoothing on the
     # fine level: one cycle of four MR steps per 4^4 block (Sec. 9 outlook)
     sap = None
@@ -444,6 +448,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n0, free0)
         vs = dict(vc, fine_eo=False, fine_sap=True, sap_iters=SOLVE_SAP_ITERS, nu_post=SOLVE_SAP_CYCLES)
         st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", restart=m, **kw, **vs)
+        if st["status"] not in (0, 7):
+            mg._check(st["status"])
         sap = {"nrhs": n0, "cycles": SOLVE_SAP_CYCLES, "mr_steps_per_block": SOLVE_SAP_ITERS,
                "s_per_rhs": round(st["seconds_total"] / n0, 4), "seconds": round(st["seconds_total"], 3),
                "iters": st["iters"], "converged": int(sum(st["converged"])), "max_true_resid": max(st["rel_resid"])}
@@ -453,6 +459,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         torch.cuda.empty_cache()
     except Exception as exc:
         sap = {"error": f"{type(exc).__name__}: {exc}"}
+        b = x = None
+        torch.cuda.empty_cache()
     # the same MRHS solve (first batch size) with the other outer Krylov basis precision
     other_basis = None
     try:
@@ -462,6 +470,8 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         m = solve_restart(synth.volume(SOLVE_DIMS) * 12 * n0, free0, alt)
         st = mg.solve(x, b, use_graph=True, coarse_prec="bf16", restart=m,
                       **dict(kw, krylov_prec=mrhs.F32 if alt else mrhs.F64), **vc)
+        if st["status"] not in (0, 7):
+            mg._check(st["status"])
         other_basis = {"krylov_basis": "fp32" if alt else "fp64", "nrhs": n0, "restart": m,
                        "s_per_rhs": round(st["seconds_total"] / n0, 4), "seconds": round(st["seconds_total"], 3),
                        "iters": st["iters"], "converged": int(sum(st["converged"])),
@@ -472,6 +482,9 @@ def run_solve(mrhs, torch, synth, nrhs_list, mass, cache):
         torch.cuda.empty_cache()
     except Exception as exc:
         other_basis = {"error": f"{type(exc).__name__}: {exc}"}
+        print(f"[bench] MRHS solve N={n0} with the other Krylov basis failed: {exc}", file=sys.stderr, flush=True)
+        b = x = None
+        torch.cuda.empty_cache()
     # the comparator is the faster of the two fine smoothers on one RHS, with
     # the FP32 coarse stencil kernel tuned for one RHS
     mg.tune([1])
@@ -532,7 +545,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--solve-nrhs", default="12,24,48", help="comma-separated batch sizes of the MRHS solve")
+    ap.add_argument("--solve-nrhs", default="12,24,48,64", help="comma-separated batch sizes of the MRHS solve")
     ap.add_argument("--m0", type=float, default=None,
                     help="bare mass of the solve workload (default: the tuned value in tests/golden)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner text cache (read, appended)")
