@@ -203,12 +203,12 @@ def cpu_baseline():
     host's cores with a process pool over right-hand sides (they are
     independent), on a bounded sample of each workload:
 
-      dwc       24^4 D_wc (config 2 links and clover), 8 RHS per worker
+      dwc       24^4 D_wc (Haar links, csw 1.0, kappa 0.13), 8 RHS per worker
       coarse    6^4 coarse stencil, Nb 32 (Gaussian + 4 I blocks: the cost does
                 not depend on the values), 24 RHS per worker
       restrict  24^4 -> 6^4, 16 basis vectors (Gaussian: value-independent cost), 8 RHS per worker
       dot       24^4 fields, 24 RHS per worker
-      solve     the oracle's FP64 GMRES solve of config 1 (8^4), 1 RHS per worker
+      solve     the oracle's FP64 GMRES solve on 8^4 Haar links, 1 RHS per worker
 
     Runs before anything touches the GPU, so the forked workers hold no GPU
     state.  `value` is the D_wc rate in the metric's unit."""
@@ -257,7 +257,7 @@ def cpu_baseline():
         "unit": "GFLOP/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"FP64 oracle D_wc on 24^4 (config 2 links and clover), {per_op['dwc']['nrhs']} RHS, "
+        "sample": f"FP64 oracle D_wc on 24^4 (Haar links, csw 1.0, kappa 0.13), {per_op['dwc']['nrhs']} RHS, "
                   f"a pool of {cores} single-threaded numpy processes with 8 RHS each "
                   f"({per_op['dwc']['wall_s']:.1f} s wall); other ops in per_op",
         "nproc": os.cpu_count(),
@@ -793,12 +793,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "MRHS Wilson-clover hot path, one pass: fine D_wc 24^4 FP32 Nrhs 1..64 (Haar links, "
-                        "csw 1.0, kappa 0.13, antiperiodic t); Galerkin coarse stencil 6^4 and 3^4, Nb 32, "
+            "workload": "MRHS Wilson-clover hot path, one pass: fine D_wc 24^4 FP32 Nrhs 1..64 and FP64 Nrhs "
+                        "1, 12, 48 (Haar links, csw 1.0, kappa 0.13, antiperiodic t); Galerkin coarse stencil 6^4 "
+                        "and 3^4, Nb 32, "
                         "Nrhs 12..64, FP32/BF16/FP16; restrict/prolong/block-normalise 24^4<->6^4 and dot/norm, "
                         "Nrhs 24",
             "lattice": list(DIMS),
             "nrhs_fine": list(NRHS_FINE),
+            "nrhs_fine_f64": list(NRHS_F64),
             "nrhs_coarse": list(NRHS_COARSE),
         },
         "roofline": {

@@ -117,7 +117,7 @@ def test_blas_rejects_bad_args(ctx, gpu_lib):
         ctx.multi_dot([v] * 17, v)
 
 
-def test_dot_full_config4(ctx):
+def test_dot_full_size(ctx):
     """24^4 fine fields, 12 components, Nrhs = 24, FP32 inputs, FP64 sums."""
     import torch
 

@@ -39,7 +39,7 @@ def _dev(torch, a):
 
 @pytest.fixture(scope="module")
 def small(gpu_lib):
-    """Config 1: 8^4, Haar links, csw = 1, kappa = 0.13, antiperiodic t."""
+    """8^4, Haar links, csw = 1, kappa = 0.13, antiperiodic t."""
     dims = (8, 8, 8, 8)
     U = synth.gauge_haar(dims, 1001)
     A = O.clover_packed(U, dims, CSW, KAPPA)
@@ -62,7 +62,7 @@ def test_clover_build_nonsquare(gpu_lib):
     np.testing.assert_allclose(ctx.get_clover(), O.clover_packed(U, dims, CSW, KAPPA), atol=1e-14)
 
 
-def test_dwc_fp64_config1(small):
+def test_dwc_fp64_8888(small):
     import torch
 
     dims, U, A, ctx = small
@@ -143,7 +143,7 @@ def test_deterministic_repeat(small):
     assert torch.equal(y1, y2)
 
 
-# ---- config 2: 24^4, FP32, Nrhs in {1, 6, 12, 24, 48, 64} ---------------------------
+# ---- the benchmark's 24^4 FP32 workload, Nrhs in {1, 6, 12, 24, 48, 64} ----------
 
 NRHS_BIG = (1, 6, 12, 24, 48, 64)
 TUNE_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2211_13719_amd",
@@ -182,7 +182,7 @@ def _cached_lines(path, arch, dims):
 
 @pytest.fixture(scope="module")
 def big(gpu_lib, tmp_path_factory):
-    """Config 2 on the lattice the benchmark times, in the launch configurations
+    """The 24^4 workload the benchmark times, in the launch configurations
     it times: the fine kernel's tuned configuration per Nrhs comes from the
     committed autotuner cache (read from a copy, so that nothing is appended
     to the committed file), exactly as bench.py loads it."""

@@ -193,7 +193,7 @@ def test_restrict_prolong_bf16_unsupported(gpu_lib):
         mg.restrict(0, y, f, prec="bf16")
 
 
-def test_intergrid_config4_full(gpu_lib):
+def test_intergrid_full_size(gpu_lib):
     """24^4 fine lattice, 4^4 aggregates, 16 Gaussian vectors block-orthonormalised
     in FP64 on the GPU, restrict / prolong / block-normalise of Nrhs = 24 FP32 fields."""
     import torch
@@ -563,8 +563,8 @@ def test_galerkin_nonsquare_periodic(gpu_lib):
     assert rel(mg.get_blocks(1), want) < 1e-12
 
 
-def test_galerkin_config3_full(gpu_lib):
-    """Config 3 blocks at full size: 24^4 Haar links (csw 1, kappa 0.13), 16
+def test_galerkin_full_size(gpu_lib):
+    """Galerkin blocks at full size: 24^4 Haar links (csw 1, kappa 0.13), 16
     Gaussian vectors -> 6^4, then 16 more -> 3^4.  Checked by what holds at
     any size: D_c e = P^dag D P e for the GPU's own P and D (FP64), and the
     coarse gamma_5-hermiticity B_{-mu}(A + mu) = G5 B_{+mu}(A)^dag G5,
