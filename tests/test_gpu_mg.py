@@ -362,6 +362,36 @@ def test_coarse_lowp_launch_shapes(gpu_lib, cdims, cfg):
                 np.testing.assert_array_equal(host(ok)[:, :, 0], host(o)[:, :, k])
 
 
+@pytest.mark.parametrize("cdims", [(6, 6, 6, 6), (3, 3, 3, 3)])
+@pytest.mark.parametrize("cfg", [4, 5])
+def test_coarse_lowp_pair_shapes_even_counts(gpu_lib, cdims, cfg):
+    """The interleaved column-pair shapes at even column counts that leave
+    the last pairs of a 64-column group empty (2, 30) or one pair short (62):
+    against the rounded-operand oracle (1e-6), and each column equal to the
+    column applied alone."""
+    import torch
+
+    nb = 32
+    ctx, mg = coarse_mg(gpu_lib, cdims, nb)
+    Vc = synth.volume(cdims)
+    B = synth.gaussian_blocks(Vc, nb, 27)
+    mg.set_blocks(1, B)
+    for n in (2, 30, 62):
+        mg.set_lowp_cfg(1, n, cfg)
+        e32 = synth.coarse_source(Vc, nb, n, 31, np.complex64)
+        for fmt in ("bf16", "f16"):
+            o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+            mg.coarse_apply(1, o, dev(e32), fmt)
+            assert rel(host(o), O.coarse_apply_lowprec(B, e32, cdims, fmt)) < 1e-6, (n, fmt)
+        o = torch.empty((Vc, nb, n), dtype=torch.complex64, device="cuda")
+        mg.coarse_apply(1, o, dev(e32), "bf16")
+        mg.set_lowp_cfg(1, 1, cfg - 4)  # one column: the same wavefronts, one tile
+        for k in (0, n - 1):
+            ok = torch.empty((Vc, nb, 1), dtype=torch.complex64, device="cuda")
+            mg.coarse_apply(1, ok, dev(np.ascontiguousarray(e32[:, :, k:k + 1])), "bf16")
+            np.testing.assert_array_equal(host(ok)[:, :, 0], host(o)[:, :, k])
+
+
 def test_coarse_tune_lowp_keeps_parity(gpu_lib):
     """mrhs_mg_tune also picks the BF16/FP16 launch shape per Nrhs; whichever
     it picks matches the rounded-operand oracle."""

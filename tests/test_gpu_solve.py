@@ -608,3 +608,24 @@ def test_vcycle_same_with_walk_and_fused_residual(small, tmp_path):
         z_walk = run((4, 4, 2, 2), 2, fine_eo)
         z_tiled = run((2, 2, 2, 2), 0, fine_eo)
         assert torch.equal(z_tiled, z_walk), fine_eo
+
+
+def test_solve_same_with_f64_walk(small):
+    """The outer solver's FP64 residuals run the tiled FP64 kernel or the FP64
+    t-walk; the two give the same bits, so the whole solve does too."""
+    import torch
+
+    dims, U, A, ctx, mg = small
+    n = 4
+    b = dev(synth.spinor_source(dims, n, 9500))
+    out = []
+    for tile in (None, (4, 4, 4, 4), (8, 2, 4, 2)):
+        ctx.set_f64_walk(n, tile, 1 if tile else 0)
+        x = torch.zeros_like(b)
+        st = mg.solve(x, b, use_graph=False, coarse_prec="bf16", restart=6)
+        assert all(st["converged"])
+        out.append((st["iters"], x))
+    ctx.set_f64_walk(n, None)
+    for iters, x in out[1:]:
+        assert iters == out[0][0]
+        assert torch.equal(x, out[0][1])
