@@ -226,9 +226,8 @@ __device__ __forceinline__ void stencil_units(const Geom& g, int s, int io, int 
   // first matrix instruction, so a wavefront waits for memory once per batch
   // instead of once per unit (with one tile all of a wavefront's units form
   // one batch; with two tiles batches of three bound the registers, and for
-  // column pairs smaller batches buy occupancy: measured on 6^3x32 at 64
-  // columns, one-unit batches on four wavefronts run 129 us against 135 us
-  // for two and 153 us for the one-tile shape)
+  // column pairs smaller batches buy occupancy: one-unit batches on four
+  // wavefronts measured fastest, 3 wavefronts per SIMD against 2)
   constexpr int PB = NT == 1 ? KMAX : (PAIR ? (WV == 4 ? 1 : 2) : 3);
 #pragma unroll
   for (int k0 = 0; k0 < KMAX; k0 += PB) {
